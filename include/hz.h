@@ -1,0 +1,228 @@
+/*
+ * hz.h -- C ABI of libhz, an MI355X (gfx950) solver for the frequency-domain Helmholtz
+ * equation discretised with continuous P3 Lagrange elements on tetrahedra and solved by
+ * block FGMRES with a two-level optimized restricted additive Schwarz (ORAS)
+ * preconditioner, for many source right-hand sides at once.
+ *
+ * Method: Dolean, Jolivet, Operto, Tournier, "Large-scale frequency-domain seismic wave
+ * modeling on h-adaptive tetrahedral meshes with iterative solver and multi-level
+ * domain-decomposition preconditioners" (arXiv 2004.07930).  Each entry point below names
+ * the passage of that paper that defines what it computes.
+ *
+ * General conventions
+ *  - C11, no C++ types cross the ABI.  Complex numbers are interleaved (re, im) pairs of
+ *    double (complex128) unless stated otherwise.
+ *  - The caller owns every pointer it passes.  The library copies inputs before returning
+ *    and keeps no caller pointer, except serving requests, whose rhs / x / info buffers
+ *    must stay valid until the ticket completes.
+ *  - Handles (mesh, operator, ddm) are owned by the library and reference counted: an
+ *    operator pins its mesh, a ddm pins its operator.  0 is never a valid handle.
+ *  - Every function returns an hz_status; nothing throws or aborts across the ABI.
+ *    hz_last_error() holds a message for the last failure on the context.  After
+ *    HZ_ERR_HIP the context is poisoned and only hz_finalize is valid.
+ *  - Non-serving calls on one context must be serialised by the caller.  All GPU work of
+ *    a context runs on the stream given at hz_init (NULL = the null stream).
+ *  - Multi-RHS blocks are laid out [n_rhs][n_dofs] (each right-hand side contiguous).
+ *    *_mem arguments say whether a pointer is host (HZ_MEM_HOST) or device memory
+ *    (HZ_MEM_DEVICE) of the context's GPU.
+ */
+#ifndef HZ_H_
+#define HZ_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HZ_ABI_VERSION 1
+
+typedef enum {
+  HZ_OK = 0,
+  HZ_ERR_ARG = -1,            /* invalid argument (null pointer, bad size, NaN input ...) */
+  HZ_ERR_OOM = -2,            /* device allocation failed or over the memory budget      */
+  HZ_ERR_HIP = -3,            /* a HIP runtime call failed; the context is poisoned      */
+  HZ_ERR_NOT_CONVERGED = -4,  /* max_iter reached; x holds the best iterate              */
+  HZ_ERR_SINGULAR = -5,       /* a local or coarse factorisation met a zero pivot        */
+  HZ_ERR_BUSY = -6,           /* serving: request can never be admitted                   */
+  HZ_ERR_STATE = -7,          /* call not valid in the current state                      */
+  HZ_ERR_ABI = -8             /* struct_size / ABI version mismatch                       */
+} hz_status;
+
+typedef struct hz_ctx hz_ctx;
+typedef uint64_t hz_handle;
+
+enum { HZ_BC_NONE = 0, HZ_BC_IMPEDANCE = 1, HZ_BC_DIRICHLET = 2 };
+enum { HZ_PREC_C128 = 0, HZ_PREC_MIXED = 1 };
+enum { HZ_MEM_HOST = 0, HZ_MEM_DEVICE = 1 };
+
+typedef struct {
+  size_t struct_size;  /* sizeof(hz_init_opts)                                        */
+  int device;          /* HIP device ordinal                                           */
+  size_t hbm_budget;   /* bytes the serving admission may use; 0 = 90% of free memory  */
+  void* stream;        /* hipStream_t for all GPU work; NULL = null stream              */
+} hz_init_opts;
+
+/* Create a context on one GPU.  Builds the P3 reference tables on the device. */
+hz_status hz_init(hz_ctx** out, const hz_init_opts* opts);
+/* Destroy a context and everything it owns (waits for its GPU work). */
+void hz_finalize(hz_ctx* ctx);
+/* Message of the last failure on ctx (valid until the next call on ctx). */
+const char* hz_last_error(const hz_ctx* ctx);
+/* Drop the caller's reference to a handle. */
+hz_status hz_release(hz_ctx* ctx, hz_handle h);
+
+/*
+ * hz_mesh -- ingest a tetrahedral mesh and number its P3 degrees of freedom.
+ * Paper: section "Tetrahedral finite element method" (Lagrange P3 elements on a
+ * tetrahedral mesh of the domain).
+ *   tets    [n_tets][4] int32, 0-based vertex ids (any orientation)
+ *   coords  [n_verts][3] float64, z pointing down
+ *   face_bc nullable [n_tets][4] int8: tag of the face opposite local vertex v, read only
+ *           on boundary faces (faces of one tet): HZ_BC_IMPEDANCE (first-order absorbing)
+ *           or HZ_BC_DIRICHLET (free surface).  NULL = impedance everywhere.
+ * Dof numbering: every node gets an integer key -- vertex g: (g,-1,-1,0); edge lo<hi:
+ * (lo,hi,-1,0) at 2/3 lo + 1/3 hi and (lo,hi,-1,1) at 1/3 lo + 2/3 hi; face a<b<c:
+ * (a,b,c,0) -- and its id is the rank of the key in ascending lexicographic order.
+ * Also builds the CSR pattern of the global operator (columns ascending).
+ * Errors: HZ_ERR_ARG on null pointers, out-of-range vertex ids or degenerate tets.
+ */
+hz_status hz_mesh(hz_ctx* ctx, int64_t n_tets, const int32_t* tets, int64_t n_verts,
+                  const double* coords, const int8_t* face_bc, hz_handle* mesh, int64_t* n_dofs);
+
+/*
+ * hz_assemble -- element matrices and the global sparse operator A of eq. (2).
+ * Paper: eq. (1) (Helmholtz with k = omega / c, c complex in viscous media) and the
+ * boundary conditions stated after eq. (2).
+ *   velocity [n_tets] m/s (any consistent length unit), > 0, constant per tet
+ *   Q        nullable [n_tets] quality factors > 0: c = v (1 + i / (2 Q))
+ *   freq_hz  frequency f, omega = 2 pi f
+ * A = K - k^2 M + i k M_G (exp(+i omega t) convention; complex symmetric), Dirichlet dofs
+ * are identity rows/columns kept in the pattern.  Values are FP64 on the device, with a
+ * complex64 copy.  Errors: HZ_ERR_ARG on non-positive / non-finite coefficients.
+ */
+hz_status hz_assemble(hz_ctx* ctx, hz_handle mesh, const double* velocity, const double* Q,
+                      double freq_hz, hz_handle* op);
+
+typedef struct {
+  int64_t n_tets;
+  const int32_t* tets;   /* [n_tets][4] */
+  int64_t n_verts;
+  const double* coords;  /* [n_verts][3] */
+} hz_coarse_mesh;
+
+/*
+ * hz_setup_ddm -- overlapping decomposition, local Robin operators, their LDL^T factors
+ * and the coarse space.  Paper: eqs. (2lvl) and (oras) and the text around them.
+ *   partition [n_tets] int32 in [0, n_sub): non-overlapping subdomain of each tet
+ *   overlap   number of tet layers added (vertex adjacency), >= 0
+ *   coarse    NULL = one-level ORAS; else a P1 coarse mesh covering the fine one
+ *   precision HZ_PREC_C128 (factors, ORAS and coarse solve in complex128) or
+ *             HZ_PREC_MIXED (complex64 factors, ORAS and coarse solve; FGMRES in FP64)
+ * Errors: HZ_ERR_ARG (bad partition, fine node outside the coarse mesh), HZ_ERR_OOM.
+ * Tiny pivots are replaced by a threshold (static pivoting) and counted (hz_ddm_stats).
+ */
+hz_status hz_setup_ddm(hz_ctx* ctx, hz_handle op, const int32_t* partition, int32_t n_sub,
+                       int32_t overlap, const hz_coarse_mesh* coarse, int precision, hz_handle* ddm);
+
+typedef struct {
+  int32_t iters;        /* inner FGMRES iterations done for this column's block */
+  int32_t restarts;
+  double rel_residual;  /* explicit ||b - A x|| / ||b|| in FP64 */
+  int32_t status;       /* HZ_OK or HZ_ERR_NOT_CONVERGED */
+} hz_col_info;
+
+typedef struct {
+  size_t struct_size;   /* sizeof(hz_solve_opts) */
+  double tol;           /* per-column relative residual target (paper: backward error) */
+  int32_t max_iter;     /* total inner iterations allowed */
+  int32_t restart;      /* FGMRES restart length m (0 = default 40, capped by memory) */
+  int32_t fixed_iters;  /* > 0: run exactly this many steps in one cycle, ignore tol */
+  int32_t block;        /* max right-hand sides per Arnoldi block (0 = all, max 32) */
+} hz_solve_opts;
+
+/*
+ * hz_solve -- right-preconditioned block FGMRES(m) with two-level ORAS, x0 = 0.
+ * Paper: section "Domain decomposition preconditioner" (GMRES with M^{-1}, eq. 2lvl) and
+ * the stopping test ||A u - b|| / ||b|| <= eps of the FE section.  Classical Gram-Schmidt
+ * applied twice, CholQR2 block normalisation, Householder least squares, all FP64.
+ *   rhs [n_rhs][n_dofs] complex128, x same layout (may not alias rhs)
+ * Returns HZ_ERR_NOT_CONVERGED (x = best iterate, info filled) when max_iter is hit.
+ */
+hz_status hz_solve(hz_ctx* ctx, hz_handle ddm, int64_t n_rhs, const void* rhs, int rhs_mem,
+                   double tol, int32_t max_iter, void* x, int x_mem, hz_col_info* info);
+hz_status hz_solve_ex(hz_ctx* ctx, hz_handle ddm, int64_t n_rhs, const void* rhs, int rhs_mem,
+                      const hz_solve_opts* opts, void* x, int x_mem, hz_col_info* info);
+
+/*
+ * hz_point_sources -- load vectors of point sources: rhs[s][j] = amp_s phi_j(x_s), zero on
+ * Dirichlet dofs, the containing tet being the lowest id whose barycentrics are all
+ * >= -1e-12.  Paper: the point source of section "Numerical results".
+ *   xyz [n_src][3]; amp nullable [n_src] complex128 (NULL = 1); rhs [n_src][n_dofs] c128
+ * Errors: HZ_ERR_ARG if a source lies outside the mesh.
+ */
+hz_status hz_point_sources(hz_ctx* ctx, hz_handle mesh, int64_t n_src, const double* xyz,
+                           const double* amp, void* rhs, int rhs_mem);
+
+/*
+ * Building blocks exposed for parity tests and measurement (same kernels as hz_solve).
+ * hz_spmm:        y = A x for a block (FP64 operator), Paper eq. (2).
+ * hz_precond:     z = M^{-1} v (eq. 2lvl; eq. oras without a coarse space), in the ddm's
+ *                 precision, FP64 in and out.
+ * All blocks [n_rhs][n_dofs] complex128.
+ */
+hz_status hz_spmm(hz_ctx* ctx, hz_handle op, int64_t n_rhs, const void* x, int x_mem, void* y, int y_mem);
+hz_status hz_precond(hz_ctx* ctx, hz_handle ddm, int64_t n_rhs, const void* v, int v_mem, void* z, int z_mem);
+
+typedef struct {
+  int64_t n_dofs, nnz, n_sub;
+  int64_t local_dofs_total;   /* sum of overlapped subdomain sizes */
+  int64_t factor_entries;     /* stored entries of all L factors (incl. diagonal blocks) */
+  int64_t n_fronts, n_levels, max_front;
+  int64_t n_coarse;
+  int64_t static_pivots;      /* pivots replaced by the static threshold */
+  int64_t device_bytes;       /* device memory held by the ddm (operator excluded) */
+  double setup_seconds;
+} hz_ddm_stats;
+hz_status hz_ddm_stats_get(hz_ctx* ctx, hz_handle ddm, hz_ddm_stats* out);
+
+/* serving: continuous batching of solve requests (thread-safe) */
+typedef struct {
+  size_t struct_size;
+  hz_handle ddm;
+  int64_t n_rhs;
+  const void* rhs;   /* [n_rhs][n_dofs] complex128 */
+  void* x;           /* [n_rhs][n_dofs] complex128 */
+  int mem;           /* HZ_MEM_HOST or HZ_MEM_DEVICE, for both rhs and x */
+  double tol;
+  int32_t max_iter;
+  hz_col_info* info; /* [n_rhs] */
+} hz_request;
+
+typedef struct {
+  double p50_s, p99_s, sources_per_s;
+  int64_t completed, rejected;
+} hz_serve_stats;
+
+hz_status hz_serve_start(hz_ctx* ctx, int32_t max_slots);
+hz_status hz_serve_submit(hz_ctx* ctx, const hz_request* req, uint64_t* ticket);
+hz_status hz_serve_poll(hz_ctx* ctx, uint64_t ticket, int* done);
+hz_status hz_serve_wait(hz_ctx* ctx, uint64_t ticket, int32_t* status);
+hz_status hz_serve_stats_get(hz_ctx* ctx, hz_serve_stats* out);
+hz_status hz_serve_stop(hz_ctx* ctx);
+
+/* introspection for bit-exact parity tests (host output buffers) */
+hz_status hz_get_dofmap(hz_ctx* ctx, hz_handle mesh, int32_t* tet_dofs /*[n_tets][20]*/);
+hz_status hz_get_csr_size(hz_ctx* ctx, hz_handle op, int64_t* n, int64_t* nnz);
+hz_status hz_get_csr(hz_ctx* ctx, hz_handle op, int64_t* rowptr, int32_t* col, double* val /*c128*/);
+hz_status hz_get_subdomain_size(hz_ctx* ctx, hz_handle ddm, int32_t i, int64_t* n_i, int64_t* nnz_i);
+hz_status hz_get_subdomain(hz_ctx* ctx, hz_handle ddm, int32_t i, int32_t* gdofs, uint8_t* owned,
+                           int64_t* rowptr, int32_t* col, double* val /*c128, nullable*/);
+hz_status hz_get_coarse_size(hz_ctx* ctx, hz_handle ddm, int64_t* n_c, int64_t* nnz);
+hz_status hz_get_coarse(hz_ctx* ctx, hz_handle ddm, int64_t* rowptr, int32_t* col, double* val /*Z, real*/);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HZ_H_ */

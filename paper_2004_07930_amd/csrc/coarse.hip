@@ -1,0 +1,425 @@
+// Coarse space of the two-level preconditioner (paper eq. 2lvl):
+//   Q = Z E^{-1} Z^T,  E = Z^T A Z,
+// with Z the P1 interpolation from a coarse tetrahedral mesh: Z[j, c] is the barycentric
+// coordinate of coarse vertex c at fine node j, taken in the lowest-id coarse tet that
+// contains the node (|lambda| <= 1e-12 dropped, Dirichlet rows zero).  The paper solves
+// the coarse problem with 10 inner GMRES iterations; here E is factored by LU with partial
+// pivoting on the GPU and its inverse is formed once (same bytes per apply as two
+// triangular solves, but one fully parallel product).
+#include <algorithm>
+#include <cmath>
+
+#include "ddm.h"
+
+namespace hz {
+
+// ---------------------------------------------------------------- host: Z by point location
+
+void build_coarse_host(const Mesh& m, const hz_coarse_mesh* cm, CoarseSpace& cs) {
+  HZ_REQUIRE(cm->n_tets > 0 && cm->n_verts >= 4 && cm->tets && cm->coords, HZ_ERR_ARG, "coarse mesh: empty");
+  const int64_t CT = cm->n_tets, CV = cm->n_verts;
+  for (int64_t k = 0; k < 4 * CT; ++k)
+    HZ_REQUIRE(cm->tets[k] >= 0 && cm->tets[k] < CV, HZ_ERR_ARG, "coarse mesh: vertex id out of range");
+  cs.nc = CV;
+  // per coarse tet: p0 and J^{-1}
+  std::vector<double> Jinv(9 * CT), p0(3 * CT), lo(3 * CT), hi(3 * CT);
+  double gmin[3] = {INFINITY, INFINITY, INFINITY}, gmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t t = 0; t < CT; ++t) {
+    double P[4][3];
+    for (int v = 0; v < 4; ++v)
+      for (int d = 0; d < 3; ++d) P[v][d] = cm->coords[3 * (int64_t)cm->tets[4 * t + v] + d];
+    double J[3][3];
+    for (int c = 0; c < 3; ++c)
+      for (int d = 0; d < 3; ++d) J[d][c] = P[c + 1][d] - P[0][d];
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    HZ_REQUIRE(det != 0 && std::isfinite(det), HZ_ERR_ARG, "coarse mesh: degenerate tet");
+    double* I = &Jinv[9 * t];
+    I[0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+    I[1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    I[2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    I[3] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+    I[4] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    I[5] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    I[6] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+    I[7] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    I[8] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    for (int d = 0; d < 3; ++d) {
+      p0[3 * t + d] = P[0][d];
+      lo[3 * t + d] = std::min(std::min(P[0][d], P[1][d]), std::min(P[2][d], P[3][d]));
+      hi[3 * t + d] = std::max(std::max(P[0][d], P[1][d]), std::max(P[2][d], P[3][d]));
+      gmin[d] = std::min(gmin[d], lo[3 * t + d]);
+      gmax[d] = std::max(gmax[d], hi[3 * t + d]);
+    }
+  }
+  // uniform bucket grid over the coarse tets' bounding boxes (candidates kept in id order)
+  const int nb = std::max(1, (int)std::cbrt((double)CT));
+  double cell[3];
+  for (int d = 0; d < 3; ++d) cell[d] = (gmax[d] - gmin[d]) / nb + 1e-300;
+  auto cidx = [&](double x, int d) {
+    int64_t k = (int64_t)std::floor((x - gmin[d]) / cell[d]);
+    return (int)std::min<int64_t>(std::max<int64_t>(k, 0), nb - 1);
+  };
+  std::vector<std::vector<int32_t>> bucket((size_t)nb * nb * nb);
+  for (int64_t t = 0; t < CT; ++t) {
+    int a0[3], a1[3];
+    for (int d = 0; d < 3; ++d) {
+      const double pad = 1e-9 * (gmax[d] - gmin[d]);
+      a0[d] = cidx(lo[3 * t + d] - pad, d);
+      a1[d] = cidx(hi[3 * t + d] + pad, d);
+    }
+    for (int x = a0[0]; x <= a1[0]; ++x)
+      for (int y = a0[1]; y <= a1[1]; ++y)
+        for (int z = a0[2]; z <= a1[2]; ++z) bucket[((size_t)z * nb + y) * nb + x].push_back((int32_t)t);
+  }
+  cs.zptr.assign(m.n + 1, 0);
+  std::vector<std::array<std::pair<int32_t, double>, 4>> rowv(m.n);
+  std::vector<int8_t> rown(m.n, 0);
+  std::vector<uint8_t> bad(m.n, 0);
+  parallel_for(m.n, [&](int64_t a, int64_t b) {
+    for (int64_t j = a; j < b; ++j) {
+      if (m.dirichlet[j]) continue;
+      const double* x = &m.dof_xyz[3 * j];
+      const auto& cand = bucket[((size_t)cidx(x[2], 2) * nb + cidx(x[1], 1)) * nb + cidx(x[0], 0)];
+      bool found = false;
+      for (int32_t t : cand) {
+        const double* I = &Jinv[9 * t];
+        const double r[3] = {x[0] - p0[3 * t], x[1] - p0[3 * t + 1], x[2] - p0[3 * t + 2]};
+        double lam[4];
+        for (int k = 0; k < 3; ++k) lam[k + 1] = I[3 * k] * r[0] + I[3 * k + 1] * r[1] + I[3 * k + 2] * r[2];
+        lam[0] = 1.0 - lam[1] - lam[2] - lam[3];
+        if (lam[0] >= -1e-12 && lam[1] >= -1e-12 && lam[2] >= -1e-12 && lam[3] >= -1e-12) {
+          // columns sorted ascending, duplicates impossible (distinct vertices)
+          int cnt = 0;
+          std::pair<int32_t, double> e[4];
+          for (int v = 0; v < 4; ++v)
+            if (std::fabs(lam[v]) > 1e-12) e[cnt++] = {cm->tets[4 * t + v], lam[v]};
+          std::sort(e, e + cnt);
+          for (int k = 0; k < cnt; ++k) rowv[j][k] = e[k];
+          rown[j] = (int8_t)cnt;
+          found = true;
+          break;
+        }
+      }
+      if (!found) bad[j] = 1;
+    }
+  });
+  for (int64_t j = 0; j < m.n; ++j) HZ_REQUIRE(!bad[j], HZ_ERR_ARG, "coarse mesh does not cover fine node");
+  for (int64_t j = 0; j < m.n; ++j) cs.zptr[j + 1] = cs.zptr[j] + rown[j];
+  cs.zcol.resize(cs.zptr[m.n]);
+  cs.zval.resize(cs.zptr[m.n]);
+  for (int64_t j = 0; j < m.n; ++j)
+    for (int k = 0; k < rown[j]; ++k) {
+      cs.zcol[cs.zptr[j] + k] = rowv[j][k].first;
+      cs.zval[cs.zptr[j] + k] = rowv[j][k].second;
+    }
+  // Z^T
+  cs.ztptr.assign(CV + 1, 0);
+  for (int32_t c : cs.zcol) cs.ztptr[c + 1]++;
+  for (int64_t c = 0; c < CV; ++c) cs.ztptr[c + 1] += cs.ztptr[c];
+  cs.ztcol.resize(cs.zcol.size());
+  cs.ztval.resize(cs.zcol.size());
+  {
+    std::vector<int64_t> fill(cs.ztptr.begin(), cs.ztptr.end() - 1);
+    for (int64_t j = 0; j < m.n; ++j)
+      for (int64_t k = cs.zptr[j]; k < cs.zptr[j + 1]; ++k) {
+        const int64_t pos = fill[cs.zcol[k]]++;
+        cs.ztcol[pos] = (int32_t)j;
+        cs.ztval[pos] = cs.zval[k];
+      }
+  }
+  // pattern of A Z
+  cs.azptr.assign(m.n + 1, 0);
+  std::vector<std::vector<int32_t>> rows(m.n);
+  parallel_for(m.n, [&](int64_t a, int64_t b) {
+    std::vector<int32_t> buf;
+    for (int64_t i = a; i < b; ++i) {
+      buf.clear();
+      for (int64_t k = m.rowptr[i]; k < m.rowptr[i + 1]; ++k) {
+        const int32_t j = m.col[k];
+        for (int64_t q = cs.zptr[j]; q < cs.zptr[j + 1]; ++q) buf.push_back(cs.zcol[q]);
+      }
+      std::sort(buf.begin(), buf.end());
+      buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+      rows[i] = buf;
+    }
+  });
+  for (int64_t i = 0; i < m.n; ++i) cs.azptr[i + 1] = cs.azptr[i] + (int64_t)rows[i].size();
+  cs.azcol.resize(cs.azptr[m.n]);
+  for (int64_t i = 0; i < m.n; ++i) std::copy(rows[i].begin(), rows[i].end(), cs.azcol.begin() + cs.azptr[i]);
+}
+
+namespace {
+
+// AZ[i, c] = sum_k A[i, j_k] Z[j_k, c]  (one thread per AZ entry, fixed order over k)
+__global__ void k_az(int64_t n, const int64_t* __restrict__ arow, const int32_t* __restrict__ acol,
+                     const c128* __restrict__ aval, const int64_t* __restrict__ zptr, const int32_t* __restrict__ zcol,
+                     const double* __restrict__ zval, const int64_t* __restrict__ azptr,
+                     const int32_t* __restrict__ azcol, const int32_t* __restrict__ azrow, int64_t nnz_az,
+                     c128* __restrict__ az, c64* __restrict__ az32) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz_az) return;
+  const int64_t i = azrow[e];
+  const int32_t c = azcol[e];
+  c128 s = cmk(0.0, 0.0);
+  for (int64_t k = arow[i]; k < arow[i + 1]; ++k) {
+    const int32_t j = acol[k];
+    for (int64_t q = zptr[j]; q < zptr[j + 1]; ++q)
+      if (zcol[q] == c) s = s + aval[k] * cmk(zval[q], 0.0);
+  }
+  az[e] = s;
+  az32[e] = cmk((float)s.re, (float)s.im);
+}
+
+// E[c, :] = sum_{i in supp Z[:, c]} Z[i, c] AZ[i, :], dense row accumulated in LDS
+__global__ __launch_bounds__(64) void k_ztaz(int64_t nc, const int64_t* __restrict__ ztptr,
+                                             const int32_t* __restrict__ ztcol, const double* __restrict__ ztval,
+                                             const int64_t* __restrict__ azptr, const int32_t* __restrict__ azcol,
+                                             const c128* __restrict__ az, c128* __restrict__ E) {
+  extern __shared__ c128 row[];
+  const int64_t c = blockIdx.x;
+  for (int64_t d = threadIdx.x; d < nc; d += blockDim.x) row[d] = cmk(0.0, 0.0);
+  __syncthreads();
+  for (int64_t k = ztptr[c]; k < ztptr[c + 1]; ++k) {
+    const int64_t i = ztcol[k];
+    const double z = ztval[k];
+    for (int64_t q = azptr[i] + threadIdx.x; q < azptr[i + 1]; q += blockDim.x) {
+      const int32_t d = azcol[q];
+      row[d] = row[d] + az[q] * cmk(z, 0.0);
+    }
+    __syncthreads();
+  }
+  // E column-major: E[c + d*nc]
+  for (int64_t d = threadIdx.x; d < nc; d += blockDim.x) E[c + d * nc] = row[d];
+}
+
+// ---- LU with partial pivoting, right looking, one column per step
+template <typename T>
+__global__ void k_lu_pivot(int64_t nc, int64_t k, cplx<T>* A, int32_t* piv) {
+  __shared__ T bv[256];
+  __shared__ int64_t bi[256];
+  T best = -1;
+  int64_t arg = k;
+  for (int64_t i = k + threadIdx.x; i < nc; i += blockDim.x) {
+    const cplx<T> v = A[i + k * nc];
+    const T a = fabs(v.re) + fabs(v.im);
+    if (a > best) {
+      best = a;
+      arg = i;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = arg;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      const T o = bv[threadIdx.x + s];
+      const int64_t oi = bi[threadIdx.x + s];
+      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+        bv[threadIdx.x] = o;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t p = bi[0];
+  if (threadIdx.x == 0) piv[k] = (int32_t)p;
+  // swap rows k and p over all columns
+  if (p != k)
+    for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) {
+      const cplx<T> t = A[k + j * nc];
+      A[k + j * nc] = A[p + j * nc];
+      A[p + j * nc] = t;
+    }
+  __syncthreads();
+  const cplx<T> d = A[k + k * nc];
+  for (int64_t i = k + 1 + threadIdx.x; i < nc; i += blockDim.x) A[i + k * nc] = cdiv(A[i + k * nc], d);
+}
+
+template <typename T>
+__global__ void k_lu_update(int64_t nc, int64_t k, cplx<T>* A) {
+  const int64_t i = k + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = k + 1 + blockIdx.y;
+  if (i >= nc || j >= nc) return;
+  cfms(A[i + j * nc], A[i + k * nc], A[k + j * nc]);
+}
+
+// X = E^{-1}: column j solves L U x = P e_j (one thread per column)
+template <typename T>
+__global__ void k_lu_inverse(int64_t nc, const cplx<T>* LU, const int32_t* piv, cplx<T>* X) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nc) return;
+  cplx<T>* x = X + j * nc;
+  for (int64_t i = 0; i < nc; ++i) x[i] = cmk((T)(i == j ? 1 : 0), (T)0);
+  for (int64_t k = 0; k < nc; ++k) {
+    const int64_t p = piv[k];
+    if (p != k) {
+      const cplx<T> t = x[k];
+      x[k] = x[p];
+      x[p] = t;
+    }
+  }
+  for (int64_t k = 0; k < nc; ++k) {
+    const cplx<T> xk = x[k];
+    for (int64_t i = k + 1; i < nc; ++i) cfms(x[i], LU[i + k * nc], xk);
+  }
+  for (int64_t k = nc - 1; k >= 0; --k) {
+    x[k] = cdiv(x[k], LU[k + k * nc]);
+    const cplx<T> xk = x[k];
+    for (int64_t i = 0; i < k; ++i) cfms(x[i], LU[i + k * nc], xk);
+  }
+}
+
+__global__ void k_c128_to_c64(int64_t n, const c128* a, c64* b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = cmk((float)a[i].re, (float)a[i].im);
+}
+
+template <typename T>
+void lu_and_inverse(Ctx* ctx, int64_t nc, cplx<T>* E, int32_t* piv, cplx<T>* Einv) {
+  hipStream_t st = ctx->stream;
+  for (int64_t k = 0; k < nc; ++k) {
+    hipLaunchKernelGGL(k_lu_pivot<T>, dim3(1), dim3(256), 0, st, nc, k, E, piv);
+    if (k + 1 < nc) {
+      const int64_t m = nc - k - 1;
+      hipLaunchKernelGGL(k_lu_update<T>, dim3((unsigned)((m + 255) / 256), (unsigned)m), dim3(256), 0, st, nc, k, E);
+    }
+  }
+  HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_lu_inverse<T>, dim3((unsigned)((nc + 63) / 64)), dim3(64), 0, st, nc, E, piv, Einv);
+  HIP_CHECK(hipGetLastError());
+}
+
+// y[c][col] = sum_{i in Z^T row c} Z[i,c] v[i][col]  (fixed-order partial sums per column)
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict(int64_t nc, int s, const int64_t* __restrict__ ztptr,
+                                                  const int32_t* __restrict__ ztcol, const double* __restrict__ ztval,
+                                                  const c128* __restrict__ v, cplx<T>* __restrict__ y) {
+  __shared__ c128 part[256];
+  const int64_t c = blockIdx.x;
+  const int groups = 256 / s;
+  const int g = threadIdx.x / s, col = threadIdx.x - (threadIdx.x / s) * s;
+  c128 acc = cmk(0.0, 0.0);
+  if (g < groups)
+    for (int64_t k = ztptr[c] + g; k < ztptr[c + 1]; k += groups)
+      acc = acc + v[(int64_t)ztcol[k] * s + col] * cmk(ztval[k], 0.0);
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < s) {
+    c128 t = cmk(0.0, 0.0);
+    for (int q = 0; q < groups; ++q) t = t + part[q * s + threadIdx.x];
+    y[c * s + threadIdx.x] = cmk((T)t.re, (T)t.im);
+  }
+}
+
+// y2 = Einv y  (nc x nc times nc x s), one block per 64 rows x all columns
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_apply(int64_t nc, int s, const cplx<T>* __restrict__ Ei,
+                                                     const cplx<T>* __restrict__ y, cplx<T>* __restrict__ y2) {
+  const int64_t i = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int cg = threadIdx.x >> 6;  // 4 column groups
+  if (i >= nc) return;
+  for (int col = cg; col < s; col += 4) {
+    cplx<T> acc = cmk((T)0, (T)0);
+    for (int64_t k = 0; k < nc; ++k) cfma(acc, Ei[i + k * nc], y[k * s + col]);
+    y2[i * s + col] = acc;
+  }
+}
+
+// q = Z y2 ; t = v - AZ y2
+template <typename T>
+__global__ void k_prolong(int64_t n, int s, const int64_t* __restrict__ zptr, const int32_t* __restrict__ zcol,
+                          const double* __restrict__ zval, const int64_t* __restrict__ azptr,
+                          const int32_t* __restrict__ azcol, const cplx<T>* __restrict__ az,
+                          const cplx<T>* __restrict__ y2, const c128* __restrict__ v, c128* __restrict__ q,
+                          c128* __restrict__ t) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n * s) return;
+  const int64_t i = k / s;
+  const int col = (int)(k - i * s);
+  cplx<T> qa = cmk((T)0, (T)0), ta = cmk((T)0, (T)0);
+  for (int64_t e = zptr[i]; e < zptr[i + 1]; ++e) cfma(qa, cmk((T)zval[e], (T)0), y2[(int64_t)zcol[e] * s + col]);
+  for (int64_t e = azptr[i]; e < azptr[i + 1]; ++e) cfma(ta, az[e], y2[(int64_t)azcol[e] * s + col]);
+  q[k] = cmk((double)qa.re, (double)qa.im);
+  t[k] = v[k] - cmk((double)ta.re, (double)ta.im);
+}
+
+}  // namespace
+
+void coarse_setup(Ctx* ctx, Ddm& d) {
+  CoarseSpace& cs = *d.coarse;
+  const Mesh& m = *d.op->mesh;
+  hipStream_t st = ctx->stream;
+  cs.d_zptr.upload(ctx, cs.zptr);
+  cs.d_zcol.upload(ctx, cs.zcol);
+  cs.d_zval.upload(ctx, cs.zval);
+  cs.d_ztptr.upload(ctx, cs.ztptr);
+  cs.d_ztcol.upload(ctx, cs.ztcol);
+  cs.d_ztval.upload(ctx, cs.ztval);
+  cs.d_azptr.upload(ctx, cs.azptr);
+  cs.d_azcol.upload(ctx, cs.azcol);
+  const int64_t nnz_az = (int64_t)cs.azcol.size();
+  {
+    std::vector<int32_t> azrow(nnz_az);
+    for (int64_t i = 0; i < m.n; ++i)
+      for (int64_t e = cs.azptr[i]; e < cs.azptr[i + 1]; ++e) azrow[e] = (int32_t)i;
+    DevArray<int32_t> d_azrow;
+    d_azrow.upload(ctx, azrow);
+    cs.d_az.alloc(ctx, std::max<int64_t>(1, nnz_az));
+    cs.d_az32.alloc(ctx, std::max<int64_t>(1, nnz_az));
+    hipLaunchKernelGGL(k_az, dim3((unsigned)((nnz_az + 255) / 256)), dim3(256), 0, st, m.n, d.op->mesh->d_rowptr.ptr(),
+                       d.op->mesh->d_col.ptr(), d.op->d_val.ptr(), cs.d_zptr.ptr(), cs.d_zcol.ptr(), cs.d_zval.ptr(),
+                       cs.d_azptr.ptr(), cs.d_azcol.ptr(), d_azrow.ptr(), nnz_az, cs.d_az.ptr(), cs.d_az32.ptr());
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(st));
+  }
+  const int64_t nc = cs.nc;
+  HZ_REQUIRE(nc * (int64_t)sizeof(c128) <= 64 * 1024, HZ_ERR_ARG, "coarse space too large (max 4096 coarse vertices)");
+  DevArray<c128> E;
+  E.alloc(ctx, nc * nc);
+  hipLaunchKernelGGL(k_ztaz, dim3((unsigned)nc), dim3(64), nc * sizeof(c128), st, nc, cs.d_ztptr.ptr(),
+                     cs.d_ztcol.ptr(), cs.d_ztval.ptr(), cs.d_azptr.ptr(), cs.d_azcol.ptr(), cs.d_az.ptr(), E.ptr());
+  HIP_CHECK(hipGetLastError());
+  cs.d_piv.alloc(ctx, nc);
+  if (d.precision == HZ_PREC_MIXED) {
+    DevArray<c64> E32;
+    E32.alloc(ctx, nc * nc);
+    hipLaunchKernelGGL(k_c128_to_c64, dim3((unsigned)((nc * nc + 255) / 256)), dim3(256), 0, st, nc * nc, E.ptr(),
+                       E32.ptr());
+    cs.d_E32.alloc(ctx, nc * nc);
+    lu_and_inverse<float>(ctx, nc, E32.ptr(), cs.d_piv.ptr(), cs.d_E32.ptr());
+    HIP_CHECK(hipStreamSynchronize(st));
+  } else {
+    cs.d_E.alloc(ctx, nc * nc);
+    lu_and_inverse<double>(ctx, nc, E.ptr(), cs.d_piv.ptr(), cs.d_E.ptr());
+    HIP_CHECK(hipStreamSynchronize(st));
+  }
+}
+
+template <typename T>
+static void coarse_apply_t(Ctx* ctx, Ddm& d, int s, const c128* v, c128* q, c128* t, const cplx<T>* Einv,
+                           const cplx<T>* az) {
+  CoarseSpace& cs = *d.coarse;
+  hipStream_t st = ctx->stream;
+  const int64_t nc = cs.nc, n = d.op->mesh->n;
+  DevArray<cplx<T>> y, y2;
+  y.alloc(ctx, nc * s);
+  y2.alloc(ctx, nc * s);
+  hipLaunchKernelGGL(k_restrict<T>, dim3((unsigned)nc), dim3(256), 0, st, nc, s, cs.d_ztptr.ptr(), cs.d_ztcol.ptr(),
+                     cs.d_ztval.ptr(), v, y.ptr());
+  hipLaunchKernelGGL(k_dense_apply<T>, dim3((unsigned)((nc + 63) / 64)), dim3(256), 0, st, nc, s, Einv, y.ptr(),
+                     y2.ptr());
+  hipLaunchKernelGGL(k_prolong<T>, dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, st, n, s, cs.d_zptr.ptr(),
+                     cs.d_zcol.ptr(), cs.d_zval.ptr(), cs.d_azptr.ptr(), cs.d_azcol.ptr(), az, y2.ptr(), v, q, t);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(st));  // y, y2 are freed on return
+}
+
+void coarse_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c128* q, c128* t) {
+  if (d.precision == HZ_PREC_MIXED)
+    coarse_apply_t<float>(ctx, d, s, v, q, t, d.coarse->d_E32.ptr(), d.coarse->d_az32.ptr());
+  else
+    coarse_apply_t<double>(ctx, d, s, v, q, t, d.coarse->d_E.ptr(), d.coarse->d_az.ptr());
+}
+
+}  // namespace hz

@@ -1,0 +1,583 @@
+// ORAS set-up on the host: overlapping subdomains, Boolean partition of unity, local
+// Robin operators (patterns + gather maps), nested-dissection ordering and the
+// multifrontal symbolic analysis.  Numeric work (local values, LDL^T, coarse E) runs on
+// the GPU (factor.hip, coarse.hip).
+//
+// Paper, section "Domain decomposition preconditioner", eq. (oras):
+//   M1^{-1} = sum_i R_i^T D_i A_i^{-1} R_i
+// Readings (the abstract leaves the construction to its references):
+//  * overlap: delta layers, each adding every tet that shares a vertex with the set;
+//  * D_i Boolean: a dof is owned by the lowest subdomain id whose own tets touch it, so
+//    sum_i R_i^T D_i R_i = I and the prolongation is a pure gather;
+//  * A_i: the tets of the overlapped subdomain, the physical boundary conditions, and the
+//    first-order absorbing (Robin) term on every face whose neighbour tet is outside.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <numeric>
+#include <thread>
+
+#include "ddm.h"
+
+namespace hz {
+
+namespace {
+
+int env_int(const char* name, int def) {
+  const char* s = std::getenv(name);
+  return s ? std::atoi(s) : def;
+}
+
+// ---------------------------------------------------------------- nested dissection
+
+struct NDNode {
+  std::vector<int32_t> piv;  // local dof ids
+  int child[2] = {-1, -1};
+  int nchild = 0;
+};
+
+struct NDContext {
+  const Mesh* m;
+  const std::vector<int64_t>* tets;  // local tet -> global tet
+  const std::vector<int32_t>* ltd;   // local tet -> 20 local dofs
+  std::vector<double> cen;           // local tet centroid (3)
+  std::vector<double> vmin, vmax;    // per local tet, per axis, min/max vertex coordinate
+  std::vector<uint32_t> stampL, stampR;
+  uint32_t gen = 0;
+  int leaf;
+  std::vector<NDNode> nodes;
+};
+
+int nd_recurse(NDContext& c, std::vector<int32_t>& tets, std::vector<int32_t>& dofs) {
+  auto make_leaf = [&]() {
+    NDNode nd;
+    nd.piv = dofs;
+    std::sort(nd.piv.begin(), nd.piv.end());
+    c.nodes.push_back(std::move(nd));
+    return (int)c.nodes.size() - 1;
+  };
+  if ((int64_t)dofs.size() <= c.leaf || tets.size() < 2) return make_leaf();
+
+  struct Split {
+    std::vector<int32_t> EL, ER, sep, DL, DR;
+  };
+  auto evaluate = [&](const std::vector<int32_t>& EL, const std::vector<int32_t>& ER, Split& sp) {
+    ++c.gen;
+    const uint32_t g = c.gen;
+    for (int32_t q : EL)
+      for (int l = 0; l < 20; ++l) c.stampL[(*c.ltd)[q * 20 + l]] = g;
+    for (int32_t q : ER)
+      for (int l = 0; l < 20; ++l) c.stampR[(*c.ltd)[q * 20 + l]] = g;
+    sp.sep.clear();
+    sp.DL.clear();
+    sp.DR.clear();
+    for (int32_t d : dofs) {
+      bool l = c.stampL[d] == g, r = c.stampR[d] == g;
+      if (l && r)
+        sp.sep.push_back(d);
+      else if (l)
+        sp.DL.push_back(d);
+      else
+        sp.DR.push_back(d);
+    }
+  };
+  Split best;
+  bool have = false;
+  std::vector<double> xs;
+  for (int ax = 0; ax < 3; ++ax) {
+    xs.resize(tets.size());
+    for (size_t i = 0; i < tets.size(); ++i) xs[i] = c.cen[3 * tets[i] + ax];
+    std::vector<double> tmp = xs;
+    std::nth_element(tmp.begin(), tmp.begin() + tmp.size() / 2, tmp.end());
+    const double med = tmp[tmp.size() / 2];
+    // snap the cut to the nearest vertex coordinate so that whole element layers stay together
+    double x0 = med, bestd = INFINITY;
+    for (int32_t q : tets)
+      for (const double v : {c.vmin[3 * q + ax], c.vmax[3 * q + ax]}) {
+        const double dd = std::fabs(v - med);
+        if (dd < bestd) {
+          bestd = dd;
+          x0 = v;
+        }
+      }
+    Split sp;
+    for (size_t i = 0; i < tets.size(); ++i) (xs[i] < x0 ? sp.EL : sp.ER).push_back(tets[i]);
+    if (sp.EL.empty() || sp.ER.empty()) continue;
+    evaluate(sp.EL, sp.ER, sp);
+    const size_t mn = std::min(sp.DL.size(), sp.DR.size());
+    if (mn * 5 < dofs.size()) continue;  // too unbalanced
+    if (!have || sp.sep.size() < best.sep.size()) {
+      best = std::move(sp);
+      have = true;
+    }
+  }
+  if (!have) {  // fallback: split the tets at the median index along the widest axis
+    int ax = 0;
+    double wmax = -1;
+    for (int a = 0; a < 3; ++a) {
+      double lo = INFINITY, hi = -INFINITY;
+      for (int32_t q : tets) {
+        lo = std::min(lo, c.cen[3 * q + a]);
+        hi = std::max(hi, c.cen[3 * q + a]);
+      }
+      if (hi - lo > wmax) {
+        wmax = hi - lo;
+        ax = a;
+      }
+    }
+    std::vector<int32_t> s = tets;
+    std::stable_sort(s.begin(), s.end(), [&](int32_t a, int32_t b) { return c.cen[3 * a + ax] < c.cen[3 * b + ax]; });
+    best.EL.assign(s.begin(), s.begin() + s.size() / 2);
+    best.ER.assign(s.begin() + s.size() / 2, s.end());
+    evaluate(best.EL, best.ER, best);
+  }
+  if (best.sep.size() == dofs.size() || (best.DL.empty() && best.DR.empty())) return make_leaf();
+  // restrict each side's tets to those touching its dofs
+  auto restrict_tets = [&](std::vector<int32_t>& E, const std::vector<int32_t>& D) {
+    ++c.gen;
+    for (int32_t d : D) c.stampL[d] = c.gen;
+    std::vector<int32_t> out;
+    for (int32_t q : E) {
+      bool hit = false;
+      for (int l = 0; l < 20 && !hit; ++l) hit = c.stampL[(*c.ltd)[q * 20 + l]] == c.gen;
+      if (hit) out.push_back(q);
+    }
+    E.swap(out);
+  };
+  restrict_tets(best.EL, best.DL);
+  restrict_tets(best.ER, best.DR);
+  NDNode nd;
+  nd.piv = best.sep;
+  std::sort(nd.piv.begin(), nd.piv.end());
+  std::vector<int32_t> DL = std::move(best.DL), DR = std::move(best.DR), EL = std::move(best.EL),
+                       ER = std::move(best.ER);
+  tets.clear();
+  tets.shrink_to_fit();
+  dofs.clear();
+  dofs.shrink_to_fit();
+  int kids[2], nk = 0;
+  if (!DL.empty()) kids[nk++] = nd_recurse(c, EL, DL);
+  if (!DR.empty()) kids[nk++] = nd_recurse(c, ER, DR);
+  nd.nchild = nk;
+  for (int i = 0; i < nk; ++i) nd.child[i] = kids[i];
+  c.nodes.push_back(std::move(nd));
+  return (int)c.nodes.size() - 1;
+}
+
+// per-subdomain symbolic result
+struct SubSym {
+  std::vector<Front> fronts;           // local front ids = index; child/parent local
+  std::vector<std::vector<int32_t>> U;  // update rows (positions)
+};
+
+void build_subdomain(const Mesh& m, const std::vector<int32_t>& part, const std::vector<int32_t>& owner,
+                     const std::vector<int64_t>& v2t_ptr, const std::vector<int64_t>& v2t, int32_t i, int32_t delta,
+                     std::vector<int32_t>& loc, std::vector<uint8_t>& inside, Subdomain& S, SubSym& sym, int leaf) {
+  const int64_t T = m.T;
+  // --- overlap: delta vertex-adjacency layers
+  std::vector<int64_t> cur;
+  for (int64_t t = 0; t < T; ++t)
+    if (part[t] == i) {
+      cur.push_back(t);
+      inside[t] = 1;
+    }
+  for (int32_t layer = 0; layer < delta; ++layer) {
+    std::vector<int64_t> add;
+    for (int64_t t : cur)
+      for (int v = 0; v < 4; ++v) {
+        const int64_t g = m.tets[4 * t + v];
+        for (int64_t k = v2t_ptr[g]; k < v2t_ptr[g + 1]; ++k) {
+          const int64_t u = v2t[k];
+          if (!inside[u]) {
+            inside[u] = 1;
+            add.push_back(u);
+          }
+        }
+      }
+    cur.insert(cur.end(), add.begin(), add.end());
+  }
+  std::sort(cur.begin(), cur.end());
+  // --- local dofs R_i (sorted global ids)
+  std::vector<int32_t> gd;
+  gd.reserve(cur.size() * 4);
+  for (int64_t t : cur)
+    for (int l = 0; l < 20; ++l) gd.push_back(m.tet_dofs[t * 20 + l]);
+  std::sort(gd.begin(), gd.end());
+  gd.erase(std::unique(gd.begin(), gd.end()), gd.end());
+  S.n = (int64_t)gd.size();
+  for (int64_t k = 0; k < S.n; ++k) loc[gd[k]] = (int32_t)k;
+  S.owned.resize(S.n);
+  S.dir.resize(S.n);
+  for (int64_t k = 0; k < S.n; ++k) {
+    S.owned[k] = owner[gd[k]] == i;
+    S.dir[k] = m.dirichlet[gd[k]];
+  }
+  // --- Robin faces: physical impedance or a cut (neighbour outside the overlapped set)
+  std::vector<uint8_t> robin(cur.size(), 0);
+  for (size_t q = 0; q < cur.size(); ++q) {
+    const int64_t t = cur[q];
+    for (int f = 0; f < 4; ++f) {
+      const int64_t nb = m.nbr[4 * t + f];
+      const bool imp = m.tag[4 * t + f] == HZ_BC_IMPEDANCE;
+      const bool cut = nb >= 0 && !inside[nb];
+      if (imp || cut) robin[q] |= (uint8_t)(1u << f);
+    }
+  }
+  build_pattern_and_map(m, cur, loc, S.n, robin, S.rowptr, S.col, S.gm);
+  // --- nested dissection over the overlapped tets
+  std::vector<int32_t> ltd(cur.size() * 20);
+  for (size_t q = 0; q < cur.size(); ++q)
+    for (int l = 0; l < 20; ++l) ltd[q * 20 + l] = loc[m.tet_dofs[cur[q] * 20 + l]];
+  NDContext c;
+  c.m = &m;
+  c.tets = &cur;
+  c.ltd = &ltd;
+  c.leaf = leaf;
+  c.cen.resize(cur.size() * 3);
+  c.vmin.resize(cur.size() * 3);
+  c.vmax.resize(cur.size() * 3);
+  for (size_t q = 0; q < cur.size(); ++q)
+    for (int d = 0; d < 3; ++d) {
+      double s = 0, lo = INFINITY, hi = -INFINITY;
+      for (int v = 0; v < 4; ++v) {
+        const double x = m.coords[3 * (int64_t)m.tets[4 * cur[q] + v] + d];
+        s += x;
+        lo = std::min(lo, x);
+        hi = std::max(hi, x);
+      }
+      c.cen[3 * q + d] = 0.25 * s;
+      c.vmin[3 * q + d] = lo;
+      c.vmax[3 * q + d] = hi;
+    }
+  c.stampL.assign(S.n, 0);
+  c.stampR.assign(S.n, 0);
+  std::vector<int32_t> all_t(cur.size()), all_d(S.n);
+  std::iota(all_t.begin(), all_t.end(), 0);
+  std::iota(all_d.begin(), all_d.end(), 0);
+  const int root = nd_recurse(c, all_t, all_d);
+  // post-order positions
+  S.perm.clear();
+  S.perm.reserve(S.n);
+  S.ipos.assign(S.n, -1);
+  std::vector<int> order;  // nodes in post-order
+  {
+    std::vector<std::pair<int, int>> st{{root, 0}};
+    while (!st.empty()) {
+      auto& [nd, k] = st.back();
+      if (k < c.nodes[nd].nchild) {
+        const int ch = c.nodes[nd].child[k++];
+        st.push_back({ch, 0});
+      } else {
+        order.push_back(nd);
+        st.pop_back();
+      }
+    }
+  }
+  std::vector<int> node2front(c.nodes.size(), -1);
+  sym.fronts.clear();
+  for (int nd : order) {
+    Front F;
+    F.pos0 = (int64_t)S.perm.size();
+    F.p = (int64_t)c.nodes[nd].piv.size();
+    for (int32_t d : c.nodes[nd].piv) {
+      S.ipos[d] = (int32_t)S.perm.size();
+      S.perm.push_back(d);
+    }
+    F.nchild = c.nodes[nd].nchild;
+    for (int k = 0; k < F.nchild; ++k) F.child[k] = node2front[c.nodes[nd].child[k]];
+    node2front[nd] = (int)sym.fronts.size();
+    sym.fronts.push_back(F);
+  }
+  for (size_t fi = 0; fi < sym.fronts.size(); ++fi)
+    for (int k = 0; k < sym.fronts[fi].nchild; ++k) sym.fronts[sym.fronts[fi].child[k]].parent = (int32_t)fi;
+  // --- symbolic: update rows of every front (post-order, children first)
+  sym.U.assign(sym.fronts.size(), {});
+  std::vector<int64_t> mark(S.n, -1);
+  for (size_t fi = 0; fi < sym.fronts.size(); ++fi) {
+    Front& F = sym.fronts[fi];
+    const int64_t end = F.pos0 + F.p;
+    std::vector<int32_t> u;
+    for (int64_t q = F.pos0; q < end; ++q) {
+      const int32_t v = S.perm[q];
+      for (int64_t k = S.rowptr[v]; k < S.rowptr[v + 1]; ++k) {
+        const int32_t pc = S.ipos[S.col[k]];
+        if (pc >= end && mark[pc] != (int64_t)fi) {
+          mark[pc] = (int64_t)fi;
+          u.push_back(pc);
+        }
+      }
+    }
+    for (int k = 0; k < F.nchild; ++k)
+      for (int32_t pc : sym.U[F.child[k]])
+        if (pc >= end && mark[pc] != (int64_t)fi) {
+          mark[pc] = (int64_t)fi;
+          u.push_back(pc);
+        }
+    std::sort(u.begin(), u.end());
+    F.r = (int64_t)u.size();
+    sym.U[fi] = std::move(u);
+  }
+  for (size_t fi = 0; fi < sym.fronts.size(); ++fi) {
+    int lvl = 0;
+    for (int k = 0; k < sym.fronts[fi].nchild; ++k) lvl = std::max(lvl, sym.fronts[sym.fronts[fi].child[k]].level + 1);
+    sym.fronts[fi].level = lvl;
+  }
+  for (int64_t t : cur) inside[t] = 0;
+  for (int64_t k = 0; k < S.n; ++k) loc[gd[k]] = -1;
+  S.gdofs = std::move(gd);
+}
+
+// index of elimination position q inside front F (with update rows U); q must be one of
+// the front's rows, anything else means the elimination tree is inconsistent
+inline int64_t front_index(const Front& F, const std::vector<int32_t>& U, int64_t q) {
+  if (q >= F.pos0 && q < F.pos0 + F.p) return q - F.pos0;
+  auto it = std::lower_bound(U.begin(), U.end(), (int32_t)q);
+  HZ_REQUIRE(it != U.end() && *it == q, HZ_ERR_STATE, "symbolic analysis: row missing from its front");
+  return F.p + (it - U.begin());
+}
+
+}  // namespace
+
+int64_t Ddm::device_bytes() const {
+  int64_t b = 0;
+  b += d_fronts.bytes() + d_urows.bytes() + d_emap.bytes() + d_gidx.bytes() + d_orig_src.bytes() +
+       d_orig_dst.bytes() + d_own_src.bytes() + d_lrowptr.bytes() + d_lgptr.bytes() + d_lcol.bytes() +
+       d_lgsrc.bytes() + d_ldir.bytes() + d_lval.bytes() + d_level_fronts.bytes();
+  b += d_factor.bytes + d_update.bytes;
+  if (coarse)
+    b += coarse->d_zptr.bytes() + coarse->d_ztptr.bytes() + coarse->d_azptr.bytes() + coarse->d_zcol.bytes() +
+         coarse->d_ztcol.bytes() + coarse->d_azcol.bytes() + coarse->d_zval.bytes() + coarse->d_ztval.bytes() +
+         coarse->d_az.bytes() + coarse->d_az32.bytes() + coarse->d_E.bytes() + coarse->d_E32.bytes();
+  return b;
+}
+
+void build_coarse_host(const Mesh& m, const hz_coarse_mesh* cm, CoarseSpace& cs);
+
+std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int32_t* partition, int32_t n_sub,
+                               int32_t overlap, const hz_coarse_mesh* coarse, int precision) {
+  const double t0 = wall_time();
+  const Mesh& m = *op->mesh;
+  HZ_REQUIRE(partition && n_sub >= 1 && overlap >= 0, HZ_ERR_ARG, "hz_setup_ddm: bad arguments");
+  HZ_REQUIRE(precision == HZ_PREC_C128 || precision == HZ_PREC_MIXED, HZ_ERR_ARG, "hz_setup_ddm: bad precision");
+  std::vector<int32_t> part(partition, partition + m.T);
+  std::vector<int64_t> cnt(n_sub, 0);
+  for (int64_t t = 0; t < m.T; ++t) {
+    HZ_REQUIRE(part[t] >= 0 && part[t] < n_sub, HZ_ERR_ARG, "hz_setup_ddm: partition id out of range");
+    cnt[part[t]]++;
+  }
+  for (int32_t i = 0; i < n_sub; ++i) HZ_REQUIRE(cnt[i] > 0, HZ_ERR_ARG, "hz_setup_ddm: empty subdomain");
+  auto d = std::make_shared<Ddm>();
+  d->op = op;
+  d->precision = precision;
+  d->n_sub = n_sub;
+  d->overlap = overlap;
+  // owners: lowest subdomain whose own tets touch the dof
+  std::vector<int32_t> owner(m.n, INT32_MAX);
+  for (int64_t t = 0; t < m.T; ++t)
+    for (int l = 0; l < 20; ++l) {
+      int32_t& o = owner[m.tet_dofs[t * 20 + l]];
+      o = std::min(o, part[t]);
+    }
+  // vertex -> tets
+  std::vector<int64_t> v2t_ptr(m.V + 1, 0), v2t(m.T * 4);
+  for (int64_t k = 0; k < m.T * 4; ++k) v2t_ptr[m.tets[k] + 1]++;
+  for (int64_t v = 0; v < m.V; ++v) v2t_ptr[v + 1] += v2t_ptr[v];
+  {
+    std::vector<int64_t> fill(v2t_ptr.begin(), v2t_ptr.end() - 1);
+    for (int64_t k = 0; k < m.T * 4; ++k) v2t[fill[m.tets[k]]++] = k / 4;
+  }
+  const int leaf = env_int("HZ_ND_LEAF", 256);
+  d->subs.resize(n_sub);
+  std::vector<SubSym> syms(n_sub);
+  {
+    const int nt = std::max(1, std::min<int>(n_sub, std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
+    std::atomic<int32_t> next{0};
+    std::vector<std::string> errs(nt);
+    std::vector<std::thread> th;
+    for (int w = 0; w < nt; ++w)
+      th.emplace_back([&, w] {
+        std::vector<int32_t> loc(m.n, -1);
+        std::vector<uint8_t> inside(m.T, 0);
+        try {
+          for (int32_t i; (i = next.fetch_add(1)) < n_sub;)
+            build_subdomain(m, part, owner, v2t_ptr, v2t, i, overlap, loc, inside, d->subs[i], syms[i], leaf);
+        } catch (const std::exception& e) {
+          errs[w] = e.what();
+        }
+      });
+    for (auto& t : th) t.join();
+    for (auto& e : errs) HZ_REQUIRE(e.empty(), HZ_ERR_STATE, "hz_setup_ddm: " + e);
+  }
+  // --- concatenate fronts, offsets
+  int64_t vec = 0, csr = 0, rows = 0, Loff = 0, Uoff = 0, urow = 0, orig = 0, cvec = 0;
+  int max_level = 0;
+  for (int32_t i = 0; i < n_sub; ++i) {
+    Subdomain& S = d->subs[i];
+    SubSym& sy = syms[i];
+    S.vec_off = vec;
+    S.csr_off = csr;
+    S.row_off = rows;
+    const int32_t base = (int32_t)d->fronts.size();
+    for (size_t fi = 0; fi < sy.fronts.size(); ++fi) {
+      Front F = sy.fronts[fi];
+      F.sub = i;
+      if (F.parent >= 0) F.parent += base;
+      for (int k = 0; k < F.nchild; ++k) F.child[k] += base;
+      F.L_off = Loff;
+      Loff += F.f() * F.p;
+      F.U_off = Uoff;
+      Uoff += F.r * F.r;
+      F.rows_off = urow;
+      F.emap_off = urow;
+      urow += F.r;
+      cvec += F.r;
+      d->max_front = std::max(d->max_front, F.f());
+      max_level = std::max(max_level, F.level);
+      S.fronts.push_back((int32_t)d->fronts.size());
+      d->fronts.push_back(F);
+    }
+    vec += S.n;
+    csr += (int64_t)S.col.size();
+    rows += S.n + 1;
+  }
+  d->n_local_total = vec;
+  d->factor_entries = Loff;
+  d->update_entries = Uoff;
+  d->urows_total = urow;
+  d->cvec_total = cvec;
+  d->urows.resize(urow);
+  d->emap.assign(urow, 0);
+  // update rows, extend-add maps and original-entry scatter lists
+  for (int32_t i = 0; i < n_sub; ++i) {
+    Subdomain& S = d->subs[i];
+    SubSym& sy = syms[i];
+    for (size_t fi = 0; fi < sy.fronts.size(); ++fi) {
+      Front& F = d->fronts[S.fronts[fi]];
+      std::copy(sy.U[fi].begin(), sy.U[fi].end(), d->urows.begin() + F.rows_off);
+      if (F.parent >= 0) {
+        const Front& P = d->fronts[F.parent];
+        const auto& UP = sy.U[(size_t)(F.parent - S.fronts[0])];
+        for (int64_t k = 0; k < F.r; ++k) d->emap[F.emap_off + k] = (int32_t)front_index(P, UP, sy.U[fi][k]);
+      }
+      F.orig_off = orig;
+      const int64_t f = F.f();
+      for (int64_t q = F.pos0; q < F.pos0 + F.p; ++q) {
+        const int32_t v = S.perm[q];
+        for (int64_t k = S.rowptr[v]; k < S.rowptr[v + 1]; ++k) {
+          const int64_t pc = S.ipos[S.col[k]];
+          if (pc < q) continue;
+          d->orig_src.push_back(S.csr_off + k);
+          d->orig_dst.push_back((q - F.pos0) * f + front_index(F, sy.U[fi], pc));
+        }
+      }
+      F.orig_cnt = (int64_t)d->orig_src.size() - orig;
+      orig = (int64_t)d->orig_src.size();
+    }
+  }
+  d->orig_total = orig;
+  // levels
+  d->levels.assign(max_level + 1, Level{});
+  for (size_t fi = 0; fi < d->fronts.size(); ++fi) d->levels[d->fronts[fi].level].fronts.push_back((int32_t)fi);
+  std::vector<int32_t> lf;
+  for (auto& L : d->levels) {
+    std::stable_sort(L.fronts.begin(), L.fronts.end(),
+                     [&](int32_t a, int32_t b) { return d->fronts[a].p > d->fronts[b].p; });
+    for (int32_t fi : L.fronts) {
+      L.max_p = std::max(L.max_p, d->fronts[fi].p);
+      L.max_f = std::max(L.max_f, d->fronts[fi].f());
+      L.max_r = std::max(L.max_r, d->fronts[fi].r);
+    }
+    d->level_off.push_back((int64_t)lf.size());
+    lf.insert(lf.end(), L.fronts.begin(), L.fronts.end());
+  }
+  d->level_off.push_back((int64_t)lf.size());
+  // local vector <-> global maps
+  d->gidx.resize(vec);
+  d->own_src.assign(m.n, -1);
+  for (int32_t i = 0; i < n_sub; ++i) {
+    const Subdomain& S = d->subs[i];
+    for (int64_t q = 0; q < S.n; ++q) {
+      const int32_t l = S.perm[q];
+      d->gidx[S.vec_off + q] = S.gdofs[l];
+      if (S.owned[l]) d->own_src[S.gdofs[l]] = S.vec_off + q;
+    }
+  }
+  for (int64_t g = 0; g < m.n; ++g) HZ_REQUIRE(d->own_src[g] >= 0, HZ_ERR_STATE, "hz_setup_ddm: unowned dof");
+  // --- device: front descriptors, maps, local operators
+  std::vector<FrontDesc> fd(d->fronts.size());
+  int64_t cv = 0;
+  for (size_t fi = 0; fi < d->fronts.size(); ++fi) {
+    const Front& F = d->fronts[fi];
+    FrontDesc& x = fd[fi];
+    x.L_off = F.L_off;
+    x.U_off = F.U_off;
+    x.rows_off = F.rows_off;
+    x.emap_off = F.emap_off;
+    x.orig_off = F.orig_off;
+    x.orig_cnt = F.orig_cnt;
+    x.vec_off = d->subs[F.sub].vec_off;
+    x.cvec_off = cv;
+    cv += F.r;
+    x.p = (int32_t)F.p;
+    x.r = (int32_t)F.r;
+    x.parent = F.parent;
+    x.child0 = F.child[0];
+    x.child1 = F.child[1];
+    x.pos0 = (int32_t)F.pos0;
+    x.pad = 0;
+  }
+  d->d_fronts.upload(ctx, fd);
+  d->d_urows.upload(ctx, d->urows);
+  d->d_emap.upload(ctx, d->emap);
+  d->d_gidx.upload(ctx, d->gidx);
+  d->d_own_src.upload(ctx, d->own_src);
+  d->d_orig_src.upload(ctx, d->orig_src);
+  d->d_orig_dst.upload(ctx, d->orig_dst);
+  d->d_level_fronts.upload(ctx, lf);
+  {
+    std::vector<int64_t> rp, gp;
+    std::vector<int32_t> cl;
+    std::vector<uint32_t> gs;
+    std::vector<uint8_t> dr;
+    rp.reserve(rows);
+    cl.reserve(csr);
+    int64_t gbase = 0;
+    for (int32_t i = 0; i < n_sub; ++i) {
+      const Subdomain& S = d->subs[i];
+      for (int64_t k = 0; k <= S.n; ++k) rp.push_back(S.rowptr[k]);
+      cl.insert(cl.end(), S.col.begin(), S.col.end());
+      for (size_t k = 0; k + 1 < S.gm.ptr.size(); ++k) gp.push_back(S.gm.ptr[k] + gbase);
+      gbase += S.gm.ptr.back();
+      gs.insert(gs.end(), S.gm.src.begin(), S.gm.src.end());
+      dr.insert(dr.end(), S.dir.begin(), S.dir.end());
+    }
+    gp.push_back(gbase);
+    d->d_lrowptr.upload(ctx, rp);
+    d->d_lcol.upload(ctx, cl);
+    d->d_lgptr.upload(ctx, gp);
+    d->d_lgsrc.upload(ctx, gs);
+    d->d_ldir.upload(ctx, dr);
+    d->d_lval.alloc(ctx, csr);
+    // one launch per subdomain (row pointers are subdomain-relative)
+    for (int32_t i = 0; i < n_sub; ++i) {
+      const Subdomain& S = d->subs[i];
+      launch_gather_fill(ctx->stream, S.n, d->d_lrowptr.ptr() + S.row_off, d->d_lcol.ptr() + S.csr_off,
+                         d->d_lgptr.ptr() + S.csr_off, d->d_lgsrc.ptr(), op->d_elem.ptr(), d->d_ldir.ptr() + S.vec_off,
+                         d->d_lval.ptr() + S.csr_off, nullptr);
+    }
+  }
+  for (auto& S : d->subs) S.gm = GatherMap();  // the gather maps live on the device now
+  // --- numeric factorisation
+  factor_all(ctx, *d);
+  // --- coarse space
+  if (coarse) {
+    d->coarse = std::make_unique<CoarseSpace>();
+    build_coarse_host(m, coarse, *d->coarse);
+    coarse_setup(ctx, *d);
+  }
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  d->setup_seconds = wall_time() - t0;
+  return d;
+}
+
+}  // namespace hz

@@ -1,0 +1,135 @@
+// Two-level ORAS preconditioner data (host + device), see ddm.cpp / factor.hip / oras.hip.
+#pragma once
+
+#include "hz_internal.h"
+
+namespace hz {
+
+// One supernode of a subdomain's elimination tree (multifrontal LDL^T).
+// Its dense front has f = p + r rows: the p pivots (contiguous elimination positions
+// [pos0, pos0 + p) of the subdomain) then the r update rows (later positions, ascending).
+// Storage: L block f x p column-major (ld = f) in the factor array at L_off; the diagonal
+// holds D, below it L (unit diagonal implied).  The r x r update (Schur) block lives in a
+// workspace at U_off (ld = r) until the parent has absorbed it.
+struct Front {
+  int32_t sub = 0;
+  int32_t level = 0;       // height in the tree: leaves 0
+  int32_t parent = -1;     // global front id
+  int32_t nchild = 0;
+  int32_t child[2] = {-1, -1};
+  int64_t p = 0, r = 0;
+  int64_t pos0 = 0;        // first pivot position (subdomain-local elimination order)
+  int64_t L_off = 0;       // factor array offset (elements)
+  int64_t U_off = 0;       // update workspace offset (elements)
+  int64_t rows_off = 0;    // offset of the r update-row positions in Ddm::urows
+  int64_t emap_off = 0;    // offset of the r extend-add targets in the parent's front
+  int64_t orig_off = 0, orig_cnt = 0;  // original-entry scatter list
+  int64_t f() const { return p + r; }
+};
+
+// device-side compact description of a front (used by kernels)
+struct FrontDesc {
+  int64_t L_off, U_off, rows_off, emap_off, orig_off, orig_cnt;
+  int64_t vec_off;   // offset of the subdomain's local vector (concatenated over subdomains)
+  int64_t cvec_off;  // offset of this front's r x s contribution block in the solve workspace
+  int32_t p, r;
+  int32_t parent;    // global front id or -1
+  int32_t child0, child1;
+  int32_t pos0;
+  int32_t pad;
+};
+
+struct Subdomain {
+  int64_t n = 0;                  // overlapped local dofs
+  std::vector<int32_t> gdofs;     // R_i: sorted global dofs
+  std::vector<uint8_t> owned;     // D_i (Boolean)
+  std::vector<int32_t> perm;      // elimination position -> local id (index into gdofs)
+  std::vector<int32_t> ipos;      // local id -> elimination position
+  std::vector<int64_t> rowptr;    // local CSR pattern (local ids)
+  std::vector<int32_t> col;
+  GatherMap gm;
+  std::vector<uint8_t> dir;       // local Dirichlet flags
+  int64_t vec_off = 0;            // offset in the concatenated local vector
+  int64_t csr_off = 0;            // offset of its nnz in the concatenated local CSR values
+  int64_t row_off = 0;            // offset of its rows in the concatenated rowptr
+  std::vector<int32_t> fronts;    // global front ids (post-order)
+};
+
+struct Level {
+  std::vector<int32_t> fronts;    // global front ids, sorted by p descending
+  int64_t max_p = 0, max_f = 0, max_r = 0;
+};
+
+struct CoarseSpace {
+  int64_t nc = 0;
+  std::vector<int64_t> zptr;      // Z CSR (n x nc)
+  std::vector<int32_t> zcol;
+  std::vector<double> zval;
+  std::vector<int64_t> ztptr;     // Z^T CSR (nc x n)
+  std::vector<int32_t> ztcol;
+  std::vector<double> ztval;
+  std::vector<int64_t> azptr;     // pattern of A Z (n x nc)
+  std::vector<int32_t> azcol;
+  DevArray<int64_t> d_zptr, d_ztptr, d_azptr;
+  DevArray<int32_t> d_zcol, d_ztcol, d_azcol;
+  DevArray<double> d_zval, d_ztval;
+  DevArray<c128> d_az;            // A Z values (FP64)
+  DevArray<c64> d_az32;
+  DevArray<c128> d_E;             // E = Z^T A Z, then its LU factors (column-major nc x nc)
+  DevArray<c64> d_E32;
+  DevArray<int32_t> d_piv;        // LU row pivots
+};
+
+struct Ddm {
+  std::shared_ptr<Operator> op;
+  int precision = HZ_PREC_C128;
+  int32_t n_sub = 0, overlap = 0;
+  std::vector<Subdomain> subs;
+  std::vector<Front> fronts;
+  std::vector<Level> levels;
+  int64_t n_local_total = 0;      // sum of n_i
+  int64_t factor_entries = 0, update_entries = 0, urows_total = 0, orig_total = 0;
+  int64_t max_front = 0;
+  int64_t static_pivots = 0;
+  double setup_seconds = 0;
+  std::unique_ptr<CoarseSpace> coarse;
+
+  // host index arrays
+  std::vector<int32_t> urows;     // update-row positions per front (subdomain-local)
+  std::vector<int32_t> emap;      // extend-add targets per front
+  std::vector<int64_t> orig_src;  // concatenated local CSR index of each original entry
+  std::vector<int64_t> orig_dst;  // front-relative flat index (L region)
+  std::vector<int32_t> gidx;      // concatenated local vector position -> global dof
+  std::vector<int64_t> own_src;   // global dof -> concatenated local vector position of its owner
+
+  // device arrays
+  DevArray<FrontDesc> d_fronts;
+  DevArray<int32_t> d_urows, d_emap, d_gidx;
+  DevArray<int64_t> d_orig_src, d_orig_dst, d_own_src;
+  DevArray<int64_t> d_lrowptr, d_lgptr;
+  DevArray<int32_t> d_lcol;
+  DevArray<uint32_t> d_lgsrc;
+  DevArray<uint8_t> d_ldir;
+  DevArray<c128> d_lval;          // local operator values (FP64), concatenated
+  DevArray<int32_t> d_level_fronts;  // fronts of every level, concatenated
+  std::vector<int64_t> level_off;    // offsets into d_level_fronts
+  DevBuf d_factor;                // c128 or c64 L blocks
+  DevBuf d_update;                // update workspace
+  DevArray<unsigned long long> d_npiv;  // static pivot counter
+  int64_t cvec_total = 0;         // solve workspace rows (sum of r over fronts)
+  int64_t device_bytes() const;
+};
+
+// ddm.cpp
+std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int32_t* partition, int32_t n_sub,
+                               int32_t overlap, const hz_coarse_mesh* coarse, int precision);
+// factor.hip
+void factor_all(Ctx* ctx, Ddm& d);
+// coarse.hip
+void coarse_setup(Ctx* ctx, Ddm& d);
+// oras.hip: z = M^{-1} v for a block in node-major layout [n][s] (c128 in/out)
+struct OrasWork;
+void precond_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c128* z);
+void precond_release_workspace(Ddm& d);
+
+}  // namespace hz

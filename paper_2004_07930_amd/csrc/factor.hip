@@ -1,0 +1,380 @@
+// Batched multifrontal LDL^T of all local ORAS operators (complex symmetric: A_i = L D L^T
+// with a plain transpose, no conjugation), level by level over the elimination trees of
+// every subdomain at once.  The paper factors each fine local matrix with a complete
+// Cholesky-type direct solver (section "Numerical results", the local solver comparison);
+// here the factorisation is a supernodal LDL^T on nested-dissection order with static
+// pivoting (tiny pivots replaced by a threshold, counted).
+//
+// Per level: scatter the original entries into the fronts, extend-add the children's
+// update blocks (one child slot per launch, so every sum has a fixed order), then for each
+// panel of kNb pivot columns: factor the diagonal block, solve the panel rows below it,
+// and apply the rank-kNb update to the trailing lower triangle (L region and Schur block).
+// Finally each kNb x kNb diagonal block gets its inverse unit-lower factor stored
+// transposed in its (otherwise unused) strict upper triangle, for the triangular solves.
+#include <cmath>
+#include <cstdlib>
+
+#include "ddm.h"
+
+namespace hz {
+
+namespace {
+
+constexpr int kNb = 32;     // panel width
+constexpr int kTile = 64;   // trailing-update tile
+
+template <typename T>
+__device__ __forceinline__ cplx<T> ld_front(const cplx<T>* L, const cplx<T>* U, const FrontDesc& F, int64_t i,
+                                            int64_t j) {
+  const int64_t f = F.p + F.r;
+  return j < F.p ? L[F.L_off + j * f + i] : U[F.U_off + (j - F.p) * F.r + (i - F.p)];
+}
+template <typename T>
+__device__ __forceinline__ cplx<T>* at_front(cplx<T>* L, cplx<T>* U, const FrontDesc& F, int64_t i, int64_t j) {
+  const int64_t f = F.p + F.r;
+  return j < F.p ? &L[F.L_off + j * f + i] : &U[F.U_off + (j - F.p) * F.r + (i - F.p)];
+}
+
+template <typename T>
+__global__ void k_scatter_orig(const int32_t* __restrict__ lf, int nf, const FrontDesc* __restrict__ fr,
+                               const int64_t* __restrict__ osrc, const int64_t* __restrict__ odst,
+                               const c128* __restrict__ lval, cplx<T>* __restrict__ L) {
+  const FrontDesc F = fr[lf[blockIdx.x]];
+  for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < F.orig_cnt; k += (int64_t)gridDim.y * blockDim.x) {
+    const c128 v = lval[osrc[F.orig_off + k]];
+    L[F.L_off + odst[F.orig_off + k]] = cmk((T)v.re, (T)v.im);
+  }
+}
+
+// add child `slot`'s update block into its parent (the fronts in lf are parents)
+template <typename T>
+__global__ void k_extend_add(const int32_t* __restrict__ lf, int nf, const FrontDesc* __restrict__ fr, int slot,
+                             const int32_t* __restrict__ emap, cplx<T>* __restrict__ L, cplx<T>* __restrict__ U) {
+  const FrontDesc P = fr[lf[blockIdx.x]];
+  const int c = slot == 0 ? P.child0 : P.child1;
+  if (c < 0) return;
+  const FrontDesc C = fr[c];
+  const int64_t rc = C.r;
+  const int64_t total = rc * rc;
+  for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.y * blockDim.x) {
+    const int64_t j = k / rc, i = k - j * rc;
+    if (i < j) continue;
+    const cplx<T> v = U[C.U_off + j * rc + i];
+    const int64_t pi = emap[C.emap_off + i], pj = emap[C.emap_off + j];
+    cplx<T>* dst = at_front(L, U, P, pi, pj);
+    *dst = *dst + v;
+  }
+}
+
+// unblocked LDL^T of the diagonal block [k0, k0+nb) of every active front (one block each)
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag_block(const int32_t* __restrict__ lf, const FrontDesc* __restrict__ fr,
+                                                    int k0, cplx<T>* __restrict__ L, const double* __restrict__ tau_sub,
+                                                    const int32_t* __restrict__ front_sub,
+                                                    unsigned long long* __restrict__ npiv) {
+  __shared__ cplx<T> A[kNb][kNb + 1];
+  const int fid = lf[blockIdx.x];
+  const FrontDesc F = fr[fid];
+  const int nb = min(kNb, F.p - k0);
+  const int64_t f = F.p + F.r;
+  cplx<T>* base = L + F.L_off + (int64_t)k0 * f + k0;
+  for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
+    const int j = t / kNb, i = t % kNb;
+    A[i][j] = (i < nb && j < nb && i >= j) ? base[(int64_t)j * f + i] : cmk((T)0, (T)0);
+  }
+  __syncthreads();
+  const T tau = (T)tau_sub[front_sub[fid]];
+  for (int j = 0; j < nb; ++j) {
+    if (threadIdx.x == 0) {
+      cplx<T> d = A[j][j];
+      const T ad = sqrt(d.re * d.re + d.im * d.im);
+      if (!(ad >= tau)) {
+        d = ad > (T)0 ? cmk(d.re * (tau / ad), d.im * (tau / ad)) : cmk(tau, (T)0);
+        atomicAdd(npiv, 1ull);
+        A[j][j] = d;
+      }
+    }
+    __syncthreads();
+    const cplx<T> d = A[j][j];
+    // a_ik -= a_ij a_kj / d for i >= k > j
+    for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
+      const int k = t / kNb, i = t % kNb;
+      if (k > j && i >= k && i < nb) {
+        const cplx<T> lij = cdiv(A[i][j], d);
+        cfms(A[i][k], lij, A[k][j]);
+      }
+    }
+    __syncthreads();
+    for (int i = j + 1 + (int)threadIdx.x; i < nb; i += blockDim.x) A[i][j] = cdiv(A[i][j], d);
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
+    const int j = t / kNb, i = t % kNb;
+    if (i < nb && j < nb && i >= j) base[(int64_t)j * f + i] = A[i][j];
+  }
+}
+
+// rows below the diagonal block: L[i, panel] = F[i, panel] L_kk^{-T} D^{-1}
+template <typename T>
+__global__ __launch_bounds__(256) void k_panel_rows(const int32_t* __restrict__ lf, const FrontDesc* __restrict__ fr,
+                                                    int k0, cplx<T>* __restrict__ L) {
+  __shared__ cplx<T> Lkk[kNb][kNb + 1];
+  const FrontDesc F = fr[lf[blockIdx.x]];
+  const int nb = min(kNb, F.p - k0);
+  const int64_t f = F.p + F.r;
+  const int64_t r0 = k0 + nb;
+  const int64_t rows = f - r0;
+  const int64_t chunk = (int64_t)blockIdx.y * blockDim.x;
+  if (chunk >= rows) return;
+  cplx<T>* col0 = L + F.L_off + (int64_t)k0 * f;
+  for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
+    const int j = t / kNb, i = t % kNb;
+    Lkk[i][j] = (i < nb && j < nb && i >= j) ? col0[(int64_t)j * f + k0 + i] : cmk((T)0, (T)0);
+  }
+  __syncthreads();
+  for (int64_t i = r0 + chunk + threadIdx.x; i < f; i += (int64_t)gridDim.y * blockDim.x) {
+    cplx<T> y[kNb];
+#pragma unroll
+    for (int j = 0; j < kNb; ++j) y[j] = j < nb ? col0[(int64_t)j * f + i] : cmk((T)0, (T)0);
+#pragma unroll
+    for (int j = 0; j < kNb; ++j) {
+#pragma unroll
+      for (int l = 0; l < j; ++l) cfms(y[j], y[l], Lkk[j][l]);
+    }
+#pragma unroll
+    for (int j = 0; j < kNb; ++j)
+      if (j < nb) col0[(int64_t)j * f + i] = cdiv(y[j], Lkk[j][j]);
+  }
+}
+
+// trailing update: F[i][j] -= sum_l L[i][l] d_l L[j][l] for i >= j >= k0 + nb
+template <typename T>
+__global__ __launch_bounds__(256) void k_trailing(const int32_t* __restrict__ lf, const FrontDesc* __restrict__ fr,
+                                                  int k0, cplx<T>* __restrict__ L, cplx<T>* __restrict__ U) {
+  __shared__ cplx<T> As[kNb][kTile + 1];
+  __shared__ cplx<T> Bs[kNb][kTile + 1];
+  const FrontDesc F = fr[lf[blockIdx.x]];
+  const int nb = min(kNb, F.p - k0);
+  const int64_t f = F.p + F.r;
+  const int64_t c0 = k0 + nb;
+  const int64_t nrem = f - c0;
+  if (nrem <= 0) return;
+  const int64_t nt = (nrem + kTile - 1) / kTile;
+  const int64_t tid = blockIdx.y;
+  if (tid >= nt * (nt + 1) / 2) return;
+  // triangular tile index -> (ti, tj), ti >= tj
+  int64_t ti = (int64_t)((sqrt(8.0 * (double)tid + 1.0) - 1.0) / 2.0);
+  while (ti * (ti + 1) / 2 > tid) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= tid) ++ti;
+  const int64_t tj = tid - ti * (ti + 1) / 2;
+  const int64_t i0 = c0 + ti * kTile, j0 = c0 + tj * kTile;
+  const cplx<T>* pan = L + F.L_off + (int64_t)k0 * f;
+  const cplx<T>* dg = pan + k0;  // diagonal entries at pan[l*f + k0 + l]
+  for (int t = threadIdx.x; t < kNb * kTile; t += blockDim.x) {
+    const int l = t / kTile, r = t % kTile;
+    cplx<T> a = cmk((T)0, (T)0), b = cmk((T)0, (T)0);
+    if (l < nb) {
+      if (i0 + r < f) a = pan[(int64_t)l * f + i0 + r];
+      if (j0 + r < f) b = pan[(int64_t)l * f + j0 + r] * dg[(int64_t)l * f + l];
+    }
+    As[l][r] = a;
+    Bs[l][r] = b;
+  }
+  __syncthreads();
+  // each thread: 4 x 4 micro tile
+  const int tr = (threadIdx.x % 16) * 4, tc = (threadIdx.x / 16) * 4;
+  cplx<T> acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = cmk((T)0, (T)0);
+  for (int l = 0; l < nb; ++l) {
+    cplx<T> av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = As[l][tr + a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bv[b] = Bs[l][tc + b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) cfma(acc[a][b], av[a], bv[b]);
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int64_t j = j0 + tc + b;
+    if (j >= f) continue;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int64_t i = i0 + tr + a;
+      if (i >= f || i < j) continue;
+      cplx<T>* dst = at_front(L, U, F, i, j);
+      *dst = *dst - acc[a][b];
+    }
+  }
+}
+
+// inverse of each unit-lower diagonal block, stored transposed in the strict upper part:
+// Lkk^{-1}[i][j] (i > j) goes to position (j, i) of the block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag_inverse(const FrontDesc* __restrict__ fr, const int32_t* __restrict__ blk_front,
+                                                      const int32_t* __restrict__ blk_k0, cplx<T>* __restrict__ L) {
+  __shared__ cplx<T> A[kNb][kNb + 1];
+  __shared__ cplx<T> X[kNb][kNb + 1];
+  const FrontDesc F = fr[blk_front[blockIdx.x]];
+  const int k0 = blk_k0[blockIdx.x];
+  const int nb = min(kNb, F.p - k0);
+  const int64_t f = F.p + F.r;
+  cplx<T>* base = L + F.L_off + (int64_t)k0 * f + k0;
+  for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
+    const int j = t / kNb, i = t % kNb;
+    A[i][j] = (i < nb && j < nb && i > j) ? base[(int64_t)j * f + i] : cmk((T)0, (T)0);
+    X[i][j] = cmk((T)(i == j ? 1 : 0), (T)0);
+  }
+  __syncthreads();
+  // column j of the inverse: forward substitution, thread per column
+  if (threadIdx.x < nb) {
+    const int j = threadIdx.x;
+    for (int i = j + 1; i < nb; ++i) {
+      cplx<T> s = cmk((T)0, (T)0);
+      for (int l = j; l < i; ++l) cfma(s, A[i][l], X[l][j]);
+      X[i][j] = cmk(-s.re, -s.im);
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
+    const int j = t / kNb, i = t % kNb;
+    if (i < nb && j < nb && i > j) base[(int64_t)i * f + j] = X[i][j];
+  }
+}
+
+// max |a_ij| of each subdomain's local operator (deterministic: one block per subdomain)
+__global__ void k_sub_norm(const int64_t* __restrict__ csr_off, const c128* __restrict__ lval, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int64_t a = csr_off[blockIdx.x], b = csr_off[blockIdx.x + 1];
+  double m = 0;
+  for (int64_t k = a + threadIdx.x; k < b; k += blockDim.x) {
+    const c128 v = lval[k];
+    m = fmax(m, sqrt(v.re * v.re + v.im * v.im));
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+__global__ void k_scale(double* x, int n, double s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= s;
+}
+
+template <typename T>
+void factor_typed(Ctx* ctx, Ddm& d) {
+  hipStream_t st = ctx->stream;
+  d.d_factor.alloc(ctx, std::max<int64_t>(1, d.factor_entries) * sizeof(cplx<T>));
+  d.d_update.alloc(ctx, std::max<int64_t>(1, d.update_entries) * sizeof(cplx<T>));
+  HIP_CHECK(hipMemsetAsync(d.d_factor.p, 0, d.d_factor.bytes, st));
+  HIP_CHECK(hipMemsetAsync(d.d_update.p, 0, d.d_update.bytes, st));
+  cplx<T>* L = d.d_factor.as<cplx<T>>();
+  cplx<T>* U = d.d_update.as<cplx<T>>();
+  // static pivot threshold per subdomain
+  const char* e = std::getenv("HZ_PIVOT_EPS");
+  const double eps = e ? std::atof(e) : (sizeof(T) == 8 ? 1e-12 : 1e-6);
+  DevArray<int64_t> d_csroff;
+  DevArray<double> d_tau;
+  DevArray<int32_t> d_fsub;
+  {
+    std::vector<int64_t> co;
+    for (auto& S : d.subs) co.push_back(S.csr_off);
+    co.push_back(d.subs.back().csr_off + (int64_t)d.subs.back().col.size());
+    d_csroff.upload(ctx, co);
+    d_tau.alloc(ctx, d.n_sub);
+    hipLaunchKernelGGL(k_sub_norm, dim3(d.n_sub), dim3(256), 0, st, d_csroff.ptr(), d.d_lval.ptr(), d_tau.ptr());
+    hipLaunchKernelGGL(k_scale, dim3((d.n_sub + 255) / 256), dim3(256), 0, st, d_tau.ptr(), d.n_sub, eps);
+    std::vector<int32_t> fs(d.fronts.size());
+    for (size_t i = 0; i < d.fronts.size(); ++i) fs[i] = d.fronts[i].sub;
+    d_fsub.upload(ctx, fs);
+  }
+  d.d_npiv.alloc(ctx, 1);
+  HIP_CHECK(hipMemsetAsync(d.d_npiv.ptr(), 0, sizeof(unsigned long long), st));
+  const FrontDesc* fr = d.d_fronts.ptr();
+  for (size_t lv = 0; lv < d.levels.size(); ++lv) {
+    const Level& Lv = d.levels[lv];
+    const int nf = (int)Lv.fronts.size();
+    const int32_t* lf = d.d_level_fronts.ptr() + d.level_off[lv];
+    int64_t max_orig = 1, max_child_u = 1;
+    for (int32_t fi : Lv.fronts) {
+      max_orig = std::max(max_orig, d.fronts[fi].orig_cnt);
+      for (int k = 0; k < d.fronts[fi].nchild; ++k)
+        max_child_u = std::max(max_child_u, d.fronts[d.fronts[fi].child[k]].r * d.fronts[d.fronts[fi].child[k]].r);
+    }
+    const unsigned gy_o = (unsigned)std::min<int64_t>((max_orig + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_scatter_orig<T>, dim3(nf, gy_o), dim3(256), 0, st, lf, nf, fr, d.d_orig_src.ptr(),
+                       d.d_orig_dst.ptr(), d.d_lval.ptr(), L);
+    HIP_CHECK(hipGetLastError());
+    if (lv > 0) {
+      const unsigned gy_e = (unsigned)std::min<int64_t>((max_child_u + 255) / 256, 4096);
+      for (int slot = 0; slot < 2; ++slot) {
+        hipLaunchKernelGGL(k_extend_add<T>, dim3(nf, gy_e), dim3(256), 0, st, lf, nf, fr, slot, d.d_emap.ptr(), L, U);
+        HIP_CHECK(hipGetLastError());
+      }
+    }
+    for (int64_t k0 = 0; k0 < Lv.max_p; k0 += kNb) {
+      int cnt = 0;  // fronts sorted by p descending: active prefix
+      int64_t max_f = 0;
+      while (cnt < nf && d.fronts[Lv.fronts[cnt]].p > k0) {
+        max_f = std::max(max_f, d.fronts[Lv.fronts[cnt]].f());
+        ++cnt;
+      }
+      hipLaunchKernelGGL(k_diag_block<T>, dim3(cnt), dim3(256), 0, st, lf, fr, (int)k0, L, d_tau.ptr(), d_fsub.ptr(),
+                         d.d_npiv.ptr());
+      HIP_CHECK(hipGetLastError());
+      const int64_t rows = max_f - k0;
+      const unsigned gy_r = (unsigned)std::max<int64_t>(1, std::min<int64_t>((rows + 255) / 256, 64));
+      hipLaunchKernelGGL(k_panel_rows<T>, dim3(cnt, gy_r), dim3(256), 0, st, lf, fr, (int)k0, L);
+      HIP_CHECK(hipGetLastError());
+      const int64_t nrem = max_f - k0 - 1;
+      const int64_t nt = std::max<int64_t>(1, (nrem + kTile - 1) / kTile);
+      const int64_t tiles = nt * (nt + 1) / 2;
+      HZ_REQUIRE(tiles < 65536, HZ_ERR_STATE, "factor: front too large for the tile grid");
+      hipLaunchKernelGGL(k_trailing<T>, dim3(cnt, (unsigned)tiles), dim3(256), 0, st, lf, fr, (int)k0, L, U);
+      HIP_CHECK(hipGetLastError());
+    }
+  }
+  // inverses of the diagonal blocks
+  {
+    std::vector<int32_t> bf, bk;
+    for (size_t fi = 0; fi < d.fronts.size(); ++fi)
+      for (int64_t k0 = 0; k0 < d.fronts[fi].p; k0 += kNb) {
+        bf.push_back((int32_t)fi);
+        bk.push_back((int32_t)k0);
+      }
+    DevArray<int32_t> d_bf, d_bk;
+    d_bf.upload(ctx, bf);
+    d_bk.upload(ctx, bk);
+    for (size_t a = 0; a < bf.size(); a += 65535) {
+      const unsigned nb = (unsigned)std::min<size_t>(65535, bf.size() - a);
+      hipLaunchKernelGGL(k_diag_inverse<T>, dim3(nb), dim3(256), 0, st, fr, d_bf.ptr() + a, d_bk.ptr() + a, L);
+      HIP_CHECK(hipGetLastError());
+    }
+    unsigned long long np = 0;
+    HIP_CHECK(hipMemcpyAsync(&np, d.d_npiv.ptr(), sizeof(np), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    d.static_pivots = (int64_t)np;
+  }
+  // the update workspace is only needed during the factorisation
+  d.d_update.release();
+}
+
+}  // namespace
+
+void factor_all(Ctx* ctx, Ddm& d) {
+  if (d.precision == HZ_PREC_MIXED)
+    factor_typed<float>(ctx, d);
+  else
+    factor_typed<double>(ctx, d);
+}
+
+}  // namespace hz

@@ -1,0 +1,46 @@
+// Host-side launchers of the FP64 Krylov kernels (krylov.hip) and the block FGMRES driver.
+#pragma once
+
+#include "ddm.h"
+
+namespace hz {
+
+struct KrylovKernels {
+  Ctx* ctx;
+  int64_t n;
+  int s;
+  int nchunk;
+  KrylovKernels(Ctx* c, int64_t n_, int s_);
+  void to_node(const c128* src, c128* dst);
+  void from_node(const c128* src, c128* dst);
+  // H[J][c] (+)= sum_rows conj(V_J) W   for J < nblk * s ; partial buffer >= nchunk * nblk * s * s;
+  // if H2 is given the same sums are also added into it
+  void gram(int nblk, const c128* V, int64_t ldv, const c128* W, c128* part, c128* H, bool accumulate,
+            c128* H2 = nullptr);
+  // Y = Yin + beta * sum_J V_J H[J][:]
+  void block_axpy(int nblk, const c128* V, int64_t ldv, const c128* H, double beta, const c128* Yin, c128* Y);
+  // one CholQR pass: G = W^H W = R^H R, out = W R^{-1}, Racc = R Racc
+  void cholqr_pass(const c128* W, c128* out, c128* part, c128* G, c128* R, c128* Rinv, c128* Racc, int* flag);
+  void identity(c128* M);
+  void lsq_step(int jj, c128* Hc, c128* Rm, int64_t ldr, c128* refl, c128* tau, c128* G, double* res);
+  void lsq_solve(int J, const c128* Rm, int64_t ldr, const c128* G, c128* Y);
+  void colnorms(const c128* X, double* part, double* out);
+};
+
+struct SolveOptions {
+  double tol = 1e-6;
+  int max_iter = 500;
+  int restart = 40;
+  int fixed_iters = 0;
+};
+
+struct ColInfo {
+  int iters = 0, restarts = 0, status = 0;
+  double rel_residual = 0;
+};
+
+// Solve A X = B for a node-major block B [n][s] (device, c128).  X (device) receives the
+// solution.  Returns per-column info; status HZ_ERR_NOT_CONVERGED if max_iter is hit.
+void fgmres(Ctx* ctx, Ddm& d, int s, const c128* B, c128* X, const SolveOptions& o, std::vector<ColInfo>& info);
+
+}  // namespace hz
