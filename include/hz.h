@@ -187,6 +187,29 @@ typedef struct {
 } hz_ddm_stats;
 hz_status hz_ddm_stats_get(hz_ctx* ctx, hz_handle ddm, hz_ddm_stats* out);
 
+/*
+ * Live kernel accounting for measurement (not needed to solve).  While enabled, the
+ * library brackets every launch of the kernel classes below with HIP events on the
+ * context stream and records the launch's algorithmic bytes and flops (the minimum
+ * traffic / arithmetic of the operation, not counter readings).
+ *   HZ_K_SPMM        multi-RHS operator product (FP64 CSR)
+ *   HZ_K_ORAS_FWD    forward multifrontal sweep, one launch per tree level
+ *   HZ_K_ORAS_BWD    backward multifrontal sweep, one launch per tree level
+ *   HZ_K_CGS_GRAM    V^H W partial products of classical Gram-Schmidt
+ *   HZ_K_CGS_UPDATE  W -= V H (and X += Z Y) block updates
+ * hz_profile_enable(ctx, 1) clears and starts recording, (ctx, 0) stops.
+ * hz_profile_get synchronises the stream and returns the totals of one class.
+ */
+enum { HZ_K_SPMM = 0, HZ_K_ORAS_FWD = 1, HZ_K_ORAS_BWD = 2, HZ_K_CGS_GRAM = 3, HZ_K_CGS_UPDATE = 4, HZ_K_COUNT = 5 };
+typedef struct {
+  int64_t launches;
+  double seconds;  /* sum of event-timed launch durations */
+  double bytes;    /* sum of algorithmic bytes */
+  double flops;    /* sum of algorithmic flops */
+} hz_kernel_stat;
+hz_status hz_profile_enable(hz_ctx* ctx, int on);
+hz_status hz_profile_get(hz_ctx* ctx, int kernel_class, hz_kernel_stat* out);
+
 /* serving: continuous batching of solve requests (thread-safe) */
 typedef struct {
   size_t struct_size;

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhz.so")
 
-SOURCES = ["api.cpp", "mesh.cpp", "p3ref.cpp", "ddm.cpp", "fgmres.cpp", "serve.cpp",
+SOURCES = ["api.cpp", "mesh.cpp", "p3ref.cpp", "ddm.cpp", "fgmres.cpp", "serve.cpp", "prof.cpp",
            "assemble.hip", "spmm.hip", "factor.hip", "oras.hip", "coarse.hip", "krylov.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

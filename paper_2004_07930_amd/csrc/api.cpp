@@ -4,6 +4,7 @@
 #include <new>
 
 #include "krylov.h"
+#include "prof.h"
 #include "serve.h"
 
 struct hz_ctx : hz::Ctx {};
@@ -193,6 +194,8 @@ void hz_finalize(hz_ctx* c) {
     c->ops.clear();
     c->meshes.clear();
   }
+  delete c->prof;
+  c->prof = nullptr;
   delete c;
 }
 

@@ -244,30 +244,39 @@ __global__ void k_lu_update(int64_t nc, int64_t k, cplx<T>* A) {
   cfms(A[i + j * nc], A[i + k * nc], A[k + j * nc]);
 }
 
-// X = E^{-1}: column j solves L U x = P e_j (one thread per column)
+// X = E^{-1}: block j solves L U x = P e_j with the vector in LDS, rows in parallel
 template <typename T>
-__global__ void k_lu_inverse(int64_t nc, const cplx<T>* LU, const int32_t* piv, cplx<T>* X) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nc) return;
-  cplx<T>* x = X + j * nc;
-  for (int64_t i = 0; i < nc; ++i) x[i] = cmk((T)(i == j ? 1 : 0), (T)0);
-  for (int64_t k = 0; k < nc; ++k) {
-    const int64_t p = piv[k];
-    if (p != k) {
-      const cplx<T> t = x[k];
-      x[k] = x[p];
-      x[p] = t;
+__global__ __launch_bounds__(256) void k_lu_inverse(int64_t nc, const cplx<T>* LU, const int32_t* piv, cplx<T>* X) {
+  extern __shared__ unsigned char smem[];
+  cplx<T>* x = reinterpret_cast<cplx<T>*>(smem);
+  const int64_t j = blockIdx.x;
+  for (int64_t i = threadIdx.x; i < nc; i += blockDim.x) x[i] = cmk((T)(i == j ? 1 : 0), (T)0);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int64_t k = 0; k < nc; ++k) {
+      const int64_t p = piv[k];
+      if (p != k) {
+        const cplx<T> t = x[k];
+        x[k] = x[p];
+        x[p] = t;
+      }
     }
-  }
+  __syncthreads();
   for (int64_t k = 0; k < nc; ++k) {
     const cplx<T> xk = x[k];
-    for (int64_t i = k + 1; i < nc; ++i) cfms(x[i], LU[i + k * nc], xk);
+    __syncthreads();
+    if (xk.re != (T)0 || xk.im != (T)0)
+      for (int64_t i = k + 1 + threadIdx.x; i < nc; i += blockDim.x) cfms(x[i], LU[i + k * nc], xk);
+    __syncthreads();
   }
   for (int64_t k = nc - 1; k >= 0; --k) {
-    x[k] = cdiv(x[k], LU[k + k * nc]);
-    const cplx<T> xk = x[k];
-    for (int64_t i = 0; i < k; ++i) cfms(x[i], LU[i + k * nc], xk);
+    const cplx<T> xk = cdiv(x[k], LU[k + k * nc]);
+    __syncthreads();
+    if (threadIdx.x == 0) x[k] = xk;
+    for (int64_t i = threadIdx.x; i < k; i += blockDim.x) cfms(x[i], LU[i + k * nc], xk);
+    __syncthreads();
   }
+  for (int64_t i = threadIdx.x; i < nc; i += blockDim.x) X[i + j * nc] = x[i];
 }
 
 __global__ void k_c128_to_c64(int64_t n, const c128* a, c64* b) {
@@ -286,7 +295,7 @@ void lu_and_inverse(Ctx* ctx, int64_t nc, cplx<T>* E, int32_t* piv, cplx<T>* Ein
     }
   }
   HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_lu_inverse<T>, dim3((unsigned)((nc + 63) / 64)), dim3(64), 0, st, nc, E, piv, Einv);
+  hipLaunchKernelGGL(k_lu_inverse<T>, dim3((unsigned)nc), dim3(256), nc * sizeof(cplx<T>), st, nc, E, piv, Einv);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -312,18 +321,29 @@ __global__ __launch_bounds__(256) void k_restrict(int64_t nc, int s, const int64
   }
 }
 
-// y2 = Einv y  (nc x nc times nc x s), one block per 64 rows x all columns
+// partial products of y2 = Einv y over K chunks: part[kc][i][col] (64 rows x all columns
+// per block, K chunk blockIdx.y)
 template <typename T>
-__global__ __launch_bounds__(256) void k_dense_apply(int64_t nc, int s, const cplx<T>* __restrict__ Ei,
-                                                     const cplx<T>* __restrict__ y, cplx<T>* __restrict__ y2) {
+__global__ __launch_bounds__(256) void k_dense_apply(int64_t nc, int s, int64_t kchunk, const cplx<T>* __restrict__ Ei,
+                                                     const cplx<T>* __restrict__ y, cplx<T>* __restrict__ part) {
   const int64_t i = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
   const int cg = threadIdx.x >> 6;  // 4 column groups
+  const int64_t k0 = (int64_t)blockIdx.y * kchunk, k1 = min<int64_t>(nc, k0 + kchunk);
   if (i >= nc) return;
   for (int col = cg; col < s; col += 4) {
     cplx<T> acc = cmk((T)0, (T)0);
-    for (int64_t k = 0; k < nc; ++k) cfma(acc, Ei[i + k * nc], y[k * s + col]);
-    y2[i * s + col] = acc;
+    for (int64_t k = k0; k < k1; ++k) cfma(acc, Ei[i + k * nc], y[k * s + col]);
+    part[((int64_t)blockIdx.y * nc + i) * s + col] = acc;
   }
+}
+
+template <typename T>
+__global__ void k_dense_reduce(int nk, int64_t m, const cplx<T>* __restrict__ part, cplx<T>* __restrict__ y2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  cplx<T> a = cmk((T)0, (T)0);
+  for (int k = 0; k < nk; ++k) a = a + part[(int64_t)k * m + e];
+  y2[e] = a;
 }
 
 // q = Z y2 ; t = v - AZ y2
@@ -402,17 +422,25 @@ static void coarse_apply_t(Ctx* ctx, Ddm& d, int s, const c128* v, c128* q, c128
   CoarseSpace& cs = *d.coarse;
   hipStream_t st = ctx->stream;
   const int64_t nc = cs.nc, n = d.op->mesh->n;
-  DevArray<cplx<T>> y, y2;
-  y.alloc(ctx, nc * s);
-  y2.alloc(ctx, nc * s);
+  constexpr int KS = 32;
+  const int64_t kchunk = (nc + KS - 1) / KS;
+  const size_t need = (size_t)(nc * s) * sizeof(cplx<T>);
+  if (cs.w_y.bytes < need) {  // kept for the life of the ddm: no allocation on the solve path after the first call
+    cs.w_y.alloc(ctx, need);
+    cs.w_y2.alloc(ctx, need);
+    cs.w_part.alloc(ctx, need * KS);
+  }
+  cplx<T>* y = cs.w_y.as<cplx<T>>();
+  cplx<T>* y2 = cs.w_y2.as<cplx<T>>();
   hipLaunchKernelGGL(k_restrict<T>, dim3((unsigned)nc), dim3(256), 0, st, nc, s, cs.d_ztptr.ptr(), cs.d_ztcol.ptr(),
-                     cs.d_ztval.ptr(), v, y.ptr());
-  hipLaunchKernelGGL(k_dense_apply<T>, dim3((unsigned)((nc + 63) / 64)), dim3(256), 0, st, nc, s, Einv, y.ptr(),
-                     y2.ptr());
+                     cs.d_ztval.ptr(), v, y);
+  hipLaunchKernelGGL(k_dense_apply<T>, dim3((unsigned)((nc + 63) / 64), KS), dim3(256), 0, st, nc, s, kchunk, Einv, y,
+                     cs.w_part.as<cplx<T>>());
+  hipLaunchKernelGGL(k_dense_reduce<T>, dim3((unsigned)((nc * s + 255) / 256)), dim3(256), 0, st, KS, nc * s,
+                     cs.w_part.as<cplx<T>>(), y2);
   hipLaunchKernelGGL(k_prolong<T>, dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, st, n, s, cs.d_zptr.ptr(),
-                     cs.d_zcol.ptr(), cs.d_zval.ptr(), cs.d_azptr.ptr(), cs.d_azcol.ptr(), az, y2.ptr(), v, q, t);
+                     cs.d_zcol.ptr(), cs.d_zval.ptr(), cs.d_azptr.ptr(), cs.d_azcol.ptr(), az, y2, v, q, t);
   HIP_CHECK(hipGetLastError());
-  HIP_CHECK(hipStreamSynchronize(st));  // y, y2 are freed on return
 }
 
 void coarse_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c128* q, c128* t) {

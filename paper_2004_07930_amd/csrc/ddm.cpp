@@ -409,7 +409,7 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     for (auto& e : errs) HZ_REQUIRE(e.empty(), HZ_ERR_STATE, "hz_setup_ddm: " + e);
   }
   // --- concatenate fronts, offsets
-  int64_t vec = 0, csr = 0, rows = 0, Loff = 0, Uoff = 0, urow = 0, orig = 0, cvec = 0;
+  int64_t vec = 0, csr = 0, rows = 0, Loff = 0, Uoff = 0, urow = 0, orig = 0;
   int max_level = 0;
   for (int32_t i = 0; i < n_sub; ++i) {
     Subdomain& S = d->subs[i];
@@ -430,7 +430,6 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
       F.rows_off = urow;
       F.emap_off = urow;
       urow += F.r;
-      cvec += F.r;
       d->max_front = std::max(d->max_front, F.f());
       max_level = std::max(max_level, F.level);
       S.fronts.push_back((int32_t)d->fronts.size());
@@ -444,7 +443,6 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   d->factor_entries = Loff;
   d->update_entries = Uoff;
   d->urows_total = urow;
-  d->cvec_total = cvec;
   d->urows.resize(urow);
   d->emap.assign(urow, 0);
   // update rows, extend-add maps and original-entry scatter lists
@@ -483,9 +481,13 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     std::stable_sort(L.fronts.begin(), L.fronts.end(),
                      [&](int32_t a, int32_t b) { return d->fronts[a].p > d->fronts[b].p; });
     for (int32_t fi : L.fronts) {
-      L.max_p = std::max(L.max_p, d->fronts[fi].p);
-      L.max_f = std::max(L.max_f, d->fronts[fi].f());
-      L.max_r = std::max(L.max_r, d->fronts[fi].r);
+      const Front& F = d->fronts[fi];
+      L.max_p = std::max(L.max_p, F.p);
+      L.max_f = std::max(L.max_f, F.f());
+      L.max_r = std::max(L.max_r, F.r);
+      L.useful += F.p * (F.p + 1) / 2 + F.r * F.p;
+      L.sum_f += F.f();
+      L.sum_p += F.p;
     }
     d->level_off.push_back((int64_t)lf.size());
     lf.insert(lf.end(), L.fronts.begin(), L.fronts.end());
@@ -505,7 +507,8 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   for (int64_t g = 0; g < m.n; ++g) HZ_REQUIRE(d->own_src[g] >= 0, HZ_ERR_STATE, "hz_setup_ddm: unowned dof");
   // --- device: front descriptors, maps, local operators
   std::vector<FrontDesc> fd(d->fronts.size());
-  int64_t cv = 0;
+  int64_t wrows = 0;
+  std::vector<int32_t> imap;  // per front: 2 x f inverse extend-add maps (parent row -> child row, or -1)
   for (size_t fi = 0; fi < d->fronts.size(); ++fi) {
     const Front& F = d->fronts[fi];
     FrontDesc& x = fd[fi];
@@ -516,8 +519,19 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     x.orig_off = F.orig_off;
     x.orig_cnt = F.orig_cnt;
     x.vec_off = d->subs[F.sub].vec_off;
-    x.cvec_off = cv;
-    cv += F.r;
+    x.w_off = wrows;
+    wrows += F.f();
+    x.imap_off = (int64_t)imap.size();
+    imap.resize(imap.size() + 2 * F.f(), -1);
+    for (int k = 0; k < F.nchild; ++k) {
+      const Front& Cf = d->fronts[F.child[k]];
+      for (int64_t q = 0; q < Cf.r; ++q) {
+        const int32_t tgt = d->emap[Cf.emap_off + q];
+        HZ_REQUIRE(tgt >= 0 && tgt < F.f(), HZ_ERR_STATE, "symbolic analysis: extend-add target out of range");
+        imap[x.imap_off + k * F.f() + tgt] = (int32_t)q;
+      }
+    }
+    d->factor_useful += F.p * (F.p + 1) / 2 + F.r * F.p;
     x.p = (int32_t)F.p;
     x.r = (int32_t)F.r;
     x.parent = F.parent;
@@ -534,6 +548,30 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   d->d_orig_src.upload(ctx, d->orig_src);
   d->d_orig_dst.upload(ctx, d->orig_dst);
   d->d_level_fronts.upload(ctx, lf);
+  d->w_total = wrows;
+  d->d_imap.upload(ctx, imap);
+  {  // solve worklists: forward row tiles of 64, backward column tiles of 32
+    std::vector<int32_t> fw, bw;
+    for (const Level& L : d->levels) {
+      d->fwd_off.push_back((int64_t)fw.size() / 2);
+      d->bwd_off.push_back((int64_t)bw.size() / 2);
+      for (int32_t fi : L.fronts) {
+        const Front& F = d->fronts[fi];
+        for (int64_t i0 = 0; i0 < F.f(); i0 += 64) {
+          fw.push_back(fi);
+          fw.push_back((int32_t)i0);
+        }
+        for (int64_t j0 = 0; j0 < F.p; j0 += 32) {
+          bw.push_back(fi);
+          bw.push_back((int32_t)j0);
+        }
+      }
+    }
+    d->fwd_off.push_back((int64_t)fw.size() / 2);
+    d->bwd_off.push_back((int64_t)bw.size() / 2);
+    d->d_fwd_work.upload(ctx, fw);
+    d->d_bwd_work.upload(ctx, bw);
+  }
   {
     std::vector<int64_t> rp, gp;
     std::vector<int32_t> cl;

@@ -31,7 +31,8 @@ struct Front {
 struct FrontDesc {
   int64_t L_off, U_off, rows_off, emap_off, orig_off, orig_cnt;
   int64_t vec_off;   // offset of the subdomain's local vector (concatenated over subdomains)
-  int64_t cvec_off;  // offset of this front's r x s contribution block in the solve workspace
+  int64_t w_off;     // offset (rows) of this front's f x s work block in the solve workspace
+  int64_t imap_off;  // offset of the inverse extend-add maps: 2 x f entries (child slot 0, 1)
   int32_t p, r;
   int32_t parent;    // global front id or -1
   int32_t child0, child1;
@@ -58,6 +59,8 @@ struct Subdomain {
 struct Level {
   std::vector<int32_t> fronts;    // global front ids, sorted by p descending
   int64_t max_p = 0, max_f = 0, max_r = 0;
+  int64_t useful = 0;             // stored factor nonzeros of the level: sum p(p+1)/2 + r p
+  int64_t sum_f = 0, sum_p = 0;
 };
 
 struct CoarseSpace {
@@ -78,6 +81,7 @@ struct CoarseSpace {
   DevArray<c128> d_E;             // E = Z^T A Z, then its LU factors (column-major nc x nc)
   DevArray<c64> d_E32;
   DevArray<int32_t> d_piv;        // LU row pivots
+  DevBuf w_y, w_y2, w_part;       // apply workspace (restricted vector, product, K-chunk partials)
 };
 
 struct Ddm {
@@ -115,8 +119,14 @@ struct Ddm {
   std::vector<int64_t> level_off;    // offsets into d_level_fronts
   DevBuf d_factor;                // c128 or c64 L blocks
   DevBuf d_update;                // update workspace
+  DevBuf d_dinv;                  // inverse pivots per local position (factor precision)
   DevArray<unsigned long long> d_npiv;  // static pivot counter
-  int64_t cvec_total = 0;         // solve workspace rows (sum of r over fronts)
+  int64_t w_total = 0;            // solve workspace rows (sum of f over fronts)
+  int64_t factor_useful = 0;      // stored nonzeros: sum p(p+1)/2 + r p
+  // solve worklists per level: forward (front, 64-row tile start), backward (front, 32-column start)
+  std::vector<int64_t> fwd_off, bwd_off;
+  DevArray<int32_t> d_fwd_work, d_bwd_work;  // pairs
+  DevArray<int32_t> d_imap;
   int64_t device_bytes() const;
 };
 

@@ -213,37 +213,120 @@ __global__ __launch_bounds__(256) void k_trailing(const int32_t* __restrict__ lf
   }
 }
 
-// inverse of each unit-lower diagonal block, stored transposed in the strict upper part:
-// Lkk^{-1}[i][j] (i > j) goes to position (j, i) of the block.
+// ---- partitioned inverse: [L11; L21] -> [L11^{-1}; L21 L11^{-1}] (unit diagonal kept)
+//
+// With F = [L11^{-1}; L21 L11^{-1}] the multifrontal solves need no sequential
+// substitution: forward  [y; c] = [F_top w_p; w_r - F_bot w_p]
+//              backward x_p = F^T [z_p / d; -x_r].
+// Column blocks are transformed from the right: with K the already transformed columns
+// right of block J and L_JJ the unit-lower diagonal block,
+//   M[:, J] = ([E_J; L21[:, J]] - M[:, K] L11[K, J]) L_JJ^{-1}.
+// Each front's pivots D are first moved to a compact inverse-pivot array.
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_diag_inverse(const FrontDesc* __restrict__ fr, const int32_t* __restrict__ blk_front,
-                                                      const int32_t* __restrict__ blk_k0, cplx<T>* __restrict__ L) {
-  __shared__ cplx<T> A[kNb][kNb + 1];
-  __shared__ cplx<T> X[kNb][kNb + 1];
-  const FrontDesc F = fr[blk_front[blockIdx.x]];
-  const int k0 = blk_k0[blockIdx.x];
-  const int nb = min(kNb, F.p - k0);
+__global__ void k_extract_dinv(int nf, const FrontDesc* __restrict__ fr, cplx<T>* __restrict__ L,
+                               cplx<T>* __restrict__ dinv) {
+  const FrontDesc F = fr[blockIdx.x];
   const int64_t f = F.p + F.r;
-  cplx<T>* base = L + F.L_off + (int64_t)k0 * f + k0;
-  for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
-    const int j = t / kNb, i = t % kNb;
-    A[i][j] = (i < nb && j < nb && i > j) ? base[(int64_t)j * f + i] : cmk((T)0, (T)0);
-    X[i][j] = cmk((T)(i == j ? 1 : 0), (T)0);
+  for (int j = threadIdx.x; j < F.p; j += blockDim.x) {
+    cplx<T>* dg = L + F.L_off + (int64_t)j * f + j;
+    dinv[F.vec_off + F.pos0 + j] = cdiv(cmk((T)1, (T)0), *dg);
   }
-  __syncthreads();
-  // column j of the inverse: forward substitution, thread per column
-  if (threadIdx.x < nb) {
-    const int j = threadIdx.x;
-    for (int i = j + 1; i < nb; ++i) {
-      cplx<T> s = cmk((T)0, (T)0);
-      for (int l = j; l < i; ++l) cfma(s, A[i][l], X[l][j]);
-      X[i][j] = cmk(-s.re, -s.im);
+}
+
+// copy L11[j0:p, J] of every active front into a compact panel buffer (ld = p - j0)
+template <typename T>
+__global__ void k_inv_copy(const int32_t* __restrict__ act, const FrontDesc* __restrict__ fr,
+                           const int64_t* __restrict__ poff, int t, cplx<T>* __restrict__ L, cplx<T>* __restrict__ P) {
+  const int fid = act[blockIdx.x];
+  const FrontDesc F = fr[fid];
+  const int nblk = (F.p + kNb - 1) / kNb;
+  const int J = nblk - 1 - t;
+  const int j0 = J * kNb;
+  const int nbJ = min(kNb, F.p - j0);
+  const int64_t f = F.p + F.r;
+  const int64_t rows = F.p - j0;
+  cplx<T>* dst = P + poff[blockIdx.x];
+  for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < rows * nbJ; k += (int64_t)gridDim.y * blockDim.x) {
+    const int64_t jj = k / rows, r = k - jj * rows;
+    dst[jj * rows + r] = L[F.L_off + (int64_t)(j0 + jj) * f + j0 + r];
+  }
+}
+
+// one block per (active front, 64-row tile of rows >= j0): new column block J
+template <typename T>
+__global__ __launch_bounds__(256) void k_inv_block(const int32_t* __restrict__ act, const FrontDesc* __restrict__ fr,
+                                                   const int64_t* __restrict__ poff, int t,
+                                                   cplx<T>* __restrict__ L, const cplx<T>* __restrict__ P) {
+  constexpr int RT = 64, KC = 32;
+  __shared__ cplx<T> Lt[KC][kNb + 1];     // L11[k, J] chunk
+  __shared__ cplx<T> Mt[KC][RT + 1];      // M[rows, k] chunk
+  __shared__ cplx<T> Rr[RT][kNb + 1];     // result rows
+  __shared__ cplx<T> Ljj[kNb][kNb + 1];
+  const int fid = act[blockIdx.x];
+  const FrontDesc F = fr[fid];
+  const int nblk = (F.p + kNb - 1) / kNb;
+  const int J = nblk - 1 - t;
+  const int j0 = J * kNb;
+  const int nbJ = min(kNb, F.p - j0);
+  const int64_t f = F.p + F.r;
+  const int64_t i0 = j0 + (int64_t)blockIdx.y * RT;
+  if (i0 >= f) return;
+  const int64_t prow = F.p - j0;  // ld of the panel copy
+  const cplx<T>* Pp = P + poff[blockIdx.x];
+  cplx<T>* Lf = L + F.L_off;
+  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {
+    const int a = e / kNb, b = e % kNb;  // Ljj[a][b] = L11[j0 + a][j0 + b]
+    Ljj[a][b] = (a < nbJ && b < nbJ) ? Pp[(int64_t)b * prow + a] : cmk((T)0, (T)0);
+  }
+  const int r = threadIdx.x & 63, g = threadIdx.x >> 6;  // row, column group (8 columns each)
+  const int64_t i = i0 + r;
+  cplx<T> acc[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) acc[a] = cmk((T)0, (T)0);
+  // GEMM over the transformed columns K = [j0 + nbJ, kend)
+  const int64_t k1 = j0 + nbJ;
+  const int64_t kend = i0 < F.p ? min<int64_t>(F.p, i0 + RT) : F.p;
+  for (int64_t kc = k1; kc < kend; kc += KC) {
+    const int kn = (int)min<int64_t>(KC, kend - kc);
+    __syncthreads();
+    for (int e = threadIdx.x; e < KC * kNb; e += 256) {
+      const int k = e / kNb, jj = e % kNb;
+      Lt[k][jj] = (k < kn && jj < nbJ) ? Pp[(int64_t)jj * prow + (kc + k - j0)] : cmk((T)0, (T)0);
+    }
+    for (int e = threadIdx.x; e < KC * RT; e += 256) {
+      const int k = e / RT, rr = e % RT;
+      Mt[k][rr] = (k < kn && i0 + rr < f) ? Lf[(kc + k) * f + i0 + rr] : cmk((T)0, (T)0);
+    }
+    __syncthreads();
+    for (int k = 0; k < kn; ++k) {
+      const cplx<T> m = Mt[k][r];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) cfma(acc[a], m, Lt[k][g * 8 + a]);
     }
   }
+  // R = base - acc ; base = e_J on the top block, L21[i, J] below
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int jj = g * 8 + a;
+    cplx<T> base = cmk((T)0, (T)0);
+    if (i < f && jj < nbJ) {
+      if (i < F.p)
+        base = cmk((T)(i == j0 + jj ? 1 : 0), (T)0);
+      else
+        base = Lf[(int64_t)(j0 + jj) * f + i];
+    }
+    Rr[r][jj] = base - acc[a];
+  }
   __syncthreads();
-  for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
-    const int j = t / kNb, i = t % kNb;
-    if (i < nb && j < nb && i > j) base[(int64_t)i * f + j] = X[i][j];
+  // x L_JJ = R  (unit lower L_JJ):  x_jj = R_jj - sum_{l > jj} x_l L_JJ[l][jj]
+  if (threadIdx.x < RT && i < f) {
+    for (int jj = nbJ - 1; jj >= 0; --jj) {
+      cplx<T> x = Rr[r][jj];
+      for (int l = jj + 1; l < nbJ; ++l) cfms(x, Rr[r][l], Ljj[l][jj]);
+      Rr[r][jj] = x;
+    }
+    for (int jj = 0; jj < nbJ; ++jj) Lf[(int64_t)(j0 + jj) * f + i] = Rr[r][jj];
   }
 }
 
@@ -343,29 +426,56 @@ void factor_typed(Ctx* ctx, Ddm& d) {
       HIP_CHECK(hipGetLastError());
     }
   }
-  // inverses of the diagonal blocks
+  // the update workspace is only needed during the factorisation
+  d.d_update.release();
+  // partitioned inverse of every front, all fronts at once, column blocks from the right
   {
-    std::vector<int32_t> bf, bk;
-    for (size_t fi = 0; fi < d.fronts.size(); ++fi)
-      for (int64_t k0 = 0; k0 < d.fronts[fi].p; k0 += kNb) {
-        bf.push_back((int32_t)fi);
-        bk.push_back((int32_t)k0);
+    const int nfr = (int)d.fronts.size();
+    d.d_dinv.alloc(ctx, (size_t)std::max<int64_t>(1, d.n_local_total) * sizeof(cplx<T>));
+    hipLaunchKernelGGL(k_extract_dinv<T>, dim3(nfr), dim3(256), 0, st, nfr, fr, L, d.d_dinv.as<cplx<T>>());
+    HIP_CHECK(hipGetLastError());
+    std::vector<int32_t> order(nfr);
+    for (int i = 0; i < nfr; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return d.fronts[a].p > d.fronts[b].p; });
+    // panel copies: front fi needs (p - j0) * nbJ <= p * kNb entries
+    std::vector<int64_t> poff(nfr);
+    int64_t tot = 0;
+    for (int k = 0; k < nfr; ++k) {
+      poff[k] = tot;
+      tot += d.fronts[order[k]].p * kNb;
+    }
+    DevArray<int32_t> d_act;
+    DevArray<int64_t> d_poff;
+    d_act.upload(ctx, order);
+    d_poff.upload(ctx, poff);
+    DevBuf panel;
+    panel.alloc(ctx, (size_t)std::max<int64_t>(1, tot) * sizeof(cplx<T>));
+    const int64_t maxp = d.fronts[order[0]].p;
+    const int tmax = (int)((maxp + kNb - 1) / kNb);
+    for (int t = 0; t < tmax; ++t) {
+      int cnt = 0;
+      int64_t maxrows = 0;
+      while (cnt < nfr && (d.fronts[order[cnt]].p + kNb - 1) / kNb > t) {
+        const Front& Fr = d.fronts[order[cnt]];
+        const int64_t j0 = ((Fr.p + kNb - 1) / kNb - 1 - t) * kNb;
+        maxrows = std::max(maxrows, Fr.f() - j0);
+        ++cnt;
       }
-    DevArray<int32_t> d_bf, d_bk;
-    d_bf.upload(ctx, bf);
-    d_bk.upload(ctx, bk);
-    for (size_t a = 0; a < bf.size(); a += 65535) {
-      const unsigned nb = (unsigned)std::min<size_t>(65535, bf.size() - a);
-      hipLaunchKernelGGL(k_diag_inverse<T>, dim3(nb), dim3(256), 0, st, fr, d_bf.ptr() + a, d_bk.ptr() + a, L);
+      hipLaunchKernelGGL(k_inv_copy<T>, dim3(cnt, 8), dim3(256), 0, st, d_act.ptr(), fr, d_poff.ptr(), t, L,
+                         panel.as<cplx<T>>());
+      const unsigned gy = (unsigned)((maxrows + 63) / 64);
+      hipLaunchKernelGGL(k_inv_block<T>, dim3(cnt, gy), dim3(256), 0, st, d_act.ptr(), fr, d_poff.ptr(), t, L,
+                         panel.as<cplx<T>>());
       HIP_CHECK(hipGetLastError());
     }
+    HIP_CHECK(hipStreamSynchronize(st));
+  }
+  {
     unsigned long long np = 0;
     HIP_CHECK(hipMemcpyAsync(&np, d.d_npiv.ptr(), sizeof(np), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
     d.static_pivots = (int64_t)np;
   }
-  // the update workspace is only needed during the factorisation
-  d.d_update.release();
 }
 
 }  // namespace

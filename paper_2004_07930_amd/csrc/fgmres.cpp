@@ -9,6 +9,7 @@
 #include <cmath>
 
 #include "krylov.h"
+#include "prof.h"
 
 namespace hz {
 
@@ -73,13 +74,22 @@ void fgmres(Ctx* ctx, Ddm& d, int s, const c128* B, c128* X, const SolveOptions&
     K.cholqr_pass(Wt.ptr(), out, part.ptr(), Gs.ptr(), Rs.ptr(), Ri.ptr(), Racc.ptr(), flag.ptr());
   };
   const c128 one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0), mone = cmk(-1.0, 0.0);
+  const double nnz = (double)op.nnz();
+  // y = alpha A x + beta yin ; algorithmic traffic: CSR once (16 B value + 4 B column per
+  // nonzero, 8 B row pointer per row), x once, y written once (+ yin read once)
+  auto spmm = [&](const c128* x, c128* y, c128 alpha, c128 beta, const c128* yin) {
+    const double vec = (double)n * s * sizeof(c128);
+    ProfScope ps(ctx, HZ_K_SPMM, 20.0 * nnz + 8.0 * (n + 1) + (yin ? 3.0 : 2.0) * vec, 8.0 * nnz * s);
+    launch_spmm<double>(st, n, s, op.mesh->d_rowptr.ptr(), op.mesh->d_col.ptr(), op.d_val.ptr(), x, y, alpha, beta,
+                        yin);
+  };
   int total = 0, restarts = 0;
   for (;;) {
     // R = B - A X
     if (total == 0)
       HIP_CHECK(hipMemcpyAsync(R.ptr(), B, ns * sizeof(c128), hipMemcpyDeviceToDevice, st));
     else
-      launch_spmm<double>(st, n, s, op.mesh->d_rowptr.ptr(), op.mesh->d_col.ptr(), op.d_val.ptr(), X, R.ptr(), mone, one, B);
+      spmm(X, R.ptr(), mone, one, B);
     cholqr2(R.ptr(), V.ptr());
     HIP_CHECK(hipMemsetAsync(G.ptr(), 0, ldr * s * sizeof(c128), st));
     HIP_CHECK(hipMemcpyAsync(G.ptr(), Racc.ptr(), s * s * sizeof(c128), hipMemcpyDeviceToDevice, st));
@@ -88,7 +98,7 @@ void fgmres(Ctx* ctx, Ddm& d, int s, const c128* B, c128* X, const SolveOptions&
       c128* Vj = V.ptr() + jj * ns;
       c128* Zj = Zb.ptr() + jj * ns;
       precond_apply(ctx, d, s, Vj, Zj);
-      launch_spmm<double>(st, n, s, op.mesh->d_rowptr.ptr(), op.mesh->d_col.ptr(), op.d_val.ptr(), Zj, W.ptr(), one, zero, nullptr);
+      spmm(Zj, W.ptr(), one, zero, nullptr);
       // CGS2
       K.gram(jj + 1, V.ptr(), ns, W.ptr(), part.ptr(), Hc.ptr(), false);
       K.block_axpy(jj + 1, V.ptr(), ns, Hc.ptr(), -1.0, W.ptr(), W.ptr());
@@ -113,7 +123,7 @@ void fgmres(Ctx* ctx, Ddm& d, int s, const c128* B, c128* X, const SolveOptions&
     const int J = (jj + 1) * s;
     K.lsq_solve(J, Rm.ptr(), ldr, G.ptr(), Y.ptr());
     K.block_axpy(jj + 1, Zb.ptr(), ns, Y.ptr(), 1.0, X, X);
-    launch_spmm<double>(st, n, s, op.mesh->d_rowptr.ptr(), op.mesh->d_col.ptr(), op.d_val.ptr(), X, R.ptr(), mone, one, B);
+    spmm(X, R.ptr(), mone, one, B);
     K.colnorms(R.ptr(), npart.ptr(), nrm.ptr());
     std::vector<double> rn(s);
     HIP_CHECK(hipMemcpyAsync(rn.data(), nrm.ptr(), s * sizeof(double), hipMemcpyDeviceToHost, st));

@@ -16,6 +16,7 @@
 
 #include "ddm.h"
 #include "krylov.h"
+#include "prof.h"
 
 namespace hz {
 
@@ -43,12 +44,12 @@ __global__ void k_from_node(int64_t n, int s, const c128* __restrict__ src, c128
 // V_J = column (J mod s) of block (J / s), blocks spaced by ldv elements.
 template <int S>
 __global__ __launch_bounds__(256) void k_gram(int64_t n, int s, int Jtot, const c128* __restrict__ V, int64_t ldv,
-                                              const c128* __restrict__ W, c128* __restrict__ part) {
+                                              const c128* __restrict__ W, c128* __restrict__ part, int64_t rpc) {
   constexpr int R = 16;  // rows staged per step
   __shared__ c128 Vt[R][kJT];
   __shared__ c128 Wt[R][S];
-  const int64_t r0 = (int64_t)blockIdx.x * kChunkRows;
-  const int64_t r1 = min<int64_t>(n, r0 + kChunkRows);
+  const int64_t r0 = (int64_t)blockIdx.x * rpc;
+  const int64_t r1 = min<int64_t>(n, r0 + rpc);
   const int J0 = blockIdx.y * kJT;
   const int jj = threadIdx.x & 63;
   const int cg = threadIdx.x >> 6;  // 4 column groups
@@ -100,34 +101,58 @@ __global__ void k_reduce_part(int nchunk, int64_t m, const c128* __restrict__ pa
 }
 
 // Y[row][c] = Yin[row][c] + beta * sum_J V_J[row] H[J][c]
+// 64 rows per block; V tiles (64 rows x 32 basis columns) staged through LDS with
+// coalesced loads, H chunk (32 x s) in LDS; thread = (row, group of s/4 columns).
 template <int S>
 __global__ __launch_bounds__(256) void k_block_axpy(int64_t n, int s, int Jtot, const c128* __restrict__ V, int64_t ldv,
                                                     const c128* __restrict__ H, double beta,
                                                     const c128* __restrict__ Yin, c128* __restrict__ Y) {
-  constexpr int RPB = 256 / S;  // rows per block
-  __shared__ c128 Ht[kJT][S];
-  const int c = threadIdx.x % S;
-  const int64_t row = (int64_t)blockIdx.x * RPB + threadIdx.x / S;
-  c128 acc = cmk(0.0, 0.0);
-  for (int J0 = 0; J0 < Jtot; J0 += kJT) {
+  constexpr int RB = 64, JC = 32, NC = (S + 3) / 4;
+  __shared__ c128 Vt[JC][RB + 1];  // [basis column][row]: conflict-free reads along rows
+  __shared__ c128 Ht[JC][S];
+  const int64_t r0 = (int64_t)blockIdx.x * RB;
+  const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
+  c128 acc[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) acc[q] = cmk(0.0, 0.0);
+  for (int J0 = 0; J0 < Jtot; J0 += JC) {
+    const int jn = min(JC, Jtot - J0);
     __syncthreads();
-    for (int t = threadIdx.x; t < kJT * S; t += 256) {
-      const int j = t / S, cc = t - (t / S) * S;
-      Ht[j][cc] = (J0 + j < Jtot && cc < s) ? H[(int64_t)(J0 + j) * s + cc] : cmk(0.0, 0.0);
+    for (int e = threadIdx.x; e < RB * JC; e += 256) {
+      const int rr = e / JC, jj = e - (e / JC) * JC;
+      const int64_t row = r0 + rr;
+      c128 v = cmk(0.0, 0.0);
+      if (jj < jn && row < n) {
+        const int J = J0 + jj;
+        const int b = J / s, jc = J - (J / s) * s;
+        v = V[(int64_t)b * ldv + row * s + jc];
+      }
+      Vt[jj][rr] = v;
+    }
+    for (int e = threadIdx.x; e < JC * S; e += 256) {
+      const int jj = e / S, c = e - (e / S) * S;
+      Ht[jj][c] = (jj < jn && c < s) ? H[(int64_t)(J0 + jj) * s + c] : cmk(0.0, 0.0);
     }
     __syncthreads();
-    if (row < n && c < s) {
-      const int jn = min(kJT, Jtot - J0);
-      for (int j = 0; j < jn; ++j) {
-        const int J = J0 + j;
-        const int b = J / s, jc = J - (J / s) * s;
-        cfma(acc, V[(int64_t)b * ldv + row * s + jc], Ht[j][c]);
+    if (cg < S) {
+      for (int jj = 0; jj < jn; ++jj) {
+        const c128 v = Vt[jj][r];
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+          if (cg + 4 * q < S) cfma(acc[q], v, Ht[jj][cg + 4 * q]);
       }
     }
   }
-  if (row < n && c < s) {
-    const int64_t k = row * s + c;
-    Y[k] = (Yin ? Yin[k] : cmk(0.0, 0.0)) + cmk(beta * acc.re, beta * acc.im);
+  const int64_t row = r0 + r;
+  if (row < n) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const int c = cg + 4 * q;
+      if (c < s) {
+        const int64_t k = row * s + c;
+        Y[k] = (Yin ? Yin[k] : cmk(0.0, 0.0)) + cmk(beta * acc[q].re, beta * acc[q].im);
+      }
+    }
   }
 }
 
@@ -144,51 +169,70 @@ __global__ void k_right_mult(int64_t n, int s, const c128* __restrict__ W, const
 }
 
 // Cholesky G = R^H R (upper R, real positive diagonal), Rinv = R^{-1}; Racc = R * Racc.
-// flag[0] = 1 on breakdown (non-positive pivot).
-__global__ void k_chol_small(int s, const c128* __restrict__ G, c128* __restrict__ R, c128* __restrict__ Rinv,
-                             c128* __restrict__ Racc, int* __restrict__ flag) {
-  if (threadIdx.x != 0) return;
-  for (int i = 0; i < s * s; ++i) R[i] = cmk(0.0, 0.0);
-  for (int k = 0; k < s; ++k) {
-    double d = G[k * s + k].re;
-    for (int l = 0; l < k; ++l) d -= R[l * s + k].re * R[l * s + k].re + R[l * s + k].im * R[l * s + k].im;
-    const double scale = fabs(G[k * s + k].re) + 1e-300;
-    if (!(d > 1e-28 * scale) || !isfinite(d)) {
-      flag[0] = 1;
-      d = fmax(d, 1e-28 * scale);
-    }
-    const double rk = sqrt(d);
-    R[k * s + k] = cmk(rk, 0.0);
-    for (int j = k + 1; j < s; ++j) {
-      c128 v = G[k * s + j];
-      for (int l = 0; l < k; ++l) {
-        // v -= conj(R[l][k]) R[l][j]
-        const c128 a = R[l * s + k], b = R[l * s + j];
-        v.re -= a.re * b.re + a.im * b.im;
-        v.im -= a.re * b.im - a.im * b.re;
-      }
-      R[k * s + j] = cmk(v.re / rk, v.im / rk);
-    }
+// flag[0] = 1 on breakdown (non-positive pivot).  One block, s <= 32.
+__global__ __launch_bounds__(256) void k_chol_small(int s, const c128* __restrict__ G, c128* __restrict__ R,
+                                                    c128* __restrict__ Rinv, c128* __restrict__ Racc,
+                                                    int* __restrict__ flag) {
+  __shared__ c128 A[32][33];
+  __shared__ c128 Rs[32][33];
+  __shared__ c128 Xs[32][33];
+  const int t = threadIdx.x;
+  for (int e = t; e < 32 * 32; e += 256) {
+    const int i = e / 32, j = e % 32;
+    A[i][j] = (i < s && j < s) ? G[i * s + j] : cmk(0.0, 0.0);
+    Rs[i][j] = cmk(0.0, 0.0);
+    Xs[i][j] = cmk(0.0, 0.0);
   }
-  for (int i = 0; i < s * s; ++i) Rinv[i] = cmk(0.0, 0.0);
-  for (int c = 0; c < s; ++c) {
-    // solve R x = e_c (upper): back substitution
+  __syncthreads();
+  for (int k = 0; k < s; ++k) {
+    if (t == 0) {
+      double d = A[k][k].re;
+      const double scale = fabs(G[k * s + k].re) + 1e-300;
+      if (!(d > 1e-28 * scale) || !isfinite(d)) {
+        flag[0] = 1;
+        d = fmax(d, 1e-28 * scale);
+      }
+      Rs[k][k] = cmk(sqrt(d), 0.0);
+    }
+    __syncthreads();
+    const double rk = Rs[k][k].re;
+    for (int j = k + 1 + t; j < s; j += 256) Rs[k][j] = cmk(A[k][j].re / rk, A[k][j].im / rk);
+    __syncthreads();
+    // A[i][j] -= conj(R[k][i]) R[k][j] for k < i <= j
+    for (int e = t; e < s * s; e += 256) {
+      const int i = e / s, j = e % s;
+      if (i > k && j >= i) cfma_conj(A[i][j], cmk(-Rs[k][i].re, -Rs[k][i].im), Rs[k][j]);
+    }
+    __syncthreads();
+  }
+  // Rinv: column c by thread c (back substitution)
+  if (t < s) {
+    const int c = t;
     for (int i = c; i >= 0; --i) {
       c128 v = cmk(i == c ? 1.0 : 0.0, 0.0);
-      for (int l = i + 1; l <= c; ++l) cfms(v, R[i * s + l], Rinv[l * s + c]);
-      Rinv[i * s + c] = cmk(v.re / R[i * s + i].re, v.im / R[i * s + i].re);
+      for (int l = i + 1; l <= c; ++l) cfms(v, Rs[i][l], Xs[l][c]);
+      Xs[i][c] = cmk(v.re / Rs[i][i].re, v.im / Rs[i][i].re);
     }
   }
+  __syncthreads();
+  for (int e = t; e < s * s; e += 256) {
+    const int i = e / s, j = e % s;
+    R[e] = Rs[i][j];
+    Rinv[e] = Xs[i][j];
+  }
   if (Racc) {
-    // Racc <- R * Racc (both upper)
-    c128 tmp[32 * 32];
-    for (int i = 0; i < s; ++i)
-      for (int j = 0; j < s; ++j) {
-        c128 v = cmk(0.0, 0.0);
-        for (int l = i; l <= j; ++l) cfma(v, R[i * s + l], Racc[l * s + j]);
-        tmp[i * s + j] = v;
-      }
-    for (int i = 0; i < s * s; ++i) Racc[i] = tmp[i];
+    // Racc <- R * Racc (both upper); read all of Racc before anyone writes
+    c128 v[4];
+    int cnt = 0;
+    for (int e = t; e < s * s; e += 256, ++cnt) {
+      const int i = e / s, j = e % s;
+      c128 acc = cmk(0.0, 0.0);
+      for (int l = i; l <= j; ++l) cfma(acc, Rs[i][l], Racc[l * s + j]);
+      v[cnt] = acc;
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int e = t; e < s * s; e += 256, ++cnt) Racc[e] = v[cnt];
   }
 }
 
@@ -199,99 +243,114 @@ __global__ void k_set_identity(int s, c128* M) {
 // ---------------------------------------------------------------- least squares (one block)
 // State: Hc (rows x s, row-major, the new block column), Rm (column-major, ld = ldr),
 // refl[step][2s][s] reflector vectors (v[0] = 1) and tau[step][s], G (ldg x s row-major).
+// Each column of the block is handled by a group of L lanes of one wavefront; dot
+// products reduce with cross-lane shuffles in a fixed order.
+__device__ __forceinline__ c128 group_sum(c128 v, int L) {
+  for (int m = L >> 1; m > 0; m >>= 1) {
+    v.re += __shfl_xor(v.re, m, 64);
+    v.im += __shfl_xor(v.im, m, 64);
+  }
+  return v;
+}
+
+// apply H^H = I - conj(tau) v v^H (v on rows [r0 + k, r0 + 2s), v[k] = 1) to column c of X
+__device__ __forceinline__ void apply_refl(c128* X, int s, int r0, int k, const c128* V, c128 tau, int c, int lane,
+                                           int L) {
+  const int s2 = 2 * s;
+  c128 w = cmk(0.0, 0.0);
+  for (int r = k + lane; r < s2; r += L) cfma_conj(w, V[r * s + k], X[(int64_t)(r0 + r) * s + c]);
+  w = group_sum(w, L);
+  const c128 ct = conj(tau) * w;
+  for (int r = k + lane; r < s2; r += L) cfms(X[(int64_t)(r0 + r) * s + c], V[r * s + k], ct);
+}
+
 __global__ __launch_bounds__(256) void k_lsq_step(int s, int jj, c128* __restrict__ Hc, c128* __restrict__ Rm,
                                                   int64_t ldr, c128* __restrict__ refl, c128* __restrict__ tau,
                                                   c128* __restrict__ G, double* __restrict__ res) {
-  const int c = threadIdx.x;
+  int sp = 1;
+  while (sp < s) sp <<= 1;
+  const int L = min(64, 256 / sp);
+  const int c = threadIdx.x / L, lane = threadIdx.x % L;
+  const bool act = c < s;
   const int s2 = 2 * s;
-  __shared__ c128 beta_tau[2];
-  // 1. previous reflectors, in order
-  for (int i = 0; i < jj; ++i) {
-    const c128* Vi = refl + (int64_t)i * s2 * s;
-    const c128* ti = tau + (int64_t)i * s;
-    for (int k = 0; k < s; ++k) {
-      if (c < s) {
-        c128 w = cmk(0.0, 0.0);
-        for (int r = k; r < s2; ++r) cfma_conj(w, Vi[r * s + k], Hc[(int64_t)(i * s + r) * s + c]);
-        const c128 ct = conj(ti[k]) * w;
-        for (int r = k; r < s2; ++r) cfms(Hc[(int64_t)(i * s + r) * s + c], Vi[r * s + k], ct);
-      }
+  const int64_t base = (int64_t)jj * s;
+  // 1. previous reflectors, in order, on the new column block
+  if (act)
+    for (int i = 0; i < jj; ++i) {
+      const c128* Vi = refl + (int64_t)i * s2 * s;
+      for (int k = 0; k < s; ++k) apply_refl(Hc, s, i * s, k, Vi, tau[(int64_t)i * s + k], c, lane, L);
     }
-  }
   __syncthreads();
   // 2. new reflectors on rows [jj s, jj s + 2s)
   c128* Vn = refl + (int64_t)jj * s2 * s;
   c128* tn = tau + (int64_t)jj * s;
-  const int64_t base = (int64_t)jj * s;
   for (int k = 0; k < s; ++k) {
-    if (c == 0) {
+    if (c == k) {
       const c128 alpha = Hc[(base + k) * s + k];
       double xn = 0;
-      for (int r = k + 1; r < s2; ++r) {
+      for (int r = k + 1 + lane; r < s2; r += L) {
         const c128 x = Hc[(base + r) * s + k];
         xn += x.re * x.re + x.im * x.im;
       }
-      c128 t = cmk(0.0, 0.0), beta = alpha;
-      for (int r = 0; r < s2; ++r) Vn[r * s + k] = cmk(0.0, 0.0);
-      Vn[k * s + k] = cmk(1.0, 0.0);
-      if (xn > 0 || alpha.im != 0) {
+      for (int m = L >> 1; m > 0; m >>= 1) xn += __shfl_xor(xn, m, 64);
+      c128 t = cmk(0.0, 0.0), beta = alpha, sc = cmk(0.0, 0.0);
+      const bool refl_needed = xn > 0 || alpha.im != 0;
+      if (refl_needed) {
         const double nrm = sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn);
         const double b = alpha.re >= 0 ? -nrm : nrm;
         t = cmk((b - alpha.re) / b, -alpha.im / b);
-        const c128 sc = cdiv(cmk(1.0, 0.0), cmk(alpha.re - b, alpha.im));
-        for (int r = k + 1; r < s2; ++r) Vn[r * s + k] = Hc[(base + r) * s + k] * sc;
+        sc = cdiv(cmk(1.0, 0.0), cmk(alpha.re - b, alpha.im));
         beta = cmk(b, 0.0);
       }
-      tn[k] = t;
-      Hc[(base + k) * s + k] = beta;
-      for (int r = k + 1; r < s2; ++r) Hc[(base + r) * s + k] = cmk(0.0, 0.0);
+      for (int r = lane; r < s2; r += L) {
+        c128 v = cmk(0.0, 0.0);
+        if (r == k) v = cmk(1.0, 0.0);
+        else if (r > k && refl_needed) v = Hc[(base + r) * s + k] * sc;
+        Vn[r * s + k] = v;
+      }
+      if (lane == 0) {
+        tn[k] = t;
+        Hc[(base + k) * s + k] = beta;
+      }
+      for (int r = k + 1 + lane; r < s2; r += L) Hc[(base + r) * s + k] = cmk(0.0, 0.0);
     }
     __syncthreads();
-    if (c > k && c < s) {
-      c128 w = cmk(0.0, 0.0);
-      for (int r = k; r < s2; ++r) cfma_conj(w, Vn[r * s + k], Hc[(base + r) * s + c]);
-      const c128 ct = conj(tn[k]) * w;
-      for (int r = k; r < s2; ++r) cfms(Hc[(base + r) * s + c], Vn[r * s + k], ct);
-    }
+    if (act && c > k) apply_refl(Hc, s, (int)base, k, Vn, tn[k], c, lane, L);
     __syncthreads();
   }
   // 3. R column block jj: rows 0 .. (jj+1)s-1
   const int64_t rows = (int64_t)(jj + 1) * s;
-  for (int64_t t = threadIdx.x; t < rows * s; t += blockDim.x) {
-    const int64_t r = t / s;
-    const int cc = (int)(t - r * s);
+  for (int64_t e = threadIdx.x; e < rows * s; e += blockDim.x) {
+    const int64_t r = e / s;
+    const int cc = (int)(e - r * s);
     Rm[(base + cc) * ldr + r] = Hc[r * s + cc];
   }
-  // 4. apply the new reflectors to G rows [jj s, jj s + 2s)
-  for (int k = 0; k < s; ++k) {
-    if (c < s) {
-      c128 w = cmk(0.0, 0.0);
-      for (int r = k; r < s2; ++r) cfma_conj(w, Vn[r * s + k], G[(base + r) * s + c]);
-      const c128 ct = conj(tn[k]) * w;
-      for (int r = k; r < s2; ++r) cfms(G[(base + r) * s + c], Vn[r * s + k], ct);
-    }
-  }
-  __syncthreads();
-  if (c < s) {
+  // 4. the new reflectors on G rows [jj s, jj s + 2s); residual estimates
+  if (act) {
+    for (int k = 0; k < s; ++k) apply_refl(G, s, (int)base, k, Vn, tn[k], c, lane, L);
     double q = 0;
-    for (int r = 0; r < s; ++r) {
+    for (int r = lane; r < s; r += L) {
       const c128 g = G[(base + s + r) * s + c];
       q += g.re * g.re + g.im * g.im;
     }
-    res[c] = sqrt(q);
+    for (int m = L >> 1; m > 0; m >>= 1) q += __shfl_xor(q, m, 64);
+    if (lane == 0) res[c] = sqrt(q);
   }
-  (void)beta_tau;
 }
 
-// Y = Rm[0:J, 0:J]^{-1} G[0:J]  (back substitution, one thread per column)
-__global__ void k_lsq_solve(int s, int J, const c128* __restrict__ Rm, int64_t ldr, const c128* __restrict__ G,
-                            c128* __restrict__ Y) {
-  const int c = threadIdx.x;
-  if (c >= s) return;
+// Y = Rm[0:J, 0:J]^{-1} G[0:J]  (column-oriented back substitution, one block)
+__global__ __launch_bounds__(256) void k_lsq_solve(int s, int J, const c128* __restrict__ Rm, int64_t ldr,
+                                                   const c128* __restrict__ G, c128* __restrict__ Y) {
+  for (int e = threadIdx.x; e < J * s; e += blockDim.x) Y[e] = G[e];
+  __syncthreads();
   for (int i = J - 1; i >= 0; --i) {
-    c128 v = G[(int64_t)i * s + c];
-    for (int l = i + 1; l < J; ++l) cfms(v, Rm[(int64_t)l * ldr + i], Y[(int64_t)l * s + c]);
-    Y[(int64_t)i * s + c] = cdiv(v, Rm[(int64_t)i * ldr + i]);
+    if (threadIdx.x < s) Y[(int64_t)i * s + threadIdx.x] = cdiv(Y[(int64_t)i * s + threadIdx.x], Rm[(int64_t)i * ldr + i]);
+    __syncthreads();
+    for (int e = threadIdx.x; e < i * s; e += blockDim.x) {
+      const int r = e / s, c = e % s;
+      cfms(Y[(int64_t)r * s + c], Rm[(int64_t)i * ldr + r], Y[(int64_t)i * s + c]);
+    }
+    __syncthreads();
   }
 }
 
@@ -340,41 +399,51 @@ void KrylovKernels::from_node(const c128* src, c128* dst) {
 }
 
 template <int S>
-static void gram_t(KrylovKernels& k, int Jtot, const c128* V, int64_t ldv, const c128* W, c128* part) {
-  hipLaunchKernelGGL(k_gram<S>, dim3((unsigned)k.nchunk, (unsigned)((Jtot + kJT - 1) / kJT)), dim3(256), 0,
-                     k.ctx->stream, k.n, k.s, Jtot, V, ldv, W, part);
+static void gram_t(KrylovKernels& k, int Jtot, const c128* V, int64_t ldv, const c128* W, c128* part, int nch,
+                   int64_t rpc) {
+  hipLaunchKernelGGL(k_gram<S>, dim3((unsigned)nch, (unsigned)((Jtot + kJT - 1) / kJT)), dim3(256), 0, k.ctx->stream,
+                     k.n, k.s, Jtot, V, ldv, W, part, rpc);
 }
 
 void KrylovKernels::gram(int nblk, const c128* V, int64_t ldv, const c128* W, c128* part, c128* H, bool accumulate,
                          c128* H2) {
   const int Jtot = nblk * s;
+  // about 2048 blocks in total: fewer, longer row chunks when there are many basis tiles
+  // (never more chunks than `nchunk`: the partial-sum workspace is sized for nchunk)
+  const int jtiles = (Jtot + kJT - 1) / kJT;
+  int nch = std::min(nchunk, std::max(16, 2048 / jtiles));
+  int64_t rpc = ((n + nch - 1) / nch + 15) / 16 * 16;
+  nch = (int)((n + rpc - 1) / rpc);
+  HZ_REQUIRE(nch >= 1 && nch <= nchunk, HZ_ERR_STATE, "gram: chunk count exceeds the partial-sum workspace");
+  // algorithmic traffic: the Jtot basis columns and W once; 8 flops per complex multiply-add
+  ProfScope ps(ctx, HZ_K_CGS_GRAM, (double)n * (Jtot + s) * sizeof(c128), 8.0 * n * Jtot * s);
   if (s <= 4)
-    gram_t<4>(*this, Jtot, V, ldv, W, part);
+    gram_t<4>(*this, Jtot, V, ldv, W, part, nch, rpc);
   else if (s <= 8)
-    gram_t<8>(*this, Jtot, V, ldv, W, part);
+    gram_t<8>(*this, Jtot, V, ldv, W, part, nch, rpc);
   else if (s <= 16)
-    gram_t<16>(*this, Jtot, V, ldv, W, part);
+    gram_t<16>(*this, Jtot, V, ldv, W, part, nch, rpc);
   else
-    gram_t<32>(*this, Jtot, V, ldv, W, part);
+    gram_t<32>(*this, Jtot, V, ldv, W, part, nch, rpc);
   const int64_t m = (int64_t)Jtot * s;
-  hipLaunchKernelGGL(k_reduce_part, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, ctx->stream, nchunk, m, part, H,
+  hipLaunchKernelGGL(k_reduce_part, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, ctx->stream, nch, m, part, H,
                      accumulate ? 1 : 0);
   if (H2)
-    hipLaunchKernelGGL(k_reduce_part, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, ctx->stream, nchunk, m, part, H2, 1);
+    hipLaunchKernelGGL(k_reduce_part, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, ctx->stream, nch, m, part, H2, 1);
   HIP_CHECK(hipGetLastError());
 }
 
 template <int S>
 static void axpy_t(KrylovKernels& k, int Jtot, const c128* V, int64_t ldv, const c128* H, double beta, const c128* Yin,
                    c128* Y) {
-  constexpr int RPB = 256 / S;
-  hipLaunchKernelGGL(k_block_axpy<S>, dim3((unsigned)((k.n + RPB - 1) / RPB)), dim3(256), 0, k.ctx->stream, k.n, k.s,
-                     Jtot, V, ldv, H, beta, Yin, Y);
+  hipLaunchKernelGGL(k_block_axpy<S>, dim3((unsigned)((k.n + 63) / 64)), dim3(256), 0, k.ctx->stream, k.n, k.s, Jtot, V,
+                     ldv, H, beta, Yin, Y);
 }
 
 void KrylovKernels::block_axpy(int nblk, const c128* V, int64_t ldv, const c128* H, double beta, const c128* Yin,
                                c128* Y) {
   const int Jtot = nblk * s;
+  ProfScope ps(ctx, HZ_K_CGS_UPDATE, (double)n * (Jtot + (Yin ? 2 : 1) * s) * sizeof(c128), 8.0 * n * Jtot * s);
   if (s == 1)
     axpy_t<1>(*this, Jtot, V, ldv, H, beta, Yin, Y);
   else if (s == 2)
@@ -393,7 +462,7 @@ void KrylovKernels::block_axpy(int nblk, const c128* V, int64_t ldv, const c128*
 void KrylovKernels::cholqr_pass(const c128* W, c128* out, c128* part, c128* G, c128* R, c128* Rinv, c128* Racc,
                                 int* flag) {
   gram(1, W, n * s, W, part, G, false);
-  hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(64), 0, ctx->stream, s, G, R, Rinv, Racc, flag);
+  hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(256), 0, ctx->stream, s, G, R, Rinv, Racc, flag);
   hipLaunchKernelGGL(k_right_mult, dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, ctx->stream, n, s, W, Rinv, out);
   HIP_CHECK(hipGetLastError());
 }
@@ -403,12 +472,12 @@ void KrylovKernels::identity(c128* M) {
 }
 
 void KrylovKernels::lsq_step(int jj, c128* Hc, c128* Rm, int64_t ldr, c128* refl, c128* tau, c128* G, double* res) {
-  hipLaunchKernelGGL(k_lsq_step, dim3(1), dim3(64), 0, ctx->stream, s, jj, Hc, Rm, ldr, refl, tau, G, res);
+  hipLaunchKernelGGL(k_lsq_step, dim3(1), dim3(256), 0, ctx->stream, s, jj, Hc, Rm, ldr, refl, tau, G, res);
   HIP_CHECK(hipGetLastError());
 }
 
 void KrylovKernels::lsq_solve(int J, const c128* Rm, int64_t ldr, const c128* G, c128* Y) {
-  hipLaunchKernelGGL(k_lsq_solve, dim3(1), dim3(64), 0, ctx->stream, s, J, Rm, ldr, G, Y);
+  hipLaunchKernelGGL(k_lsq_solve, dim3(1), dim3(256), 0, ctx->stream, s, J, Rm, ldr, G, Y);
   HIP_CHECK(hipGetLastError());
 }
 

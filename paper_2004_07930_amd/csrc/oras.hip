@@ -9,6 +9,7 @@
 #include <cstdlib>
 
 #include "ddm.h"
+#include "prof.h"
 
 namespace hz {
 
@@ -43,209 +44,237 @@ __global__ void k_scatter_owner(int64_t n, int s, const int64_t* __restrict__ ow
   z[k] = r;
 }
 
-// Forward multifrontal sweep of one level: one block per front.
-// bloc: concatenated local vectors [pos][s]; cbuf: per-front r x s contributions.
-template <typename T, int S>
-__global__ __launch_bounds__(kThreads) void k_fwd(const int32_t* __restrict__ lf, const FrontDesc* __restrict__ fr,
-                                                  const cplx<T>* __restrict__ L, const int32_t* __restrict__ emap,
-                                                  cplx<T>* __restrict__ bloc, cplx<T>* __restrict__ cbuf, int s) {
-  __shared__ cplx<T> yk[kNb][S];
-  const FrontDesc F = fr[lf[blockIdx.x]];
-  const int64_t f = F.p + F.r;
-  cplx<T>* bp = bloc + (F.vec_off + F.pos0) * s;  // pivot rows
-  cplx<T>* cb = cbuf + F.cvec_off * s;            // update rows
-  for (int64_t k = threadIdx.x; k < (int64_t)F.r * s; k += kThreads) cb[k] = cmk((T)0, (T)0);
-  __syncthreads();
-  for (int slot = 0; slot < 2; ++slot) {
-    const int c = slot == 0 ? F.child0 : F.child1;
-    if (c < 0) continue;
-    const FrontDesc C = fr[c];
-    const cplx<T>* cc = cbuf + C.cvec_off * s;
-    for (int64_t k = threadIdx.x; k < (int64_t)C.r * s; k += kThreads) {
-      const int64_t i = k / s;
-      const int col = (int)(k - i * s);
-      const int64_t t = emap[C.emap_off + i];
-      cplx<T>* dst = t < F.p ? &bp[t * s + col] : &cb[(t - F.p) * s + col];
-      *dst = *dst + cc[k];
-    }
-    __syncthreads();
-  }
-  const cplx<T>* Lf = L + F.L_off;
-  for (int kb = 0; kb < F.p; kb += kNb) {
-    const int nb = min(kNb, F.p - kb);
-    // y_k = inv(L_kk) b_k ; inverse stored transposed in the block's strict upper part
-    const cplx<T>* blk = Lf + (int64_t)kb * f + kb;
-    for (int k = threadIdx.x; k < nb * s; k += kThreads) {
-      const int i = k / s, col = k - (k / s) * s;
-      cplx<T> acc = bp[(int64_t)(kb + i) * s + col];
-      for (int l = 0; l < i; ++l) cfma(acc, blk[(int64_t)i * f + l], bp[(int64_t)(kb + l) * s + col]);
-      yk[i][col] = acc;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < nb * s; k += kThreads) {
-      const int i = k / s, col = k - (k / s) * s;
-      bp[(int64_t)(kb + i) * s + col] = yk[i][col];
-    }
-    // rows below: b_i -= L[i][kb:kb+nb] y_k
-    for (int64_t i = kb + nb + threadIdx.x; i < f; i += kThreads) {
-      cplx<T> acc[S];
-#pragma unroll
-      for (int col = 0; col < S; ++col) acc[col] = cmk((T)0, (T)0);
-      for (int l = 0; l < nb; ++l) {
-        const cplx<T> a = Lf[(int64_t)(kb + l) * f + i];
-#pragma unroll
-        for (int col = 0; col < S; ++col) cfma(acc[col], a, yk[l][col]);
-      }
-      cplx<T>* dst = i < F.p ? &bp[i * s] : &cb[(i - F.p) * s];
-#pragma unroll
-      for (int col = 0; col < S; ++col)
-        if (col < s) dst[col] = dst[col] - acc[col];
-    }
-    __syncthreads();
-  }
-}
-
-// Backward sweep of one level: x_k = inv(L_kk)^T (z_k / d_k - L[below, k]^T x_below),
-// blocks from the last to the first; rows >= p read the ancestors' solutions.
-template <typename T, int S>
-__global__ __launch_bounds__(kThreads) void k_bwd(const int32_t* __restrict__ lf, const FrontDesc* __restrict__ fr,
-                                                  const cplx<T>* __restrict__ L, const int32_t* __restrict__ urows,
-                                                  cplx<T>* __restrict__ bloc, int s) {
-  constexpr int kRows = 64;
-  __shared__ cplx<T> Lt[kRows][kNb + 1];
-  __shared__ cplx<T> Xt[kRows][S];
-  __shared__ cplx<T> W[kNb][S];
-  const FrontDesc F = fr[lf[blockIdx.x]];
-  const int64_t f = F.p + F.r;
-  cplx<T>* bv = bloc + F.vec_off * s;
-  cplx<T>* bp = bv + (int64_t)F.pos0 * s;
-  const cplx<T>* Lf = L + F.L_off;
-  const int nblk = (F.p + kNb - 1) / kNb;
-  // each thread owns (j, col) pairs of the 32 x S accumulator
-  for (int b = nblk - 1; b >= 0; --b) {
-    const int kb = b * kNb;
-    const int nb = min(kNb, F.p - kb);
-    cplx<T> acc[(kNb * S + kThreads - 1) / kThreads];
-#pragma unroll
-    for (int a = 0; a < (kNb * S + kThreads - 1) / kThreads; ++a) acc[a] = cmk((T)0, (T)0);
-    for (int64_t i0 = kb + nb; i0 < f; i0 += kRows) {
-      const int rows = (int)min<int64_t>(kRows, f - i0);
-      __syncthreads();
-      for (int t = threadIdx.x; t < kRows * kNb; t += kThreads) {
-        const int l = t / kRows, r = t - (t / kRows) * kRows;
-        Lt[r][l] = (r < rows && l < nb) ? Lf[(int64_t)(kb + l) * f + i0 + r] : cmk((T)0, (T)0);
-      }
-      for (int t = threadIdx.x; t < kRows * S; t += kThreads) {
-        const int r = t / S, col = t - (t / S) * S;
-        cplx<T> x = cmk((T)0, (T)0);
-        if (r < rows && col < s) {
-          const int64_t i = i0 + r;
-          const int64_t pos = i < F.p ? F.pos0 + i : urows[F.rows_off + (i - F.p)];
-          x = bv[pos * s + col];
-        }
-        Xt[r][col] = x;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int a = 0; a < (kNb * S + kThreads - 1) / kThreads; ++a) {
-        const int t = threadIdx.x + a * kThreads;
-        if (t < kNb * S) {
-          const int j = t / S, col = t - (t / S) * S;
-          for (int r = 0; r < rows; ++r) cfma(acc[a], Lt[r][j], Xt[r][col]);
-        }
-      }
-    }
-    __syncthreads();
-    const cplx<T>* blk = Lf + (int64_t)kb * f + kb;
-#pragma unroll
-    for (int a = 0; a < (kNb * S + kThreads - 1) / kThreads; ++a) {
-      const int t = threadIdx.x + a * kThreads;
-      if (t < kNb * S) {
-        const int j = t / S, col = t - (t / S) * S;
-        if (j < nb && col < s) {
-          const cplx<T> dj = blk[(int64_t)j * f + j];
-          W[j][col] = cdiv(bp[(int64_t)(kb + j) * s + col], dj) - acc[a];
-        } else {
-          W[j][col] = cmk((T)0, (T)0);
-        }
-      }
-    }
-    __syncthreads();
-    // x_k = inv(L_kk)^T w : x[l] = w[l] + sum_{m > l} X[m][l] w[m], X[m][l] at blk[m*f + l]
-    for (int t = threadIdx.x; t < nb * s; t += kThreads) {
-      const int l = t / s, col = t - (t / s) * s;
-      cplx<T> x = W[l][col];
-      for (int m = l + 1; m < nb; ++m) cfma(x, blk[(int64_t)m * f + l], W[m][col]);
-      bp[(int64_t)(kb + l) * s + col] = x;
-    }
-    __syncthreads();
-  }
-}
-
+// Forward, step 1 of a level: work block w = [b_p; 0] + extend-add of the children's
+// contributions, through the inverse maps (own, child 0, child 1: a fixed order).
 template <typename T>
-struct Work {
-  DevBuf bloc, cbuf;
-  DevBuf t, q;
-  int s = 0;
-};
+__global__ __launch_bounds__(256) void k_fwd_assemble(const int32_t* __restrict__ lf, const FrontDesc* __restrict__ fr,
+                                                      const int32_t* __restrict__ imap, const cplx<T>* __restrict__ bin,
+                                                      cplx<T>* __restrict__ wbuf, int s) {
+  const FrontDesc F = fr[lf[blockIdx.x]];
+  const int64_t f = F.p + F.r;
+  const int64_t tot = f * s;
+  const cplx<T>* w0 = nullptr;
+  const cplx<T>* w1 = nullptr;
+  if (F.child0 >= 0) {
+    const FrontDesc C = fr[F.child0];
+    w0 = wbuf + (C.w_off + C.p) * s;
+  }
+  if (F.child1 >= 0) {
+    const FrontDesc C = fr[F.child1];
+    w1 = wbuf + (C.w_off + C.p) * s;
+  }
+  const int32_t* m0 = imap + F.imap_off;
+  const int32_t* m1 = m0 + f;
+  for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.y * blockDim.x) {
+    const int64_t i = k / s;
+    const int c = (int)(k - i * s);
+    cplx<T> v = i < F.p ? bin[(F.vec_off + F.pos0 + i) * s + c] : cmk((T)0, (T)0);
+    if (w0) {
+      const int32_t q = m0[i];
+      if (q >= 0) v = v + w0[(int64_t)q * s + c];
+    }
+    if (w1) {
+      const int32_t q = m1[i];
+      if (q >= 0) v = v + w1[(int64_t)q * s + c];
+    }
+    wbuf[(F.w_off + i) * s + c] = v;
+  }
+}
+
+// Forward, step 2: rows [i0, i0 + 64) of  [y; c] = [F_top w_p; w_r - F_bot w_p].
+// F_top = L11^{-1} is unit lower triangular, so a tile of top rows stops at its diagonal.
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_fwd_gemm(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
+                                                  const cplx<T>* __restrict__ L, cplx<T>* __restrict__ wbuf,
+                                                  cplx<T>* __restrict__ bout, int s) {
+  constexpr int RT = 64, JC = 32, NA = (S + 3) / 4;
+  __shared__ cplx<T> Ft[JC][RT + 1];
+  __shared__ cplx<T> Wt[JC][S];
+  const int fid = work[2 * blockIdx.x];
+  const int64_t i0 = work[2 * blockIdx.x + 1];
+  const FrontDesc F = fr[fid];
+  const int64_t f = F.p + F.r;
+  const int64_t jend = i0 < F.p ? min<int64_t>(F.p, i0 + RT) : F.p;
+  const int r = threadIdx.x & 63, cg = threadIdx.x >> 6;
+  const cplx<T>* Lf = L + F.L_off;
+  const cplx<T>* wp = wbuf + F.w_off * s;
+  cplx<T> acc[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) acc[q] = cmk((T)0, (T)0);
+  for (int64_t j = 0; j < jend; j += JC) {
+    const int jn = (int)min<int64_t>(JC, jend - j);
+    __syncthreads();
+    for (int e = threadIdx.x; e < JC * RT; e += 256) {
+      const int jj = e / RT, rr = e - (e / RT) * RT;
+      Ft[jj][rr] = (jj < jn && i0 + rr < f) ? Lf[(j + jj) * f + i0 + rr] : cmk((T)0, (T)0);
+    }
+    for (int e = threadIdx.x; e < JC * S; e += 256) {
+      const int jj = e / S, c = e - (e / S) * S;
+      Wt[jj][c] = (jj < jn && c < s) ? wp[(j + jj) * s + c] : cmk((T)0, (T)0);
+    }
+    __syncthreads();
+    if (cg < S) {
+      for (int jj = 0; jj < jn; ++jj) {
+        const cplx<T> a = Ft[jj][r];
+#pragma unroll
+        for (int q = 0; q < NA; ++q)
+          if (cg + 4 * q < S) cfma(acc[q], a, Wt[jj][cg + 4 * q]);
+      }
+    }
+  }
+  const int64_t i = i0 + r;
+  if (i < f) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int c = cg + 4 * q;
+      if (c >= s) continue;
+      if (i < F.p) {
+        bout[(F.vec_off + F.pos0 + i) * s + c] = acc[q];
+      } else {
+        cplx<T>* w = &wbuf[(F.w_off + i) * s + c];
+        *w = *w - acc[q];
+      }
+    }
+  }
+}
+
+// Backward: columns [j0, j0 + 32) of  x_p = F^T u,  u = [y_p / d; -x_r]  (rows from j0 on;
+// F_top is unit lower so rows above a column contribute nothing).
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_bwd_gemm(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
+                                                  const cplx<T>* __restrict__ L, const int32_t* __restrict__ urows,
+                                                  const cplx<T>* __restrict__ dinv, const cplx<T>* __restrict__ bout,
+                                                  cplx<T>* __restrict__ bin, int s) {
+  constexpr int CT = 32, RC = 64, NB = (S + 7) / 8;
+  __shared__ cplx<T> Ft[RC][CT + 1];
+  __shared__ cplx<T> Ut[RC][S];
+  const int fid = work[2 * blockIdx.x];
+  const int64_t j0 = work[2 * blockIdx.x + 1];
+  const FrontDesc F = fr[fid];
+  const int64_t f = F.p + F.r;
+  const int nj = (int)min<int64_t>(CT, F.p - j0);
+  const int jj = threadIdx.x & 31, cgp = threadIdx.x >> 5;
+  const cplx<T>* Lf = L + F.L_off;
+  cplx<T> acc[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) acc[q] = cmk((T)0, (T)0);
+  for (int64_t i = j0; i < f; i += RC) {
+    const int rn = (int)min<int64_t>(RC, f - i);
+    __syncthreads();
+    for (int e = threadIdx.x; e < RC * CT; e += 256) {
+      const int cc = e / RC, rr = e - (e / RC) * RC;
+      Ft[rr][cc] = (rr < rn && cc < nj) ? Lf[(j0 + cc) * f + i + rr] : cmk((T)0, (T)0);
+    }
+    for (int e = threadIdx.x; e < RC * S; e += 256) {
+      const int rr = e / S, c = e - (e / S) * S;
+      cplx<T> v = cmk((T)0, (T)0);
+      if (rr < rn && c < s) {
+        const int64_t row = i + rr;
+        if (row < F.p) {
+          const int64_t pos = F.vec_off + F.pos0 + row;
+          v = bout[pos * s + c] * dinv[pos];
+        } else {
+          const int64_t pos = F.vec_off + urows[F.rows_off + (row - F.p)];
+          const cplx<T> x = bin[pos * s + c];
+          v = cmk(-x.re, -x.im);
+        }
+      }
+      Ut[rr][c] = v;
+    }
+    __syncthreads();
+    if (cgp < S) {
+      for (int rr = 0; rr < rn; ++rr) {
+        const cplx<T> a = Ft[rr][jj];
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          if (cgp + 8 * q < S) cfma(acc[q], a, Ut[rr][cgp + 8 * q]);
+      }
+    }
+  }
+  if (jj < nj) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int c = cgp + 8 * q;
+      if (c < s) bin[(F.vec_off + F.pos0 + j0 + jj) * s + c] = acc[q];
+    }
+  }
+}
 
 template <typename T, int S>
-void sweep(Ctx* ctx, Ddm& d, int s, cplx<T>* bloc, cplx<T>* cbuf) {
+void sweep(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) {
   hipStream_t st = ctx->stream;
   const cplx<T>* L = d.d_factor.as<cplx<T>>();
   for (size_t lv = 0; lv < d.levels.size(); ++lv) {
     const int nf = (int)d.levels[lv].fronts.size();
-    hipLaunchKernelGGL((k_fwd<T, S>), dim3(nf), dim3(kThreads), 0, st, d.d_level_fronts.ptr() + d.level_off[lv],
-                       d.d_fronts.ptr(), L, d.d_emap.ptr(), bloc, cbuf, s);
+    const int64_t tot = d.levels[lv].max_f * s;
+    const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 64));
+    hipLaunchKernelGGL((k_fwd_assemble<T>), dim3(nf, gy), dim3(256), 0, st, d.d_level_fronts.ptr() + d.level_off[lv],
+                       d.d_fronts.ptr(), d.d_imap.ptr(), bin, wbuf, s);
+    const int64_t nw = d.fwd_off[lv + 1] - d.fwd_off[lv];
+    const Level& Lv = d.levels[lv];
+    // algorithmic traffic: the level's stored factor once, its work rows read and written once
+    const double esz = (double)sizeof(cplx<T>);
+    ProfScope ps(ctx, HZ_K_ORAS_FWD, esz * ((double)Lv.useful + 2.0 * (double)Lv.sum_f * s),
+                 8.0 * (double)Lv.useful * s);
+    hipLaunchKernelGGL((k_fwd_gemm<T, S>), dim3((unsigned)nw), dim3(256), 0, st, d.d_fwd_work.ptr() + 2 * d.fwd_off[lv],
+                       d.d_fronts.ptr(), L, wbuf, bout, s);
   }
   for (size_t lv = d.levels.size(); lv-- > 0;) {
-    const int nf = (int)d.levels[lv].fronts.size();
-    hipLaunchKernelGGL((k_bwd<T, S>), dim3(nf), dim3(kThreads), 0, st, d.d_level_fronts.ptr() + d.level_off[lv],
-                       d.d_fronts.ptr(), L, d.d_urows.ptr(), bloc, s);
+    const int64_t nw = d.bwd_off[lv + 1] - d.bwd_off[lv];
+    const Level& Lv = d.levels[lv];
+    const double esz = (double)sizeof(cplx<T>);
+    ProfScope ps(ctx, HZ_K_ORAS_BWD, esz * ((double)Lv.useful + (double)(Lv.sum_f + Lv.sum_p) * s),
+                 8.0 * (double)Lv.useful * s);
+    hipLaunchKernelGGL((k_bwd_gemm<T, S>), dim3((unsigned)nw), dim3(256), 0, st, d.d_bwd_work.ptr() + 2 * d.bwd_off[lv],
+                       d.d_fronts.ptr(), L, d.d_urows.ptr(), d.d_dinv.as<cplx<T>>(), bout, bin, s);
   }
   HIP_CHECK(hipGetLastError());
 }
 
 template <typename T>
-void one_level(Ctx* ctx, Ddm& d, int s, const c128* v, const c128* add, c128* z, DevBuf& bloc, DevBuf& cbuf) {
+void one_level(Ctx* ctx, Ddm& d, int s, const c128* v, const c128* add, c128* z, DevBuf& bin, DevBuf& bout,
+               DevBuf& wbuf) {
   hipStream_t st = ctx->stream;
   const int64_t nl = d.n_local_total;
   const int64_t n = d.op->mesh->n;
-  if (bloc.bytes < (size_t)(nl * s) * sizeof(cplx<T>)) {
-    bloc.release();
-    bloc.alloc(ctx, (size_t)(nl * s) * sizeof(cplx<T>));
-  }
-  if (cbuf.bytes < (size_t)(std::max<int64_t>(1, d.cvec_total) * s) * sizeof(cplx<T>)) {
-    cbuf.release();
-    cbuf.alloc(ctx, (size_t)(std::max<int64_t>(1, d.cvec_total) * s) * sizeof(cplx<T>));
-  }
-  cplx<T>* bl = bloc.as<cplx<T>>();
-  cplx<T>* cb = cbuf.as<cplx<T>>();
+  auto ensure = [&](DevBuf& b, int64_t elems) {
+    const size_t need = (size_t)std::max<int64_t>(1, elems) * sizeof(cplx<T>);
+    if (b.bytes < need) {
+      b.release();
+      b.alloc(ctx, need);
+    }
+  };
+  ensure(bin, nl * s);
+  ensure(bout, nl * s);
+  ensure(wbuf, d.w_total * s);
+  cplx<T>* bi = bin.as<cplx<T>>();
+  cplx<T>* bo = bout.as<cplx<T>>();
+  cplx<T>* wb = wbuf.as<cplx<T>>();
   hipLaunchKernelGGL(k_gather_local<T>, dim3((unsigned)((nl * s + 255) / 256)), dim3(256), 0, st, nl, s,
-                     d.d_gidx.ptr(), v, bl);
+                     d.d_gidx.ptr(), v, bi);
   if (s <= 1)
-    sweep<T, 1>(ctx, d, s, bl, cb);
+    sweep<T, 1>(ctx, d, s, bi, bo, wb);
   else if (s <= 2)
-    sweep<T, 2>(ctx, d, s, bl, cb);
+    sweep<T, 2>(ctx, d, s, bi, bo, wb);
   else if (s <= 4)
-    sweep<T, 4>(ctx, d, s, bl, cb);
+    sweep<T, 4>(ctx, d, s, bi, bo, wb);
   else if (s <= 8)
-    sweep<T, 8>(ctx, d, s, bl, cb);
+    sweep<T, 8>(ctx, d, s, bi, bo, wb);
   else if (s <= 16)
-    sweep<T, 16>(ctx, d, s, bl, cb);
+    sweep<T, 16>(ctx, d, s, bi, bo, wb);
   else if (s <= 32)
-    sweep<T, 32>(ctx, d, s, bl, cb);
+    sweep<T, 32>(ctx, d, s, bi, bo, wb);
   else
     fail(HZ_ERR_ARG, "preconditioner: at most 32 columns per block");
   hipLaunchKernelGGL(k_scatter_owner<T>, dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, st, n, s,
-                     d.d_own_src.ptr(), bl, add, z);
+                     d.d_own_src.ptr(), bi, add, z);
   HIP_CHECK(hipGetLastError());
 }
 
 }  // namespace
 
 struct PrecondWork {
-  DevBuf bloc, cbuf, q, t;
+  DevBuf bin, bout, wbuf, q, t;
 };
 static std::map<const Ddm*, std::unique_ptr<PrecondWork>> g_work;
 static std::mutex g_work_mu;
@@ -280,9 +309,9 @@ void precond_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c128* z) {
     add = w.q.as<c128>();
   }
   if (d.precision == HZ_PREC_MIXED)
-    one_level<float>(ctx, d, s, rhs, add, z, w.bloc, w.cbuf);
+    one_level<float>(ctx, d, s, rhs, add, z, w.bin, w.bout, w.wbuf);
   else
-    one_level<double>(ctx, d, s, rhs, add, z, w.bloc, w.cbuf);
+    one_level<double>(ctx, d, s, rhs, add, z, w.bin, w.bout, w.wbuf);
 }
 
 }  // namespace hz

@@ -30,11 +30,26 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, int s, const int64_t* _
   if (row >= n) return;
   const bool act = c < s;
   cplx<T> acc = cmk((T)0, (T)0);
-  const int64_t e1 = rowptr[row + 1];
-  for (int64_t e = rowptr[row] + g; e < e1; e += G) {
-    const cplx<T> a = val[e];
-    const int64_t j = col[e];
-    if (act) cfma(acc, a, x[j * s + c]);
+  const int64_t e0 = rowptr[row], e1 = rowptr[row + 1];
+  for (int64_t base = e0; base < e1; base += 64) {
+    // lanes fetch 64 (column, value) pairs at once; groups read them back by shuffles
+    const int cnt = (int)min<int64_t>(64, e1 - base);
+    int32_t mj = 0;
+    cplx<T> mv = cmk((T)0, (T)0);
+    if (lane < cnt) {
+      mj = col[base + lane];
+      mv = val[base + lane];
+    }
+    // uniform trip count over the wavefront: every lane takes part in every shuffle
+    const int iters = (cnt + G - 1) / G;
+#pragma unroll 4
+    for (int t = 0; t < iters; ++t) {
+      const int k = g + t * G;
+      const int src = k < cnt ? k : 0;
+      const int64_t j = __shfl(mj, src, 64);
+      const cplx<T> a = cmk(__shfl(mv.re, src, 64), __shfl(mv.im, src, 64));
+      if (act && k < cnt) cfma(acc, a, x[j * s + c]);
+    }
   }
 #pragma unroll
   for (int m = S; m < 64; m <<= 1) {

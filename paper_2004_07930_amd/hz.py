@@ -29,8 +29,11 @@ EXPORTS = [
     "hz_solve", "hz_solve_ex", "hz_point_sources", "hz_spmm", "hz_precond", "hz_ddm_stats_get",
     "hz_serve_start", "hz_serve_submit", "hz_serve_poll", "hz_serve_wait", "hz_serve_stats_get",
     "hz_serve_stop", "hz_get_dofmap", "hz_get_csr_size", "hz_get_csr", "hz_get_subdomain_size",
-    "hz_get_subdomain", "hz_get_coarse_size", "hz_get_coarse",
+    "hz_get_subdomain", "hz_get_coarse_size", "hz_get_coarse", "hz_profile_enable", "hz_profile_get",
 ]
+
+HZ_K_SPMM, HZ_K_ORAS_FWD, HZ_K_ORAS_BWD, HZ_K_CGS_GRAM, HZ_K_CGS_UPDATE = range(5)
+KERNEL_CLASSES = {"spmm": 0, "oras_fwd": 1, "oras_bwd": 2, "cgs_gram": 3, "cgs_update": 4}
 
 
 class HzError(RuntimeError):
@@ -69,6 +72,10 @@ class Request(C.Structure):
                 ("info", C.c_void_p)]
 
 
+class KernelStat(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("seconds", C.c_double), ("bytes", C.c_double), ("flops", C.c_double)]
+
+
 class ServeStats(C.Structure):
     _fields_ = [("p50_s", C.c_double), ("p99_s", C.c_double), ("sources_per_s", C.c_double),
                 ("completed", C.c_int64), ("rejected", C.c_int64)]
@@ -85,6 +92,12 @@ def load(path: str | None = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise ImportError(f"libhz.so not found at {p}: build it with `python -m paper_2004_07930_amd.build`")
+    # torch (ROCm) ships its own libamdhip64.so.7; load it first so that libhz binds to the
+    # same HIP runtime that owns torch's streams and allocations
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(p)
     vp, i64, i32, u64 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint64
     sig = {
@@ -114,6 +127,8 @@ def load(path: str | None = None):
         "hz_get_subdomain": [vp, u64, i32, vp, vp, vp, vp, vp],
         "hz_get_coarse_size": [vp, u64, C.POINTER(i64), C.POINTER(i64)],
         "hz_get_coarse": [vp, u64, vp, vp, vp],
+        "hz_profile_enable": [vp, C.c_int],
+        "hz_profile_get": [vp, C.c_int, C.POINTER(KernelStat)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -274,6 +289,19 @@ class Context:
             out = np.empty((s, ddm.n), np.complex128) if not _is_torch(v) else v.new_empty(v.shape)
         zp, zm, keep2 = _block_arg(out, ddm.n)
         self._check(self.lib.hz_precond(self.h, ddm.handle, s, vp, vm, zp, zm))
+        return out
+
+    # ---------------------------------------------------------------- measurement
+    def profile(self, on=True):
+        """Start (clear) or stop live event timing of the kernel classes in KERNEL_CLASSES."""
+        self._check(self.lib.hz_profile_enable(self.h, 1 if on else 0))
+
+    def profile_stats(self):
+        out = {}
+        for name, k in KERNEL_CLASSES.items():
+            st = KernelStat()
+            self._check(self.lib.hz_profile_get(self.h, k, C.byref(st)))
+            out[name] = dict(launches=st.launches, seconds=st.seconds, bytes=st.bytes, flops=st.flops)
         return out
 
     # ---------------------------------------------------------------- introspection
