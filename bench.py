@@ -40,18 +40,36 @@ HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
 def build_workload(name):
     import workloads as w
 
-    if name == "cfg2":
+    if name == "layered-2.5hz":
         p = w.layered_problem(freq=2.5, r=1.4, parts=(8, 8, 1), overlap=2, n_sources=(4, 4), src_depth=0.5)
         desc = ("layered 20x20x4.65 km, 2.5 Hz, Kuhn P3 %dx%dx%d cubes, 64 subdomains, overlap 2, "
                 "P1 coarse (4x coarser), 16 point sources at 0.5 km, tol 1e-6" % p.grid)
         return p, desc
-    if name == "cfg1":
+    if name == "cube8":
         p = w.unit_cube_problem(8)
         return p, "unit cube 8^3 x 6 tets, k = 8 pi, impedance, 8 subdomains, overlap 1, tol 1e-8"
-    if name == "small":
+    if name == "layered-1hz":
         p = w.layered_problem(freq=1.0, r=1.4, parts=(4, 4, 1), overlap=2, n_sources=(4, 4), src_depth=0.5)
         return p, "layered 20x20x4.65 km, 1 Hz, %dx%dx%d cubes, 16 subdomains, overlap 2, P1 coarse" % p.grid
     raise SystemExit(f"unknown workload {name}")
+
+
+def counter_traffic(kernel_class, workload):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (profiles/traffic_<workload>.json), or None when there is no record or
+    the kernel's source file has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel_class)
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"] / 1e9  # GB per launch, same unit basis as "achieved"
 
 
 def cpu_baseline(p, n_global, iters, s):
@@ -115,12 +133,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="layered-2.5hz",
+                    choices=["layered-2.5hz", "cube8", "layered-1hz"])
     ap.add_argument("--restart", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain 1 GiB device copy (reference for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no collectives); use --gpus 1", file=sys.stderr)
@@ -134,6 +155,12 @@ def main():
         if args.verbose:
             print(*a, file=sys.stderr, flush=True)
 
+    if args.copy_calibration:  # 1 GiB read + 1 GiB written by one copy kernel
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     p, desc = build_workload(args.workload)
     stream = torch.cuda.current_stream()
     ctx = hz.Context(0, stream=stream)
@@ -203,7 +230,8 @@ def main():
     kd = kraw[dom]
     achieved = kd["bytes"] / kd["seconds"] if kd["seconds"] > 0 else 0.0
     roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": None,
+                "frac": achieved / HBM_PEAK, "traffic": counter_traffic(dom, args.workload),
+                "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x fetch scale + WRITE_SIZE x write scale)",
                 "launches": kd["launches"], "avg_launch_ms": 1e3 * kd["seconds"] / max(1, kd["launches"]),
                 "algorithmic_bytes_per_launch": kd["bytes"] / max(1, kd["launches"])}
     cpu = None
