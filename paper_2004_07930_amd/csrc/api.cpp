@@ -94,6 +94,10 @@ hz_status guard(hz_ctx* c, F&& f) {
     c->last_error = "context poisoned by an earlier HIP error";
     return HZ_ERR_HIP;
   }
+  if (c->serving) {
+    c->last_error = "the context is serving: only hz_serve_* calls until hz_serve_stop";
+    return HZ_ERR_STATE;
+  }
   try {
     HIP_CHECK(hipSetDevice(c->device));
     f();
@@ -320,7 +324,7 @@ hz_status hz_solve_ex(hz_ctx* c, hz_handle ddm, int64_t n_rhs, const void* rhs, 
       KrylovKernels K(c, n, s);
       K.to_node(B.ptr + c0 * n, Bn.ptr());
       std::vector<ColInfo> ci;
-      fgmres(c, *d, s, Bn.ptr(), Xn.ptr(), so, ci);
+      fgmres(c, d, s, Bn.ptr(), Xn.ptr(), so, ci);
       K.from_node(Xn.ptr(), Xd.ptr() + c0 * n);
       for (int k = 0; k < s; ++k) {
         info[c0 + k].iters = ci[k].iters;

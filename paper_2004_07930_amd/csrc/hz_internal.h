@@ -196,6 +196,7 @@ struct Ctx {
   std::map<uint64_t, std::shared_ptr<Ddm>> ddms;
   // reference element tables live in __constant__ memory (per device, set at init)
   struct Serve* serve = nullptr;
+  std::atomic<bool> serving{false};  // a scheduler thread owns the stream: only hz_serve_* calls
   struct Prof* prof = nullptr;  // live kernel accounting (hz_profile_*)
 };
 

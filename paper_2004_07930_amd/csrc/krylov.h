@@ -39,8 +39,47 @@ struct ColInfo {
   double rel_residual = 0;
 };
 
+// One block FGMRES(m) solve as a resumable state machine.  Driver protocol:
+//   start();  loop { Z = M^{-1} v_cur() -> z_cur();  w_cur() = A z_cur();  after_matvec();
+//                    synchronise;  if (cycle_done() && end_cycle()) finished; }
+// B and X are node-major [n][s] device blocks owned by the caller.
+struct FgmresJob {
+  Ctx* ctx;
+  std::shared_ptr<Ddm> d;
+  int s;
+  const c128* B;
+  c128* X;
+  SolveOptions o;
+  int m;
+  int64_t n, ldr = 0;
+  KrylovKernels K;
+  DevArray<c128> V, Zb, W, Wt, R, part, Hc, Hp, Rm, refl, tau, G, Y, Gs, Rs, Ri, Racc;
+  DevArray<double> res, npart, nrm;
+  DevArray<int> flag;
+  std::vector<double> bnorm, est, rel;
+  int total = 0, restarts = 0, jj = 0;
+  std::vector<ColInfo> info;
+
+  FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c128* X_, const SolveOptions& o_, int m_);
+  static int64_t bytes_needed(int64_t n, int s, int m);
+  static int restart_for(Ctx* ctx, int64_t n, int s, int want, int fixed);
+  void start();                 // norms of B (synchronises), X = 0, first cycle
+  c128* v_cur();                // block to precondition this step
+  c128* z_cur();                // where M^{-1} v goes (kept for the update of X)
+  c128* w_cur();                // where A z goes
+  void after_matvec();          // CGS2, CholQR2, least-squares step; estimates copied to host (async)
+  bool cycle_done();            // after a synchronisation: end of this cycle?
+  bool end_cycle();             // X update and explicit residual (synchronises); true when finished
+  void spmm(const c128* x, c128* y, c128 alpha, c128 beta, const c128* yin);
+
+ private:
+  void start_cycle();
+  void cholqr2(const c128* in, c128* out);
+};
+
 // Solve A X = B for a node-major block B [n][s] (device, c128).  X (device) receives the
 // solution.  Returns per-column info; status HZ_ERR_NOT_CONVERGED if max_iter is hit.
-void fgmres(Ctx* ctx, Ddm& d, int s, const c128* B, c128* X, const SolveOptions& o, std::vector<ColInfo>& info);
+void fgmres(Ctx* ctx, std::shared_ptr<Ddm> d, int s, const c128* B, c128* X, const SolveOptions& o,
+            std::vector<ColInfo>& info);
 
 }  // namespace hz

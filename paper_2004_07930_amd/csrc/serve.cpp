@@ -1,11 +1,430 @@
-// Serving entry points (placeholder until the scheduler lands).
+// Serving: continuous batching of solve requests (hz_serve_*).
+//
+// A scheduler thread owns the context's stream while serving.  Requests wait in a FIFO
+// queue and are admitted when a slot is free and their Krylov memory fits in the HBM
+// budget next to the resident operators and factors.  Every admitted request runs as one
+// or more block-FGMRES jobs (blocks of at most 32 sources).  Each scheduler tick advances
+// every active job by one Arnoldi step: the blocks M^{-1} v of all jobs on the same
+// operator are packed column-wise into shared launches of the preconditioner and of the
+// SpMM (so the factors and the matrix are read once for all of them), then each job does
+// its own CGS2 / CholQR2 / least-squares step.  Jobs finish, free their memory and
+// complete their request independently, and new requests join at the next tick.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+
 #include "serve.h"
 
-extern "C" {
-hz_status hz_serve_start(hz_ctx*, int32_t) { return HZ_ERR_STATE; }
-hz_status hz_serve_submit(hz_ctx*, const hz_request*, uint64_t*) { return HZ_ERR_STATE; }
-hz_status hz_serve_poll(hz_ctx*, uint64_t, int*) { return HZ_ERR_STATE; }
-hz_status hz_serve_wait(hz_ctx*, uint64_t, int32_t*) { return HZ_ERR_STATE; }
-hz_status hz_serve_stats_get(hz_ctx*, hz_serve_stats*) { return HZ_ERR_STATE; }
-hz_status hz_serve_stop(hz_ctx*) { return HZ_ERR_STATE; }
+namespace hz {
+
+namespace {
+
+__global__ void k_pack_cols(int64_t n, int s, int S, int off, const c128* __restrict__ src, c128* __restrict__ dst) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n * s) return;
+  const int64_t i = k / s;
+  const int c = (int)(k - i * s);
+  dst[i * S + off + c] = src[k];
 }
+__global__ void k_unpack_cols(int64_t n, int s, int S, int off, const c128* __restrict__ src, c128* __restrict__ dst) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n * s) return;
+  const int64_t i = k / s;
+  const int c = (int)(k - i * s);
+  dst[k] = src[i * S + off + c];
+}
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct Ticket {
+  uint64_t id = 0;
+  hz_request req{};
+  std::shared_ptr<Ddm> ddm;
+  double t_submit = 0, t_done = 0;
+  int state = 0;  // 0 queued, 1 running, 2 done
+  int32_t status = HZ_OK;
+  int64_t bytes = 0;  // admitted memory
+  DevArray<c128> Bu;  // device copy of the rhs in user layout (host requests only)
+  struct Part {
+    int c0 = 0, s = 0;
+    DevArray<c128> Bn, Xn;
+    std::unique_ptr<FgmresJob> job;
+    bool done = false;
+  };
+  std::vector<std::unique_ptr<Part>> parts;
+  int parts_left = 0;
+};
+
+struct Serve {
+  Ctx* ctx = nullptr;
+  int max_slots = 8;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv, done_cv;
+  bool stop = false, failed = false;
+  std::string error;
+  std::deque<std::shared_ptr<Ticket>> queue;
+  std::map<uint64_t, std::shared_ptr<Ticket>> tickets;
+  std::vector<std::shared_ptr<Ticket>> running;
+  uint64_t next_id = 1;
+  int active_parts = 0;
+  // stats
+  std::vector<double> lat;
+  int64_t completed = 0, rejected = 0, sources = 0;
+  double t_first = -1, t_last = 0;
+  DevArray<c128> packV, packZ, packW;
+};
+
+static int64_t request_bytes(int64_t n, int64_t n_rhs, int m, bool host) {
+  int64_t b = 0;
+  for (int64_t c0 = 0; c0 < n_rhs; c0 += 32) {
+    const int s = (int)std::min<int64_t>(32, n_rhs - c0);
+    b += FgmresJob::bytes_needed(n, s, m) + 2 * n * s * (int64_t)sizeof(c128);
+  }
+  if (host) b += n * n_rhs * (int64_t)sizeof(c128);
+  return b;
+}
+
+static constexpr int kServeRestart = 40;
+
+// admission + start of a request's jobs (scheduler thread, no lock held)
+static void start_ticket(Serve& S, Ticket& t) {
+  Ctx* ctx = S.ctx;
+  const int64_t n = t.ddm->op->mesh->n;
+  const c128* base = nullptr;
+  if (t.req.mem == HZ_MEM_HOST) {
+    t.Bu.upload(ctx, static_cast<const c128*>(t.req.rhs), t.req.n_rhs * n);
+    base = t.Bu.ptr();
+  } else {
+    base = static_cast<const c128*>(t.req.rhs);
+  }
+  SolveOptions o;
+  o.tol = t.req.tol;
+  o.max_iter = t.req.max_iter > 0 ? t.req.max_iter : 500;
+  o.restart = kServeRestart;
+  for (int64_t c0 = 0; c0 < t.req.n_rhs; c0 += 32) {
+    auto p = std::make_unique<Ticket::Part>();
+    p->c0 = (int)c0;
+    p->s = (int)std::min<int64_t>(32, t.req.n_rhs - c0);
+    p->Bn.alloc(ctx, n * p->s);
+    p->Xn.alloc(ctx, n * p->s);
+    KrylovKernels K(ctx, n, p->s);
+    K.to_node(base + c0 * n, p->Bn.ptr());
+    p->job = std::make_unique<FgmresJob>(ctx, t.ddm, p->s, p->Bn.ptr(), p->Xn.ptr(), o, kServeRestart);
+    p->job->start();
+    t.parts.push_back(std::move(p));
+  }
+  t.parts_left = (int)t.parts.size();
+}
+
+static void finish_ticket(Serve& S, Ticket& t) {
+  Ctx* ctx = S.ctx;
+  const int64_t n = t.ddm->op->mesh->n;
+  DevArray<c128> Xu;
+  c128* out = nullptr;
+  if (t.req.mem == HZ_MEM_HOST) {
+    Xu.alloc(ctx, t.req.n_rhs * n);
+    out = Xu.ptr();
+  } else {
+    out = static_cast<c128*>(t.req.x);
+  }
+  int32_t st = HZ_OK;
+  for (auto& p : t.parts) {
+    KrylovKernels K(ctx, n, p->s);
+    K.from_node(p->Xn.ptr(), out + (int64_t)p->c0 * n);
+    for (int k = 0; k < p->s; ++k) {
+      const ColInfo& ci = p->job->info[k];
+      if (t.req.info) {
+        hz_col_info& hi = t.req.info[p->c0 + k];
+        hi.iters = ci.iters;
+        hi.restarts = ci.restarts;
+        hi.rel_residual = ci.rel_residual;
+        hi.status = ci.status;
+      }
+      if (ci.status != HZ_OK) st = HZ_ERR_NOT_CONVERGED;
+    }
+  }
+  if (t.req.mem == HZ_MEM_HOST)
+    HIP_CHECK(hipMemcpyAsync(t.req.x, Xu.ptr(), t.req.n_rhs * n * sizeof(c128), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  t.parts.clear();
+  t.Bu = DevArray<c128>();
+  t.status = st;
+}
+
+static void tick(Serve& S) {
+  Ctx* ctx = S.ctx;
+  hipStream_t st = ctx->stream;
+  // group the active jobs by operator, pack up to 32 columns per shared launch
+  std::map<Ddm*, std::vector<FgmresJob*>> groups;
+  for (auto& t : S.running)
+    for (auto& p : t->parts)
+      if (!p->done) groups[t->ddm.get()].push_back(p->job.get());
+  for (auto& [dp, jobs] : groups) {
+    size_t a = 0;
+    while (a < jobs.size()) {
+      int cols = 0;
+      size_t b = a;
+      while (b < jobs.size() && cols + jobs[b]->s <= 32) cols += jobs[b++]->s;
+      const int64_t n = dp->op->mesh->n;
+      if (b - a == 1) {  // a single job needs no packing
+        FgmresJob* j = jobs[a];
+        precond_apply(ctx, *dp, j->s, j->v_cur(), j->z_cur());
+        j->spmm(j->z_cur(), j->w_cur(), cmk(1.0, 0.0), cmk(0.0, 0.0), nullptr);
+      } else {
+        const int64_t need = n * 32;
+        if ((int64_t)S.packV.n < need) {
+          S.packV.alloc(ctx, need);
+          S.packZ.alloc(ctx, need);
+          S.packW.alloc(ctx, need);
+        }
+        int off = 0;
+        for (size_t q = a; q < b; ++q) {
+          FgmresJob* j = jobs[q];
+          hipLaunchKernelGGL(k_pack_cols, dim3((unsigned)((n * j->s + 255) / 256)), dim3(256), 0, st, n, j->s, cols, off,
+                             j->v_cur(), S.packV.ptr());
+          off += j->s;
+        }
+        precond_apply(ctx, *dp, cols, S.packV.ptr(), S.packZ.ptr());
+        // one SpMM for all packed columns (the first job's launcher; the operator is shared)
+        launch_spmm<double>(st, n, cols, dp->op->mesh->d_rowptr.ptr(), dp->op->mesh->d_col.ptr(), dp->op->d_val.ptr(),
+                            S.packZ.ptr(), S.packW.ptr(), cmk(1.0, 0.0), cmk(0.0, 0.0), nullptr);
+        off = 0;
+        for (size_t q = a; q < b; ++q) {
+          FgmresJob* j = jobs[q];
+          hipLaunchKernelGGL(k_unpack_cols, dim3((unsigned)((n * j->s + 255) / 256)), dim3(256), 0, st, n, j->s, cols,
+                             off, S.packZ.ptr(), j->z_cur());
+          hipLaunchKernelGGL(k_unpack_cols, dim3((unsigned)((n * j->s + 255) / 256)), dim3(256), 0, st, n, j->s, cols,
+                             off, S.packW.ptr(), j->w_cur());
+          off += j->s;
+        }
+        HIP_CHECK(hipGetLastError());
+      }
+      a = b;
+    }
+    for (FgmresJob* j : jobs) j->after_matvec();
+  }
+  HIP_CHECK(hipStreamSynchronize(st));
+  for (auto& t : S.running)
+    for (auto& p : t->parts)
+      if (!p->done && p->job->cycle_done() && p->job->end_cycle()) {
+        p->done = true;
+        --t->parts_left;
+      }
+}
+
+static void scheduler(Serve* S) {
+  Ctx* ctx = S->ctx;
+  try {
+    HIP_CHECK(hipSetDevice(ctx->device));
+    for (;;) {
+      std::vector<std::shared_ptr<Ticket>> admit;
+      {
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->running.empty(); });
+        if (S->stop && S->running.empty() && S->queue.empty()) break;  // stop drains every request
+        // FIFO admission by slots and memory (no overtaking, so large requests are not starved)
+        while (!S->queue.empty()) {
+          auto& t = S->queue.front();
+          const int nparts = (int)((t->req.n_rhs + 31) / 32);
+          const bool slots_ok = S->active_parts == 0 || S->active_parts + nparts <= S->max_slots;
+          const bool mem_ok = S->running.empty() || ctx->bytes_in_use + t->bytes <= (int64_t)ctx->hbm_budget;
+          if (!slots_ok || !mem_ok) break;
+          S->active_parts += nparts;
+          t->state = 1;
+          admit.push_back(t);
+          S->queue.pop_front();
+        }
+      }
+      for (auto& t : admit) {
+        start_ticket(*S, *t);
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->running.push_back(t);
+      }
+      if (!S->running.empty()) tick(*S);
+      // complete finished requests
+      std::vector<std::shared_ptr<Ticket>> fin;
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (auto it = S->running.begin(); it != S->running.end();) {
+          if ((*it)->parts_left == 0) {
+            fin.push_back(*it);
+            it = S->running.erase(it);
+          } else {
+            ++it;
+          }
+        }
+      }
+      for (auto& t : fin) {
+        finish_ticket(*S, *t);
+        std::lock_guard<std::mutex> lk(S->mu);
+        t->t_done = now_s();
+        t->state = 2;
+        S->active_parts -= (int)((t->req.n_rhs + 31) / 32);
+        S->lat.push_back(t->t_done - t->t_submit);
+        S->completed += 1;
+        S->sources += t->req.n_rhs;
+        S->t_last = t->t_done;
+        S->done_cv.notify_all();
+      }
+    }
+  } catch (const std::exception& e) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->failed = true;
+    S->error = e.what();
+    for (auto& t : S->running) {
+      t->state = 2;
+      t->status = HZ_ERR_HIP;
+    }
+    for (auto& t : S->queue) {
+      t->state = 2;
+      t->status = HZ_ERR_STATE;
+    }
+    S->running.clear();
+    S->queue.clear();
+    S->done_cv.notify_all();
+  }
+}
+
+}  // namespace hz
+
+using namespace hz;
+
+extern "C" {
+
+hz_status hz_serve_start(hz_ctx* c, int32_t max_slots) {
+  Ctx* x = reinterpret_cast<Ctx*>(c);
+  if (!x || max_slots < 1) return HZ_ERR_ARG;
+  if (x->poisoned) return HZ_ERR_HIP;
+  if (x->serve) return HZ_ERR_STATE;
+  auto* S = new Serve();
+  S->ctx = x;
+  S->max_slots = max_slots;
+  x->serving = true;
+  x->serve = S;
+  S->th = std::thread(scheduler, S);
+  return HZ_OK;
+}
+
+hz_status hz_serve_submit(hz_ctx* c, const hz_request* req, uint64_t* ticket) {
+  Ctx* x = reinterpret_cast<Ctx*>(c);
+  if (!x || !req || !ticket) return HZ_ERR_ARG;
+  if (req->struct_size != sizeof(hz_request)) return HZ_ERR_ABI;
+  Serve* S = x->serve;
+  if (!S) return HZ_ERR_STATE;
+  if (req->n_rhs < 1 || !req->rhs || !req->x || !(req->tol >= 0) || (req->mem != HZ_MEM_HOST && req->mem != HZ_MEM_DEVICE))
+    return HZ_ERR_ARG;
+  std::shared_ptr<Ddm> d;
+  {
+    std::lock_guard<std::mutex> lk(x->mu);
+    auto it = x->ddms.find(req->ddm);
+    if (it == x->ddms.end()) return HZ_ERR_ARG;
+    d = it->second;
+  }
+  auto t = std::make_shared<Ticket>();
+  t->req = *req;
+  t->ddm = d;
+  t->t_submit = now_s();
+  t->bytes = request_bytes(d->op->mesh->n, req->n_rhs, kServeRestart, req->mem == HZ_MEM_HOST);
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->failed) return HZ_ERR_STATE;
+  // never admissible: more than the whole budget left after the resident objects
+  int64_t running_bytes = 0;
+  for (auto& r : S->running) running_bytes += r->bytes;
+  if (x->bytes_in_use - running_bytes + t->bytes > (int64_t)x->hbm_budget ||
+      (req->n_rhs + 31) / 32 > S->max_slots) {
+    S->rejected += 1;
+    return HZ_ERR_BUSY;
+  }
+  t->id = S->next_id++;
+  if (S->t_first < 0) S->t_first = t->t_submit;
+  S->tickets[t->id] = t;
+  S->queue.push_back(t);
+  *ticket = t->id;
+  S->cv.notify_all();
+  return HZ_OK;
+}
+
+hz_status hz_serve_poll(hz_ctx* c, uint64_t ticket, int* done) {
+  Ctx* x = reinterpret_cast<Ctx*>(c);
+  if (!x || !done) return HZ_ERR_ARG;
+  Serve* S = x->serve;
+  if (!S) return HZ_ERR_STATE;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->tickets.find(ticket);
+  if (it == S->tickets.end()) return HZ_ERR_ARG;
+  *done = it->second->state == 2;
+  return HZ_OK;
+}
+
+hz_status hz_serve_wait(hz_ctx* c, uint64_t ticket, int32_t* status) {
+  Ctx* x = reinterpret_cast<Ctx*>(c);
+  if (!x) return HZ_ERR_ARG;
+  Serve* S = x->serve;
+  if (!S) return HZ_ERR_STATE;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->tickets.find(ticket);
+  if (it == S->tickets.end()) return HZ_ERR_ARG;
+  auto t = it->second;
+  S->done_cv.wait(lk, [&] { return t->state == 2; });
+  if (status) *status = t->status;
+  S->tickets.erase(ticket);
+  if (S->failed) {
+    x->last_error = "serving stopped: " + S->error;
+    return HZ_ERR_HIP;
+  }
+  return HZ_OK;
+}
+
+hz_status hz_serve_stats_get(hz_ctx* c, hz_serve_stats* out) {
+  Ctx* x = reinterpret_cast<Ctx*>(c);
+  if (!x || !out) return HZ_ERR_ARG;
+  Serve* S = x->serve;
+  if (!S) return HZ_ERR_STATE;
+  std::lock_guard<std::mutex> lk(S->mu);
+  std::vector<double> l = S->lat;
+  std::sort(l.begin(), l.end());
+  auto pct = [&](double q) {
+    if (l.empty()) return 0.0;
+    const double pos = q * (double)(l.size() - 1);
+    const size_t i = (size_t)std::floor(pos);
+    const double f = pos - (double)i;
+    return i + 1 < l.size() ? l[i] * (1 - f) + l[i + 1] * f : l[i];
+  };
+  out->p50_s = pct(0.50);
+  out->p99_s = pct(0.99);
+  out->sources_per_s = (S->completed > 0 && S->t_last > S->t_first) ? S->sources / (S->t_last - S->t_first) : 0.0;
+  out->completed = S->completed;
+  out->rejected = S->rejected;
+  return HZ_OK;
+}
+
+hz_status hz_serve_stop(hz_ctx* c) {
+  Ctx* x = reinterpret_cast<Ctx*>(c);
+  if (!x) return HZ_ERR_ARG;
+  Serve* S = x->serve;
+  if (!S) return HZ_ERR_STATE;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    S->cv.notify_all();
+  }
+  if (S->th.joinable()) S->th.join();  // running requests finish first
+  const bool failed = S->failed;
+  if (failed) x->last_error = "serving stopped: " + S->error;
+  x->serve = nullptr;
+  x->serving = false;
+  delete S;
+  if (failed) x->poisoned = true;
+  return failed ? HZ_ERR_HIP : HZ_OK;
+}
+
+}  // extern "C"

@@ -291,6 +291,52 @@ class Context:
         self._check(self.lib.hz_precond(self.h, ddm.handle, s, vp, vm, zp, zm))
         return out
 
+    # ---------------------------------------------------------------- serving
+    def serve_start(self, max_slots=8):
+        """Start the scheduler thread; until serve_stop only the serving calls are valid."""
+        self._check(self.lib.hz_serve_start(self.h, int(max_slots)))
+
+    def submit(self, ddm, rhs, tol=1e-6, max_iter=500, out=None):
+        """Queue a solve request; returns a ticket (rhs / out must stay alive until wait)."""
+        rp, rm, keep = _block_arg(rhs, ddm.n)
+        s = int(np.prod(rhs.shape[:-1])) if len(rhs.shape) > 1 else 1
+        if out is None:
+            if _is_torch(rhs):
+                import torch
+
+                out = torch.empty_like(rhs)
+            else:
+                out = np.empty((s, ddm.n), np.complex128)
+        xp, xm, keep2 = _block_arg(out, ddm.n)
+        if xm != rm:
+            raise ValueError("rhs and out must both be host or both be device blocks")
+        info = (ColInfo * s)()
+        req = Request(C.sizeof(Request), ddm.handle, s, rp.value, xp.value, rm, float(tol), int(max_iter),
+                      C.cast(info, C.c_void_p).value)
+        t = C.c_uint64()
+        self._check(self.lib.hz_serve_submit(self.h, C.byref(req), C.byref(t)))
+        return {"id": t.value, "out": out, "info": info, "keep": (keep, keep2, rhs)}
+
+    def poll(self, ticket):
+        done = C.c_int()
+        self._check(self.lib.hz_serve_poll(self.h, ticket["id"], C.byref(done)))
+        return bool(done.value)
+
+    def wait(self, ticket):
+        st = C.c_int32()
+        self._check(self.lib.hz_serve_wait(self.h, ticket["id"], C.byref(st)))
+        info = [dict(iters=i.iters, restarts=i.restarts, rel_residual=i.rel_residual, status=i.status)
+                for i in ticket["info"]]
+        return ticket["out"], info, st.value
+
+    def serve_stats(self):
+        s = ServeStats()
+        self._check(self.lib.hz_serve_stats_get(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServeStats._fields_}
+
+    def serve_stop(self):
+        self._check(self.lib.hz_serve_stop(self.h))
+
     # ---------------------------------------------------------------- measurement
     def profile(self, on=True):
         """Start (clear) or stop live event timing of the kernel classes in KERNEL_CLASSES."""

@@ -1,0 +1,93 @@
+"""Serving (continuous batching): every request's result is the same alone and in the mix.
+
+Requests of different sizes and on two different operators are submitted together; the
+scheduler packs their preconditioner and SpMM products into shared launches while each
+keeps its own Arnoldi process.  Each result must match the same request solved alone
+(hz_solve) within the stated tolerance, reach its residual, and the statistics must
+account for every request."""
+import numpy as np
+import pytest
+
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    from paper_2004_07930_amd import hz
+
+    ctx = hz.Context(0, stream=torch.cuda.current_stream())
+    ops = []
+    for freq in (0.4, 0.6):
+        p = w.layered_problem(freq=freq, r=1.4, parts=(2, 2, 1), overlap=1, n_sources=(3, 3), max_cubes=(8, 8, 4))
+        mesh = ctx.mesh(p.tets, p.coords, p.face_bc)
+        op = ctx.assemble(mesh, p.velocity, p.freq)
+        d = ctx.setup_ddm(op, p.partition, p.n_sub, p.overlap, coarse=(p.coarse_tets, p.coarse_coords),
+                          precision=hz.HZ_PREC_MIXED)
+        F = ctx.point_sources(mesh, p.sources)
+        ops.append((p, d, F))
+    yield ctx, ops
+    ctx.close()
+
+
+def test_serve_results_same_alone_and_in_mix(setup):
+    import torch
+
+    ctx, ops = setup
+    rng = np.random.default_rng(4)
+    reqs = []
+    for k, ns in enumerate([1, 4, 2, 9, 3, 5]):
+        p, d, F = ops[k % 2]
+        cols = rng.choice(F.shape[0], size=ns, replace=ns > F.shape[0])
+        B = F[cols] + 0.1 * (rng.standard_normal((ns, F.shape[1])) + 1j * rng.standard_normal((ns, F.shape[1])))
+        reqs.append((d, B))
+    alone = [ctx.solve(d, B, tol=1e-6)[0] for d, B in reqs]
+    ctx.serve_start(max_slots=8)
+    try:
+        # host and device requests mixed
+        tickets = []
+        for k, (d, B) in enumerate(reqs):
+            rhs = torch.from_numpy(B).cuda() if k % 2 else B
+            tickets.append(ctx.submit(d, rhs, tol=1e-6))
+        outs = [ctx.wait(t) for t in tickets]
+        st = ctx.serve_stats()
+    finally:
+        ctx.serve_stop()
+    for (d, B), x1, (x2, info, status) in zip(reqs, alone, outs):
+        x2 = x2.cpu().numpy() if hasattr(x2, "cpu") else x2
+        assert status == 0
+        assert all(i["rel_residual"] <= 1e-6 for i in info)
+        assert _rel(x2, x1) <= 1e-5, _rel(x2, x1)
+    assert st["completed"] == len(reqs)
+    assert 0 < st["p50_s"] <= st["p99_s"]
+    assert st["sources_per_s"] > 0
+
+
+def test_serve_admission_refuses_impossible_request():
+    import torch
+    from paper_2004_07930_amd import hz
+
+    ctx = hz.Context(0, stream=torch.cuda.current_stream(), hbm_budget=1 << 20)  # 1 MiB budget
+    p = w.unit_cube_problem(3, freq=1.0, parts=(2, 1, 1), overlap=1)
+    mesh = ctx.mesh(p.tets, p.coords, p.face_bc)
+    op = ctx.assemble(mesh, p.velocity, p.freq)
+    d = ctx.setup_ddm(op, p.partition, p.n_sub, p.overlap)
+    ctx.serve_start(max_slots=2)
+    try:
+        with pytest.raises(hz.HzError) as e:
+            ctx.submit(d, np.ones((2, mesh.n), np.complex128))
+        assert e.value.code == hz.HZ_ERR_BUSY
+        st = ctx.serve_stats()
+        assert st["rejected"] == 1 and st["completed"] == 0
+        with pytest.raises(hz.HzError) as e2:  # other calls are refused while serving
+            ctx.solve(d, np.ones((1, mesh.n), np.complex128))
+        assert e2.value.code == hz.HZ_ERR_STATE
+    finally:
+        ctx.serve_stop()
+    ctx.close()
