@@ -182,6 +182,8 @@ typedef struct {
   int64_t n_fronts, n_levels, max_front;
   int64_t n_coarse;
   int64_t static_pivots;      /* pivots replaced by the static threshold */
+  int64_t update_entries;     /* peak entries of the Schur-update arena during the factorisation */
+  int64_t factor_useful;      /* stored factor nonzeros: sum over fronts of p(p+1)/2 + r p */
   int64_t device_bytes;       /* device memory held by the ddm (operator excluded) */
   double setup_seconds;
 } hz_ddm_stats;

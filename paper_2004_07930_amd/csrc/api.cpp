@@ -425,6 +425,8 @@ hz_status hz_ddm_stats_get(hz_ctx* c, hz_handle ddm, hz_ddm_stats* out) {
     out->max_front = d->max_front;
     out->n_coarse = d->coarse ? d->coarse->nc : 0;
     out->static_pivots = d->static_pivots;
+    out->update_entries = d->update_entries;
+    out->factor_useful = d->factor_useful;
     out->device_bytes = d->device_bytes();
     out->setup_seconds = d->setup_seconds;
   });

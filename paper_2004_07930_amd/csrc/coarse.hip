@@ -171,15 +171,15 @@ __global__ void k_az(int64_t n, const int64_t* __restrict__ arow, const int32_t*
   az32[e] = cmk((float)s.re, (float)s.im);
 }
 
-// E[c, :] = sum_{i in supp Z[:, c]} Z[i, c] AZ[i, :], dense row accumulated in LDS
+// Er[c, :] = sum_{i in supp Z[:, c]} Z[i, c] AZ[i, :]: one block owns row c of the zeroed
+// row-major buffer Er and adds the fine rows in a fixed order (the entries of one AZ row
+// have distinct columns, so the lanes never collide)
 __global__ __launch_bounds__(64) void k_ztaz(int64_t nc, const int64_t* __restrict__ ztptr,
                                              const int32_t* __restrict__ ztcol, const double* __restrict__ ztval,
                                              const int64_t* __restrict__ azptr, const int32_t* __restrict__ azcol,
-                                             const c128* __restrict__ az, c128* __restrict__ E) {
-  extern __shared__ c128 row[];
+                                             const c128* __restrict__ az, c128* __restrict__ Er) {
   const int64_t c = blockIdx.x;
-  for (int64_t d = threadIdx.x; d < nc; d += blockDim.x) row[d] = cmk(0.0, 0.0);
-  __syncthreads();
+  c128* row = Er + c * nc;
   for (int64_t k = ztptr[c]; k < ztptr[c + 1]; ++k) {
     const int64_t i = ztcol[k];
     const double z = ztval[k];
@@ -189,8 +189,14 @@ __global__ __launch_bounds__(64) void k_ztaz(int64_t nc, const int64_t* __restri
     }
     __syncthreads();
   }
-  // E column-major: E[c + d*nc]
-  for (int64_t d = threadIdx.x; d < nc; d += blockDim.x) E[c + d * nc] = row[d];
+}
+
+// column-major E from the row-major Er
+__global__ void k_to_colmajor(int64_t nc, const c128* __restrict__ Er, c128* __restrict__ E) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nc * nc) return;
+  const int64_t c = k / nc, d = k - c * nc;
+  E[c + d * nc] = Er[k];
 }
 
 // ---- LU with partial pivoting, right looking, one column per step
@@ -244,12 +250,11 @@ __global__ void k_lu_update(int64_t nc, int64_t k, cplx<T>* A) {
   cfms(A[i + j * nc], A[i + k * nc], A[k + j * nc]);
 }
 
-// X = E^{-1}: block j solves L U x = P e_j with the vector in LDS, rows in parallel
+// X = E^{-1}: block j solves L U x = P e_j in place in column j of X, rows in parallel
 template <typename T>
 __global__ __launch_bounds__(256) void k_lu_inverse(int64_t nc, const cplx<T>* LU, const int32_t* piv, cplx<T>* X) {
-  extern __shared__ unsigned char smem[];
-  cplx<T>* x = reinterpret_cast<cplx<T>*>(smem);
   const int64_t j = blockIdx.x;
+  cplx<T>* x = X + j * nc;
   for (int64_t i = threadIdx.x; i < nc; i += blockDim.x) x[i] = cmk((T)(i == j ? 1 : 0), (T)0);
   __syncthreads();
   if (threadIdx.x == 0)
@@ -276,7 +281,6 @@ __global__ __launch_bounds__(256) void k_lu_inverse(int64_t nc, const cplx<T>* L
     for (int64_t i = threadIdx.x; i < k; i += blockDim.x) cfms(x[i], LU[i + k * nc], xk);
     __syncthreads();
   }
-  for (int64_t i = threadIdx.x; i < nc; i += blockDim.x) X[i + j * nc] = x[i];
 }
 
 __global__ void k_c128_to_c64(int64_t n, const c128* a, c64* b) {
@@ -295,7 +299,7 @@ void lu_and_inverse(Ctx* ctx, int64_t nc, cplx<T>* E, int32_t* piv, cplx<T>* Ein
     }
   }
   HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_lu_inverse<T>, dim3((unsigned)nc), dim3(256), nc * sizeof(cplx<T>), st, nc, E, piv, Einv);
+  hipLaunchKernelGGL(k_lu_inverse<T>, dim3((unsigned)nc), dim3(256), 0, st, nc, E, piv, Einv);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -394,12 +398,19 @@ void coarse_setup(Ctx* ctx, Ddm& d) {
     HIP_CHECK(hipStreamSynchronize(st));
   }
   const int64_t nc = cs.nc;
-  HZ_REQUIRE(nc * (int64_t)sizeof(c128) <= 64 * 1024, HZ_ERR_ARG, "coarse space too large (max 4096 coarse vertices)");
+  HZ_REQUIRE(nc >= 1 && nc <= 65535, HZ_ERR_ARG, "coarse space: 1 to 65535 coarse vertices");
   DevArray<c128> E;
   E.alloc(ctx, nc * nc);
-  hipLaunchKernelGGL(k_ztaz, dim3((unsigned)nc), dim3(64), nc * sizeof(c128), st, nc, cs.d_ztptr.ptr(),
-                     cs.d_ztcol.ptr(), cs.d_ztval.ptr(), cs.d_azptr.ptr(), cs.d_azcol.ptr(), cs.d_az.ptr(), E.ptr());
-  HIP_CHECK(hipGetLastError());
+  {
+    DevArray<c128> Er;
+    Er.alloc(ctx, nc * nc);
+    Er.zero(ctx);
+    hipLaunchKernelGGL(k_ztaz, dim3((unsigned)nc), dim3(64), 0, st, nc, cs.d_ztptr.ptr(), cs.d_ztcol.ptr(),
+                       cs.d_ztval.ptr(), cs.d_azptr.ptr(), cs.d_azcol.ptr(), cs.d_az.ptr(), Er.ptr());
+    hipLaunchKernelGGL(k_to_colmajor, dim3((unsigned)((nc * nc + 255) / 256)), dim3(256), 0, st, nc, Er.ptr(), E.ptr());
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(st));
+  }
   cs.d_piv.alloc(ctx, nc);
   if (d.precision == HZ_PREC_MIXED) {
     DevArray<c64> E32;

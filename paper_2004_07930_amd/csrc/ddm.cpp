@@ -493,6 +493,62 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     lf.insert(lf.end(), L.fronts.begin(), L.fronts.end());
   }
   d->level_off.push_back((int64_t)lf.size());
+  // Update (Schur) blocks live from their front's level until their parent's level has
+  // absorbed them.  Place them in one arena with a first-fit allocator over those lifetimes:
+  // at each level the new blocks are placed while the children being absorbed at that level
+  // are still held, and only then are those children released.
+  {
+    std::map<int64_t, int64_t> holes;  // offset -> length
+    int64_t arena = 0;
+    auto take = [&](int64_t len) {
+      for (auto it = holes.begin(); it != holes.end(); ++it)
+        if (it->second >= len) {
+          const int64_t off = it->first, rest = it->second - len;
+          holes.erase(it);
+          if (rest > 0) holes[off + len] = rest;
+          return off;
+        }
+      const int64_t off = arena;
+      arena += len;
+      return off;
+    };
+    auto give = [&](int64_t off, int64_t len) {
+      auto it = holes.emplace(off, len).first;
+      if (it != holes.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+          pv->second += it->second;
+          holes.erase(it);
+          it = pv;
+        }
+      }
+      auto nx = std::next(it);
+      if (nx != holes.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        holes.erase(nx);
+      }
+      if (it->first + it->second == arena) {  // trailing hole: shrink the arena
+        arena = it->first;
+        holes.erase(it);
+      }
+    };
+    int64_t peak = 0;
+    for (const Level& L : d->levels) {
+      for (int32_t fi : L.fronts) {
+        Front& F = d->fronts[fi];
+        F.U_off = F.r > 0 ? take(F.r * F.r) : 0;
+        peak = std::max(peak, arena);
+      }
+      for (int32_t fi : L.fronts) {
+        const Front& F = d->fronts[fi];
+        for (int k = 0; k < F.nchild; ++k) {
+          const Front& C = d->fronts[F.child[k]];
+          if (C.r > 0) give(C.U_off, C.r * C.r);
+        }
+      }
+    }
+    d->update_entries = peak;
+  }
   // local vector <-> global maps
   d->gidx.resize(vec);
   d->own_src.assign(m.n, -1);
@@ -604,7 +660,11 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
                          d->d_lval.ptr() + S.csr_off, nullptr);
     }
   }
-  for (auto& S : d->subs) S.gm = GatherMap();  // the gather maps live on the device now
+  for (auto& S : d->subs) S.gm = GatherMap();
+  // the local values are assembled: their gather maps are no longer needed on either side
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  d->d_lgptr = DevArray<int64_t>();
+  d->d_lgsrc = DevArray<uint32_t>();
   // --- numeric factorisation
   factor_all(ctx, *d);
   // --- coarse space

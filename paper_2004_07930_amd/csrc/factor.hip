@@ -46,6 +46,15 @@ __global__ void k_scatter_orig(const int32_t* __restrict__ lf, int nf, const Fro
   }
 }
 
+// zero the update blocks of a level's fronts (the arena is shared over lifetimes)
+template <typename T>
+__global__ void k_zero_update(const int32_t* __restrict__ lf, const FrontDesc* __restrict__ fr, cplx<T>* __restrict__ U) {
+  const FrontDesc F = fr[lf[blockIdx.x]];
+  const int64_t tot = (int64_t)F.r * F.r;
+  for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.y * blockDim.x)
+    U[F.U_off + k] = cmk((T)0, (T)0);
+}
+
 // add child `slot`'s update block into its parent (the fronts in lf are parents)
 template <typename T>
 __global__ void k_extend_add(const int32_t* __restrict__ lf, int nf, const FrontDesc* __restrict__ fr, int slot,
@@ -356,10 +365,17 @@ __global__ void k_scale(double* x, int n, double s) {
 template <typename T>
 void factor_typed(Ctx* ctx, Ddm& d) {
   hipStream_t st = ctx->stream;
-  d.d_factor.alloc(ctx, std::max<int64_t>(1, d.factor_entries) * sizeof(cplx<T>));
-  d.d_update.alloc(ctx, std::max<int64_t>(1, d.update_entries) * sizeof(cplx<T>));
+  try {
+    d.d_factor.alloc(ctx, std::max<int64_t>(1, d.factor_entries) * sizeof(cplx<T>));
+  } catch (const Error& e) {
+    fail(e.code, std::string("factor array (") + std::to_string(d.factor_entries) + " entries): " + e.what());
+  }
+  try {
+    d.d_update.alloc(ctx, std::max<int64_t>(1, d.update_entries) * sizeof(cplx<T>));
+  } catch (const Error& e) {
+    fail(e.code, std::string("update arena (") + std::to_string(d.update_entries) + " entries): " + e.what());
+  }
   HIP_CHECK(hipMemsetAsync(d.d_factor.p, 0, d.d_factor.bytes, st));
-  HIP_CHECK(hipMemsetAsync(d.d_update.p, 0, d.d_update.bytes, st));
   cplx<T>* L = d.d_factor.as<cplx<T>>();
   cplx<T>* U = d.d_update.as<cplx<T>>();
   // static pivot threshold per subdomain
@@ -394,6 +410,10 @@ void factor_typed(Ctx* ctx, Ddm& d) {
         max_child_u = std::max(max_child_u, d.fronts[d.fronts[fi].child[k]].r * d.fronts[d.fronts[fi].child[k]].r);
     }
     const unsigned gy_o = (unsigned)std::min<int64_t>((max_orig + 255) / 256, 1024);
+    if (Lv.max_r > 0) {
+      const unsigned gy_z = (unsigned)std::min<int64_t>((Lv.max_r * Lv.max_r + 255) / 256, 4096);
+      hipLaunchKernelGGL(k_zero_update<T>, dim3(nf, gy_z), dim3(256), 0, st, lf, fr, U);
+    }
     hipLaunchKernelGGL(k_scatter_orig<T>, dim3(nf, gy_o), dim3(256), 0, st, lf, nf, fr, d.d_orig_src.ptr(),
                        d.d_orig_dst.ptr(), d.d_lval.ptr(), L);
     HIP_CHECK(hipGetLastError());

@@ -7,6 +7,7 @@
 // L (D (L^T x)) = b, level by level over all subdomains at once; the Boolean partition of
 // unity makes sum_i R_i^T D_i a gather from each dof's owner.  No step uses atomics.
 #include <cstdlib>
+#include <type_traits>
 
 #include "ddm.h"
 #include "prof.h"
@@ -200,6 +201,159 @@ __global__ __launch_bounds__(256) void k_bwd_gemm(const int32_t* __restrict__ wo
   }
 }
 
+// ---- complex64 sweeps on the matrix cores (blocks of 16 or 32 columns)
+//
+// A complex product C = A B is the real product
+//   [C_re | C_im] = A' [[B_re, B_im], [-B_im, B_re]]  (rows of the right factor interleaved),
+// where A' is the complex A read as interleaved (re, im) floats -- exactly its memory layout.
+// v_mfma_f32_16x16x4f32 (lane l: A[l%16][l/16], B[l/16][l%16], D[4(l/16)+v][l%16]) takes
+// 4 real k per step = 2 complex columns of A; per group of 16 right-hand columns two MFMAs
+// (sharing the A operand) give the real and imaginary output tiles.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void mfma_cplx(float a, c64 b, bool im, f32x4& cre, f32x4& cim) {
+  const float bre = im ? -b.im : b.re;
+  const float bim = im ? b.re : b.im;
+  cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bre, cre, 0, 0, 0);
+  cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bim, cim, 0, 0, 0);
+}
+
+// Forward rows [i0, i0 + 64) (same tile and result as k_fwd_gemm): wavefront wv owns rows
+// 16 wv .. 16 wv + 15; NG groups of 16 columns.
+template <int NG>
+__global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
+                                                  const c64* __restrict__ L, c64* __restrict__ wbuf,
+                                                  c64* __restrict__ bout, int s) {
+  constexpr int RT = 64, JC = 32, SC = 16 * NG;
+  __shared__ c64 Ft[JC][RT + 1];
+  __shared__ c64 Wt[JC][SC];
+  const int fid = work[2 * blockIdx.x];
+  const int64_t i0 = work[2 * blockIdx.x + 1];
+  const FrontDesc F = fr[fid];
+  const int64_t f = F.p + F.r;
+  const int64_t jend = i0 < F.p ? min<int64_t>(F.p, i0 + RT) : F.p;
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lr = l & 15, lq = l >> 4;
+  const bool im = lq & 1;
+  const c64* Lf = L + F.L_off;
+  const c64* wp = wbuf + F.w_off * s;
+  f32x4 cre[NG], cim[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) cre[g] = cim[g] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t j = 0; j < jend; j += JC) {
+    const int jn = (int)min<int64_t>(JC, jend - j);
+    __syncthreads();
+    for (int e = threadIdx.x; e < JC * RT; e += 256) {
+      const int jj = e / RT, rr = e - (e / RT) * RT;
+      Ft[jj][rr] = (jj < jn && i0 + rr < f) ? Lf[(j + jj) * f + i0 + rr] : cmk(0.f, 0.f);
+    }
+    for (int e = threadIdx.x; e < JC * SC; e += 256) {
+      const int jj = e / SC, c = e - (e / SC) * SC;
+      Wt[jj][c] = (jj < jn && c < s) ? wp[(j + jj) * s + c] : cmk(0.f, 0.f);
+    }
+    __syncthreads();
+    const int steps = (jn + 1) >> 1;  // a zero-filled column pads an odd count
+    for (int t = 0; t < steps; ++t) {
+      const int kc = 2 * t + (lq >> 1);
+      const c64 av = Ft[kc][16 * wv + lr];
+      const float a = im ? av.im : av.re;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) mfma_cplx(a, Wt[kc][16 * g + lr], im, cre[g], cim[g]);
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int c = 16 * g + lr;
+    if (c >= s) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = i0 + 16 * wv + 4 * lq + v;
+      if (i >= f) continue;
+      const c64 val = cmk(cre[g][v], cim[g][v]);
+      if (i < F.p) {
+        bout[(F.vec_off + F.pos0 + i) * s + c] = val;
+      } else {
+        c64* w = &wbuf[(F.w_off + i) * s + c];
+        *w = *w - val;
+      }
+    }
+  }
+}
+
+// Backward columns [j0, j0 + 32) (same tile and result as k_bwd_gemm): wavefront wv owns
+// columns 16 wv .. 16 wv + 15 of the front; rows from j0 in chunks of 32.
+template <int NG>
+__global__ __launch_bounds__(128) void k_bwd_mfma(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
+                                                  const c64* __restrict__ L, const int32_t* __restrict__ urows,
+                                                  const c64* __restrict__ dinv, const c64* __restrict__ bout,
+                                                  c64* __restrict__ bin, int s) {
+  constexpr int CT = 32, RC = 32, SC = 16 * NG;
+  __shared__ c64 Ft[RC][CT + 1];
+  __shared__ c64 Ut[RC][SC];
+  const int fid = work[2 * blockIdx.x];
+  const int64_t j0 = work[2 * blockIdx.x + 1];
+  const FrontDesc F = fr[fid];
+  const int64_t f = F.p + F.r;
+  const int nj = (int)min<int64_t>(CT, F.p - j0);
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lr = l & 15, lq = l >> 4;
+  const bool im = lq & 1;
+  const c64* Lf = L + F.L_off;
+  f32x4 cre[NG], cim[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) cre[g] = cim[g] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t i = j0; i < f; i += RC) {
+    const int rn = (int)min<int64_t>(RC, f - i);
+    __syncthreads();
+    for (int e = threadIdx.x; e < RC * CT; e += 128) {
+      const int cc = e / RC, rr = e - (e / RC) * RC;
+      Ft[rr][cc] = (rr < rn && cc < nj) ? Lf[(j0 + cc) * f + i + rr] : cmk(0.f, 0.f);
+    }
+    for (int e = threadIdx.x; e < RC * SC; e += 128) {
+      const int rr = e / SC, c = e - (e / SC) * SC;
+      c64 v = cmk(0.f, 0.f);
+      if (rr < rn && c < s) {
+        const int64_t row = i + rr;
+        if (row < F.p) {
+          const int64_t pos = F.vec_off + F.pos0 + row;
+          v = bout[pos * s + c] * dinv[pos];
+        } else {
+          const int64_t pos = F.vec_off + urows[F.rows_off + (row - F.p)];
+          const c64 x = bin[pos * s + c];
+          v = cmk(-x.re, -x.im);
+        }
+      }
+      Ut[rr][c] = v;
+    }
+    __syncthreads();
+    const int steps = (rn + 1) >> 1;
+    for (int t = 0; t < steps; ++t) {
+      const int rr = 2 * t + (lq >> 1);
+      const c64 av = Ft[rr][16 * wv + lr];
+      const float a = im ? av.im : av.re;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) mfma_cplx(a, Ut[rr][16 * g + lr], im, cre[g], cim[g]);
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int c = 16 * g + lr;
+    if (c >= s) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int jj = 16 * wv + 4 * lq + v;
+      if (jj < nj) bin[(F.vec_off + F.pos0 + j0 + jj) * s + c] = cmk(cre[g][v], cim[g][v]);
+    }
+  }
+}
+
+// Matrix-core sweeps serve complex64 blocks of at least 8 columns; narrower blocks (and
+// complex128) stay on the vector-unit kernels.
+template <typename T, int S>
+constexpr bool use_mfma() {
+  return std::is_same<T, float>::value && S >= 8;
+}
+
 template <typename T, int S>
 void sweep(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) {
   hipStream_t st = ctx->stream;
@@ -216,8 +370,12 @@ void sweep(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) 
     const double esz = (double)sizeof(cplx<T>);
     ProfScope ps(ctx, HZ_K_ORAS_FWD, esz * ((double)Lv.useful + 2.0 * (double)Lv.sum_f * s),
                  8.0 * (double)Lv.useful * s);
-    hipLaunchKernelGGL((k_fwd_gemm<T, S>), dim3((unsigned)nw), dim3(256), 0, st, d.d_fwd_work.ptr() + 2 * d.fwd_off[lv],
-                       d.d_fronts.ptr(), L, wbuf, bout, s);
+    if constexpr (use_mfma<T, S>())
+      hipLaunchKernelGGL((k_fwd_mfma<(S + 15) / 16>), dim3((unsigned)nw), dim3(256), 0, st,
+                         d.d_fwd_work.ptr() + 2 * d.fwd_off[lv], d.d_fronts.ptr(), L, wbuf, bout, s);
+    else
+      hipLaunchKernelGGL((k_fwd_gemm<T, S>), dim3((unsigned)nw), dim3(256), 0, st,
+                         d.d_fwd_work.ptr() + 2 * d.fwd_off[lv], d.d_fronts.ptr(), L, wbuf, bout, s);
   }
   for (size_t lv = d.levels.size(); lv-- > 0;) {
     const int64_t nw = d.bwd_off[lv + 1] - d.bwd_off[lv];
@@ -225,8 +383,14 @@ void sweep(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) 
     const double esz = (double)sizeof(cplx<T>);
     ProfScope ps(ctx, HZ_K_ORAS_BWD, esz * ((double)Lv.useful + (double)(Lv.sum_f + Lv.sum_p) * s),
                  8.0 * (double)Lv.useful * s);
-    hipLaunchKernelGGL((k_bwd_gemm<T, S>), dim3((unsigned)nw), dim3(256), 0, st, d.d_bwd_work.ptr() + 2 * d.bwd_off[lv],
-                       d.d_fronts.ptr(), L, d.d_urows.ptr(), d.d_dinv.as<cplx<T>>(), bout, bin, s);
+    if constexpr (use_mfma<T, S>())
+      hipLaunchKernelGGL((k_bwd_mfma<(S + 15) / 16>), dim3((unsigned)nw), dim3(128), 0, st,
+                         d.d_bwd_work.ptr() + 2 * d.bwd_off[lv], d.d_fronts.ptr(), L, d.d_urows.ptr(),
+                         d.d_dinv.as<cplx<T>>(), bout, bin, s);
+    else
+      hipLaunchKernelGGL((k_bwd_gemm<T, S>), dim3((unsigned)nw), dim3(256), 0, st,
+                         d.d_bwd_work.ptr() + 2 * d.bwd_off[lv], d.d_fronts.ptr(), L, d.d_urows.ptr(),
+                         d.d_dinv.as<cplx<T>>(), bout, bin, s);
   }
   HIP_CHECK(hipGetLastError());
 }

@@ -63,6 +63,7 @@ class DdmStats(C.Structure):
     _fields_ = [("n_dofs", C.c_int64), ("nnz", C.c_int64), ("n_sub", C.c_int64), ("local_dofs_total", C.c_int64),
                 ("factor_entries", C.c_int64), ("n_fronts", C.c_int64), ("n_levels", C.c_int64),
                 ("max_front", C.c_int64), ("n_coarse", C.c_int64), ("static_pivots", C.c_int64),
+                ("update_entries", C.c_int64), ("factor_useful", C.c_int64),
                 ("device_bytes", C.c_int64), ("setup_seconds", C.c_double)]
 
 

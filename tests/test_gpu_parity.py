@@ -141,6 +141,32 @@ def test_precond_one_level_c128(case, ddm_case, ctx):
     assert st["static_pivots"] == 0
 
 
+def test_precond_one_level_mixed(case, ddm_case, ctx):
+    """complex64 factors and sweeps (vector kernels below 8 columns, matrix-core kernels from
+    8 on, 16-column groups with a ragged last group): each column within 1e-4 of the FP64
+    oracle's ORAS application, and a column's result independent of the block it sits in
+    (to single-precision rounding)."""
+    from paper_2004_07930_amd import hz
+
+    name, p, om, gm, A, gop = case
+    d, subs = ddm_case
+    if subs[0].lu is None:
+        odd.factor_subdomains(subs)
+    P = odd.ORAS(A, subs)
+    d32 = ctx.setup_ddm(gop, p.partition, p.n_sub, p.overlap, precision=hz.HZ_PREC_MIXED)
+    rng = np.random.default_rng(13)
+    V = rng.standard_normal((32, om.n)) + 1j * rng.standard_normal((32, om.n))
+    Zo = P.apply(V.T).T
+    Z1 = ctx.precond(d32, V[:1])
+    for s in (1, 3, 8, 16, 21, 32):
+        Z = ctx.precond(d32, V[:s])
+        errs = [_rel(Z[c], Zo[c]) for c in range(s)]
+        print(f"{name} s={s}: max column error vs FP64 oracle {max(errs):.2e}")
+        assert max(errs) <= 1e-4, (s, max(errs))
+        assert _rel(Z[0], Z1[0]) <= 1e-5, (s, _rel(Z[0], Z1[0]))
+    ctx.release(d32)
+
+
 def test_fgmres_fixed_iterations_c128(case, ddm_case, ctx):
     """Same algorithm, same iteration count: the iterate is unique, FP64 parity 1e-10."""
     name, p, om, gm, A, gop = case
