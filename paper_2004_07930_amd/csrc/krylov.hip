@@ -92,12 +92,200 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, int s, int Jtot, const 
     }
 }
 
-__global__ void k_reduce_part(int nchunk, int64_t m, const c128* __restrict__ part, c128* __restrict__ out, int accumulate) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m) return;
+// ---- FP64 matrix-core variants for blocks of 16 or 32 columns
+//
+// v_mfma_f64_16x16x4f64, lane l: A[l%16][l/16], B[l/16][l%16], D[l/16 + 4v][l%16] in
+// register v.  A complex product is a real one over twice the k range; here the k index is
+// ordered so that one complex element held by a lane feeds two consecutive steps (its real
+// part, then its imaginary part), the right operand supplying the matching signs:
+//   conj(a) b :  (a_re, [b_re, b_im]) then (a_im, [ b_im, -b_re])
+//        a  b :  (a_re, [b_re, b_im]) then (a_im, [-b_im,  b_re])
+// Both kernels load the operands of the next step before issuing this step's products, so
+// that memory latency overlaps the matrix-core work of the same wavefront.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+#define HZ_MFMA64 __builtin_amdgcn_mfma_f64_16x16x4f64
+
+// Partial sums of H = V^H W over one chunk of rows, s = 16 NCT columns.  A wavefront holds
+// GJ tiles of 16 basis columns; the block's 4 wavefronts take interleaved groups of 4 rows
+// (lane l reads row 4 (wave) + l/16 of each group of 16, column l%16: 256 contiguous bytes
+// per row), RG groups per step, and are summed through LDS in a fixed order.
+template <int NCT, int GJ, int RG>
+__global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int Jtot, const c128* __restrict__ V, int64_t ldv,
+                                                   const c128* __restrict__ W, c128* __restrict__ part, int64_t rpc) {
+  constexpr int S = 16 * NCT;
+  __shared__ c128 red[GJ * 16][S];
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, lc = l & 15, q = l >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * rpc;
+  const int64_t r1 = min<int64_t>(n, r0 + rpc);
+  const int J0 = blockIdx.y * GJ * 16;
+  f64x4 hre[GJ][NCT], him[GJ][NCT];
+  const c128* vp[GJ];
+  bool jv[GJ];
+#pragma unroll
+  for (int g = 0; g < GJ; ++g) {
+    const int J = J0 + 16 * g;
+    jv[g] = J < Jtot;
+    const int b = J / S, jc = J - (J / S) * S;
+    vp[g] = jv[g] ? V + (int64_t)b * ldv + jc + lc : V;
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) hre[g][ct] = him[g][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+  }
+  auto load = [&](int64_t rb, c128 (&w)[RG][NCT], c128 (&a)[RG][GJ]) {
+#pragma unroll
+    for (int u = 0; u < RG; ++u) {
+      const int64_t r = rb + 16 * u + q;
+      const bool ok = r < r1;
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) w[u][ct] = ok ? W[r * S + 16 * ct + lc] : cmk(0.0, 0.0);
+#pragma unroll
+      for (int g = 0; g < GJ; ++g) a[u][g] = (ok && jv[g]) ? vp[g][r * S] : cmk(0.0, 0.0);
+    }
+  };
+  c128 wc[RG][NCT], ac[RG][GJ];
+  int64_t rb = r0 + 4 * wv;
+  load(rb, wc, ac);
+  for (; rb < r1; rb += 16 * RG) {
+    c128 wn[RG][NCT], an[RG][GJ];
+    load(rb + 16 * RG, wn, an);
+#pragma unroll
+    for (int u = 0; u < RG; ++u) {
+#pragma unroll
+      for (int g = 0; g < GJ; ++g)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          hre[g][ct] = HZ_MFMA64(ac[u][g].re, wc[u][ct].re, hre[g][ct], 0, 0, 0);
+          him[g][ct] = HZ_MFMA64(ac[u][g].re, wc[u][ct].im, him[g][ct], 0, 0, 0);
+        }
+#pragma unroll
+      for (int g = 0; g < GJ; ++g)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          hre[g][ct] = HZ_MFMA64(ac[u][g].im, wc[u][ct].im, hre[g][ct], 0, 0, 0);
+          him[g][ct] = HZ_MFMA64(ac[u][g].im, -wc[u][ct].re, him[g][ct], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RG; ++u) {
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) wc[u][ct] = wn[u][ct];
+#pragma unroll
+      for (int g = 0; g < GJ; ++g) ac[u][g] = an[u][g];
+    }
+  }
+  for (int w = 0; w < 4; ++w) {
+    if (wv == w) {
+#pragma unroll
+      for (int g = 0; g < GJ; ++g)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            c128& d = red[16 * g + q + 4 * v][16 * ct + lc];
+            const c128 x = cmk(hre[g][ct][v], him[g][ct][v]);
+            d = w == 0 ? x : d + x;
+          }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < GJ * 16 * S; e += 256) {
+    const int j = e / S, c = e - (e / S) * S;
+    if (J0 + j < Jtot) part[((int64_t)blockIdx.x * Jtot + J0 + j) * S + c] = red[j][c];
+  }
+}
+
+// Y = Yin + beta V H, s = 16 NCT columns.  A wavefront holds RT tiles of 16 rows; the basis
+// columns go 16 at a time, lane l taking columns 4 (l/16) .. 4 (l/16) + 3 of row l%16 of
+// each tile (64 contiguous bytes) for eight consecutive k steps.
+template <int NCT, int RT>
+__global__ __launch_bounds__(256) void k_axpy_mfma(int64_t n, int Jtot, const c128* __restrict__ V, int64_t ldv,
+                                                   const c128* __restrict__ H, double beta,
+                                                   const c128* __restrict__ Yin, c128* __restrict__ Y) {
+  constexpr int S = 16 * NCT;
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, lc = l & 15, q = l >> 4;
+  const int64_t rbase = ((int64_t)blockIdx.x * 4 + wv) * (16 * RT);
+  f64x4 cre[RT][NCT], cim[RT][NCT];
+  int64_t row[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    row[t] = rbase + 16 * t + lc;
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) cre[t][ct] = cim[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+  }
+  auto load = [&](int J, c128 (&h)[4][NCT], c128 (&a)[RT][4]) {
+    const bool jok = J < Jtot;
+    const int b = J / S, jc = J - (J / S) * S;
+    const c128* vb = V + (int64_t)b * ldv + jc + 4 * q;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct)
+        h[k][ct] = jok ? H[(int64_t)(J + 4 * q + k) * S + 16 * ct + lc] : cmk(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) a[t][k] = (jok && row[t] < n) ? vb[row[t] * S + k] : cmk(0.0, 0.0);
+  };
+  c128 hc[4][NCT], ac[RT][4];
+  load(0, hc, ac);
+  for (int J = 0; J < Jtot; J += 16) {
+    c128 hn[4][NCT], an[RT][4];
+    load(J + 16, hn, an);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          cre[t][ct] = HZ_MFMA64(ac[t][k].re, hc[k][ct].re, cre[t][ct], 0, 0, 0);
+          cim[t][ct] = HZ_MFMA64(ac[t][k].re, hc[k][ct].im, cim[t][ct], 0, 0, 0);
+        }
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          cre[t][ct] = HZ_MFMA64(ac[t][k].im, -hc[k][ct].im, cre[t][ct], 0, 0, 0);
+          cim[t][ct] = HZ_MFMA64(ac[t][k].im, hc[k][ct].re, cim[t][ct], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) hc[k][ct] = hn[k][ct];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ac[t][k] = an[t][k];
+  }
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = rbase + 16 * t + q + 4 * v;
+        if (r >= n) continue;
+        const int64_t k = r * S + 16 * ct + lc;
+        Y[k] = (Yin ? Yin[k] : cmk(0.0, 0.0)) + cmk(beta * cre[t][ct][v], beta * cim[t][ct][v]);
+      }
+}
+
+// out[e] (+)= sum over chunks of part[chunk][e]: 4 groups of 64 threads take every fourth
+// chunk, then the group sums are added in a fixed order
+__global__ __launch_bounds__(256) void k_reduce_part(int nchunk, int64_t m, const c128* __restrict__ part,
+                                                     c128* __restrict__ out, int accumulate) {
+  __shared__ c128 red[4][64];
+  const int g = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
   c128 s = cmk(0.0, 0.0);
-  for (int k = 0; k < nchunk; ++k) s = s + part[(int64_t)k * m + e];
-  out[e] = accumulate ? out[e] + s : s;
+  if (e < m)
+    for (int k = g; k < nchunk; k += 4) s = s + part[(int64_t)k * m + e];
+  red[g][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (g == 0 && e < m) {
+    const int i = threadIdx.x;
+    const c128 t = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+    out[e] = accumulate ? out[e] + t : t;
+  }
 }
 
 // Y[row][c] = Yin[row][c] + beta * sum_J V_J[row] H[J][c]
@@ -408,28 +596,37 @@ static void gram_t(KrylovKernels& k, int Jtot, const c128* V, int64_t ldv, const
 void KrylovKernels::gram(int nblk, const c128* V, int64_t ldv, const c128* W, c128* part, c128* H, bool accumulate,
                          c128* H2) {
   const int Jtot = nblk * s;
+  const bool mfma = s == 16 || s == 32;
   // about 2048 blocks in total: fewer, longer row chunks when there are many basis tiles
   // (never more chunks than `nchunk`: the partial-sum workspace is sized for nchunk)
-  const int jtiles = (Jtot + kJT - 1) / kJT;
+  const int jper = s == 16 ? 64 : s == 32 ? 32 : kJT;
+  const int jtiles = (Jtot + jper - 1) / jper;
   int nch = std::min(nchunk, std::max(16, 2048 / jtiles));
   int64_t rpc = ((n + nch - 1) / nch + 15) / 16 * 16;
   nch = (int)((n + rpc - 1) / rpc);
   HZ_REQUIRE(nch >= 1 && nch <= nchunk, HZ_ERR_STATE, "gram: chunk count exceeds the partial-sum workspace");
   // algorithmic traffic: the Jtot basis columns and W once; 8 flops per complex multiply-add
   ProfScope ps(ctx, HZ_K_CGS_GRAM, (double)n * (Jtot + s) * sizeof(c128), 8.0 * n * Jtot * s);
-  if (s <= 4)
+  if (mfma) {
+    const dim3 grid((unsigned)nch, (unsigned)jtiles);
+    if (s == 16)
+      hipLaunchKernelGGL((k_gram_mfma<1, 4, 2>), grid, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc);
+    else
+      hipLaunchKernelGGL((k_gram_mfma<2, 2, 2>), grid, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc);
+  } else if (s <= 4) {
     gram_t<4>(*this, Jtot, V, ldv, W, part, nch, rpc);
-  else if (s <= 8)
+  } else if (s <= 8) {
     gram_t<8>(*this, Jtot, V, ldv, W, part, nch, rpc);
-  else if (s <= 16)
+  } else if (s <= 16) {
     gram_t<16>(*this, Jtot, V, ldv, W, part, nch, rpc);
-  else
+  } else {
     gram_t<32>(*this, Jtot, V, ldv, W, part, nch, rpc);
+  }
   const int64_t m = (int64_t)Jtot * s;
-  hipLaunchKernelGGL(k_reduce_part, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, ctx->stream, nch, m, part, H,
+  hipLaunchKernelGGL(k_reduce_part, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, ctx->stream, nch, m, part, H,
                      accumulate ? 1 : 0);
   if (H2)
-    hipLaunchKernelGGL(k_reduce_part, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, ctx->stream, nch, m, part, H2, 1);
+    hipLaunchKernelGGL(k_reduce_part, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, ctx->stream, nch, m, part, H2, 1);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -444,7 +641,13 @@ void KrylovKernels::block_axpy(int nblk, const c128* V, int64_t ldv, const c128*
                                c128* Y) {
   const int Jtot = nblk * s;
   ProfScope ps(ctx, HZ_K_CGS_UPDATE, (double)n * (Jtot + (Yin ? 2 : 1) * s) * sizeof(c128), 8.0 * n * Jtot * s);
-  if (s == 1)
+  if (s == 16)  // 4 wavefronts x 2 tiles of 16 rows per block
+    hipLaunchKernelGGL((k_axpy_mfma<1, 2>), dim3((unsigned)((n + 127) / 128)), dim3(256), 0, ctx->stream, n, Jtot, V,
+                       ldv, H, beta, Yin, Y);
+  else if (s == 32)  // 4 wavefronts x 1 tile of 16 rows per block
+    hipLaunchKernelGGL((k_axpy_mfma<2, 1>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, ctx->stream, n, Jtot, V,
+                       ldv, H, beta, Yin, Y);
+  else if (s == 1)
     axpy_t<1>(*this, Jtot, V, ldv, H, beta, Yin, Y);
   else if (s == 2)
     axpy_t<2>(*this, Jtot, V, ldv, H, beta, Yin, Y);

@@ -211,6 +211,9 @@ __global__ __launch_bounds__(256) void k_bwd_gemm(const int32_t* __restrict__ wo
 // (sharing the A operand) give the real and imaginary output tiles.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// c ? a : b per component (a select on the struct itself is lowered through scratch memory)
+__device__ __forceinline__ c64 csel(bool c, c64 a, c64 b) { return cmk(c ? a.re : b.re, c ? a.im : b.im); }
+
 __device__ __forceinline__ void mfma_cplx(float a, c64 b, bool im, f32x4& cre, f32x4& cim) {
   const float bre = im ? -b.im : b.re;
   const float bim = im ? b.re : b.im;
@@ -219,12 +222,15 @@ __device__ __forceinline__ void mfma_cplx(float a, c64 b, bool im, f32x4& cre, f
 }
 
 // Forward rows [i0, i0 + 64) (same tile and result as k_fwd_gemm): wavefront wv owns rows
-// 16 wv .. 16 wv + 15; NG groups of 16 columns.
+// 16 wv .. 16 wv + 15; NG groups of 16 columns.  Each thread stages a fixed share of the next
+// chunk in registers (loads from a clamped, always valid index, so they issue back to back)
+// while the current chunk is multiplied out of LDS.
 template <int NG>
 __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
                                                   const c64* __restrict__ L, c64* __restrict__ wbuf,
                                                   c64* __restrict__ bout, int s) {
   constexpr int RT = 64, JC = 32, SC = 16 * NG;
+  constexpr int NF = JC * RT / 256, NW = JC * SC / 256;
   __shared__ c64 Ft[JC][RT + 1];
   __shared__ c64 Wt[JC][SC];
   const int fid = work[2 * blockIdx.x];
@@ -232,27 +238,52 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
   const FrontDesc F = fr[fid];
   const int64_t f = F.p + F.r;
   const int64_t jend = i0 < F.p ? min<int64_t>(F.p, i0 + RT) : F.p;
-  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6, l = tid & 63;
   const int lr = l & 15, lq = l >> 4;
   const bool im = lq & 1;
   const c64* Lf = L + F.L_off;
   const c64* wp = wbuf + F.w_off * s;
+  const c64 zero = cmk(0.f, 0.f);
+  // raw register copies of the next chunk; the bounds predicate is applied when they are
+  // written to LDS, so the loads stay in flight while the current chunk is multiplied
+  c64 rf[NF], rw[NW];
+  auto fetch = [&](int64_t j) {
+    const int jn = (int)min<int64_t>(JC, jend - j);
+#pragma unroll
+    for (int u = 0; u < NF; ++u) {
+      const int jj = (tid >> 6) + 4 * u, rr = tid & 63;  // element tid + 256 u of [JC][RT]
+      rf[u] = Lf[(jj < jn && i0 + rr < f) ? (j + jj) * f + i0 + rr : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+      const int e = tid + 256 * u, jj = e / SC, c = e - (e / SC) * SC;
+      rw[u] = wp[(jj < jn && c < s) ? (j + jj) * s + c : 0];
+    }
+  };
   f32x4 cre[NG], cim[NG];
 #pragma unroll
   for (int g = 0; g < NG; ++g) cre[g] = cim[g] = f32x4{0.f, 0.f, 0.f, 0.f};
+  fetch(0);
   for (int64_t j = 0; j < jend; j += JC) {
     const int jn = (int)min<int64_t>(JC, jend - j);
     __syncthreads();
-    for (int e = threadIdx.x; e < JC * RT; e += 256) {
-      const int jj = e / RT, rr = e - (e / RT) * RT;
-      Ft[jj][rr] = (jj < jn && i0 + rr < f) ? Lf[(j + jj) * f + i0 + rr] : cmk(0.f, 0.f);
+#pragma unroll
+    for (int u = 0; u < NF; ++u) {
+      const int jj = (tid >> 6) + 4 * u, rr = tid & 63;
+      Ft[jj][rr] = csel(jj < jn && i0 + rr < f, rf[u], zero);
     }
-    for (int e = threadIdx.x; e < JC * SC; e += 256) {
-      const int jj = e / SC, c = e - (e / SC) * SC;
-      Wt[jj][c] = (jj < jn && c < s) ? wp[(j + jj) * s + c] : cmk(0.f, 0.f);
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+      const int e = tid + 256 * u, jj = e / SC, c = e - (e / SC) * SC;
+      Wt[jj][c] = csel(jj < jn && c < s, rw[u], zero);
     }
     __syncthreads();
-    const int steps = (jn + 1) >> 1;  // a zero-filled column pads an odd count
+    if (j + JC < jend) fetch(j + JC);
+    // two complex columns per step; columns past jn are zero in LDS, so the step count may
+    // be rounded up to a multiple of 4
+    const int steps = (((jn + 1) >> 1) + 3) & ~3;
+#pragma unroll 4
     for (int t = 0; t < steps; ++t) {
       const int kc = 2 * t + (lq >> 1);
       const c64 av = Ft[kc][16 * wv + lr];
@@ -281,13 +312,15 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
 }
 
 // Backward columns [j0, j0 + 32) (same tile and result as k_bwd_gemm): wavefront wv owns
-// columns 16 wv .. 16 wv + 15 of the front; rows from j0 in chunks of 32.
+// columns 16 wv .. 16 wv + 15 of the front; rows from j0 in chunks of 32, staged as in the
+// forward kernel.  u rows below the pivot block are gathered through the update-row map.
 template <int NG>
 __global__ __launch_bounds__(128) void k_bwd_mfma(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
                                                   const c64* __restrict__ L, const int32_t* __restrict__ urows,
                                                   const c64* __restrict__ dinv, const c64* __restrict__ bout,
                                                   c64* __restrict__ bin, int s) {
   constexpr int CT = 32, RC = 32, SC = 16 * NG;
+  constexpr int NF = RC * CT / 128, NU = RC * SC / 128;
   __shared__ c64 Ft[RC][CT + 1];
   __shared__ c64 Ut[RC][SC];
   const int fid = work[2 * blockIdx.x];
@@ -295,38 +328,80 @@ __global__ __launch_bounds__(128) void k_bwd_mfma(const int32_t* __restrict__ wo
   const FrontDesc F = fr[fid];
   const int64_t f = F.p + F.r;
   const int nj = (int)min<int64_t>(CT, F.p - j0);
-  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6, l = tid & 63;
   const int lr = l & 15, lq = l >> 4;
   const bool im = lq & 1;
   const c64* Lf = L + F.L_off;
+  const int64_t pbase = F.vec_off + F.pos0;  // first pivot position: a valid clamp target
+  const c64 zero = cmk(0.f, 0.f);
+  // raw register copies of the next chunk (factor tile, gathered u sources and 1/d), turned
+  // into LDS values only when stored, so the loads overlap the current chunk's products.
+  // The update-row indices are loaded first: the factor loads stay in flight while the
+  // dependent gathers wait for them.
+  c64 rf[NF], rx[NU], rd[NU];
+  auto fetch = [&](int64_t i) {
+    const int rn = (int)min<int64_t>(RC, f - i);
+    // update-row indices from a clamped (valid) index; a front without update rows reads
+    // none (the map may be empty), a block-uniform test
+    int32_t ui[NU];
+    if (F.r > 0) {
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int rr = (tid + 128 * u) / SC;
+        const int64_t row = i + rr;
+        ui[u] = urows[F.rows_off + ((rr < rn && row >= F.p) ? row - F.p : 0)];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < NU; ++u) ui[u] = 0;
+    }
+    int64_t pos[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int rr = (tid + 128 * u) / SC;
+      const int64_t row = i + rr;
+      pos[u] = (rr < rn && row >= F.p) ? F.vec_off + ui[u] : pbase + min<int64_t>(row, F.p - 1);
+    }
+#pragma unroll
+    for (int u = 0; u < NF; ++u) {
+      const int cc = (tid >> 5) + 4 * u, rr = tid & 31;  // element tid + 128 u of [CT][RC]
+      rf[u] = Lf[(rr < rn && cc < nj) ? (j0 + cc) * f + i + rr : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int e = tid + 128 * u, rr = e / SC, c = e - (e / SC) * SC;
+      const int64_t row = i + rr;
+      const bool ok = rr < rn && c < s;
+      const bool piv = row < F.p;
+      rx[u] = (piv ? bout : bin)[(ok ? pos[u] : pbase) * s + (ok ? c : 0)];
+      rd[u] = dinv[(ok && piv) ? pos[u] : pbase];
+    }
+  };
   f32x4 cre[NG], cim[NG];
 #pragma unroll
   for (int g = 0; g < NG; ++g) cre[g] = cim[g] = f32x4{0.f, 0.f, 0.f, 0.f};
+  fetch(j0);
   for (int64_t i = j0; i < f; i += RC) {
     const int rn = (int)min<int64_t>(RC, f - i);
     __syncthreads();
-    for (int e = threadIdx.x; e < RC * CT; e += 128) {
-      const int cc = e / RC, rr = e - (e / RC) * RC;
-      Ft[rr][cc] = (rr < rn && cc < nj) ? Lf[(j0 + cc) * f + i + rr] : cmk(0.f, 0.f);
+#pragma unroll
+    for (int u = 0; u < NF; ++u) {
+      const int cc = (tid >> 5) + 4 * u, rr = tid & 31;
+      Ft[rr][cc] = csel(rr < rn && cc < nj, rf[u], zero);
     }
-    for (int e = threadIdx.x; e < RC * SC; e += 128) {
-      const int rr = e / SC, c = e - (e / SC) * SC;
-      c64 v = cmk(0.f, 0.f);
-      if (rr < rn && c < s) {
-        const int64_t row = i + rr;
-        if (row < F.p) {
-          const int64_t pos = F.vec_off + F.pos0 + row;
-          v = bout[pos * s + c] * dinv[pos];
-        } else {
-          const int64_t pos = F.vec_off + urows[F.rows_off + (row - F.p)];
-          const c64 x = bin[pos * s + c];
-          v = cmk(-x.re, -x.im);
-        }
-      }
-      Ut[rr][c] = v;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int e = tid + 128 * u, rr = e / SC, c = e - (e / SC) * SC;
+      const bool ok = rr < rn && c < s;
+      const bool piv = i + rr < F.p;
+      const c64 x = rx[u];
+      Ut[rr][c] = csel(ok, csel(piv, x * rd[u], cmk(-x.re, -x.im)), zero);
     }
     __syncthreads();
-    const int steps = (rn + 1) >> 1;
+    if (i + RC < f) fetch(i + RC);
+    const int steps = (((rn + 1) >> 1) + 3) & ~3;
+#pragma unroll 4
     for (int t = 0; t < steps; ++t) {
       const int rr = 2 * t + (lq >> 1);
       const c64 av = Ft[rr][16 * wv + lr];

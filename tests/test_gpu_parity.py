@@ -175,13 +175,15 @@ def test_fgmres_fixed_iterations_c128(case, ddm_case, ctx):
         odd.factor_subdomains(subs)
     P = odd.ORAS(A, subs)
     rng = np.random.default_rng(12)
-    B = rng.standard_normal((3, om.n)) + 1j * rng.standard_normal((3, om.n))
-    for k in (1, 4):
-        X, info = ctx.solve(d, B, fixed_iters=k, restart=k)
-        Xo, io = krylov.block_fgmres(lambda x: A @ x, B.T, P.apply, fixed_iters=k, m=k)
-        assert info[0]["iters"] == k
-        assert _rel(X, Xo.T) <= 1e-10, (k, _rel(X, Xo.T))
-        np.testing.assert_allclose([i["rel_residual"] for i in info], io["rel_residual"], rtol=1e-8)
+    # 3 columns: vector-unit Gram-Schmidt kernels; 16 and 32: FP64 matrix-core kernels
+    for s, ks in ((3, (1, 4)), (16, (3,)), (32, (2,))):
+        B = rng.standard_normal((s, om.n)) + 1j * rng.standard_normal((s, om.n))
+        for k in ks:
+            X, info = ctx.solve(d, B, fixed_iters=k, restart=k)
+            Xo, io = krylov.block_fgmres(lambda x: A @ x, B.T, P.apply, fixed_iters=k, m=k)
+            assert info[0]["iters"] == k
+            assert _rel(X, Xo.T) <= 1e-10, (s, k, _rel(X, Xo.T))
+            np.testing.assert_allclose([i["rel_residual"] for i in info], io["rel_residual"], rtol=1e-8)
 
 
 def test_solve_to_tolerance_matches_direct(ctx):
