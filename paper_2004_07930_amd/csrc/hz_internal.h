@@ -59,6 +59,12 @@ __host__ __device__ __forceinline__ cplx<T> operator*(cplx<T> a, cplx<T> b) {
 }
 template <typename T>
 __host__ __device__ __forceinline__ cplx<T> conj(cplx<T> a) { return cmk(a.re, -a.im); }
+// c ? a : b per component (in device code a select on the struct itself can be lowered
+// through scratch memory, which serialises the loads feeding it)
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> csel(bool c, cplx<T> a, cplx<T> b) {
+  return cmk(c ? a.re : b.re, c ? a.im : b.im);
+}
 // a += b * c
 template <typename T>
 __host__ __device__ __forceinline__ void cfma(cplx<T>& a, cplx<T> b, cplx<T> c) {

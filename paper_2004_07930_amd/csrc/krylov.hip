@@ -666,7 +666,11 @@ void KrylovKernels::cholqr_pass(const c128* W, c128* out, c128* part, c128* G, c
                                 int* flag) {
   gram(1, W, n * s, W, part, G, false);
   hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(256), 0, ctx->stream, s, G, R, Rinv, Racc, flag);
-  hipLaunchKernelGGL(k_right_mult, dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, ctx->stream, n, s, W, Rinv, out);
+  if (s == 16 || s == 32)  // Rinv is stored whole (zero below the diagonal): a one-block update
+    block_axpy(1, W, n * s, Rinv, 1.0, nullptr, out);
+  else
+    hipLaunchKernelGGL(k_right_mult, dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, ctx->stream, n, s, W, Rinv,
+                       out);
   HIP_CHECK(hipGetLastError());
 }
 

@@ -211,9 +211,6 @@ __global__ __launch_bounds__(256) void k_bwd_gemm(const int32_t* __restrict__ wo
 // (sharing the A operand) give the real and imaginary output tiles.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// c ? a : b per component (a select on the struct itself is lowered through scratch memory)
-__device__ __forceinline__ c64 csel(bool c, c64 a, c64 b) { return cmk(c ? a.re : b.re, c ? a.im : b.im); }
-
 __device__ __forceinline__ void mfma_cplx(float a, c64 b, bool im, f32x4& cre, f32x4& cim) {
   const float bre = im ? -b.im : b.re;
   const float bim = im ? b.re : b.im;

@@ -40,15 +40,27 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, int s, const int64_t* _
       mj = col[base + lane];
       mv = val[base + lane];
     }
-    // uniform trip count over the wavefront: every lane takes part in every shuffle
+    // uniform trip count over the wavefront: every lane takes part in every shuffle.  Steps
+    // go in batches of B whose x loads are unconditional (clamped to a valid entry, the
+    // coefficient zeroed for padding), so the batch's gathers are in flight together.
+    constexpr int B = S < 8 ? S : 8;  // at most 64 / G = S steps per chunk of 64 nonzeros
     const int iters = (cnt + G - 1) / G;
-#pragma unroll 4
-    for (int t = 0; t < iters; ++t) {
-      const int k = g + t * G;
-      const int src = k < cnt ? k : 0;
-      const int64_t j = __shfl(mj, src, 64);
-      const cplx<T> a = cmk(__shfl(mv.re, src, 64), __shfl(mv.im, src, 64));
-      if (act && k < cnt) cfma(acc, a, x[j * s + c]);
+    const int cl = act ? c : 0;
+    for (int t0 = 0; t0 < iters; t0 += B) {
+      int64_t jj[B];
+      cplx<T> aa[B], xx[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int k = g + (t0 + u) * G;
+        const bool ok = k < cnt;
+        const int src = ok ? k : 0;
+        jj[u] = __shfl(mj, src, 64);
+        aa[u] = csel(ok, cmk(__shfl(mv.re, src, 64), __shfl(mv.im, src, 64)), cmk((T)0, (T)0));
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) xx[u] = x[jj[u] * s + cl];
+#pragma unroll
+      for (int u = 0; u < B; ++u) cfma(acc, aa[u], xx[u]);
     }
   }
 #pragma unroll
