@@ -178,7 +178,7 @@ hz_status hz_precond(hz_ctx* ctx, hz_handle ddm, int64_t n_rhs, const void* v, i
 typedef struct {
   int64_t n_dofs, nnz, n_sub;
   int64_t local_dofs_total;   /* sum of overlapped subdomain sizes */
-  int64_t factor_entries;     /* stored entries of all L factors (incl. diagonal blocks) */
+  int64_t factor_entries;     /* stored entries of all L factors (diagonal blocks and column padding to 16 included) */
   int64_t n_fronts, n_levels, max_front;
   int64_t n_coarse;
   int64_t static_pivots;      /* pivots replaced by the static threshold */
@@ -188,6 +188,23 @@ typedef struct {
   double setup_seconds;
 } hz_ddm_stats;
 hz_status hz_ddm_stats_get(hz_ctx* ctx, hz_handle ddm, hz_ddm_stats* out);
+
+/*
+ * Per elimination level of the multifrontal solves (level 0 holds the leaves of every
+ * subdomain's nested-dissection tree; each sweep direction makes one launch per level).
+ * hz_ddm_levels writes min(max_levels, L) entries to out and L to *n_levels; out may be
+ * null when max_levels is 0.  Errors: HZ_ERR_ARG (null n_levels, or null out with
+ * max_levels > 0).
+ */
+typedef struct {
+  int64_t n_fronts;
+  int64_t max_pivots;     /* largest pivot block p */
+  int64_t max_front;      /* largest front order f = p + r */
+  int64_t sum_pivots;     /* sum of p */
+  int64_t sum_front;      /* sum of f */
+  int64_t factor_useful;  /* stored factor nonzeros: sum of p(p+1)/2 + r p */
+} hz_ddm_level;
+hz_status hz_ddm_levels(hz_ctx* ctx, hz_handle ddm, hz_ddm_level* out, int32_t max_levels, int32_t* n_levels);
 
 /*
  * Live kernel accounting for measurement (not needed to solve).  While enabled, the

@@ -432,6 +432,25 @@ hz_status hz_ddm_stats_get(hz_ctx* c, hz_handle ddm, hz_ddm_stats* out) {
   });
 }
 
+hz_status hz_ddm_levels(hz_ctx* c, hz_handle ddm, hz_ddm_level* out, int32_t max_levels, int32_t* n_levels) {
+  return guard(c, [&] {
+    HZ_REQUIRE(n_levels, HZ_ERR_ARG, "null level count");
+    HZ_REQUIRE(out || max_levels <= 0, HZ_ERR_ARG, "null output");
+    auto d = lookup(c, c->ddms, ddm, "ddm");
+    const int32_t L = (int32_t)d->levels.size();
+    for (int32_t i = 0; i < std::min(L, max_levels); ++i) {
+      const Level& lv = d->levels[i];
+      out[i].n_fronts = (int64_t)lv.fronts.size();
+      out[i].max_pivots = lv.max_p;
+      out[i].max_front = lv.max_f;
+      out[i].sum_pivots = lv.sum_p;
+      out[i].sum_front = lv.sum_f;
+      out[i].factor_useful = lv.useful;
+    }
+    *n_levels = L;
+  });
+}
+
 hz_status hz_get_dofmap(hz_ctx* c, hz_handle mesh, int32_t* tet_dofs) {
   return guard(c, [&] {
     HZ_REQUIRE(tet_dofs, HZ_ERR_ARG, "null output");

@@ -343,7 +343,8 @@ int64_t Ddm::device_bytes() const {
   b += d_fronts.bytes() + d_urows.bytes() + d_emap.bytes() + d_gidx.bytes() + d_orig_src.bytes() +
        d_orig_dst.bytes() + d_own_src.bytes() + d_lrowptr.bytes() + d_lgptr.bytes() + d_lcol.bytes() +
        d_lgsrc.bytes() + d_ldir.bytes() + d_lval.bytes() + d_level_fronts.bytes();
-  b += d_factor.bytes + d_update.bytes;
+  b += d_factor.bytes + d_update.bytes + d_dinv.bytes;
+  b += d_fwd_work.bytes() + d_bwd_work.bytes() + d_fwdm_work.bytes() + d_bwdm_work.bytes() + d_imap.bytes();
   if (coarse)
     b += coarse->d_zptr.bytes() + coarse->d_ztptr.bytes() + coarse->d_azptr.bytes() + coarse->d_zcol.bytes() +
          coarse->d_ztcol.bytes() + coarse->d_azcol.bytes() + coarse->d_zval.bytes() + coarse->d_ztval.bytes() +
@@ -424,7 +425,7 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
       if (F.parent >= 0) F.parent += base;
       for (int k = 0; k < F.nchild; ++k) F.child[k] += base;
       F.L_off = Loff;
-      Loff += F.f() * F.p;
+      Loff += F.ld() * F.p;
       F.U_off = Uoff;
       Uoff += F.r * F.r;
       F.rows_off = urow;
@@ -458,14 +459,14 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
         for (int64_t k = 0; k < F.r; ++k) d->emap[F.emap_off + k] = (int32_t)front_index(P, UP, sy.U[fi][k]);
       }
       F.orig_off = orig;
-      const int64_t f = F.f();
+      const int64_t ld = F.ld();
       for (int64_t q = F.pos0; q < F.pos0 + F.p; ++q) {
         const int32_t v = S.perm[q];
         for (int64_t k = S.rowptr[v]; k < S.rowptr[v + 1]; ++k) {
           const int64_t pc = S.ipos[S.col[k]];
           if (pc < q) continue;
           d->orig_src.push_back(S.csr_off + k);
-          d->orig_dst.push_back((q - F.pos0) * f + front_index(F, sy.U[fi], pc));
+          d->orig_dst.push_back((q - F.pos0) * ld + front_index(F, sy.U[fi], pc));
         }
       }
       F.orig_cnt = (int64_t)d->orig_src.size() - orig;
@@ -594,7 +595,7 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     x.child0 = F.child[0];
     x.child1 = F.child[1];
     x.pos0 = (int32_t)F.pos0;
-    x.pad = 0;
+    x.ld = (int32_t)F.ld();
   }
   d->d_fronts.upload(ctx, fd);
   d->d_urows.upload(ctx, d->urows);
@@ -606,27 +607,34 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   d->d_level_fronts.upload(ctx, lf);
   d->w_total = wrows;
   d->d_imap.upload(ctx, imap);
-  {  // solve worklists: forward row tiles of 64, backward column tiles of 32
-    std::vector<int32_t> fw, bw;
-    for (const Level& L : d->levels) {
-      d->fwd_off.push_back((int64_t)fw.size() / 2);
-      d->bwd_off.push_back((int64_t)bw.size() / 2);
-      for (int32_t fi : L.fronts) {
-        const Front& F = d->fronts[fi];
-        for (int64_t i0 = 0; i0 < F.f(); i0 += 64) {
-          fw.push_back(fi);
-          fw.push_back((int32_t)i0);
-        }
-        for (int64_t j0 = 0; j0 < F.p; j0 += 32) {
-          bw.push_back(fi);
-          bw.push_back((int32_t)j0);
+  {  // solve worklists: forward row tiles of 64, backward column tiles of 32 (vector-unit
+     // sweeps) and the wider tiles of the matrix-core sweeps
+    auto build = [&](int rows, int cols, std::vector<int64_t>& foff, std::vector<int64_t>& boff,
+                     DevArray<int32_t>& dfw, DevArray<int32_t>& dbw) {
+      std::vector<int32_t> fw, bw;
+      for (const Level& L : d->levels) {
+        foff.push_back((int64_t)fw.size() / 2);
+        boff.push_back((int64_t)bw.size() / 2);
+        for (int32_t fi : L.fronts) {
+          const Front& F = d->fronts[fi];
+          for (int64_t i0 = 0; i0 < F.f(); i0 += rows) {
+            fw.push_back(fi);
+            fw.push_back((int32_t)i0);
+          }
+          for (int64_t j0 = 0; j0 < F.p; j0 += cols) {
+            bw.push_back(fi);
+            bw.push_back((int32_t)j0);
+          }
         }
       }
-    }
-    d->fwd_off.push_back((int64_t)fw.size() / 2);
-    d->bwd_off.push_back((int64_t)bw.size() / 2);
-    d->d_fwd_work.upload(ctx, fw);
-    d->d_bwd_work.upload(ctx, bw);
+      foff.push_back((int64_t)fw.size() / 2);
+      boff.push_back((int64_t)bw.size() / 2);
+      dfw.upload(ctx, fw);
+      dbw.upload(ctx, bw);
+    };
+    build(64, 32, d->fwd_off, d->bwd_off, d->d_fwd_work, d->d_bwd_work);
+    if (precision == HZ_PREC_MIXED)
+      build(kFwdRowsMfma, kBwdColsMfma, d->fwdm_off, d->bwdm_off, d->d_fwdm_work, d->d_bwdm_work);
   }
   {
     std::vector<int64_t> rp, gp;

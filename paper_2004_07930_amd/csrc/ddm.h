@@ -8,7 +8,8 @@ namespace hz {
 // One supernode of a subdomain's elimination tree (multifrontal LDL^T).
 // Its dense front has f = p + r rows: the p pivots (contiguous elimination positions
 // [pos0, pos0 + p) of the subdomain) then the r update rows (later positions, ascending).
-// Storage: L block f x p column-major (ld = f) in the factor array at L_off; the diagonal
+// Storage: L block f x p column-major in the factor array at L_off, leading dimension ld =
+// f rounded up to 16 entries (so column segments start on cache-line boundaries); the diagonal
 // holds D, below it L (unit diagonal implied).  The r x r update (Schur) block lives in a
 // workspace at U_off (ld = r) until the parent has absorbed it.
 struct Front {
@@ -25,6 +26,7 @@ struct Front {
   int64_t emap_off = 0;    // offset of the r extend-add targets in the parent's front
   int64_t orig_off = 0, orig_cnt = 0;  // original-entry scatter list
   int64_t f() const { return p + r; }
+  int64_t ld() const { return (f() + 15) / 16 * 16; }
 };
 
 // device-side compact description of a front (used by kernels)
@@ -37,7 +39,7 @@ struct FrontDesc {
   int32_t parent;    // global front id or -1
   int32_t child0, child1;
   int32_t pos0;
-  int32_t pad;
+  int32_t ld;        // leading dimension of the L block (f rounded up to 16)
 };
 
 struct Subdomain {
@@ -84,6 +86,11 @@ struct CoarseSpace {
   DevBuf w_y, w_y2, w_part;       // apply workspace (restricted vector, product, K-chunk partials)
 };
 
+// tile sizes of the complex64 matrix-core solve sweeps: forward rows per block, backward
+// pivot columns per block
+constexpr int kFwdRowsMfma = 64;
+constexpr int kBwdColsMfma = 64;
+
 struct Ddm {
   std::shared_ptr<Operator> op;
   int precision = HZ_PREC_C128;
@@ -123,9 +130,10 @@ struct Ddm {
   DevArray<unsigned long long> d_npiv;  // static pivot counter
   int64_t w_total = 0;            // solve workspace rows (sum of f over fronts)
   int64_t factor_useful = 0;      // stored nonzeros: sum p(p+1)/2 + r p
-  // solve worklists per level: forward (front, 64-row tile start), backward (front, 32-column start)
-  std::vector<int64_t> fwd_off, bwd_off;
-  DevArray<int32_t> d_fwd_work, d_bwd_work;  // pairs
+  // solve worklists per level: forward (front, 64-row tile start), backward (front, 32-column
+  // start); the matrix-core sweeps use their own, wider tiles (kFwdRowsMfma, kBwdColsMfma)
+  std::vector<int64_t> fwd_off, bwd_off, fwdm_off, bwdm_off;
+  DevArray<int32_t> d_fwd_work, d_bwd_work, d_fwdm_work, d_bwdm_work;  // pairs
   DevArray<int32_t> d_imap;
   int64_t device_bytes() const;
 };

@@ -26,13 +26,11 @@ constexpr int kTile = 64;   // trailing-update tile
 template <typename T>
 __device__ __forceinline__ cplx<T> ld_front(const cplx<T>* L, const cplx<T>* U, const FrontDesc& F, int64_t i,
                                             int64_t j) {
-  const int64_t f = F.p + F.r;
-  return j < F.p ? L[F.L_off + j * f + i] : U[F.U_off + (j - F.p) * F.r + (i - F.p)];
+  return j < F.p ? L[F.L_off + j * F.ld + i] : U[F.U_off + (j - F.p) * F.r + (i - F.p)];
 }
 template <typename T>
 __device__ __forceinline__ cplx<T>* at_front(cplx<T>* L, cplx<T>* U, const FrontDesc& F, int64_t i, int64_t j) {
-  const int64_t f = F.p + F.r;
-  return j < F.p ? &L[F.L_off + j * f + i] : &U[F.U_off + (j - F.p) * F.r + (i - F.p)];
+  return j < F.p ? &L[F.L_off + j * F.ld + i] : &U[F.U_off + (j - F.p) * F.r + (i - F.p)];
 }
 
 template <typename T>
@@ -85,11 +83,11 @@ __global__ __launch_bounds__(256) void k_diag_block(const int32_t* __restrict__ 
   const int fid = lf[blockIdx.x];
   const FrontDesc F = fr[fid];
   const int nb = min(kNb, F.p - k0);
-  const int64_t f = F.p + F.r;
-  cplx<T>* base = L + F.L_off + (int64_t)k0 * f + k0;
+  const int64_t ld = F.ld;
+  cplx<T>* base = L + F.L_off + (int64_t)k0 * ld + k0;
   for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
     const int j = t / kNb, i = t % kNb;
-    A[i][j] = (i < nb && j < nb && i >= j) ? base[(int64_t)j * f + i] : cmk((T)0, (T)0);
+    A[i][j] = (i < nb && j < nb && i >= j) ? base[(int64_t)j * ld + i] : cmk((T)0, (T)0);
   }
   __syncthreads();
   const T tau = (T)tau_sub[front_sub[fid]];
@@ -119,7 +117,7 @@ __global__ __launch_bounds__(256) void k_diag_block(const int32_t* __restrict__ 
   }
   for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
     const int j = t / kNb, i = t % kNb;
-    if (i < nb && j < nb && i >= j) base[(int64_t)j * f + i] = A[i][j];
+    if (i < nb && j < nb && i >= j) base[(int64_t)j * ld + i] = A[i][j];
   }
 }
 
@@ -135,16 +133,17 @@ __global__ __launch_bounds__(256) void k_panel_rows(const int32_t* __restrict__ 
   const int64_t rows = f - r0;
   const int64_t chunk = (int64_t)blockIdx.y * blockDim.x;
   if (chunk >= rows) return;
-  cplx<T>* col0 = L + F.L_off + (int64_t)k0 * f;
+  const int64_t ld = F.ld;
+  cplx<T>* col0 = L + F.L_off + (int64_t)k0 * ld;
   for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
     const int j = t / kNb, i = t % kNb;
-    Lkk[i][j] = (i < nb && j < nb && i >= j) ? col0[(int64_t)j * f + k0 + i] : cmk((T)0, (T)0);
+    Lkk[i][j] = (i < nb && j < nb && i >= j) ? col0[(int64_t)j * ld + k0 + i] : cmk((T)0, (T)0);
   }
   __syncthreads();
   for (int64_t i = r0 + chunk + threadIdx.x; i < f; i += (int64_t)gridDim.y * blockDim.x) {
     cplx<T> y[kNb];
 #pragma unroll
-    for (int j = 0; j < kNb; ++j) y[j] = j < nb ? col0[(int64_t)j * f + i] : cmk((T)0, (T)0);
+    for (int j = 0; j < kNb; ++j) y[j] = j < nb ? col0[(int64_t)j * ld + i] : cmk((T)0, (T)0);
 #pragma unroll
     for (int j = 0; j < kNb; ++j) {
 #pragma unroll
@@ -152,7 +151,7 @@ __global__ __launch_bounds__(256) void k_panel_rows(const int32_t* __restrict__ 
     }
 #pragma unroll
     for (int j = 0; j < kNb; ++j)
-      if (j < nb) col0[(int64_t)j * f + i] = cdiv(y[j], Lkk[j][j]);
+      if (j < nb) col0[(int64_t)j * ld + i] = cdiv(y[j], Lkk[j][j]);
   }
 }
 
@@ -177,14 +176,15 @@ __global__ __launch_bounds__(256) void k_trailing(const int32_t* __restrict__ lf
   while ((ti + 1) * (ti + 2) / 2 <= tid) ++ti;
   const int64_t tj = tid - ti * (ti + 1) / 2;
   const int64_t i0 = c0 + ti * kTile, j0 = c0 + tj * kTile;
-  const cplx<T>* pan = L + F.L_off + (int64_t)k0 * f;
-  const cplx<T>* dg = pan + k0;  // diagonal entries at pan[l*f + k0 + l]
+  const int64_t ld = F.ld;
+  const cplx<T>* pan = L + F.L_off + (int64_t)k0 * ld;
+  const cplx<T>* dg = pan + k0;  // diagonal entries at pan[l*ld + k0 + l]
   for (int t = threadIdx.x; t < kNb * kTile; t += blockDim.x) {
     const int l = t / kTile, r = t % kTile;
     cplx<T> a = cmk((T)0, (T)0), b = cmk((T)0, (T)0);
     if (l < nb) {
-      if (i0 + r < f) a = pan[(int64_t)l * f + i0 + r];
-      if (j0 + r < f) b = pan[(int64_t)l * f + j0 + r] * dg[(int64_t)l * f + l];
+      if (i0 + r < f) a = pan[(int64_t)l * ld + i0 + r];
+      if (j0 + r < f) b = pan[(int64_t)l * ld + j0 + r] * dg[(int64_t)l * ld + l];
     }
     As[l][r] = a;
     Bs[l][r] = b;
@@ -236,9 +236,8 @@ template <typename T>
 __global__ void k_extract_dinv(int nf, const FrontDesc* __restrict__ fr, cplx<T>* __restrict__ L,
                                cplx<T>* __restrict__ dinv) {
   const FrontDesc F = fr[blockIdx.x];
-  const int64_t f = F.p + F.r;
   for (int j = threadIdx.x; j < F.p; j += blockDim.x) {
-    cplx<T>* dg = L + F.L_off + (int64_t)j * f + j;
+    cplx<T>* dg = L + F.L_off + (int64_t)j * F.ld + j;
     dinv[F.vec_off + F.pos0 + j] = cdiv(cmk((T)1, (T)0), *dg);
   }
 }
@@ -253,12 +252,11 @@ __global__ void k_inv_copy(const int32_t* __restrict__ act, const FrontDesc* __r
   const int J = nblk - 1 - t;
   const int j0 = J * kNb;
   const int nbJ = min(kNb, F.p - j0);
-  const int64_t f = F.p + F.r;
   const int64_t rows = F.p - j0;
   cplx<T>* dst = P + poff[blockIdx.x];
   for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < rows * nbJ; k += (int64_t)gridDim.y * blockDim.x) {
     const int64_t jj = k / rows, r = k - jj * rows;
-    dst[jj * rows + r] = L[F.L_off + (int64_t)(j0 + jj) * f + j0 + r];
+    dst[jj * rows + r] = L[F.L_off + (int64_t)(j0 + jj) * F.ld + j0 + r];
   }
 }
 
@@ -305,7 +303,7 @@ __global__ __launch_bounds__(256) void k_inv_block(const int32_t* __restrict__ a
     }
     for (int e = threadIdx.x; e < KC * RT; e += 256) {
       const int k = e / RT, rr = e % RT;
-      Mt[k][rr] = (k < kn && i0 + rr < f) ? Lf[(kc + k) * f + i0 + rr] : cmk((T)0, (T)0);
+      Mt[k][rr] = (k < kn && i0 + rr < f) ? Lf[(kc + k) * F.ld + i0 + rr] : cmk((T)0, (T)0);
     }
     __syncthreads();
     for (int k = 0; k < kn; ++k) {
@@ -323,7 +321,7 @@ __global__ __launch_bounds__(256) void k_inv_block(const int32_t* __restrict__ a
       if (i < F.p)
         base = cmk((T)(i == j0 + jj ? 1 : 0), (T)0);
       else
-        base = Lf[(int64_t)(j0 + jj) * f + i];
+        base = Lf[(int64_t)(j0 + jj) * F.ld + i];
     }
     Rr[r][jj] = base - acc[a];
   }
@@ -335,7 +333,7 @@ __global__ __launch_bounds__(256) void k_inv_block(const int32_t* __restrict__ a
       for (int l = jj + 1; l < nbJ; ++l) cfms(x, Rr[r][l], Ljj[l][jj]);
       Rr[r][jj] = x;
     }
-    for (int jj = 0; jj < nbJ; ++jj) Lf[(int64_t)(j0 + jj) * f + i] = Rr[r][jj];
+    for (int jj = 0; jj < nbJ; ++jj) Lf[(int64_t)(j0 + jj) * F.ld + i] = Rr[r][jj];
   }
 }
 

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_fwd_gemm(const int32_t* __restrict__ wo
     __syncthreads();
     for (int e = threadIdx.x; e < JC * RT; e += 256) {
       const int jj = e / RT, rr = e - (e / RT) * RT;
-      Ft[jj][rr] = (jj < jn && i0 + rr < f) ? Lf[(j + jj) * f + i0 + rr] : cmk((T)0, (T)0);
+      Ft[jj][rr] = (jj < jn && i0 + rr < f) ? Lf[(j + jj) * F.ld + i0 + rr] : cmk((T)0, (T)0);
     }
     for (int e = threadIdx.x; e < JC * S; e += 256) {
       const int jj = e / S, c = e - (e / S) * S;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void k_bwd_gemm(const int32_t* __restrict__ wo
     __syncthreads();
     for (int e = threadIdx.x; e < RC * CT; e += 256) {
       const int cc = e / RC, rr = e - (e / RC) * RC;
-      Ft[rr][cc] = (rr < rn && cc < nj) ? Lf[(j0 + cc) * f + i + rr] : cmk((T)0, (T)0);
+      Ft[rr][cc] = (rr < rn && cc < nj) ? Lf[(j0 + cc) * F.ld + i + rr] : cmk((T)0, (T)0);
     }
     for (int e = threadIdx.x; e < RC * S; e += 256) {
       const int rr = e / S, c = e - (e / S) * S;
@@ -203,30 +203,29 @@ __global__ __launch_bounds__(256) void k_bwd_gemm(const int32_t* __restrict__ wo
 
 // ---- complex64 sweeps on the matrix cores (blocks of 16 or 32 columns)
 //
-// A complex product C = A B is the real product
-//   [C_re | C_im] = A' [[B_re, B_im], [-B_im, B_re]]  (rows of the right factor interleaved),
-// where A' is the complex A read as interleaved (re, im) floats -- exactly its memory layout.
-// v_mfma_f32_16x16x4f32 (lane l: A[l%16][l/16], B[l/16][l%16], D[4(l/16)+v][l%16]) takes
-// 4 real k per step = 2 complex columns of A; per group of 16 right-hand columns two MFMAs
-// (sharing the A operand) give the real and imaginary output tiles.
+// Complex products in the three-multiplication form: with A = Ar + i Ai, B = Br + i Bi,
+//   P1 = Ar Br,  P2 = Ai Bi,  P3 = (Ar + Ai)(Br + Bi),  AB = (P1 - P2) + i (P3 - P1 - P2),
+// three real products where the direct form needs four.  Each is a v_mfma_f32_16x16x4f32
+// (lane l: A[l%16][l/16], B[l/16][l%16], D[4(l/16)+v][l%16]) over 4 complex k at a time:
+// lane l reads one complex entry of each operand for k = l/16 of the step.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ void mfma_cplx(float a, c64 b, bool im, f32x4& cre, f32x4& cim) {
-  const float bre = im ? -b.im : b.re;
-  const float bim = im ? b.re : b.im;
-  cre = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bre, cre, 0, 0, 0);
-  cim = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bim, cim, 0, 0, 0);
+__device__ __forceinline__ void mfma_3m(c64 a, c64 b, f32x4& p1, f32x4& p2, f32x4& p3) {
+  p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, b.re, p1, 0, 0, 0);
+  p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.im, b.im, p2, 0, 0, 0);
+  p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re + a.im, b.re + b.im, p3, 0, 0, 0);
 }
 
-// Forward rows [i0, i0 + 64) (same tile and result as k_fwd_gemm): wavefront wv owns rows
-// 16 wv .. 16 wv + 15; NG groups of 16 columns.  Each thread stages a fixed share of the next
+// Forward rows [i0, i0 + 64 MT) (the k_fwd_gemm product on a wider tile): wavefront wv owns
+// MT tiles of 16 rows, NG groups of 16 columns.  Each thread stages a fixed share of the next
 // chunk in registers (loads from a clamped, always valid index, so they issue back to back)
-// while the current chunk is multiplied out of LDS.
-template <int NG>
+// while the current chunk is multiplied out of LDS; the bounds predicate is applied when the
+// registers are written to LDS, so the loads stay in flight across the products.
+template <int NG, int MT, int JC>
 __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
                                                   const c64* __restrict__ L, c64* __restrict__ wbuf,
                                                   c64* __restrict__ bout, int s) {
-  constexpr int RT = 64, JC = 32, SC = 16 * NG;
+  constexpr int RT = 64 * MT, SC = 16 * NG;
   constexpr int NF = JC * RT / 256, NW = JC * SC / 256;
   __shared__ c64 Ft[JC][RT + 1];
   __shared__ c64 Wt[JC][SC];
@@ -238,19 +237,16 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
   const int tid = threadIdx.x;
   const int wv = tid >> 6, l = tid & 63;
   const int lr = l & 15, lq = l >> 4;
-  const bool im = lq & 1;
   const c64* Lf = L + F.L_off;
   const c64* wp = wbuf + F.w_off * s;
   const c64 zero = cmk(0.f, 0.f);
-  // raw register copies of the next chunk; the bounds predicate is applied when they are
-  // written to LDS, so the loads stay in flight while the current chunk is multiplied
   c64 rf[NF], rw[NW];
   auto fetch = [&](int64_t j) {
     const int jn = (int)min<int64_t>(JC, jend - j);
 #pragma unroll
     for (int u = 0; u < NF; ++u) {
-      const int jj = (tid >> 6) + 4 * u, rr = tid & 63;  // element tid + 256 u of [JC][RT]
-      rf[u] = Lf[(jj < jn && i0 + rr < f) ? (j + jj) * f + i0 + rr : 0];
+      const int e = tid + 256 * u, jj = e / RT, rr = e - (e / RT) * RT;  // element e of [JC][RT]
+      rf[u] = Lf[(jj < jn && i0 + rr < f) ? (j + jj) * F.ld + i0 + rr : 0];
     }
 #pragma unroll
     for (int u = 0; u < NW; ++u) {
@@ -258,16 +254,18 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
       rw[u] = wp[(jj < jn && c < s) ? (j + jj) * s + c : 0];
     }
   };
-  f32x4 cre[NG], cim[NG];
+  f32x4 p1[MT][NG], p2[MT][NG], p3[MT][NG];
 #pragma unroll
-  for (int g = 0; g < NG; ++g) cre[g] = cim[g] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) p1[m][g] = p2[m][g] = p3[m][g] = f32x4{0.f, 0.f, 0.f, 0.f};
   fetch(0);
   for (int64_t j = 0; j < jend; j += JC) {
     const int jn = (int)min<int64_t>(JC, jend - j);
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < NF; ++u) {
-      const int jj = (tid >> 6) + 4 * u, rr = tid & 63;
+      const int e = tid + 256 * u, jj = e / RT, rr = e - (e / RT) * RT;
       Ft[jj][rr] = csel(jj < jn && i0 + rr < f, rf[u], zero);
     }
 #pragma unroll
@@ -277,47 +275,56 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
     }
     __syncthreads();
     if (j + JC < jend) fetch(j + JC);
-    // two complex columns per step; columns past jn are zero in LDS, so the step count may
-    // be rounded up to a multiple of 4
-    const int steps = (((jn + 1) >> 1) + 3) & ~3;
-#pragma unroll 4
+    // four complex columns per step; columns past jn are zero in LDS, so the step count may
+    // be rounded up to a multiple of 2
+    const int steps = (((jn + 3) >> 2) + 1) & ~1;
+#pragma unroll 2
     for (int t = 0; t < steps; ++t) {
-      const int kc = 2 * t + (lq >> 1);
-      const c64 av = Ft[kc][16 * wv + lr];
-      const float a = im ? av.im : av.re;
+      const int kc = 4 * t + lq;
+      c64 wb[NG];
 #pragma unroll
-      for (int g = 0; g < NG; ++g) mfma_cplx(a, Wt[kc][16 * g + lr], im, cre[g], cim[g]);
-    }
-  }
+      for (int g = 0; g < NG; ++g) wb[g] = Wt[kc][16 * g + lr];
 #pragma unroll
-  for (int g = 0; g < NG; ++g) {
-    const int c = 16 * g + lr;
-    if (c >= s) continue;
+      for (int m = 0; m < MT; ++m) {
+        const c64 av = Ft[kc][16 * (wv * MT + m) + lr];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t i = i0 + 16 * wv + 4 * lq + v;
-      if (i >= f) continue;
-      const c64 val = cmk(cre[g][v], cim[g][v]);
-      if (i < F.p) {
-        bout[(F.vec_off + F.pos0 + i) * s + c] = val;
-      } else {
-        c64* w = &wbuf[(F.w_off + i) * s + c];
-        *w = *w - val;
+        for (int g = 0; g < NG; ++g) mfma_3m(av, wb[g], p1[m][g], p2[m][g], p3[m][g]);
       }
     }
   }
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int c = 16 * g + lr;
+      if (c >= s) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = i0 + 16 * (wv * MT + m) + 4 * lq + v;
+        if (i >= f) continue;
+        const c64 val = cmk(p1[m][g][v] - p2[m][g][v], p3[m][g][v] - p1[m][g][v] - p2[m][g][v]);
+        if (i < F.p) {
+          bout[(F.vec_off + F.pos0 + i) * s + c] = val;
+        } else {
+          c64* w = &wbuf[(F.w_off + i) * s + c];
+          *w = *w - val;
+        }
+      }
+    }
 }
 
-// Backward columns [j0, j0 + 32) (same tile and result as k_bwd_gemm): wavefront wv owns
-// columns 16 wv .. 16 wv + 15 of the front; rows from j0 in chunks of 32, staged as in the
-// forward kernel.  u rows below the pivot block are gathered through the update-row map.
-template <int NG>
-__global__ __launch_bounds__(128) void k_bwd_mfma(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
+// Backward pivot columns [j0, j0 + 64 NT) (the k_bwd_gemm product on a wider tile):
+// wavefront wv owns NT tiles of 16 columns; rows from j0 in chunks of 32, staged as in the
+// forward kernel.  u rows below the pivot block are gathered through the update-row map;
+// the row indices are loaded first, so the factor loads stay in flight while the dependent
+// gathers wait for them.
+template <int NG, int NT, int RC>
+__global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
                                                   const c64* __restrict__ L, const int32_t* __restrict__ urows,
                                                   const c64* __restrict__ dinv, const c64* __restrict__ bout,
                                                   c64* __restrict__ bin, int s) {
-  constexpr int CT = 32, RC = 32, SC = 16 * NG;
-  constexpr int NF = RC * CT / 128, NU = RC * SC / 128;
+  constexpr int CT = 64 * NT, SC = 16 * NG;
+  constexpr int NF = RC * CT / 256, NU = RC * SC / 256;
   __shared__ c64 Ft[RC][CT + 1];
   __shared__ c64 Ut[RC][SC];
   const int fid = work[2 * blockIdx.x];
@@ -328,24 +335,19 @@ __global__ __launch_bounds__(128) void k_bwd_mfma(const int32_t* __restrict__ wo
   const int tid = threadIdx.x;
   const int wv = tid >> 6, l = tid & 63;
   const int lr = l & 15, lq = l >> 4;
-  const bool im = lq & 1;
   const c64* Lf = L + F.L_off;
   const int64_t pbase = F.vec_off + F.pos0;  // first pivot position: a valid clamp target
   const c64 zero = cmk(0.f, 0.f);
-  // raw register copies of the next chunk (factor tile, gathered u sources and 1/d), turned
-  // into LDS values only when stored, so the loads overlap the current chunk's products.
-  // The update-row indices are loaded first: the factor loads stay in flight while the
-  // dependent gathers wait for them.
   c64 rf[NF], rx[NU], rd[NU];
   auto fetch = [&](int64_t i) {
     const int rn = (int)min<int64_t>(RC, f - i);
     // update-row indices from a clamped (valid) index; a front without update rows reads
-    // none (the map may be empty), a block-uniform test
+    // none (its map may be empty), a block-uniform test
     int32_t ui[NU];
     if (F.r > 0) {
 #pragma unroll
       for (int u = 0; u < NU; ++u) {
-        const int rr = (tid + 128 * u) / SC;
+        const int rr = (tid + 256 * u) / SC;
         const int64_t row = i + rr;
         ui[u] = urows[F.rows_off + ((rr < rn && row >= F.p) ? row - F.p : 0)];
       }
@@ -353,43 +355,39 @@ __global__ __launch_bounds__(128) void k_bwd_mfma(const int32_t* __restrict__ wo
 #pragma unroll
       for (int u = 0; u < NU; ++u) ui[u] = 0;
     }
-    int64_t pos[NU];
-#pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      const int rr = (tid + 128 * u) / SC;
-      const int64_t row = i + rr;
-      pos[u] = (rr < rn && row >= F.p) ? F.vec_off + ui[u] : pbase + min<int64_t>(row, F.p - 1);
-    }
 #pragma unroll
     for (int u = 0; u < NF; ++u) {
-      const int cc = (tid >> 5) + 4 * u, rr = tid & 31;  // element tid + 128 u of [CT][RC]
-      rf[u] = Lf[(rr < rn && cc < nj) ? (j0 + cc) * f + i + rr : 0];
+      const int e = tid + 256 * u, cc = e / RC, rr = e - (e / RC) * RC;  // element e of [CT][RC]
+      rf[u] = Lf[(rr < rn && cc < nj) ? (j0 + cc) * F.ld + i + rr : 0];
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
-      const int e = tid + 128 * u, rr = e / SC, c = e - (e / SC) * SC;
+      const int e = tid + 256 * u, rr = e / SC, c = e - (e / SC) * SC;
       const int64_t row = i + rr;
       const bool ok = rr < rn && c < s;
       const bool piv = row < F.p;
-      rx[u] = (piv ? bout : bin)[(ok ? pos[u] : pbase) * s + (ok ? c : 0)];
-      rd[u] = dinv[(ok && piv) ? pos[u] : pbase];
+      const int64_t pos = piv ? pbase + row : F.vec_off + ui[u];
+      rx[u] = (piv ? bout : bin)[(ok ? pos : pbase) * s + (ok ? c : 0)];
+      rd[u] = dinv[(ok && piv) ? pos : pbase];
     }
   };
-  f32x4 cre[NG], cim[NG];
+  f32x4 p1[NT][NG], p2[NT][NG], p3[NT][NG];
 #pragma unroll
-  for (int g = 0; g < NG; ++g) cre[g] = cim[g] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < NT; ++m)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) p1[m][g] = p2[m][g] = p3[m][g] = f32x4{0.f, 0.f, 0.f, 0.f};
   fetch(j0);
   for (int64_t i = j0; i < f; i += RC) {
     const int rn = (int)min<int64_t>(RC, f - i);
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < NF; ++u) {
-      const int cc = (tid >> 5) + 4 * u, rr = tid & 31;
+      const int e = tid + 256 * u, cc = e / RC, rr = e - (e / RC) * RC;
       Ft[rr][cc] = csel(rr < rn && cc < nj, rf[u], zero);
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
-      const int e = tid + 128 * u, rr = e / SC, c = e - (e / SC) * SC;
+      const int e = tid + 256 * u, rr = e / SC, c = e - (e / SC) * SC;
       const bool ok = rr < rn && c < s;
       const bool piv = i + rr < F.p;
       const c64 x = rx[u];
@@ -397,26 +395,35 @@ __global__ __launch_bounds__(128) void k_bwd_mfma(const int32_t* __restrict__ wo
     }
     __syncthreads();
     if (i + RC < f) fetch(i + RC);
-    const int steps = (((rn + 1) >> 1) + 3) & ~3;
-#pragma unroll 4
+    const int steps = (((rn + 3) >> 2) + 1) & ~1;
+#pragma unroll 2
     for (int t = 0; t < steps; ++t) {
-      const int rr = 2 * t + (lq >> 1);
-      const c64 av = Ft[rr][16 * wv + lr];
-      const float a = im ? av.im : av.re;
+      const int rr = 4 * t + lq;
+      c64 ub[NG];
 #pragma unroll
-      for (int g = 0; g < NG; ++g) mfma_cplx(a, Ut[rr][16 * g + lr], im, cre[g], cim[g]);
+      for (int g = 0; g < NG; ++g) ub[g] = Ut[rr][16 * g + lr];
+#pragma unroll
+      for (int m = 0; m < NT; ++m) {
+        const c64 av = Ft[rr][16 * (wv * NT + m) + lr];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) mfma_3m(av, ub[g], p1[m][g], p2[m][g], p3[m][g]);
+      }
     }
   }
 #pragma unroll
-  for (int g = 0; g < NG; ++g) {
-    const int c = 16 * g + lr;
-    if (c >= s) continue;
+  for (int m = 0; m < NT; ++m)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int jj = 16 * wv + 4 * lq + v;
-      if (jj < nj) bin[(F.vec_off + F.pos0 + j0 + jj) * s + c] = cmk(cre[g][v], cim[g][v]);
+    for (int g = 0; g < NG; ++g) {
+      const int c = 16 * g + lr;
+      if (c >= s) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int jj = 16 * (wv * NT + m) + 4 * lq + v;
+        if (jj < nj)
+          bin[(F.vec_off + F.pos0 + j0 + jj) * s + c] =
+              cmk(p1[m][g][v] - p2[m][g][v], p3[m][g][v] - p1[m][g][v] - p2[m][g][v]);
+      }
     }
-  }
 }
 
 // Matrix-core sweeps serve complex64 blocks of at least 8 columns; narrower blocks (and
@@ -443,8 +450,9 @@ void sweep(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) 
     ProfScope ps(ctx, HZ_K_ORAS_FWD, esz * ((double)Lv.useful + 2.0 * (double)Lv.sum_f * s),
                  8.0 * (double)Lv.useful * s);
     if constexpr (use_mfma<T, S>())
-      hipLaunchKernelGGL((k_fwd_mfma<(S + 15) / 16>), dim3((unsigned)nw), dim3(256), 0, st,
-                         d.d_fwd_work.ptr() + 2 * d.fwd_off[lv], d.d_fronts.ptr(), L, wbuf, bout, s);
+      hipLaunchKernelGGL((k_fwd_mfma<(S + 15) / 16, kFwdRowsMfma / 64, 32>),
+                         dim3((unsigned)(d.fwdm_off[lv + 1] - d.fwdm_off[lv])), dim3(256), 0, st,
+                         d.d_fwdm_work.ptr() + 2 * d.fwdm_off[lv], d.d_fronts.ptr(), L, wbuf, bout, s);
     else
       hipLaunchKernelGGL((k_fwd_gemm<T, S>), dim3((unsigned)nw), dim3(256), 0, st,
                          d.d_fwd_work.ptr() + 2 * d.fwd_off[lv], d.d_fronts.ptr(), L, wbuf, bout, s);
@@ -456,8 +464,9 @@ void sweep(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) 
     ProfScope ps(ctx, HZ_K_ORAS_BWD, esz * ((double)Lv.useful + (double)(Lv.sum_f + Lv.sum_p) * s),
                  8.0 * (double)Lv.useful * s);
     if constexpr (use_mfma<T, S>())
-      hipLaunchKernelGGL((k_bwd_mfma<(S + 15) / 16>), dim3((unsigned)nw), dim3(128), 0, st,
-                         d.d_bwd_work.ptr() + 2 * d.bwd_off[lv], d.d_fronts.ptr(), L, d.d_urows.ptr(),
+      hipLaunchKernelGGL((k_bwd_mfma<(S + 15) / 16, kBwdColsMfma / 64, 32>),
+                         dim3((unsigned)(d.bwdm_off[lv + 1] - d.bwdm_off[lv])), dim3(256), 0, st,
+                         d.d_bwdm_work.ptr() + 2 * d.bwdm_off[lv], d.d_fronts.ptr(), L, d.d_urows.ptr(),
                          d.d_dinv.as<cplx<T>>(), bout, bin, s);
     else
       hipLaunchKernelGGL((k_bwd_gemm<T, S>), dim3((unsigned)nw), dim3(256), 0, st,

@@ -26,7 +26,7 @@ _STATUS = {0: "HZ_OK", -1: "HZ_ERR_ARG", -2: "HZ_ERR_OOM", -3: "HZ_ERR_HIP", -4:
 
 EXPORTS = [
     "hz_init", "hz_finalize", "hz_last_error", "hz_release", "hz_mesh", "hz_assemble", "hz_setup_ddm",
-    "hz_solve", "hz_solve_ex", "hz_point_sources", "hz_spmm", "hz_precond", "hz_ddm_stats_get",
+    "hz_solve", "hz_solve_ex", "hz_point_sources", "hz_spmm", "hz_precond", "hz_ddm_stats_get", "hz_ddm_levels",
     "hz_serve_start", "hz_serve_submit", "hz_serve_poll", "hz_serve_wait", "hz_serve_stats_get",
     "hz_serve_stop", "hz_get_dofmap", "hz_get_csr_size", "hz_get_csr", "hz_get_subdomain_size",
     "hz_get_subdomain", "hz_get_coarse_size", "hz_get_coarse", "hz_profile_enable", "hz_profile_get",
@@ -65,6 +65,11 @@ class DdmStats(C.Structure):
                 ("max_front", C.c_int64), ("n_coarse", C.c_int64), ("static_pivots", C.c_int64),
                 ("update_entries", C.c_int64), ("factor_useful", C.c_int64),
                 ("device_bytes", C.c_int64), ("setup_seconds", C.c_double)]
+
+
+class DdmLevel(C.Structure):
+    _fields_ = [("n_fronts", C.c_int64), ("max_pivots", C.c_int64), ("max_front", C.c_int64),
+                ("sum_pivots", C.c_int64), ("sum_front", C.c_int64), ("factor_useful", C.c_int64)]
 
 
 class Request(C.Structure):
@@ -115,6 +120,7 @@ def load(path: str | None = None):
         "hz_spmm": [vp, u64, i64, vp, C.c_int, vp, C.c_int],
         "hz_precond": [vp, u64, i64, vp, C.c_int, vp, C.c_int],
         "hz_ddm_stats_get": [vp, u64, C.POINTER(DdmStats)],
+        "hz_ddm_levels": [vp, u64, C.POINTER(DdmLevel), C.c_int32, C.POINTER(C.c_int32)],
         "hz_serve_start": [vp, i32],
         "hz_serve_submit": [vp, C.POINTER(Request), C.POINTER(u64)],
         "hz_serve_poll": [vp, u64, C.POINTER(C.c_int)],
@@ -356,6 +362,15 @@ class Context:
         s = DdmStats()
         self._check(self.lib.hz_ddm_stats_get(self.h, ddm.handle, C.byref(s)))
         return {k: getattr(s, k) for k, _ in DdmStats._fields_}
+
+    def ddm_levels(self, ddm):
+        """Per elimination level (leaves first): fronts, largest p and f, sums of p and f, and
+        stored factor nonzeros."""
+        n = C.c_int32()
+        self._check(self.lib.hz_ddm_levels(self.h, ddm.handle, None, 0, C.byref(n)))
+        arr = (DdmLevel * max(1, n.value))()
+        self._check(self.lib.hz_ddm_levels(self.h, ddm.handle, arr, n.value, C.byref(n)))
+        return [{k: getattr(arr[i], k) for k, _ in DdmLevel._fields_} for i in range(n.value)]
 
     def dofmap(self, mesh):
         out = np.empty((mesh.n_tets, 20), np.int32)

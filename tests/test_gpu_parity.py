@@ -141,6 +141,21 @@ def test_precond_one_level_c128(case, ddm_case, ctx):
     assert st["static_pivots"] == 0
 
 
+def test_ddm_levels_consistent(case, ddm_case, ctx):
+    """Per-level elimination statistics add up to the whole-ddm ones, and every local dof of
+    the oracle's subdomains is a pivot exactly once."""
+    name, p, om, gm, A, gop = case
+    d, subs = ddm_case
+    st = ctx.ddm_stats(d)
+    lv = ctx.ddm_levels(d)
+    assert len(lv) == st["n_levels"]
+    assert sum(x["n_fronts"] for x in lv) == st["n_fronts"]
+    assert sum(x["sum_pivots"] for x in lv) == st["local_dofs_total"] == sum(len(s.gdofs) for s in subs)
+    assert sum(x["factor_useful"] for x in lv) == st["factor_useful"]
+    assert max(x["max_front"] for x in lv) == st["max_front"]
+    assert all(x["max_pivots"] <= x["max_front"] and x["sum_pivots"] <= x["sum_front"] for x in lv)
+
+
 def test_precond_one_level_mixed(case, ddm_case, ctx):
     """complex64 factors and sweeps (vector kernels below 8 columns, matrix-core kernels from
     8 on, 16-column groups with a ragged last group): each column within 1e-4 of the FP64
