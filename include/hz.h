@@ -61,6 +61,15 @@ typedef struct {
   size_t struct_size;  /* sizeof(hz_init_opts)                                        */
   int device;          /* HIP device ordinal                                           */
   size_t hbm_budget;   /* bytes the serving admission may use; 0 = 90% of free memory  */
+  /* Optional device allocator, both or neither (NULL = hipMalloc / hipFree).  alloc returns
+   * NULL on failure (reported as HZ_ERR_OOM).  Every call passes `stream`; memory handed to
+   * free may still be read by work already queued on that stream, so the allocator must
+   * reuse it only in that stream's order (as a stream-ordered caching allocator such as
+   * PyTorch's does for the stream it is given).  Called from the caller's thread and, while
+   * serving, from the library's scheduler thread. */
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, void* stream, void* user);
+  void* alloc_user;
   void* stream;        /* hipStream_t for all GPU work; NULL = null stream              */
 } hz_init_opts;
 

@@ -38,10 +38,15 @@ void DevBuf::alloc(Ctx* c, size_t nbytes) {
   release();
   if (nbytes == 0) nbytes = 16;
   void* q = nullptr;
-  const hipError_t e = hipMalloc(&q, nbytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    fail(HZ_ERR_OOM, "device allocation of " + std::to_string(nbytes) + " bytes failed");
+  if (c->alloc_fn) {
+    q = c->alloc_fn(nbytes, (void*)c->stream, c->alloc_user);
+    if (!q) fail(HZ_ERR_OOM, "device allocation of " + std::to_string(nbytes) + " bytes failed (caller allocator)");
+  } else {
+    const hipError_t e = hipMalloc(&q, nbytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(HZ_ERR_OOM, "device allocation of " + std::to_string(nbytes) + " bytes failed");
+    }
   }
   p = q;
   bytes = nbytes;
@@ -51,7 +56,10 @@ void DevBuf::alloc(Ctx* c, size_t nbytes) {
 
 void DevBuf::release() {
   if (p) {
-    (void)hipFree(p);
+    if (ctx && ctx->free_fn)
+      ctx->free_fn(p, (void*)ctx->stream, ctx->alloc_user);  // stream-ordered release
+    else
+      (void)hipFree(p);
     if (ctx) ctx->bytes_in_use -= (int64_t)bytes;
   }
   p = nullptr;
@@ -166,6 +174,15 @@ hz_status hz_init(hz_ctx** out, const hz_init_opts* opts) {
   if (!c) return HZ_ERR_OOM;
   c->device = opts ? opts->device : 0;
   c->stream = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+  if (opts && ((opts->alloc == nullptr) != (opts->free == nullptr))) {
+    delete c;
+    return HZ_ERR_ARG;  // an allocator needs both calls
+  }
+  if (opts) {
+    c->alloc_fn = opts->alloc;
+    c->free_fn = opts->free;
+    c->alloc_user = opts->alloc_user;
+  }
   hz_status st = guard(c, [&] {
     int ndev = 0;
     HIP_CHECK(hipGetDeviceCount(&ndev));

@@ -86,6 +86,11 @@ struct CoarseSpace {
   DevBuf w_y, w_y2, w_part;       // apply workspace (restricted vector, product, K-chunk partials)
 };
 
+// solve workspace of the preconditioner, grown on demand and kept with its ddm
+struct PrecondWork {
+  DevBuf bin, bout, wbuf, q, t;
+};
+
 // tile sizes of the complex64 matrix-core solve sweeps: forward rows per block, backward
 // pivot columns per block
 constexpr int kFwdRowsMfma = 64;
@@ -135,6 +140,7 @@ struct Ddm {
   std::vector<int64_t> fwd_off, bwd_off, fwdm_off, bwdm_off;
   DevArray<int32_t> d_fwd_work, d_bwd_work, d_fwdm_work, d_bwdm_work;  // pairs
   DevArray<int32_t> d_imap;
+  PrecondWork pw;  // solve workspace (precond_apply)
   int64_t device_bytes() const;
 };
 

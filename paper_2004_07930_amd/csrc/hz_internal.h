@@ -105,7 +105,8 @@ __host__ __device__ __forceinline__ cplx<T> cdiv(cplx<T> a, cplx<T> b) {
 
 struct Ctx;
 
-// Owning device allocation (hipMalloc / hipFree); the bytes are charged to the context.
+// Owning device allocation (the context's allocator, else hipMalloc / hipFree); the bytes
+// are charged to the context.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -193,6 +194,10 @@ struct Ctx {
   hipStream_t stream = nullptr;
   std::string last_error;
   bool poisoned = false;
+  // caller-supplied device allocator (hz_init_opts), null = hipMalloc / hipFree
+  void* (*alloc_fn)(size_t, void*, void*) = nullptr;
+  void (*free_fn)(void*, void*, void*) = nullptr;
+  void* alloc_user = nullptr;
   size_t hbm_budget = 0;
   std::atomic<int64_t> bytes_in_use{0};
   std::mutex mu;  // protects handle tables

@@ -518,26 +518,10 @@ void one_level(Ctx* ctx, Ddm& d, int s, const c128* v, const c128* add, c128* z,
 
 }  // namespace
 
-struct PrecondWork {
-  DevBuf bin, bout, wbuf, q, t;
-};
-static std::map<const Ddm*, std::unique_ptr<PrecondWork>> g_work;
-static std::mutex g_work_mu;
-
-static PrecondWork& work_for(const Ddm& d) {
-  std::lock_guard<std::mutex> lk(g_work_mu);
-  auto& w = g_work[&d];
-  if (!w) w = std::make_unique<PrecondWork>();
-  return *w;
-}
-
-void precond_release_workspace(Ddm& d) {
-  std::lock_guard<std::mutex> lk(g_work_mu);
-  g_work.erase(&d);
-}
+void precond_release_workspace(Ddm& d) { d.pw = PrecondWork(); }
 
 void precond_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c128* z) {
-  PrecondWork& w = work_for(d);
+  PrecondWork& w = d.pw;
   const int64_t n = d.op->mesh->n;
   const c128* rhs = v;
   const c128* add = nullptr;

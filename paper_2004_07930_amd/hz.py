@@ -7,7 +7,9 @@ is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 import os
 
 import numpy as np
@@ -42,8 +44,13 @@ class HzError(RuntimeError):
         self.code = code
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
 class InitOpts(C.Structure):
-    _fields_ = [("struct_size", C.c_size_t), ("device", C.c_int), ("hbm_budget", C.c_size_t), ("stream", C.c_void_p)]
+    _fields_ = [("struct_size", C.c_size_t), ("device", C.c_int), ("hbm_budget", C.c_size_t), ("alloc", ALLOC_FN),
+                ("free", FREE_FN), ("alloc_user", C.c_void_p), ("stream", C.c_void_p)]
 
 
 class CoarseMesh(C.Structure):
@@ -184,19 +191,61 @@ class Ddm:
         self.ctx, self.handle, self.op, self.n, self.precision = ctx, handle, op, op.n, precision
 
 
-class Context:
-    """One GPU; all work on `stream` (a torch.cuda.Stream, a raw hipStream_t int, or None)."""
+_live_contexts = weakref.WeakSet()
 
-    def __init__(self, device=0, stream=None, hbm_budget=0):
+
+@atexit.register
+def _close_live_contexts():
+    # release library memory while torch's allocator is still alive
+    for c in list(_live_contexts):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
+def _torch_allocator(device):
+    """(alloc, free) callbacks over torch's stream-ordered caching allocator."""
+    import torch
+
+    def _alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, int(stream or 0))
+        except Exception:  # out of memory or a bad request: the library reports HZ_ERR_OOM
+            return None
+
+    def _free(ptr, stream, user):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    return ALLOC_FN(_alloc), FREE_FN(_free)
+
+
+class Context:
+    """One GPU; all work on `stream` (a torch.cuda.Stream, a raw hipStream_t int, or None).
+    allocator="torch" routes the library's device memory through torch's caching allocator
+    on that stream; "hip" uses hipMalloc / hipFree."""
+
+    def __init__(self, device=0, stream=None, hbm_budget=0, allocator="torch"):
         self.lib = load()
-        o = InitOpts(C.sizeof(InitOpts), device, hbm_budget, None)
+        self.h = None
+        o = InitOpts()
+        o.struct_size, o.device, o.hbm_budget = C.sizeof(InitOpts), device, hbm_budget
         if stream is not None:
             o.stream = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        if allocator == "torch":
+            self._alloc_cbs = _torch_allocator(device)  # kept alive as long as the context
+            o.alloc, o.free = self._alloc_cbs
+        elif allocator != "hip":
+            raise ValueError("allocator must be 'torch' or 'hip'")
         h = C.c_void_p()
         st = self.lib.hz_init(C.byref(h), C.byref(o))
         if st != HZ_OK:
             raise HzError(st, "hz_init failed")
         self.h = h
+        _live_contexts.add(self)
 
     def close(self):
         if self.h:

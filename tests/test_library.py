@@ -37,3 +37,41 @@ def test_binding_refuses_missing_library(tmp_path):
 
     with pytest.raises(ImportError):
         hz.load(str(tmp_path / "nope.so"))
+
+
+STRUCTS = {  # header type -> binding class name
+    "hz_init_opts": "InitOpts", "hz_coarse_mesh": "CoarseMesh", "hz_col_info": "ColInfo",
+    "hz_solve_opts": "SolveOpts", "hz_ddm_stats": "DdmStats", "hz_ddm_level": "DdmLevel",
+    "hz_kernel_stat": "KernelStat", "hz_request": "Request", "hz_serve_stats": "ServeStats",
+}
+
+
+def test_binding_struct_layouts_match_header(tmp_path):
+    """Every struct the binding passes through the ABI has the header's size and field offsets
+    (a C program compiled against include/hz.h prints them)."""
+    import ctypes
+    import shutil
+    import subprocess
+
+    from paper_2004_07930_amd import hz
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hz.h"', "int main(void) {"]
+    for ctype, cls in STRUCTS.items():
+        lines.append(f'  printf("{ctype} size %zu\\n", sizeof({ctype}));')
+        for fname, _ in getattr(hz, cls)._fields_:
+            lines.append(f'  printf("{ctype} {fname} %zu\\n", offsetof({ctype}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    c_side = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for ctype, cls in STRUCTS.items():
+        k = getattr(hz, cls)
+        assert c_side[(ctype, "size")] == ctypes.sizeof(k), ctype
+        for fname, _ in k._fields_:
+            assert c_side[(ctype, fname)] == getattr(k, fname).offset, (ctype, fname)
