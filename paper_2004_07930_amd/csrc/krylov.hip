@@ -605,22 +605,25 @@ void KrylovKernels::gram(int nblk, const c128* V, int64_t ldv, const c128* W, c1
   int64_t rpc = ((n + nch - 1) / nch + 15) / 16 * 16;
   nch = (int)((n + rpc - 1) / rpc);
   HZ_REQUIRE(nch >= 1 && nch <= nchunk, HZ_ERR_STATE, "gram: chunk count exceeds the partial-sum workspace");
-  // algorithmic traffic: the Jtot basis columns and W once; 8 flops per complex multiply-add
-  ProfScope ps(ctx, HZ_K_CGS_GRAM, (double)n * (Jtot + s) * sizeof(c128), 8.0 * n * Jtot * s);
-  if (mfma) {
-    const dim3 grid((unsigned)nch, (unsigned)jtiles);
-    if (s == 16)
-      hipLaunchKernelGGL((k_gram_mfma<1, 4, 2>), grid, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc);
-    else
-      hipLaunchKernelGGL((k_gram_mfma<2, 2, 2>), grid, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc);
-  } else if (s <= 4) {
-    gram_t<4>(*this, Jtot, V, ldv, W, part, nch, rpc);
-  } else if (s <= 8) {
-    gram_t<8>(*this, Jtot, V, ldv, W, part, nch, rpc);
-  } else if (s <= 16) {
-    gram_t<16>(*this, Jtot, V, ldv, W, part, nch, rpc);
-  } else {
-    gram_t<32>(*this, Jtot, V, ldv, W, part, nch, rpc);
+  {
+    // algorithmic traffic: the Jtot basis columns and W once; 8 flops per complex multiply-add
+    // (the scope times the partial-product kernel alone, not the reduction below)
+    ProfScope ps(ctx, HZ_K_CGS_GRAM, (double)n * (Jtot + s) * sizeof(c128), 8.0 * n * Jtot * s);
+    if (mfma) {
+      const dim3 grid((unsigned)nch, (unsigned)jtiles);
+      if (s == 16)
+        hipLaunchKernelGGL((k_gram_mfma<1, 4, 2>), grid, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc);
+      else
+        hipLaunchKernelGGL((k_gram_mfma<2, 2, 2>), grid, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc);
+    } else if (s <= 4) {
+      gram_t<4>(*this, Jtot, V, ldv, W, part, nch, rpc);
+    } else if (s <= 8) {
+      gram_t<8>(*this, Jtot, V, ldv, W, part, nch, rpc);
+    } else if (s <= 16) {
+      gram_t<16>(*this, Jtot, V, ldv, W, part, nch, rpc);
+    } else {
+      gram_t<32>(*this, Jtot, V, ldv, W, part, nch, rpc);
+    }
   }
   const int64_t m = (int64_t)Jtot * s;
   hipLaunchKernelGGL(k_reduce_part, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, ctx->stream, nch, m, part, H,
