@@ -45,7 +45,7 @@ typedef enum {
   HZ_ERR_HIP = -3,            /* a HIP runtime call failed; the context is poisoned      */
   HZ_ERR_NOT_CONVERGED = -4,  /* max_iter reached; x holds the best iterate              */
   HZ_ERR_SINGULAR = -5,       /* a local or coarse factorisation met a zero pivot        */
-  HZ_ERR_BUSY = -6,           /* serving: request can never be admitted                   */
+  HZ_ERR_BUSY = -6,           /* serving: request can never be admitted                  */
   HZ_ERR_STATE = -7,          /* call not valid in the current state                      */
   HZ_ERR_ABI = -8             /* struct_size / ABI version mismatch                       */
 } hz_status;
@@ -256,6 +256,30 @@ typedef struct {
   int64_t completed, rejected;
 } hz_serve_stats;
 
+/*
+ * Serving many source right-hand sides per frequency (paper: introduction and conclusion,
+ * the multi-RHS use of the solver) as a stream of requests on resident ddms.
+ * hz_serve_start: starts the scheduler thread, which owns the context stream until
+ *   hz_serve_stop; other calls on the context return HZ_ERR_STATE meanwhile.  max_slots
+ *   >= 1 bounds the parts (blocks of at most 32 sources) running at once.
+ * hz_serve_submit: queues a request (FIFO) and returns its ticket.  Each request is solved
+ *   like hz_solve (x0 = 0, per-column relative residual req->tol, req->max_iter inner
+ *   iterations, 0 = 500) with a restart length chosen at submission: the largest up to 40
+ *   with which its first part fits in hbm_budget next to the resident objects and the
+ *   requests in flight.  Its parts are admitted in order when a slot is free and their
+ *   memory fits.  rhs / x / info (info nullable, [n_rhs]) stay caller-owned and must stay
+ *   valid until the ticket completes; req->mem says whether rhs and x are host or device.
+ *   Errors: HZ_ERR_ARG (unknown ddm, n_rhs < 1, null buffers, bad mem), HZ_ERR_ABI
+ *   (struct_size), HZ_ERR_BUSY (fits at no restart length >= 8: never admissible),
+ *   HZ_ERR_STATE (not serving, or the scheduler failed).
+ * hz_serve_poll: *done = 1 once the ticket completed.  hz_serve_wait: blocks until then,
+ *   returns the request's status in *status (nullable; HZ_OK or HZ_ERR_NOT_CONVERGED) and
+ *   retires the ticket.  Both: HZ_ERR_ARG for an unknown ticket.
+ * hz_serve_stats_get: p50 / p99 of the submit-to-completion latency of completed requests,
+ *   sources per second from the first submission to the last completion, counts.
+ * hz_serve_stop: lets every queued and running request finish, then joins the scheduler.
+ *   HZ_ERR_HIP if the scheduler met a GPU failure (the context is then poisoned).
+ */
 hz_status hz_serve_start(hz_ctx* ctx, int32_t max_slots);
 hz_status hz_serve_submit(hz_ctx* ctx, const hz_request* req, uint64_t* ticket);
 hz_status hz_serve_poll(hz_ctx* ctx, uint64_t ticket, int* done);

@@ -1,14 +1,16 @@
 // Serving: continuous batching of solve requests (hz_serve_*).
 //
-// A scheduler thread owns the context's stream while serving.  Requests wait in a FIFO
-// queue and are admitted when a slot is free and their Krylov memory fits in the HBM
-// budget next to the resident operators and factors.  Every admitted request runs as one
-// or more block-FGMRES jobs (blocks of at most 32 sources).  Each scheduler tick advances
-// every active job by one Arnoldi step: the blocks M^{-1} v of all jobs on the same
-// operator are packed column-wise into shared launches of the preconditioner and of the
-// SpMM (so the factors and the matrix are read once for all of them), then each job does
-// its own CGS2 / CholQR2 / least-squares step.  Jobs finish, free their memory and
-// complete their request independently, and new requests join at the next tick.
+// A scheduler thread owns the context's stream while serving.  A request is split into
+// parts (block-FGMRES jobs of at most 32 sources).  Requests wait in a FIFO queue; the parts
+// of the queue head are admitted one at a time when a slot is free and the part's Krylov
+// memory fits in the HBM budget next to the resident operators, factors and running parts.
+// Each request's restart length is the largest up to 40 with which one of its parts fits
+// next to the resident objects (requests that fit at no useful length are refused).  Each
+// scheduler tick advances every active job by one Arnoldi step: the blocks M^{-1} v of all
+// jobs on the same operator are packed column-wise into shared launches of the
+// preconditioner and of the SpMM (so the factors and the matrix are read once for all of
+// them), then each job does its own CGS2 / CholQR2 / least-squares step.  A finished job
+// frees its Krylov memory at once; a request completes when all its parts have.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -51,16 +53,20 @@ struct Ticket {
   double t_submit = 0, t_done = 0;
   int state = 0;  // 0 queued, 1 running, 2 done
   int32_t status = HZ_OK;
-  int64_t bytes = 0;  // admitted memory
-  DevArray<c128> Bu;  // device copy of the rhs in user layout (host requests only)
+  int m = 0;             // restart length (chosen at submission)
+  int nparts = 0;        // blocks of at most 32 sources
+  int admitted = 0;      // parts admitted by the scheduler
+  int finished = 0;      // parts done
+  int64_t held = 0;      // memory reserved for the admitted parts (and the host copies)
+  DevArray<c128> Bu;     // device copy of the rhs in user layout (host requests only)
   struct Part {
     int c0 = 0, s = 0;
     DevArray<c128> Bn, Xn;
     std::unique_ptr<FgmresJob> job;
+    std::vector<ColInfo> info;  // kept when the job (and its Krylov memory) is released
     bool done = false;
   };
-  std::vector<std::unique_ptr<Part>> parts;
-  int parts_left = 0;
+  std::vector<std::unique_ptr<Part>> parts;  // the admitted parts, in column order
 };
 
 struct Serve {
@@ -76,6 +82,7 @@ struct Serve {
   std::vector<std::shared_ptr<Ticket>> running;
   uint64_t next_id = 1;
   int active_parts = 0;
+  int64_t held = 0;  // memory reserved by all admitted requests
   // stats
   std::vector<double> lat;
   int64_t completed = 0, rejected = 0, sources = 0;
@@ -83,46 +90,41 @@ struct Serve {
   DevArray<c128> packV, packZ, packW;
 };
 
-static int64_t request_bytes(int64_t n, int64_t n_rhs, int m, bool host) {
-  int64_t b = 0;
-  for (int64_t c0 = 0; c0 < n_rhs; c0 += 32) {
-    const int s = (int)std::min<int64_t>(32, n_rhs - c0);
-    b += FgmresJob::bytes_needed(n, s, m) + 2 * n * s * (int64_t)sizeof(c128);
-  }
-  if (host) b += n * n_rhs * (int64_t)sizeof(c128);
+static constexpr int kServeRestart = 40;
+static constexpr int kMinRestart = 8;
+
+static int part_cols(const Ticket& t, int k) { return (int)std::min<int64_t>(32, t.req.n_rhs - 32 * (int64_t)k); }
+
+// device memory of part k (Krylov workspace and its node-major right-hand side and
+// solution); the first part also carries the request's host copies
+static int64_t part_bytes(const Ticket& t, int k, int m) {
+  const int64_t n = t.ddm->op->mesh->n;
+  const int s = part_cols(t, k);
+  int64_t b = FgmresJob::bytes_needed(n, s, m) + 2 * n * s * (int64_t)sizeof(c128);
+  if (k == 0 && t.req.mem == HZ_MEM_HOST) b += 2 * n * t.req.n_rhs * (int64_t)sizeof(c128);
   return b;
 }
 
-static constexpr int kServeRestart = 40;
-
-// admission + start of a request's jobs (scheduler thread, no lock held)
-static void start_ticket(Serve& S, Ticket& t) {
+// start of part k of a request (scheduler thread, no lock held)
+static void start_part(Serve& S, Ticket& t, int k) {
   Ctx* ctx = S.ctx;
   const int64_t n = t.ddm->op->mesh->n;
-  const c128* base = nullptr;
-  if (t.req.mem == HZ_MEM_HOST) {
-    t.Bu.upload(ctx, static_cast<const c128*>(t.req.rhs), t.req.n_rhs * n);
-    base = t.Bu.ptr();
-  } else {
-    base = static_cast<const c128*>(t.req.rhs);
-  }
+  if (k == 0 && t.req.mem == HZ_MEM_HOST) t.Bu.upload(ctx, static_cast<const c128*>(t.req.rhs), t.req.n_rhs * n);
+  const c128* base = t.req.mem == HZ_MEM_HOST ? t.Bu.ptr() : static_cast<const c128*>(t.req.rhs);
   SolveOptions o;
   o.tol = t.req.tol;
   o.max_iter = t.req.max_iter > 0 ? t.req.max_iter : 500;
-  o.restart = kServeRestart;
-  for (int64_t c0 = 0; c0 < t.req.n_rhs; c0 += 32) {
-    auto p = std::make_unique<Ticket::Part>();
-    p->c0 = (int)c0;
-    p->s = (int)std::min<int64_t>(32, t.req.n_rhs - c0);
-    p->Bn.alloc(ctx, n * p->s);
-    p->Xn.alloc(ctx, n * p->s);
-    KrylovKernels K(ctx, n, p->s);
-    K.to_node(base + c0 * n, p->Bn.ptr());
-    p->job = std::make_unique<FgmresJob>(ctx, t.ddm, p->s, p->Bn.ptr(), p->Xn.ptr(), o, kServeRestart);
-    p->job->start();
-    t.parts.push_back(std::move(p));
-  }
-  t.parts_left = (int)t.parts.size();
+  o.restart = t.m;
+  auto p = std::make_unique<Ticket::Part>();
+  p->c0 = 32 * k;
+  p->s = part_cols(t, k);
+  p->Bn.alloc(ctx, n * p->s);
+  p->Xn.alloc(ctx, n * p->s);
+  KrylovKernels K(ctx, n, p->s);
+  K.to_node(base + (int64_t)p->c0 * n, p->Bn.ptr());
+  p->job = std::make_unique<FgmresJob>(ctx, t.ddm, p->s, p->Bn.ptr(), p->Xn.ptr(), o, t.m);
+  p->job->start();
+  t.parts.push_back(std::move(p));
 }
 
 static void finish_ticket(Serve& S, Ticket& t) {
@@ -141,7 +143,7 @@ static void finish_ticket(Serve& S, Ticket& t) {
     KrylovKernels K(ctx, n, p->s);
     K.from_node(p->Xn.ptr(), out + (int64_t)p->c0 * n);
     for (int k = 0; k < p->s; ++k) {
-      const ColInfo& ci = p->job->info[k];
+      const ColInfo& ci = p->info[k];
       if (t.req.info) {
         hz_col_info& hi = t.req.info[p->c0 + k];
         hi.iters = ci.iters;
@@ -217,7 +219,11 @@ static void tick(Serve& S) {
     for (auto& p : t->parts)
       if (!p->done && p->job->cycle_done() && p->job->end_cycle()) {
         p->done = true;
-        --t->parts_left;
+        p->info = p->job->info;
+        p->job.reset();  // the Krylov workspace goes back at once
+        std::lock_guard<std::mutex> lk(S.mu);
+        ++t->finished;
+        --S.active_parts;
       }
 }
 
@@ -226,36 +232,41 @@ static void scheduler(Serve* S) {
   try {
     HIP_CHECK(hipSetDevice(ctx->device));
     for (;;) {
-      std::vector<std::shared_ptr<Ticket>> admit;
+      std::vector<std::pair<std::shared_ptr<Ticket>, int>> admit;  // (request, part)
       {
         std::unique_lock<std::mutex> lk(S->mu);
         S->cv.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->running.empty(); });
         if (S->stop && S->running.empty() && S->queue.empty()) break;  // stop drains every request
-        // FIFO admission by slots and memory (no overtaking, so large requests are not starved)
+        // FIFO admission of parts by slots and memory (no overtaking, so large requests are
+        // not starved); the first part of an idle server is always admitted
+        int64_t pending = 0;
         while (!S->queue.empty()) {
-          auto& t = S->queue.front();
-          const int nparts = (int)((t->req.n_rhs + 31) / 32);
-          const bool slots_ok = S->active_parts == 0 || S->active_parts + nparts <= S->max_slots;
-          const bool mem_ok = S->running.empty() || ctx->bytes_in_use + t->bytes <= (int64_t)ctx->hbm_budget;
+          auto t = S->queue.front();
+          const int64_t pb = part_bytes(*t, t->admitted, t->m);
+          const bool idle = S->active_parts == 0;
+          const bool slots_ok = idle || S->active_parts + 1 <= S->max_slots;
+          const bool mem_ok = idle || ctx->bytes_in_use + pending + pb <= (int64_t)ctx->hbm_budget;
           if (!slots_ok || !mem_ok) break;
-          S->active_parts += nparts;
-          t->state = 1;
-          admit.push_back(t);
-          S->queue.pop_front();
+          ++S->active_parts;
+          pending += pb;
+          t->held += pb;
+          S->held += pb;
+          if (t->admitted == 0) {
+            t->state = 1;
+            S->running.push_back(t);
+          }
+          admit.emplace_back(t, t->admitted++);
+          if (t->admitted == t->nparts) S->queue.pop_front();
         }
       }
-      for (auto& t : admit) {
-        start_ticket(*S, *t);
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->running.push_back(t);
-      }
+      for (auto& [t, k] : admit) start_part(*S, *t, k);
       if (!S->running.empty()) tick(*S);
       // complete finished requests
       std::vector<std::shared_ptr<Ticket>> fin;
       {
         std::lock_guard<std::mutex> lk(S->mu);
         for (auto it = S->running.begin(); it != S->running.end();) {
-          if ((*it)->parts_left == 0) {
+          if ((*it)->finished == (*it)->nparts) {
             fin.push_back(*it);
             it = S->running.erase(it);
           } else {
@@ -268,7 +279,8 @@ static void scheduler(Serve* S) {
         std::lock_guard<std::mutex> lk(S->mu);
         t->t_done = now_s();
         t->state = 2;
-        S->active_parts -= (int)((t->req.n_rhs + 31) / 32);
+        S->held -= t->held;
+        t->held = 0;
         S->lat.push_back(t->t_done - t->t_submit);
         S->completed += 1;
         S->sources += t->req.n_rhs;
@@ -333,14 +345,19 @@ hz_status hz_serve_submit(hz_ctx* c, const hz_request* req, uint64_t* ticket) {
   t->req = *req;
   t->ddm = d;
   t->t_submit = now_s();
-  t->bytes = request_bytes(d->op->mesh->n, req->n_rhs, kServeRestart, req->mem == HZ_MEM_HOST);
+  t->nparts = (int)((req->n_rhs + 31) / 32);
   std::lock_guard<std::mutex> lk(S->mu);
   if (S->failed) return HZ_ERR_STATE;
-  // never admissible: more than the whole budget left after the resident objects
-  int64_t running_bytes = 0;
-  for (auto& r : S->running) running_bytes += r->bytes;
-  if (x->bytes_in_use - running_bytes + t->bytes > (int64_t)x->hbm_budget ||
-      (req->n_rhs + 31) / 32 > S->max_slots) {
+  // restart length: the largest (up to 40) with which the first part fits in the budget
+  // left after the resident objects; never admissible below kMinRestart
+  const int64_t avail = (int64_t)x->hbm_budget - (x->bytes_in_use - S->held);
+  t->m = 0;
+  for (int m = kServeRestart; m >= kMinRestart; --m)
+    if (part_bytes(*t, 0, m) <= avail) {
+      t->m = m;
+      break;
+    }
+  if (t->m == 0) {
     S->rejected += 1;
     return HZ_ERR_BUSY;
   }

@@ -91,3 +91,30 @@ def test_serve_admission_refuses_impossible_request():
     finally:
         ctx.serve_stop()
     ctx.close()
+
+
+def test_serve_parts_admitted_one_at_a_time(setup):
+    """A 40-source request on a one-slot server runs as two parts, one after the other (the
+    second admitted when the first has finished and released its Krylov memory); a request
+    behind it waits its turn.  Results match hz_solve, which splits the same blocks of 32."""
+    ctx, ops = setup
+    p, d, F = ops[0]
+    rng = np.random.default_rng(9)
+    noise = rng.standard_normal((40, F.shape[1])) + 1j * rng.standard_normal((40, F.shape[1]))
+    B1 = F[rng.integers(0, F.shape[0], 40)] + 0.1 * noise  # full column rank
+    B2 = F[:3]
+    alone1 = ctx.solve(d, B1, tol=1e-6)[0]
+    alone2 = ctx.solve(d, B2, tol=1e-6)[0]
+    ctx.serve_start(max_slots=1)
+    try:
+        t1 = ctx.submit(d, B1, tol=1e-6)
+        t2 = ctx.submit(d, B2, tol=1e-6)
+        x1, info1, s1 = ctx.wait(t1)
+        x2, info2, s2 = ctx.wait(t2)
+        st = ctx.serve_stats()
+    finally:
+        ctx.serve_stop()
+    assert s1 == 0 and s2 == 0
+    assert all(i["rel_residual"] <= 1e-6 for i in info1 + info2)
+    assert _rel(x1, alone1) <= 1e-5 and _rel(x2, alone2) <= 1e-5
+    assert st["completed"] == 2 and st["rejected"] == 0
