@@ -273,8 +273,10 @@ typedef struct {
  *   (struct_size), HZ_ERR_BUSY (fits at no restart length >= 8: never admissible),
  *   HZ_ERR_STATE (not serving, or the scheduler failed).
  * hz_serve_poll: *done = 1 once the ticket completed.  hz_serve_wait: blocks until then,
- *   returns the request's status in *status (nullable; HZ_OK or HZ_ERR_NOT_CONVERGED) and
- *   retires the ticket.  Both: HZ_ERR_ARG for an unknown ticket.
+ *   returns the request's status in *status (nullable; HZ_OK, HZ_ERR_NOT_CONVERGED, or
+ *   HZ_ERR_OOM when the allocator could not give one part its memory even with nothing else
+ *   running; x is then undefined) and retires the ticket.  A part whose allocation fails
+ *   while others run waits for their memory.  Both: HZ_ERR_ARG for an unknown ticket.
  * hz_serve_stats_get: p50 / p99 of the submit-to-completion latency of completed requests,
  *   sources per second from the first submission to the last completion, counts.
  * hz_serve_stop: lets every queued and running request finish, then joins the scheduler.

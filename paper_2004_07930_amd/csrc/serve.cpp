@@ -58,6 +58,7 @@ struct Ticket {
   int admitted = 0;      // parts admitted by the scheduler
   int finished = 0;      // parts done
   int64_t held = 0;      // memory reserved for the admitted parts (and the host copies)
+  bool oom = false;      // a part could not be allocated even with nothing else running
   DevArray<c128> Bu;     // device copy of the rhs in user layout (host requests only)
   struct Part {
     int c0 = 0, s = 0;
@@ -251,7 +252,7 @@ static void scheduler(Serve* S) {
           pending += pb;
           t->held += pb;
           S->held += pb;
-          if (t->admitted == 0) {
+          if (t->state == 0) {  // first admission (a rolled-back request stays in running)
             t->state = 1;
             S->running.push_back(t);
           }
@@ -259,7 +260,56 @@ static void scheduler(Serve* S) {
           if (t->admitted == t->nparts) S->queue.pop_front();
         }
       }
-      for (auto& [t, k] : admit) start_part(*S, *t, k);
+      // start the admitted parts; a part whose memory the allocator cannot give now goes
+      // back to the head of the queue (it is retried when running parts have freed theirs),
+      // or fails its request when nothing else is running
+      for (size_t a = 0; a < admit.size(); ++a) {
+        auto& [t, k] = admit[a];
+        try {
+          start_part(*S, *t, k);
+        } catch (const Error& e) {
+          if (e.code != HZ_ERR_OOM) throw;
+          std::lock_guard<std::mutex> lk(S->mu);
+          // undo this and every later admission of this round, latest first (FIFO order)
+          for (size_t b = admit.size(); b-- > a;) {
+            auto& [tb, kb] = admit[b];
+            const int64_t pb = part_bytes(*tb, kb, tb->m);
+            tb->held -= pb;
+            S->held -= pb;
+            --S->active_parts;
+            --tb->admitted;
+            if (S->queue.empty() || S->queue.front() != tb) S->queue.push_front(tb);
+          }
+          if (S->active_parts == 0) {  // the part cannot fit even alone: the request fails
+            t->status = HZ_ERR_OOM;
+            t->oom = true;
+          }
+          break;
+        }
+      }
+      // requests that failed to fit even alone: retire them (their started parts are dropped)
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (auto it = S->queue.begin(); it != S->queue.end();) {
+          if ((*it)->oom) {
+            auto t = *it;
+            it = S->queue.erase(it);
+            S->running.erase(std::remove(S->running.begin(), S->running.end(), t), S->running.end());
+            for (auto& p : t->parts)
+              if (!p->done) --S->active_parts;
+            t->parts.clear();
+            t->Bu = DevArray<c128>();
+            S->held -= t->held;
+            t->held = 0;
+            t->t_done = now_s();
+            t->state = 2;
+            S->rejected += 1;
+            S->done_cv.notify_all();
+          } else {
+            ++it;
+          }
+        }
+      }
       if (!S->running.empty()) tick(*S);
       // complete finished requests
       std::vector<std::shared_ptr<Ticket>> fin;
