@@ -221,9 +221,16 @@ __device__ __forceinline__ void mfma_3m(c64 a, c64 b, f32x4& p1, f32x4& p2, f32x
 // chunk in registers (loads from a clamped, always valid index, so they issue back to back)
 // while the current chunk is multiplied out of LDS; the bounds predicate is applied when the
 // registers are written to LDS, so the loads stay in flight across the products.
-template <int NG, int MT, int JC>
+// ASSEMBLED: w was formed by k_fwd_assemble (its pivot rows are read, its update rows
+// updated in place).  Otherwise w = [b_p; 0] + the children's update contributions is never
+// stored: the pivot rows are summed as they are staged and the update rows in the epilogue,
+// in the order of k_fwd_assemble (own, child 0, child 1), so the result is the same.  That
+// form saves the assembly pass where fronts have no children (the leaves); above them the
+// gathers through the child maps cost more than the pass.
+template <int NG, int MT, int JC, bool ASSEMBLED>
 __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
-                                                  const c64* __restrict__ L, c64* __restrict__ wbuf,
+                                                  const c64* __restrict__ L, const int32_t* __restrict__ imap,
+                                                  const c64* __restrict__ bin, c64* __restrict__ wbuf,
                                                   c64* __restrict__ bout, int s) {
   constexpr int RT = 64 * MT, SC = 16 * NG;
   constexpr int NF = JC * RT / 256, NW = JC * SC / 256;
@@ -238,9 +245,23 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
   const int wv = tid >> 6, l = tid & 63;
   const int lr = l & 15, lq = l >> 4;
   const c64* Lf = L + F.L_off;
-  const c64* wp = wbuf + F.w_off * s;
+  const c64* wp = wbuf + F.w_off * s;              // the assembled work block
+  const c64* bp = bin + (F.vec_off + F.pos0) * s;  // pivot rows of the right-hand side
+  const int32_t* m0 = imap + F.imap_off;           // parent row -> child row (or -1), per child
+  const int32_t* m1 = m0 + f;
+  const c64* w0 = nullptr;  // the children's update rows (only children that have some)
+  const c64* w1 = nullptr;
+  if (!ASSEMBLED && F.child0 >= 0) {
+    const FrontDesc C = fr[F.child0];
+    if (C.r > 0) w0 = wbuf + (C.w_off + C.p) * s;
+  }
+  if (!ASSEMBLED && F.child1 >= 0) {
+    const FrontDesc C = fr[F.child1];
+    if (C.r > 0) w1 = wbuf + (C.w_off + C.p) * s;
+  }
   const c64 zero = cmk(0.f, 0.f);
-  c64 rf[NF], rw[NW];
+  c64 rf[NF], rb[NW], r0[NW], r1[NW];
+  int32_t q0[NW], q1[NW];
   auto fetch = [&](int64_t j) {
     const int jn = (int)min<int64_t>(JC, jend - j);
 #pragma unroll
@@ -251,7 +272,17 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
 #pragma unroll
     for (int u = 0; u < NW; ++u) {
       const int e = tid + 256 * u, jj = e / SC, c = e - (e / SC) * SC;
-      rw[u] = wp[(jj < jn && c < s) ? (j + jj) * s + c : 0];
+      const bool ok = jj < jn && c < s;
+      const int64_t row = ok ? j + jj : 0, cc = ok ? c : 0;
+      rb[u] = ASSEMBLED ? wp[row * s + cc] : bp[row * s + cc];
+      if (w0) {  // block-uniform tests
+        q0[u] = m0[row];
+        r0[u] = w0[(int64_t)max(q0[u], 0) * s + cc];
+      }
+      if (w1) {
+        q1[u] = m1[row];
+        r1[u] = w1[(int64_t)max(q1[u], 0) * s + cc];
+      }
     }
   };
   f32x4 p1[MT][NG], p2[MT][NG], p3[MT][NG];
@@ -271,7 +302,10 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
 #pragma unroll
     for (int u = 0; u < NW; ++u) {
       const int e = tid + 256 * u, jj = e / SC, c = e - (e / SC) * SC;
-      Wt[jj][c] = csel(jj < jn && c < s, rw[u], zero);
+      c64 v = rb[u];
+      if (w0) v = v + csel(q0[u] >= 0, r0[u], zero);
+      if (w1) v = v + csel(q1[u] >= 0, r1[u], zero);
+      Wt[jj][c] = csel(jj < jn && c < s, v, zero);
     }
     __syncthreads();
     if (j + JC < jend) fetch(j + JC);
@@ -305,9 +339,20 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
         const c64 val = cmk(p1[m][g][v] - p2[m][g][v], p3[m][g][v] - p1[m][g][v] - p2[m][g][v]);
         if (i < F.p) {
           bout[(F.vec_off + F.pos0 + i) * s + c] = val;
-        } else {
+        } else if (ASSEMBLED) {
           c64* w = &wbuf[(F.w_off + i) * s + c];
           *w = *w - val;
+        } else {  // update row: (0 + child 0 + child 1) - F_bot w_p
+          c64 wr = zero;
+          if (w0) {
+            const int32_t q = m0[i];
+            if (q >= 0) wr = wr + w0[(int64_t)q * s + c];
+          }
+          if (w1) {
+            const int32_t q = m1[i];
+            if (q >= 0) wr = wr + w1[(int64_t)q * s + c];
+          }
+          wbuf[(F.w_off + i) * s + c] = wr - val;
         }
       }
     }
@@ -438,22 +483,31 @@ void sweep(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) 
   hipStream_t st = ctx->stream;
   const cplx<T>* L = d.d_factor.as<cplx<T>>();
   for (size_t lv = 0; lv < d.levels.size(); ++lv) {
-    const int nf = (int)d.levels[lv].fronts.size();
-    const int64_t tot = d.levels[lv].max_f * s;
-    const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 64));
-    hipLaunchKernelGGL((k_fwd_assemble<T>), dim3(nf, gy), dim3(256), 0, st, d.d_level_fronts.ptr() + d.level_off[lv],
-                       d.d_fronts.ptr(), d.d_imap.ptr(), bin, wbuf, s);
+    // the matrix-core kernel forms w itself on levels without children
+    const bool kids = lv > 0;
+    if (!use_mfma<T, S>() || kids) {
+      const int nf = (int)d.levels[lv].fronts.size();
+      const int64_t tot = d.levels[lv].max_f * s;
+      const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 64));
+      hipLaunchKernelGGL((k_fwd_assemble<T>), dim3(nf, gy), dim3(256), 0, st,
+                         d.d_level_fronts.ptr() + d.level_off[lv], d.d_fronts.ptr(), d.d_imap.ptr(), bin, wbuf, s);
+    }
     const int64_t nw = d.fwd_off[lv + 1] - d.fwd_off[lv];
     const Level& Lv = d.levels[lv];
     // algorithmic traffic: the level's stored factor once, its work rows read and written once
     const double esz = (double)sizeof(cplx<T>);
     ProfScope ps(ctx, HZ_K_ORAS_FWD, esz * ((double)Lv.useful + 2.0 * (double)Lv.sum_f * s),
                  8.0 * (double)Lv.useful * s);
-    if constexpr (use_mfma<T, S>())
-      hipLaunchKernelGGL((k_fwd_mfma<(S + 15) / 16, kFwdRowsMfma / 64, 32>),
-                         dim3((unsigned)(d.fwdm_off[lv + 1] - d.fwdm_off[lv])), dim3(256), 0, st,
-                         d.d_fwdm_work.ptr() + 2 * d.fwdm_off[lv], d.d_fronts.ptr(), L, wbuf, bout, s);
-    else
+    if constexpr (use_mfma<T, S>()) {
+      const dim3 grid((unsigned)(d.fwdm_off[lv + 1] - d.fwdm_off[lv]));
+      const int32_t* wl = d.d_fwdm_work.ptr() + 2 * d.fwdm_off[lv];
+      if (kids)
+        hipLaunchKernelGGL((k_fwd_mfma<(S + 15) / 16, kFwdRowsMfma / 64, 32, true>), grid, dim3(256), 0, st, wl,
+                           d.d_fronts.ptr(), L, d.d_imap.ptr(), bin, wbuf, bout, s);
+      else
+        hipLaunchKernelGGL((k_fwd_mfma<(S + 15) / 16, kFwdRowsMfma / 64, 32, false>), grid, dim3(256), 0, st, wl,
+                           d.d_fronts.ptr(), L, d.d_imap.ptr(), bin, wbuf, bout, s);
+    } else
       hipLaunchKernelGGL((k_fwd_gemm<T, S>), dim3((unsigned)nw), dim3(256), 0, st,
                          d.d_fwd_work.ptr() + 2 * d.fwd_off[lv], d.d_fronts.ptr(), L, wbuf, bout, s);
   }
