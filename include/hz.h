@@ -157,7 +157,9 @@ typedef struct {
  * the stopping test ||A u - b|| / ||b|| <= eps of the FE section.  Classical Gram-Schmidt
  * applied twice, CholQR2 block normalisation, Householder least squares, all FP64.
  *   rhs [n_rhs][n_dofs] complex128, x same layout (may not alias rhs)
- * Returns HZ_ERR_NOT_CONVERGED (x = best iterate, info filled) when max_iter is hit.
+ * Returns HZ_ERR_NOT_CONVERGED (x = best iterate, info filled) when max_iter is hit;
+ * HZ_ERR_ARG for a non-finite entry in rhs, a negative or non-finite tol, n_rhs < 1 or null
+ * x / info (x is then not written).
  */
 hz_status hz_solve(hz_ctx* ctx, hz_handle ddm, int64_t n_rhs, const void* rhs, int rhs_mem,
                    double tol, int32_t max_iter, void* x, int x_mem, hz_col_info* info);

@@ -324,6 +324,7 @@ hz_status hz_solve_ex(hz_ctx* c, hz_handle ddm, int64_t n_rhs, const void* rhs, 
     const int64_t n = d->op->mesh->n;
     Staged B;
     stage_in(c, rhs, rhs_mem, n_rhs * n, B);
+    HZ_REQUIRE(count_nonfinite(c, B.ptr, n_rhs * n) == 0, HZ_ERR_ARG, "hz_solve: non-finite right-hand side");
     DevArray<c128> Xd;
     Xd.alloc(c, n_rhs * n);
     const int blk = std::min<int64_t>(n_rhs, opts->block > 0 ? std::min(opts->block, 32) : 32);

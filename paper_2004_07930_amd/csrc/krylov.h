@@ -27,6 +27,9 @@ struct KrylovKernels {
   void colnorms(const c128* X, double* part, double* out);
 };
 
+// number of entries of a complex128 array with a non-finite real or imaginary part
+int64_t count_nonfinite(Ctx* ctx, const c128* x, int64_t m);
+
 struct SolveOptions {
   double tol = 1e-6;
   int max_iter = 500;

@@ -424,6 +424,22 @@ __global__ __launch_bounds__(256) void k_chol_small(int s, const c128* __restric
   }
 }
 
+// per-block counts of non-finite entries, summed in integers (exact, order-free)
+__global__ __launch_bounds__(256) void k_count_nonfinite(const c128* __restrict__ x, int64_t m,
+                                                         unsigned long long* __restrict__ count) {
+  __shared__ unsigned int red[256];
+  unsigned int c = 0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
+    c += (isfinite(x[k].re) && isfinite(x[k].im)) ? 0u : 1u;
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0]) atomicAdd(count, (unsigned long long)red[0]);
+}
+
 __global__ void k_set_identity(int s, c128* M) {
   for (int i = threadIdx.x; i < s * s; i += blockDim.x) M[i] = cmk((i / s) == (i % s) ? 1.0 : 0.0, 0.0);
 }
@@ -675,6 +691,20 @@ void KrylovKernels::cholqr_pass(const c128* W, c128* out, c128* part, c128* G, c
     hipLaunchKernelGGL(k_right_mult, dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, ctx->stream, n, s, W, Rinv,
                        out);
   HIP_CHECK(hipGetLastError());
+}
+
+int64_t count_nonfinite(Ctx* ctx, const c128* x, int64_t m) {
+  if (m <= 0) return 0;
+  DevArray<unsigned long long> cnt;
+  cnt.alloc(ctx, 1);
+  cnt.zero(ctx);
+  const unsigned grid = (unsigned)std::min<int64_t>(2048, (m + 255) / 256);
+  hipLaunchKernelGGL(k_count_nonfinite, dim3(grid), dim3(256), 0, ctx->stream, x, m, cnt.ptr());
+  HIP_CHECK(hipGetLastError());
+  unsigned long long h = 0;
+  HIP_CHECK(hipMemcpyAsync(&h, cnt.ptr(), sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  return (int64_t)h;
 }
 
 void KrylovKernels::identity(c128* M) {

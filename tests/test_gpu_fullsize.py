@@ -5,7 +5,8 @@ bench.py times (mixed precision, tol 1e-6).
 The oracle handles this size for everything but the preconditioner: the dof map and the CSR
 pattern must match bit for bit, the values and the point sources to 1e-13 / 1e-12, and the
 explicit residual of every column of the GPU solution, recomputed with the oracle's operator,
-must meet the tolerance and agree with the residual the library reports."""
+must meet the tolerance and agree with the residual the library reports; the mixed-precision
+solution is within 1e-5 of the FP64 solve at the same residual."""
 import time
 
 import numpy as np
@@ -35,6 +36,11 @@ def test_benchmark_workload_full_size():
                           precision=hz.HZ_PREC_MIXED)
         F = ctx.point_sources(gm, p.sources)
         X, info = ctx.solve(d, F, tol=1e-6, max_iter=500)
+        ctx.release(d)
+        d64 = ctx.setup_ddm(gop, p.partition, p.n_sub, p.overlap, coarse=(p.coarse_tets, p.coarse_coords),
+                            precision=hz.HZ_PREC_C128)
+        X64, info64 = ctx.solve(d64, F, tol=1e-6, max_iter=500)
+        ctx.release(d64)
         rp, ci, va = ctx.csr(gop)
         tet_dofs = ctx.dofmap(gm)
         _log(f"GPU side done: n={gm.n}, {info[0]['iters']} iterations", t0)
@@ -59,3 +65,7 @@ def test_benchmark_workload_full_size():
     _log(f"explicit residuals {res.min():.3e}..{res.max():.3e}; reported {rep.min():.3e}..{rep.max():.3e}", t0)
     assert res.max() <= 1e-6 * (1 + 1e-6)
     np.testing.assert_allclose(res, rep, rtol=1e-6, atol=1e-12)
+    # the mixed-precision solution against the FP64 solve at the same 1e-6 residual
+    err = np.linalg.norm(X - X64) / np.linalg.norm(X64)
+    _log(f"mixed vs FP64 solution: {err:.3e} ({info[0]['iters']} vs {info64[0]['iters']} iterations)", t0)
+    assert err <= 1e-5

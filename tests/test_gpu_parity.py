@@ -287,5 +287,41 @@ def test_mixed_precision_reaches_tolerance(ctx):
     assert abs(i32[0]["iters"] - i64[0]["iters"]) <= 1
     Xo = krylov.dense_solve(A, F.T).T
     err = _rel(X32, Xo)
-    print(f"mixed vs exact: {err:.3e}; fp64 vs exact: {_rel(X64, Xo):.3e}")
+    # the FP64 oracle's own FGMRES at the same 1e-6 residual
+    P = odd.build_preconditioner(om, A, p.velocity, p.freq, None, p.partition, p.n_sub, p.overlap,
+                                 p.coarse_tets, p.coarse_coords)
+    Xf, io = krylov.block_fgmres(lambda x: A @ x, F.T, P.apply, tol=1e-6, m=40)
+    err_f = _rel(X32, Xf.T)
+    print(f"mixed vs exact: {err:.3e}; fp64 vs exact: {_rel(X64, Xo):.3e}; mixed vs FP64 oracle FGMRES "
+          f"at 1e-6: {err_f:.3e}; FP64 GPU vs FP64 oracle FGMRES: {_rel(X64, Xf.T):.3e}")
     assert err <= 1e-4
+    assert err_f <= 1e-5  # mixed vs FP64 at the same 1e-6 residual
+
+
+def test_solve_failure_paths(ctx):
+    """Non-finite right-hand side -> HZ_ERR_ARG; max_iter reached -> HZ_ERR_NOT_CONVERGED with
+    the best iterate and its residual returned (the residual is that of the returned x)."""
+    from paper_2004_07930_amd import hz
+
+    p = w.unit_cube_problem(3, freq=1.5, parts=(2, 2, 1), overlap=1)
+    om = fem.Mesh(p.tets, p.coords, p.face_bc)
+    A = fem.assemble_operator(om, p.velocity, p.freq)
+    gm = ctx.mesh(p.tets, p.coords, p.face_bc)
+    gop = ctx.assemble(gm, p.velocity, p.freq)
+    d = ctx.setup_ddm(gop, p.partition, p.n_sub, p.overlap)
+    rng = np.random.default_rng(21)
+    B = rng.standard_normal((2, om.n)) + 1j * rng.standard_normal((2, om.n))  # full column rank
+    keep = B[1, 5]
+    B[1, 5] = np.nan
+    with pytest.raises(hz.HzError) as e:
+        ctx.solve(d, B)
+    assert e.value.code == hz.HZ_ERR_ARG
+    B[1, 5] = keep
+    with pytest.raises(hz.HzError) as e:
+        ctx.solve(d, B, tol=1e-14, max_iter=1)
+    assert e.value.code == hz.HZ_ERR_NOT_CONVERGED
+    X, info = ctx.solve(d, B, tol=1e-14, max_iter=1, raise_on_not_converged=False)
+    assert all(i["status"] == hz.HZ_ERR_NOT_CONVERGED and i["iters"] == 1 for i in info)
+    res = np.linalg.norm(B.T - A @ X.T, axis=0) / np.linalg.norm(B, axis=1)
+    np.testing.assert_allclose(res, [i["rel_residual"] for i in info], rtol=1e-8)
+    assert res.max() < 1.0  # one preconditioned step already reduces the residual
