@@ -214,6 +214,8 @@ typedef struct {
   int64_t sum_pivots;     /* sum of p */
   int64_t sum_front;      /* sum of f */
   int64_t factor_useful;  /* stored factor nonzeros: sum of p(p+1)/2 + r p */
+  int32_t fwd_tile_rows;  /* complex64 blocks of up to 16 columns: forward tile rows and */
+  int32_t bwd_tile_cols;  /* backward tile columns picked by timing (0 until the first apply) */
 } hz_ddm_level;
 hz_status hz_ddm_levels(hz_ctx* ctx, hz_handle ddm, hz_ddm_level* out, int32_t max_levels, int32_t* n_levels);
 

@@ -464,6 +464,9 @@ hz_status hz_ddm_levels(hz_ctx* c, hz_handle ddm, hz_ddm_level* out, int32_t max
       out[i].sum_pivots = lv.sum_p;
       out[i].sum_front = lv.sum_f;
       out[i].factor_useful = lv.useful;
+      const bool tuned = d->tile_fwd[0].size() == (size_t)L;
+      out[i].fwd_tile_rows = tuned ? kFwdRowsMfma[d->tile_fwd[0][i]] : 0;
+      out[i].bwd_tile_cols = tuned ? kBwdColsMfma[d->tile_bwd[0][i]] : 0;
     }
     *n_levels = L;
   });

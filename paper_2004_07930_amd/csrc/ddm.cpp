@@ -344,7 +344,8 @@ int64_t Ddm::device_bytes() const {
        d_orig_dst.bytes() + d_own_src.bytes() + d_lrowptr.bytes() + d_lgptr.bytes() + d_lcol.bytes() +
        d_lgsrc.bytes() + d_ldir.bytes() + d_lval.bytes() + d_level_fronts.bytes();
   b += d_factor.bytes + d_update.bytes + d_dinv.bytes;
-  b += d_fwd_work.bytes() + d_bwd_work.bytes() + d_fwdm_work.bytes() + d_bwdm_work.bytes() + d_imap.bytes();
+  b += d_fwd_work.bytes() + d_bwd_work.bytes() + d_imap.bytes();
+  for (int t = 0; t < 2; ++t) b += d_fwdm_work[t].bytes() + d_bwdm_work[t].bytes();
   if (coarse)
     b += coarse->d_zptr.bytes() + coarse->d_ztptr.bytes() + coarse->d_azptr.bytes() + coarse->d_zcol.bytes() +
          coarse->d_ztcol.bytes() + coarse->d_azcol.bytes() + coarse->d_zval.bytes() + coarse->d_ztval.bytes() +
@@ -634,7 +635,8 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     };
     build(64, 32, d->fwd_off, d->bwd_off, d->d_fwd_work, d->d_bwd_work);
     if (precision == HZ_PREC_MIXED)
-      build(kFwdRowsMfma, kBwdColsMfma, d->fwdm_off, d->bwdm_off, d->d_fwdm_work, d->d_bwdm_work);
+      for (int t = 0; t < 2; ++t)
+        build(kFwdRowsMfma[t], kBwdColsMfma[t], d->fwdm_off[t], d->bwdm_off[t], d->d_fwdm_work[t], d->d_bwdm_work[t]);
   }
   {
     std::vector<int64_t> rp, gp;

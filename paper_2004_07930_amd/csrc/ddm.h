@@ -91,10 +91,10 @@ struct PrecondWork {
   DevBuf bin, bout, wbuf, q, t;
 };
 
-// tile sizes of the complex64 matrix-core solve sweeps: forward rows per block, backward
-// pivot columns per block
-constexpr int kFwdRowsMfma = 64;
-constexpr int kBwdColsMfma = 64;
+// tile sizes the complex64 matrix-core solve sweeps choose from (per tree level): forward
+// rows per block, backward pivot columns per block
+constexpr int kFwdRowsMfma[2] = {64, 128};
+constexpr int kBwdColsMfma[2] = {64, 128};
 
 struct Ddm {
   std::shared_ptr<Operator> op;
@@ -136,9 +136,13 @@ struct Ddm {
   int64_t w_total = 0;            // solve workspace rows (sum of f over fronts)
   int64_t factor_useful = 0;      // stored nonzeros: sum p(p+1)/2 + r p
   // solve worklists per level: forward (front, 64-row tile start), backward (front, 32-column
-  // start); the matrix-core sweeps use their own, wider tiles (kFwdRowsMfma, kBwdColsMfma)
-  std::vector<int64_t> fwd_off, bwd_off, fwdm_off, bwdm_off;
-  DevArray<int32_t> d_fwd_work, d_bwd_work, d_fwdm_work, d_bwdm_work;  // pairs
+  // start); the matrix-core sweeps have their own for each tile size they can pick
+  // (kFwdRowsMfma[t] rows, kBwdColsMfma[t] columns)
+  std::vector<int64_t> fwd_off, bwd_off, fwdm_off[2], bwdm_off[2];
+  DevArray<int32_t> d_fwd_work, d_bwd_work, d_fwdm_work[2], d_bwdm_work[2];  // pairs
+  // tile choice per level of the matrix-core sweeps, picked by timing on the first apply
+  // (index 0: blocks of up to 16 columns, 1: up to 32); empty until tuned
+  std::vector<uint8_t> tile_fwd[2], tile_bwd[2];
   DevArray<int32_t> d_imap;
   PrecondWork pw;  // solve workspace (precond_apply)
   int64_t device_bytes() const;

@@ -478,56 +478,140 @@ constexpr bool use_mfma() {
   return std::is_same<T, float>::value && S >= 8;
 }
 
+template <typename T>
+void fwd_assemble(Ctx* ctx, Ddm& d, size_t lv, int s, const cplx<T>* bin, cplx<T>* wbuf) {
+  const int nf = (int)d.levels[lv].fronts.size();
+  const int64_t tot = d.levels[lv].max_f * s;
+  const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 64));
+  hipLaunchKernelGGL((k_fwd_assemble<T>), dim3(nf, gy), dim3(256), 0, ctx->stream,
+                     d.d_level_fronts.ptr() + d.level_off[lv], d.d_fronts.ptr(), d.d_imap.ptr(), bin, wbuf, s);
+}
+
+// Vector-unit sweeps (complex128, and complex64 blocks narrower than 8 columns).
 template <typename T, int S>
-void sweep(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) {
+void sweep_valu(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) {
   hipStream_t st = ctx->stream;
   const cplx<T>* L = d.d_factor.as<cplx<T>>();
+  const double esz = (double)sizeof(cplx<T>);
   for (size_t lv = 0; lv < d.levels.size(); ++lv) {
-    // the matrix-core kernel forms w itself on levels without children
-    const bool kids = lv > 0;
-    if (!use_mfma<T, S>() || kids) {
-      const int nf = (int)d.levels[lv].fronts.size();
-      const int64_t tot = d.levels[lv].max_f * s;
-      const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 64));
-      hipLaunchKernelGGL((k_fwd_assemble<T>), dim3(nf, gy), dim3(256), 0, st,
-                         d.d_level_fronts.ptr() + d.level_off[lv], d.d_fronts.ptr(), d.d_imap.ptr(), bin, wbuf, s);
-    }
-    const int64_t nw = d.fwd_off[lv + 1] - d.fwd_off[lv];
+    fwd_assemble<T>(ctx, d, lv, s, bin, wbuf);
     const Level& Lv = d.levels[lv];
     // algorithmic traffic: the level's stored factor once, its work rows read and written once
-    const double esz = (double)sizeof(cplx<T>);
     ProfScope ps(ctx, HZ_K_ORAS_FWD, esz * ((double)Lv.useful + 2.0 * (double)Lv.sum_f * s),
                  8.0 * (double)Lv.useful * s);
-    if constexpr (use_mfma<T, S>()) {
-      const dim3 grid((unsigned)(d.fwdm_off[lv + 1] - d.fwdm_off[lv]));
-      const int32_t* wl = d.d_fwdm_work.ptr() + 2 * d.fwdm_off[lv];
-      if (kids)
-        hipLaunchKernelGGL((k_fwd_mfma<(S + 15) / 16, kFwdRowsMfma / 64, 32, true>), grid, dim3(256), 0, st, wl,
-                           d.d_fronts.ptr(), L, d.d_imap.ptr(), bin, wbuf, bout, s);
-      else
-        hipLaunchKernelGGL((k_fwd_mfma<(S + 15) / 16, kFwdRowsMfma / 64, 32, false>), grid, dim3(256), 0, st, wl,
-                           d.d_fronts.ptr(), L, d.d_imap.ptr(), bin, wbuf, bout, s);
-    } else
-      hipLaunchKernelGGL((k_fwd_gemm<T, S>), dim3((unsigned)nw), dim3(256), 0, st,
-                         d.d_fwd_work.ptr() + 2 * d.fwd_off[lv], d.d_fronts.ptr(), L, wbuf, bout, s);
+    hipLaunchKernelGGL((k_fwd_gemm<T, S>), dim3((unsigned)(d.fwd_off[lv + 1] - d.fwd_off[lv])), dim3(256), 0, st,
+                       d.d_fwd_work.ptr() + 2 * d.fwd_off[lv], d.d_fronts.ptr(), L, wbuf, bout, s);
   }
   for (size_t lv = d.levels.size(); lv-- > 0;) {
-    const int64_t nw = d.bwd_off[lv + 1] - d.bwd_off[lv];
     const Level& Lv = d.levels[lv];
-    const double esz = (double)sizeof(cplx<T>);
     ProfScope ps(ctx, HZ_K_ORAS_BWD, esz * ((double)Lv.useful + (double)(Lv.sum_f + Lv.sum_p) * s),
                  8.0 * (double)Lv.useful * s);
-    if constexpr (use_mfma<T, S>())
-      hipLaunchKernelGGL((k_bwd_mfma<(S + 15) / 16, kBwdColsMfma / 64, 32>),
-                         dim3((unsigned)(d.bwdm_off[lv + 1] - d.bwdm_off[lv])), dim3(256), 0, st,
-                         d.d_bwdm_work.ptr() + 2 * d.bwdm_off[lv], d.d_fronts.ptr(), L, d.d_urows.ptr(),
-                         d.d_dinv.as<cplx<T>>(), bout, bin, s);
-    else
-      hipLaunchKernelGGL((k_bwd_gemm<T, S>), dim3((unsigned)nw), dim3(256), 0, st,
-                         d.d_bwd_work.ptr() + 2 * d.bwd_off[lv], d.d_fronts.ptr(), L, d.d_urows.ptr(),
-                         d.d_dinv.as<cplx<T>>(), bout, bin, s);
+    hipLaunchKernelGGL((k_bwd_gemm<T, S>), dim3((unsigned)(d.bwd_off[lv + 1] - d.bwd_off[lv])), dim3(256), 0, st,
+                       d.d_bwd_work.ptr() + 2 * d.bwd_off[lv], d.d_fronts.ptr(), L, d.d_urows.ptr(),
+                       d.d_dinv.as<cplx<T>>(), bout, bin, s);
   }
   HIP_CHECK(hipGetLastError());
+}
+
+// Matrix-core sweeps (complex64, 8..32 columns).  The tile of each level and direction is one
+// of two sizes; the first apply for a column-group width times both on every level (all tile
+// sizes give bit-identical results, and every timed launch is repeated exactly as the real
+// one: a forward level above the leaves re-assembles its work block before each try) and
+// keeps the faster one.
+template <int S>
+void sweep_mfma(Ctx* ctx, Ddm& d, int s, c64* bin, c64* bout, c64* wbuf) {
+  constexpr int NG = (S + 15) / 16;
+  hipStream_t st = ctx->stream;
+  const c64* L = d.d_factor.as<c64>();
+  const size_t nl = d.levels.size();
+  const int gi = NG - 1;
+  const bool tune = d.tile_fwd[gi].size() != nl;
+  auto fwd = [&](size_t lv, int t) {
+    const dim3 grid((unsigned)(d.fwdm_off[t][lv + 1] - d.fwdm_off[t][lv]));
+    const int32_t* wl = d.d_fwdm_work[t].ptr() + 2 * d.fwdm_off[t][lv];
+    const bool kids = lv > 0;  // leaves form their work block themselves
+    if (t == 0 && kids)
+      hipLaunchKernelGGL((k_fwd_mfma<NG, kFwdRowsMfma[0] / 64, 32, true>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(),
+                         L, d.d_imap.ptr(), bin, wbuf, bout, s);
+    else if (t == 0)
+      hipLaunchKernelGGL((k_fwd_mfma<NG, kFwdRowsMfma[0] / 64, 32, false>), grid, dim3(256), 0, st, wl,
+                         d.d_fronts.ptr(), L, d.d_imap.ptr(), bin, wbuf, bout, s);
+    else if (kids)
+      hipLaunchKernelGGL((k_fwd_mfma<NG, kFwdRowsMfma[1] / 64, 32, true>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(),
+                         L, d.d_imap.ptr(), bin, wbuf, bout, s);
+    else
+      hipLaunchKernelGGL((k_fwd_mfma<NG, kFwdRowsMfma[1] / 64, 32, false>), grid, dim3(256), 0, st, wl,
+                         d.d_fronts.ptr(), L, d.d_imap.ptr(), bin, wbuf, bout, s);
+  };
+  auto bwd = [&](size_t lv, int t) {
+    const dim3 grid((unsigned)(d.bwdm_off[t][lv + 1] - d.bwdm_off[t][lv]));
+    const int32_t* wl = d.d_bwdm_work[t].ptr() + 2 * d.bwdm_off[t][lv];
+    if (t == 0)
+      hipLaunchKernelGGL((k_bwd_mfma<NG, kBwdColsMfma[0] / 64, 32>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(), L,
+                         d.d_urows.ptr(), d.d_dinv.as<c64>(), bout, bin, s);
+    else
+      hipLaunchKernelGGL((k_bwd_mfma<NG, kBwdColsMfma[1] / 64, 32>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(), L,
+                         d.d_urows.ptr(), d.d_dinv.as<c64>(), bout, bin, s);
+  };
+  if (!tune) {
+    for (size_t lv = 0; lv < nl; ++lv) {
+      if (lv > 0) fwd_assemble<float>(ctx, d, lv, s, bin, wbuf);
+      const Level& Lv = d.levels[lv];
+      // algorithmic traffic: the level's stored factor once, its work rows read and written once
+      ProfScope ps(ctx, HZ_K_ORAS_FWD, 8.0 * ((double)Lv.useful + 2.0 * (double)Lv.sum_f * s),
+                   8.0 * (double)Lv.useful * s);
+      fwd(lv, d.tile_fwd[gi][lv]);
+    }
+    for (size_t lv = nl; lv-- > 0;) {
+      const Level& Lv = d.levels[lv];
+      ProfScope ps(ctx, HZ_K_ORAS_BWD, 8.0 * ((double)Lv.useful + (double)(Lv.sum_f + Lv.sum_p) * s),
+                   8.0 * (double)Lv.useful * s);
+      bwd(lv, d.tile_bwd[gi][lv]);
+    }
+    HIP_CHECK(hipGetLastError());
+    return;
+  }
+  // tuning apply: both tile sizes on every level, each run twice and timed the second time
+  // (the first launch of a kernel carries one-time costs); the last try leaves the result
+  std::vector<hipEvent_t> ev(8 * nl);
+  for (auto& e : ev) HIP_CHECK(hipEventCreate(&e));
+  auto at = [&](int dir, size_t lv, int t, int edge) -> hipEvent_t& { return ev[((dir * nl + lv) * 2 + t) * 2 + edge]; };
+  for (size_t lv = 0; lv < nl; ++lv)
+    for (int rep = 0; rep < 2; ++rep)
+      for (int t = 0; t < 2; ++t) {
+        if (lv > 0) fwd_assemble<float>(ctx, d, lv, s, bin, wbuf);
+        if (rep) HIP_CHECK(hipEventRecord(at(0, lv, t, 0), st));
+        fwd(lv, t);
+        if (rep) HIP_CHECK(hipEventRecord(at(0, lv, t, 1), st));
+      }
+  for (size_t lv = nl; lv-- > 0;)
+    for (int rep = 0; rep < 2; ++rep)
+      for (int t = 0; t < 2; ++t) {
+        if (rep) HIP_CHECK(hipEventRecord(at(1, lv, t, 0), st));
+        bwd(lv, t);
+        if (rep) HIP_CHECK(hipEventRecord(at(1, lv, t, 1), st));
+      }
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(st));
+  std::vector<uint8_t> cf(nl), cb(nl);
+  for (int dir = 0; dir < 2; ++dir)
+    for (size_t lv = 0; lv < nl; ++lv) {
+      float ms[2];
+      for (int t = 0; t < 2; ++t) HIP_CHECK(hipEventElapsedTime(&ms[t], at(dir, lv, t, 0), at(dir, lv, t, 1)));
+      const uint8_t pick = ms[1] < 0.97f * ms[0] ? 1 : 0;  // the smaller tile unless clearly slower
+      (dir == 0 ? cf : cb)[lv] = pick;
+    }
+  for (auto& e : ev) HIP_CHECK(hipEventDestroy(e));
+  d.tile_fwd[gi] = cf;
+  d.tile_bwd[gi] = cb;
+}
+
+template <typename T, int S>
+void sweep(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) {
+  if constexpr (use_mfma<T, S>())
+    sweep_mfma<S>(ctx, d, s, bin, bout, wbuf);
+  else
+    sweep_valu<T, S>(ctx, d, s, bin, bout, wbuf);
 }
 
 template <typename T>

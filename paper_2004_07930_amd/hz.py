@@ -76,7 +76,8 @@ class DdmStats(C.Structure):
 
 class DdmLevel(C.Structure):
     _fields_ = [("n_fronts", C.c_int64), ("max_pivots", C.c_int64), ("max_front", C.c_int64),
-                ("sum_pivots", C.c_int64), ("sum_front", C.c_int64), ("factor_useful", C.c_int64)]
+                ("sum_pivots", C.c_int64), ("sum_front", C.c_int64), ("factor_useful", C.c_int64),
+                ("fwd_tile_rows", C.c_int32), ("bwd_tile_cols", C.c_int32)]
 
 
 class Request(C.Structure):

@@ -325,3 +325,23 @@ def test_solve_failure_paths(ctx):
     res = np.linalg.norm(B.T - A @ X.T, axis=0) / np.linalg.norm(B, axis=1)
     np.testing.assert_allclose(res, [i["rel_residual"] for i in info], rtol=1e-8)
     assert res.max() < 1.0  # one preconditioned step already reduces the residual
+
+
+def test_sweep_tile_tuning(case, ctx):
+    """The first complex64 apply times both tile sizes on every level and keeps the faster;
+    tile sizes do not change results, so the tuning apply (which ends on the larger tiles) and
+    the tuned apply agree bit for bit."""
+    from paper_2004_07930_amd import hz
+
+    name, p, om, gm, A, gop = case
+    d32 = ctx.setup_ddm(gop, p.partition, p.n_sub, p.overlap, precision=hz.HZ_PREC_MIXED)
+    assert all(l["fwd_tile_rows"] == 0 and l["bwd_tile_cols"] == 0 for l in ctx.ddm_levels(d32))
+    rng = np.random.default_rng(17)
+    V = rng.standard_normal((16, om.n)) + 1j * rng.standard_normal((16, om.n))
+    Z1 = ctx.precond(d32, V)
+    lv = ctx.ddm_levels(d32)
+    print(name, "tiles", [(l["fwd_tile_rows"], l["bwd_tile_cols"]) for l in lv])
+    assert all(l["fwd_tile_rows"] in (64, 128) and l["bwd_tile_cols"] in (64, 128) for l in lv)
+    Z2 = ctx.precond(d32, V)
+    assert np.array_equal(Z1, Z2)
+    ctx.release(d32)
