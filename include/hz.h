@@ -179,11 +179,16 @@ hz_status hz_point_sources(hz_ctx* ctx, hz_handle mesh, int64_t n_src, const dou
 /*
  * Building blocks exposed for parity tests and measurement (same kernels as hz_solve).
  * hz_spmm:        y = A x for a block (FP64 operator), Paper eq. (2).
+ * hz_spmm_c64x:   the same product for a complex64 block x, as the mixed-precision solve
+ *                 applies it to its complex64 preconditioned vectors: x is widened exactly
+ *                 and every product and sum is FP64; y is complex128.
  * hz_precond:     z = M^{-1} v (eq. 2lvl; eq. oras without a coarse space), in the ddm's
  *                 precision, FP64 in and out.
- * All blocks [n_rhs][n_dofs] complex128.
+ * Blocks are [n_rhs][n_dofs], complex128 except the x of hz_spmm_c64x.  Host inputs are
+ * checked for non-finite values (HZ_ERR_ARG).
  */
 hz_status hz_spmm(hz_ctx* ctx, hz_handle op, int64_t n_rhs, const void* x, int x_mem, void* y, int y_mem);
+hz_status hz_spmm_c64x(hz_ctx* ctx, hz_handle op, int64_t n_rhs, const void* x, int x_mem, void* y, int y_mem);
 hz_status hz_precond(hz_ctx* ctx, hz_handle ddm, int64_t n_rhs, const void* v, int v_mem, void* z, int z_mem);
 
 typedef struct {

@@ -407,6 +407,37 @@ hz_status hz_spmm(hz_ctx* c, hz_handle op, int64_t n_rhs, const void* x, int x_m
   });
 }
 
+hz_status hz_spmm_c64x(hz_ctx* c, hz_handle op, int64_t n_rhs, const void* x, int x_mem, void* y, int y_mem) {
+  return guard(c, [&] {
+    HZ_REQUIRE(n_rhs >= 1 && x && y, HZ_ERR_ARG, "hz_spmm_c64x: bad arguments");
+    HZ_REQUIRE(x_mem == HZ_MEM_HOST || x_mem == HZ_MEM_DEVICE, HZ_ERR_ARG, "bad memory kind");
+    auto o = lookup(c, c->ops, op, "operator");
+    const int64_t n = o->mesh->n;
+    DevArray<c64> Xh;
+    const c64* X = static_cast<const c64*>(x);
+    if (x_mem == HZ_MEM_HOST) {
+      const float* h = static_cast<const float*>(x);
+      for (int64_t i = 0; i < 2 * n_rhs * n; ++i) HZ_REQUIRE(std::isfinite(h[i]), HZ_ERR_ARG, "non-finite input value");
+      Xh.upload(c, X, n_rhs * n);
+      X = Xh.ptr();
+    }
+    DevArray<c128> Yd, Yn;
+    DevArray<c64> Xn;
+    Yd.alloc(c, n_rhs * n);
+    for (int64_t c0 = 0; c0 < n_rhs; c0 += 32) {
+      const int s = (int)std::min<int64_t>(32, n_rhs - c0);
+      Xn.alloc(c, n * s);
+      Yn.alloc(c, n * s);
+      KrylovKernels K(c, n, s);
+      K.to_node(X + c0 * n, Xn.ptr());
+      launch_spmm<float>(c->stream, n, s, o->mesh->d_rowptr.ptr(), o->mesh->d_col.ptr(), o->d_val.ptr(), Xn.ptr(),
+                         Yn.ptr(), cmk(1.0, 0.0), cmk(0.0, 0.0), nullptr);
+      K.from_node(Yn.ptr(), Yd.ptr() + c0 * n);
+    }
+    copy_out(c, Yd.ptr(), y, y_mem, n_rhs * n);
+  });
+}
+
 hz_status hz_precond(hz_ctx* c, hz_handle ddm, int64_t n_rhs, const void* v, int v_mem, void* z, int z_mem) {
   return guard(c, [&] {
     HZ_REQUIRE(n_rhs >= 1 && z, HZ_ERR_ARG, "hz_precond: bad arguments");

@@ -158,6 +158,9 @@ void coarse_setup(Ctx* ctx, Ddm& d);
 // oras.hip: z = M^{-1} v for a block in node-major layout [n][s] (c128 in/out)
 struct OrasWork;
 void precond_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c128* z);
+// the same, z rounded to complex64 (mixed precision only): the flexible Krylov solve keeps
+// its preconditioned vectors in complex64 and multiplies exactly what it stored
+void precond_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c64* z);
 void precond_release_workspace(Ddm& d);
 
 }  // namespace hz

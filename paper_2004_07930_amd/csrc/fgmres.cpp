@@ -1,7 +1,8 @@
 // Block FGMRES(m) as a resumable job (host control flow; all arithmetic in krylov.hip /
 // spmm.hip / oras.hip kernels).  One Arnoldi process per right-hand-side block:
 //   cycle:  R = B - A X ; [V_1, S] = CholQR2(R) ; G = [S; 0]
-//   step j: Z_j = M^{-1} V_j ; W = A Z_j ; two passes of H = V^H W, W -= V H (CGS2) ;
+//   step j: Z_j = M^{-1} V_j (stored in complex64 with the mixed-precision preconditioner:
+//           the flexible method multiplies and combines exactly the stored Z_j) ; W = A Z_j ; two passes of H = V^H W, W -= V H (CGS2) ;
 //           [V_{j+1}, H_{j+1,j}] = CholQR2(W) ; Householder update of the block Hessenberg
 //           QR applied to G ; per-column residual estimate |G_{j+1}| / |b|
 //   end:    Y = R^{-1} G ; X += Z Y ; explicit residual decides restart.
@@ -15,35 +16,49 @@
 
 namespace hz {
 
-int64_t FgmresJob::bytes_needed(int64_t n, int s, int m) {
+int64_t FgmresJob::bytes_needed(int64_t n, int s, int m, bool z32) {
   const int64_t ns = n * s;
   const int nchunk = (int)((n + 4095) / 4096);
   const int64_t ldr = (int64_t)(m + 1) * s;
-  int64_t e = (2 * (int64_t)m + 4) * ns;                // V, Z, W, Wt, R
+  int64_t e = ((int64_t)m + 4) * ns;                      // V, W, Wt, R
   e += (int64_t)nchunk * (m + 1) * s * s;                 // partial sums
   e += (int64_t)(2 * m + 3) * s * s + (int64_t)m * s * ldr + 2 * (int64_t)m * s * s + ldr * s + 8 * s * s;
-  return e * (int64_t)sizeof(c128);
+  return e * (int64_t)sizeof(c128) + (int64_t)m * ns * (int64_t)(z32 ? sizeof(c64) : sizeof(c128));  // + Z
 }
 
-int FgmresJob::restart_for(Ctx* ctx, int64_t n, int s, int want, int fixed) {
+int FgmresJob::restart_for(Ctx* ctx, int64_t n, int s, int want, int fixed, bool z32) {
   int m = std::max(1, want);
   if (fixed > 0) m = std::max(m, fixed);
   size_t fr = 0, tot = 0;
   HIP_CHECK(hipMemGetInfo(&fr, &tot));
-  const double per = (double)n * s * sizeof(c128);
-  const int mcap = (int)std::floor((0.8 * (double)fr / per - 4.0) / 2.0);
+  // each step keeps one V block (complex128) and one Z block; four more blocks are fixed
+  const double blk = (double)n * s;
+  const double per_step = blk * (sizeof(c128) + (z32 ? sizeof(c64) : sizeof(c128)));
+  const int mcap = (int)std::floor((0.8 * (double)fr - 4.0 * blk * sizeof(c128)) / per_step);
   HZ_REQUIRE(mcap >= 1, HZ_ERR_OOM, "fgmres: not enough device memory for one Krylov step");
   if (fixed > 0) HZ_REQUIRE(mcap >= fixed, HZ_ERR_OOM, "fgmres: fixed_iters exceeds memory");
   return std::min(m, mcap);
 }
 
 FgmresJob::FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c128* X_, const SolveOptions& o_, int m_)
-    : ctx(c), d(std::move(dd)), s(s_), B(B_), X(X_), o(o_), m(m_), n(d->op->mesh->n), K(c, d->op->mesh->n, s_) {
+    : ctx(c),
+      d(std::move(dd)),
+      s(s_),
+      B(B_),
+      X(X_),
+      o(o_),
+      m(m_),
+      n(d->op->mesh->n),
+      K(c, d->op->mesh->n, s_),
+      z32(d->precision == HZ_PREC_MIXED) {
   HZ_REQUIRE(s >= 1 && s <= 32, HZ_ERR_ARG, "fgmres: block size must be 1..32");
   const int64_t ns = n * s;
   ldr = (int64_t)(m + 1) * s;
   V.alloc(ctx, (m + 1) * ns);
-  Zb.alloc(ctx, m * ns);
+  if (z32)
+    Zs.alloc(ctx, m * ns);
+  else
+    Zb.alloc(ctx, m * ns);
   W.alloc(ctx, ns);
   Wt.alloc(ctx, ns);
   R.alloc(ctx, ns);
@@ -77,6 +92,25 @@ void FgmresJob::spmm(const c128* x, c128* y, c128 alpha, c128 beta, const c128* 
   ProfScope ps(ctx, HZ_K_SPMM, 20.0 * nnz + 8.0 * (n + 1) + (yin ? 3.0 : 2.0) * vec, 8.0 * nnz * s);
   launch_spmm<double>(ctx->stream, n, s, op.mesh->d_rowptr.ptr(), op.mesh->d_col.ptr(), op.d_val.ptr(), x, y, alpha,
                       beta, yin);
+}
+
+void FgmresJob::spmm_z(const c64* z, c128* w) {
+  const Operator& op = *d->op;
+  const double nnz = (double)op.nnz();
+  const double vec = (double)n * s;
+  ProfScope ps(ctx, HZ_K_SPMM, 20.0 * nnz + 8.0 * (n + 1) + vec * (sizeof(c64) + sizeof(c128)), 8.0 * nnz * s);
+  launch_spmm<float>(ctx->stream, n, s, op.mesh->d_rowptr.ptr(), op.mesh->d_col.ptr(), op.d_val.ptr(), z, w,
+                     cmk(1.0, 0.0), cmk(0.0, 0.0), nullptr);
+}
+
+void FgmresJob::matvec() {
+  if (z32) {
+    precond_apply(ctx, *d, s, v_cur(), z32_cur());
+    spmm_z(z32_cur(), w_cur());
+  } else {
+    precond_apply(ctx, *d, s, v_cur(), z_cur());
+    spmm(z_cur(), w_cur(), cmk(1.0, 0.0), cmk(0.0, 0.0), nullptr);
+  }
 }
 
 void FgmresJob::cholqr2(const c128* in, c128* out) {
@@ -115,7 +149,8 @@ void FgmresJob::start_cycle() {
 }
 
 c128* FgmresJob::v_cur() { return V.ptr() + jj * n * s; }
-c128* FgmresJob::z_cur() { return Zb.ptr() + jj * n * s; }
+c128* FgmresJob::z_cur() { return z32 ? nullptr : Zb.ptr() + jj * n * s; }
+c64* FgmresJob::z32_cur() { return z32 ? Zs.ptr() + jj * n * s : nullptr; }
 c128* FgmresJob::w_cur() { return W.ptr(); }
 
 void FgmresJob::after_matvec() {
@@ -149,7 +184,10 @@ bool FgmresJob::end_cycle() {
   const c128 one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
   const int J = (jj + 1) * s;
   K.lsq_solve(J, Rm.ptr(), ldr, G.ptr(), Y.ptr());
-  K.block_axpy(jj + 1, Zb.ptr(), n * s, Y.ptr(), 1.0, X, X);
+  if (z32)
+    K.block_axpy(jj + 1, Zs.ptr(), n * s, Y.ptr(), 1.0, X, X);
+  else
+    K.block_axpy(jj + 1, Zb.ptr(), n * s, Y.ptr(), 1.0, X, X);
   spmm(X, R.ptr(), mone, one, B);
   K.colnorms(R.ptr(), npart.ptr(), nrm.ptr());
   std::vector<double> rn(s);
@@ -177,14 +215,13 @@ bool FgmresJob::end_cycle() {
 
 void fgmres(Ctx* ctx, std::shared_ptr<Ddm> d, int s, const c128* B, c128* X, const SolveOptions& o,
             std::vector<ColInfo>& info) {
-  const int m = FgmresJob::restart_for(ctx, d->op->mesh->n, s, o.restart, o.fixed_iters);
+  const int m = FgmresJob::restart_for(ctx, d->op->mesh->n, s, o.restart, o.fixed_iters, d->precision == HZ_PREC_MIXED);
   FgmresJob job(ctx, d, s, B, X, o, m);
   job.start();
   const int limit = (o.fixed_iters > 0 ? o.fixed_iters : o.max_iter) + 1;
   for (int it = 0;; ++it) {
     HZ_REQUIRE(it <= limit, HZ_ERR_STATE, "fgmres: iteration bookkeeping error");
-    precond_apply(ctx, *d, s, job.v_cur(), job.z_cur());
-    job.spmm(job.z_cur(), job.w_cur(), cmk(1.0, 0.0), cmk(0.0, 0.0), nullptr);
+    job.matvec();
     job.after_matvec();
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
     if (job.cycle_done() && job.end_cycle()) break;

@@ -245,10 +245,11 @@ void launch_gather_fill(hipStream_t st, int64_t n_rows, const int64_t* d_rowptr,
                         const int64_t* d_gptr, const uint32_t* d_gsrc, const c128* d_elem, const uint8_t* d_dir,
                         c128* d_val, c64* d_val32);
 
-// spmm.hip
-template <typename T>
-void launch_spmm(hipStream_t st, int64_t n, int s, const int64_t* rowptr, const int32_t* col, const cplx<T>* val,
-                 const cplx<T>* x, cplx<T>* y, cplx<T> alpha, cplx<T> beta, const cplx<T>* yin);
+// spmm.hip: y = alpha A x + beta yin (yin may be null), A complex128 CSR, x complex<TX>
+// (complex64 x is widened exactly), y complex128; node-major [n][s] blocks
+template <typename TX>
+void launch_spmm(hipStream_t st, int64_t n, int s, const int64_t* rowptr, const int32_t* col, const c128* val,
+                 const cplx<TX>* x, c128* y, c128 alpha, c128 beta, const c128* yin);
 
 // utilities
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& body);

@@ -12,6 +12,7 @@ struct KrylovKernels {
   int nchunk;
   KrylovKernels(Ctx* c, int64_t n_, int s_);
   void to_node(const c128* src, c128* dst);
+  void to_node(const c64* src, c64* dst);
   void from_node(const c128* src, c128* dst);
   // H[J][c] (+)= sum_rows conj(V_J) W   for J < nblk * s ; partial buffer >= nchunk * nblk * s * s;
   // if H2 is given the same sums are also added into it
@@ -19,6 +20,8 @@ struct KrylovKernels {
             c128* H2 = nullptr);
   // Y = Yin + beta * sum_J V_J H[J][:]
   void block_axpy(int nblk, const c128* V, int64_t ldv, const c128* H, double beta, const c128* Yin, c128* Y);
+  // the same with complex64 basis blocks (widened exactly)
+  void block_axpy(int nblk, const c64* V, int64_t ldv, const c128* H, double beta, const c128* Yin, c128* Y);
   // one CholQR pass: G = W^H W = R^H R, out = W R^{-1}, Racc = R Racc
   void cholqr_pass(const c128* W, c128* out, c128* part, c128* G, c128* R, c128* Rinv, c128* Racc, int* flag);
   void identity(c128* M);
@@ -43,7 +46,7 @@ struct ColInfo {
 };
 
 // One block FGMRES(m) solve as a resumable state machine.  Driver protocol:
-//   start();  loop { Z = M^{-1} v_cur() -> z_cur();  w_cur() = A z_cur();  after_matvec();
+//   start();  loop { matvec() (Z = M^{-1} v_cur(), W = A Z);  after_matvec();
 //                    synchronise;  if (cycle_done() && end_cycle()) finished; }
 // B and X are node-major [n][s] device blocks owned by the caller.
 struct FgmresJob {
@@ -56,7 +59,9 @@ struct FgmresJob {
   int m;
   int64_t n, ldr = 0;
   KrylovKernels K;
+  bool z32;  // preconditioned blocks kept in complex64 (mixed-precision preconditioner)
   DevArray<c128> V, Zb, W, Wt, R, part, Hc, Hp, Rm, refl, tau, G, Y, Gs, Rs, Ri, Racc;
+  DevArray<c64> Zs;
   DevArray<double> res, npart, nrm;
   DevArray<int> flag;
   std::vector<double> bnorm, est, rel;
@@ -64,12 +69,15 @@ struct FgmresJob {
   std::vector<ColInfo> info;
 
   FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c128* X_, const SolveOptions& o_, int m_);
-  static int64_t bytes_needed(int64_t n, int s, int m);
-  static int restart_for(Ctx* ctx, int64_t n, int s, int want, int fixed);
+  static int64_t bytes_needed(int64_t n, int s, int m, bool z32);
+  static int restart_for(Ctx* ctx, int64_t n, int s, int want, int fixed, bool z32);
   void start();                 // norms of B (synchronises), X = 0, first cycle
   c128* v_cur();                // block to precondition this step
-  c128* z_cur();                // where M^{-1} v goes (kept for the update of X)
+  c128* z_cur();                // where M^{-1} v goes (kept for the update of X); FP64 jobs
+  c64* z32_cur();               // the same for jobs that keep Z in complex64
   c128* w_cur();                // where A z goes
+  void matvec();                // z_cur() = M^{-1} v_cur(), w_cur() = A z_cur()
+  void spmm_z(const c64* z, c128* w);  // w = A z, z complex64 widened exactly
   void after_matvec();          // CGS2, CholQR2, least-squares step; estimates copied to host (async)
   bool cycle_done();            // after a synchronisation: end of this cycle?
   bool end_cycle();             // X update and explicit residual (synchronises); true when finished

@@ -25,7 +25,8 @@ namespace {
 constexpr int kChunkRows = 4096;  // rows per partial-sum chunk
 constexpr int kJT = 64;           // basis columns per gram tile
 
-__global__ void k_to_node(int64_t n, int s, const c128* __restrict__ src, c128* __restrict__ dst) {
+template <typename T>
+__global__ void k_to_node(int64_t n, int s, const cplx<T>* __restrict__ src, cplx<T>* __restrict__ dst) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n * s) return;
   const int64_t i = k / s;
@@ -196,8 +197,8 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int Jtot, const c1
 // Y = Yin + beta V H, s = 16 NCT columns.  A wavefront holds RT tiles of 16 rows; the basis
 // columns go 16 at a time, lane l taking columns 4 (l/16) .. 4 (l/16) + 3 of row l%16 of
 // each tile (64 contiguous bytes) for eight consecutive k steps.
-template <int NCT, int RT>
-__global__ __launch_bounds__(256) void k_axpy_mfma(int64_t n, int Jtot, const c128* __restrict__ V, int64_t ldv,
+template <typename TV, int NCT, int RT>
+__global__ __launch_bounds__(256) void k_axpy_mfma(int64_t n, int Jtot, const cplx<TV>* __restrict__ V, int64_t ldv,
                                                    const c128* __restrict__ H, double beta,
                                                    const c128* __restrict__ Yin, c128* __restrict__ Y) {
   constexpr int S = 16 * NCT;
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(256) void k_axpy_mfma(int64_t n, int Jtot, const c1
   auto load = [&](int J, c128 (&h)[4][NCT], c128 (&a)[RT][4]) {
     const bool jok = J < Jtot;
     const int b = J / S, jc = J - (J / S) * S;
-    const c128* vb = V + (int64_t)b * ldv + jc + 4 * q;
+    const cplx<TV>* vb = V + (int64_t)b * ldv + jc + 4 * q;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -223,7 +224,10 @@ __global__ __launch_bounds__(256) void k_axpy_mfma(int64_t n, int Jtot, const c1
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) a[t][k] = (jok && row[t] < n) ? vb[row[t] * S + k] : cmk(0.0, 0.0);
+      for (int k = 0; k < 4; ++k) {
+        const cplx<TV> v = (jok && row[t] < n) ? vb[row[t] * S + k] : cmk((TV)0, (TV)0);
+        a[t][k] = cmk((double)v.re, (double)v.im);
+      }
   };
   c128 hc[4][NCT], ac[RT][4];
   load(0, hc, ac);
@@ -291,8 +295,8 @@ __global__ __launch_bounds__(256) void k_reduce_part(int nchunk, int64_t m, cons
 // Y[row][c] = Yin[row][c] + beta * sum_J V_J[row] H[J][c]
 // 64 rows per block; V tiles (64 rows x 32 basis columns) staged through LDS with
 // coalesced loads, H chunk (32 x s) in LDS; thread = (row, group of s/4 columns).
-template <int S>
-__global__ __launch_bounds__(256) void k_block_axpy(int64_t n, int s, int Jtot, const c128* __restrict__ V, int64_t ldv,
+template <typename TV, int S>
+__global__ __launch_bounds__(256) void k_block_axpy(int64_t n, int s, int Jtot, const cplx<TV>* __restrict__ V, int64_t ldv,
                                                     const c128* __restrict__ H, double beta,
                                                     const c128* __restrict__ Yin, c128* __restrict__ Y) {
   constexpr int RB = 64, JC = 32, NC = (S + 3) / 4;
@@ -313,7 +317,8 @@ __global__ __launch_bounds__(256) void k_block_axpy(int64_t n, int s, int Jtot, 
       if (jj < jn && row < n) {
         const int J = J0 + jj;
         const int b = J / s, jc = J - (J / s) * s;
-        v = V[(int64_t)b * ldv + row * s + jc];
+        const cplx<TV> w = V[(int64_t)b * ldv + row * s + jc];
+        v = cmk((double)w.re, (double)w.im);
       }
       Vt[jj][rr] = v;
     }
@@ -596,7 +601,12 @@ KrylovKernels::KrylovKernels(Ctx* c, int64_t n_, int s_) : ctx(c), n(n_), s(s_) 
 }
 
 void KrylovKernels::to_node(const c128* src, c128* dst) {
-  hipLaunchKernelGGL(k_to_node, dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, ctx->stream, n, s, src, dst);
+  hipLaunchKernelGGL(k_to_node<double>, dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, ctx->stream, n, s, src,
+                     dst);
+}
+void KrylovKernels::to_node(const c64* src, c64* dst) {
+  hipLaunchKernelGGL(k_to_node<float>, dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, ctx->stream, n, s, src,
+                     dst);
 }
 void KrylovKernels::from_node(const c128* src, c128* dst) {
   hipLaunchKernelGGL(k_from_node, dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, ctx->stream, n, s, src, dst);
@@ -649,36 +659,51 @@ void KrylovKernels::gram(int nblk, const c128* V, int64_t ldv, const c128* W, c1
   HIP_CHECK(hipGetLastError());
 }
 
-template <int S>
-static void axpy_t(KrylovKernels& k, int Jtot, const c128* V, int64_t ldv, const c128* H, double beta, const c128* Yin,
-                   c128* Y) {
-  hipLaunchKernelGGL(k_block_axpy<S>, dim3((unsigned)((k.n + 63) / 64)), dim3(256), 0, k.ctx->stream, k.n, k.s, Jtot, V,
-                     ldv, H, beta, Yin, Y);
+template <typename TV, int S>
+static void axpy_t(KrylovKernels& k, int Jtot, const cplx<TV>* V, int64_t ldv, const c128* H, double beta,
+                   const c128* Yin, c128* Y) {
+  hipLaunchKernelGGL((k_block_axpy<TV, S>), dim3((unsigned)((k.n + 63) / 64)), dim3(256), 0, k.ctx->stream, k.n, k.s,
+                     Jtot, V, ldv, H, beta, Yin, Y);
+}
+
+template <typename TV>
+static void block_axpy_t(KrylovKernels& k, int nblk, const cplx<TV>* V, int64_t ldv, const c128* H, double beta,
+                         const c128* Yin, c128* Y) {
+  const int64_t n = k.n;
+  const int s = k.s;
+  const int Jtot = nblk * s;
+  ProfScope ps(k.ctx, HZ_K_CGS_UPDATE, (double)n * Jtot * sizeof(cplx<TV>) + (double)n * (Yin ? 2 : 1) * s * sizeof(c128),
+               8.0 * n * Jtot * s);
+  hipStream_t st = k.ctx->stream;
+  if (s == 16)  // 4 wavefronts x 2 tiles of 16 rows per block
+    hipLaunchKernelGGL((k_axpy_mfma<TV, 1, 2>), dim3((unsigned)((n + 127) / 128)), dim3(256), 0, st, n, Jtot, V, ldv, H,
+                       beta, Yin, Y);
+  else if (s == 32)  // 4 wavefronts x 1 tile of 16 rows per block
+    hipLaunchKernelGGL((k_axpy_mfma<TV, 2, 1>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, n, Jtot, V, ldv, H,
+                       beta, Yin, Y);
+  else if (s == 1)
+    axpy_t<TV, 1>(k, Jtot, V, ldv, H, beta, Yin, Y);
+  else if (s == 2)
+    axpy_t<TV, 2>(k, Jtot, V, ldv, H, beta, Yin, Y);
+  else if (s <= 4)
+    axpy_t<TV, 4>(k, Jtot, V, ldv, H, beta, Yin, Y);
+  else if (s <= 8)
+    axpy_t<TV, 8>(k, Jtot, V, ldv, H, beta, Yin, Y);
+  else if (s <= 16)
+    axpy_t<TV, 16>(k, Jtot, V, ldv, H, beta, Yin, Y);
+  else
+    axpy_t<TV, 32>(k, Jtot, V, ldv, H, beta, Yin, Y);
+  HIP_CHECK(hipGetLastError());
 }
 
 void KrylovKernels::block_axpy(int nblk, const c128* V, int64_t ldv, const c128* H, double beta, const c128* Yin,
                                c128* Y) {
-  const int Jtot = nblk * s;
-  ProfScope ps(ctx, HZ_K_CGS_UPDATE, (double)n * (Jtot + (Yin ? 2 : 1) * s) * sizeof(c128), 8.0 * n * Jtot * s);
-  if (s == 16)  // 4 wavefronts x 2 tiles of 16 rows per block
-    hipLaunchKernelGGL((k_axpy_mfma<1, 2>), dim3((unsigned)((n + 127) / 128)), dim3(256), 0, ctx->stream, n, Jtot, V,
-                       ldv, H, beta, Yin, Y);
-  else if (s == 32)  // 4 wavefronts x 1 tile of 16 rows per block
-    hipLaunchKernelGGL((k_axpy_mfma<2, 1>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, ctx->stream, n, Jtot, V,
-                       ldv, H, beta, Yin, Y);
-  else if (s == 1)
-    axpy_t<1>(*this, Jtot, V, ldv, H, beta, Yin, Y);
-  else if (s == 2)
-    axpy_t<2>(*this, Jtot, V, ldv, H, beta, Yin, Y);
-  else if (s <= 4)
-    axpy_t<4>(*this, Jtot, V, ldv, H, beta, Yin, Y);
-  else if (s <= 8)
-    axpy_t<8>(*this, Jtot, V, ldv, H, beta, Yin, Y);
-  else if (s <= 16)
-    axpy_t<16>(*this, Jtot, V, ldv, H, beta, Yin, Y);
-  else
-    axpy_t<32>(*this, Jtot, V, ldv, H, beta, Yin, Y);
-  HIP_CHECK(hipGetLastError());
+  block_axpy_t<double>(*this, nblk, V, ldv, H, beta, Yin, Y);
+}
+
+void KrylovKernels::block_axpy(int nblk, const c64* V, int64_t ldv, const c128* H, double beta, const c128* Yin,
+                               c128* Y) {
+  block_axpy_t<float>(*this, nblk, V, ldv, H, beta, Yin, Y);
 }
 
 void KrylovKernels::cholqr_pass(const c128* W, c128* out, c128* part, c128* G, c128* R, c128* Rinv, c128* Racc,

@@ -32,9 +32,10 @@ __global__ void k_gather_local(int64_t nloc, int s, const int32_t* __restrict__ 
   dst[k] = cmk((T)v.re, (T)v.im);
 }
 
-template <typename T>
+// z = owner's local value (+ add), rounded to the output type TZ
+template <typename T, typename TZ>
 __global__ void k_scatter_owner(int64_t n, int s, const int64_t* __restrict__ own, const cplx<T>* __restrict__ loc,
-                                const c128* __restrict__ add, c128* __restrict__ z) {
+                                const c128* __restrict__ add, cplx<TZ>* __restrict__ z) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n * s) return;
   const int64_t g = k / s;
@@ -42,7 +43,7 @@ __global__ void k_scatter_owner(int64_t n, int s, const int64_t* __restrict__ ow
   const cplx<T> v = loc[own[g] * s + c];
   c128 r = cmk((double)v.re, (double)v.im);
   if (add) r = r + add[k];
-  z[k] = r;
+  z[k] = cmk((TZ)r.re, (TZ)r.im);
 }
 
 // Forward, step 1 of a level: work block w = [b_p; 0] + extend-add of the children's
@@ -614,8 +615,8 @@ void sweep(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) 
     sweep_valu<T, S>(ctx, d, s, bin, bout, wbuf);
 }
 
-template <typename T>
-void one_level(Ctx* ctx, Ddm& d, int s, const c128* v, const c128* add, c128* z, DevBuf& bin, DevBuf& bout,
+template <typename T, typename TZ>
+void one_level(Ctx* ctx, Ddm& d, int s, const c128* v, const c128* add, cplx<TZ>* z, DevBuf& bin, DevBuf& bout,
                DevBuf& wbuf) {
   hipStream_t st = ctx->stream;
   const int64_t nl = d.n_local_total;
@@ -649,7 +650,7 @@ void one_level(Ctx* ctx, Ddm& d, int s, const c128* v, const c128* add, c128* z,
     sweep<T, 32>(ctx, d, s, bi, bo, wb);
   else
     fail(HZ_ERR_ARG, "preconditioner: at most 32 columns per block");
-  hipLaunchKernelGGL(k_scatter_owner<T>, dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, st, n, s,
+  hipLaunchKernelGGL((k_scatter_owner<T, TZ>), dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, st, n, s,
                      d.d_own_src.ptr(), bi, add, z);
   HIP_CHECK(hipGetLastError());
 }
@@ -658,7 +659,10 @@ void one_level(Ctx* ctx, Ddm& d, int s, const c128* v, const c128* add, c128* z,
 
 void precond_release_workspace(Ddm& d) { d.pw = PrecondWork(); }
 
-void precond_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c128* z) {
+namespace {
+
+template <typename TZ>
+void precond_apply_t(Ctx* ctx, Ddm& d, int s, const c128* v, cplx<TZ>* z) {
   PrecondWork& w = d.pw;
   const int64_t n = d.op->mesh->n;
   const c128* rhs = v;
@@ -676,9 +680,18 @@ void precond_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c128* z) {
     add = w.q.as<c128>();
   }
   if (d.precision == HZ_PREC_MIXED)
-    one_level<float>(ctx, d, s, rhs, add, z, w.bin, w.bout, w.wbuf);
+    one_level<float, TZ>(ctx, d, s, rhs, add, z, w.bin, w.bout, w.wbuf);
   else
-    one_level<double>(ctx, d, s, rhs, add, z, w.bin, w.bout, w.wbuf);
+    one_level<double, TZ>(ctx, d, s, rhs, add, z, w.bin, w.bout, w.wbuf);
+}
+
+}  // namespace
+
+void precond_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c128* z) { precond_apply_t<double>(ctx, d, s, v, z); }
+
+void precond_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c64* z) {
+  HZ_REQUIRE(d.precision == HZ_PREC_MIXED, HZ_ERR_STATE, "preconditioner: complex64 output needs mixed precision");
+  precond_apply_t<float>(ctx, d, s, v, z);
 }
 
 }  // namespace hz

@@ -31,7 +31,9 @@ __global__ void k_pack_cols(int64_t n, int s, int S, int off, const c128* __rest
   const int c = (int)(k - i * s);
   dst[i * S + off + c] = src[k];
 }
-__global__ void k_unpack_cols(int64_t n, int s, int S, int off, const c128* __restrict__ src, c128* __restrict__ dst) {
+template <typename T>
+__global__ void k_unpack_cols(int64_t n, int s, int S, int off, const cplx<T>* __restrict__ src,
+                              cplx<T>* __restrict__ dst) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n * s) return;
   const int64_t i = k / s;
@@ -89,6 +91,7 @@ struct Serve {
   int64_t completed = 0, rejected = 0, sources = 0;
   double t_first = -1, t_last = 0;
   DevArray<c128> packV, packZ, packW;
+  DevArray<c64> packZ32;  // packed preconditioned columns of mixed-precision jobs
 };
 
 static constexpr int kServeRestart = 40;
@@ -101,7 +104,7 @@ static int part_cols(const Ticket& t, int k) { return (int)std::min<int64_t>(32,
 static int64_t part_bytes(const Ticket& t, int k, int m) {
   const int64_t n = t.ddm->op->mesh->n;
   const int s = part_cols(t, k);
-  int64_t b = FgmresJob::bytes_needed(n, s, m) + 2 * n * s * (int64_t)sizeof(c128);
+  int64_t b = FgmresJob::bytes_needed(n, s, m, t.ddm->precision == HZ_PREC_MIXED) + 2 * n * s * (int64_t)sizeof(c128);
   if (k == 0 && t.req.mem == HZ_MEM_HOST) b += 2 * n * t.req.n_rhs * (int64_t)sizeof(c128);
   return b;
 }
@@ -179,16 +182,16 @@ static void tick(Serve& S) {
       while (b < jobs.size() && cols + jobs[b]->s <= 32) cols += jobs[b++]->s;
       const int64_t n = dp->op->mesh->n;
       if (b - a == 1) {  // a single job needs no packing
-        FgmresJob* j = jobs[a];
-        precond_apply(ctx, *dp, j->s, j->v_cur(), j->z_cur());
-        j->spmm(j->z_cur(), j->w_cur(), cmk(1.0, 0.0), cmk(0.0, 0.0), nullptr);
+        jobs[a]->matvec();
       } else {
+        const bool z32 = dp->precision == HZ_PREC_MIXED;
         const int64_t need = n * 32;
         if ((int64_t)S.packV.n < need) {
           S.packV.alloc(ctx, need);
-          S.packZ.alloc(ctx, need);
           S.packW.alloc(ctx, need);
         }
+        if (z32 && (int64_t)S.packZ32.n < need) S.packZ32.alloc(ctx, need);
+        if (!z32 && (int64_t)S.packZ.n < need) S.packZ.alloc(ctx, need);
         int off = 0;
         for (size_t q = a; q < b; ++q) {
           FgmresJob* j = jobs[q];
@@ -196,17 +199,30 @@ static void tick(Serve& S) {
                              j->v_cur(), S.packV.ptr());
           off += j->s;
         }
-        precond_apply(ctx, *dp, cols, S.packV.ptr(), S.packZ.ptr());
-        // one SpMM for all packed columns (the first job's launcher; the operator is shared)
-        launch_spmm<double>(st, n, cols, dp->op->mesh->d_rowptr.ptr(), dp->op->mesh->d_col.ptr(), dp->op->d_val.ptr(),
-                            S.packZ.ptr(), S.packW.ptr(), cmk(1.0, 0.0), cmk(0.0, 0.0), nullptr);
+        // one preconditioner apply and one SpMM for all packed columns (the operator is shared)
+        const int64_t* rp = dp->op->mesh->d_rowptr.ptr();
+        const int32_t* ci = dp->op->mesh->d_col.ptr();
+        if (z32) {
+          precond_apply(ctx, *dp, cols, S.packV.ptr(), S.packZ32.ptr());
+          launch_spmm<float>(st, n, cols, rp, ci, dp->op->d_val.ptr(), S.packZ32.ptr(), S.packW.ptr(), cmk(1.0, 0.0),
+                             cmk(0.0, 0.0), nullptr);
+        } else {
+          precond_apply(ctx, *dp, cols, S.packV.ptr(), S.packZ.ptr());
+          launch_spmm<double>(st, n, cols, rp, ci, dp->op->d_val.ptr(), S.packZ.ptr(), S.packW.ptr(), cmk(1.0, 0.0),
+                              cmk(0.0, 0.0), nullptr);
+        }
         off = 0;
         for (size_t q = a; q < b; ++q) {
           FgmresJob* j = jobs[q];
-          hipLaunchKernelGGL(k_unpack_cols, dim3((unsigned)((n * j->s + 255) / 256)), dim3(256), 0, st, n, j->s, cols,
-                             off, S.packZ.ptr(), j->z_cur());
-          hipLaunchKernelGGL(k_unpack_cols, dim3((unsigned)((n * j->s + 255) / 256)), dim3(256), 0, st, n, j->s, cols,
-                             off, S.packW.ptr(), j->w_cur());
+          const dim3 grid((unsigned)((n * j->s + 255) / 256));
+          if (z32)
+            hipLaunchKernelGGL(k_unpack_cols<float>, grid, dim3(256), 0, st, n, j->s, cols, off, S.packZ32.ptr(),
+                               j->z32_cur());
+          else
+            hipLaunchKernelGGL(k_unpack_cols<double>, grid, dim3(256), 0, st, n, j->s, cols, off, S.packZ.ptr(),
+                               j->z_cur());
+          hipLaunchKernelGGL(k_unpack_cols<double>, grid, dim3(256), 0, st, n, j->s, cols, off, S.packW.ptr(),
+                             j->w_cur());
           off += j->s;
         }
         HIP_CHECK(hipGetLastError());

@@ -28,7 +28,7 @@ _STATUS = {0: "HZ_OK", -1: "HZ_ERR_ARG", -2: "HZ_ERR_OOM", -3: "HZ_ERR_HIP", -4:
 
 EXPORTS = [
     "hz_init", "hz_finalize", "hz_last_error", "hz_release", "hz_mesh", "hz_assemble", "hz_setup_ddm",
-    "hz_solve", "hz_solve_ex", "hz_point_sources", "hz_spmm", "hz_precond", "hz_ddm_stats_get", "hz_ddm_levels",
+    "hz_solve", "hz_solve_ex", "hz_point_sources", "hz_spmm", "hz_spmm_c64x", "hz_precond", "hz_ddm_stats_get", "hz_ddm_levels",
     "hz_serve_start", "hz_serve_submit", "hz_serve_poll", "hz_serve_wait", "hz_serve_stats_get",
     "hz_serve_stop", "hz_get_dofmap", "hz_get_csr_size", "hz_get_csr", "hz_get_subdomain_size",
     "hz_get_subdomain", "hz_get_coarse_size", "hz_get_coarse", "hz_profile_enable", "hz_profile_get",
@@ -126,6 +126,7 @@ def load(path: str | None = None):
         "hz_solve_ex": [vp, u64, i64, vp, C.c_int, C.POINTER(SolveOpts), vp, C.c_int, vp],
         "hz_point_sources": [vp, u64, i64, vp, vp, vp, C.c_int],
         "hz_spmm": [vp, u64, i64, vp, C.c_int, vp, C.c_int],
+        "hz_spmm_c64x": [vp, u64, i64, vp, C.c_int, vp, C.c_int],
         "hz_precond": [vp, u64, i64, vp, C.c_int, vp, C.c_int],
         "hz_ddm_stats_get": [vp, u64, C.POINTER(DdmStats)],
         "hz_ddm_levels": [vp, u64, C.POINTER(DdmLevel), C.c_int32, C.POINTER(C.c_int32)],
@@ -337,6 +338,26 @@ class Context:
             out = np.empty((s, op.n), np.complex128) if not _is_torch(x) else x.new_empty(x.shape)
         yp, ym, keep2 = _block_arg(out, op.n)
         self._check(self.lib.hz_spmm(self.h, op.handle, s, xp, xm, yp, ym))
+        return out
+
+    def spmm_c64x(self, op, x):
+        """y = A x for a complex64 block x (widened exactly, FP64 products); y complex128."""
+        if _is_torch(x):
+            import torch
+
+            if x.dtype != torch.complex64 or not x.is_contiguous():
+                raise TypeError("device blocks must be contiguous torch.complex64 tensors")
+            xp, xm, keep = C.c_void_p(x.data_ptr()), (HZ_MEM_DEVICE if x.is_cuda else HZ_MEM_HOST), x
+            out = torch.empty(x.shape, dtype=torch.complex128, device=x.device)
+        else:
+            keep = np.ascontiguousarray(x, dtype=np.complex64)
+            xp, xm = _np_ptr(keep), HZ_MEM_HOST
+            out = np.empty(keep.shape, np.complex128)
+        if x.shape[-1] != op.n:
+            raise ValueError(f"block has {x.shape[-1]} dofs, expected {op.n}")
+        s = int(np.prod(x.shape[:-1])) if len(x.shape) > 1 else 1
+        yp, ym, keep2 = _block_arg(out, op.n)
+        self._check(self.lib.hz_spmm_c64x(self.h, op.handle, s, xp, xm, yp, ym))
         return out
 
     def precond(self, ddm, v, out=None):

@@ -72,13 +72,32 @@ def test_csr_pattern_bit_exact_values_close(case, ctx):
     assert abs(G - G.T).max() == 0
 
 
+SPMM_WIDTHS = (1, 3, 8, 12, 16, 17, 31, 32, 40)  # both kernels, partial column groups, odd widths, two chunks
+
+
 def test_spmm_matches(case, ctx):
     name, p, om, gm, A, gop = case
     rng = np.random.default_rng(7)
-    for s in (1, 3, 16):
+    for s in SPMM_WIDTHS:
         X = rng.standard_normal((s, om.n)) + 1j * rng.standard_normal((s, om.n))
         Y = ctx.spmm(gop, X)
-        assert _rel(Y, (A @ X.T).T) <= 1e-13
+        assert _rel(Y, (A @ X.T).T) <= 1e-13, s
+
+
+def test_spmm_complex64_input(case, ctx):
+    """The product the mixed-precision solve applies to its complex64 vectors: the exact
+    widening of x times the FP64 operator, to FP64 rounding (the oracle multiplies the same
+    widened values), from host and from device blocks."""
+    import torch
+
+    name, p, om, gm, A, gop = case
+    rng = np.random.default_rng(17)
+    for s in SPMM_WIDTHS:
+        X = (rng.standard_normal((s, om.n)) + 1j * rng.standard_normal((s, om.n))).astype(np.complex64)
+        ref = (A @ X.astype(np.complex128).T).T
+        assert _rel(ctx.spmm_c64x(gop, X), ref) <= 1e-13, s
+        Yd = ctx.spmm_c64x(gop, torch.from_numpy(X).cuda())
+        assert _rel(Yd.cpu().numpy(), ref) <= 1e-13, s
 
 
 def test_spmm_device_tensors_and_repeatable(case, ctx):
