@@ -609,24 +609,58 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   d->w_total = wrows;
   d->d_imap.upload(ctx, imap);
   {  // solve worklists: forward row tiles of 64, backward column tiles of 32 (vector-unit
-     // sweeps) and the wider tiles of the matrix-core sweeps
+     // sweeps) and the wider tiles of the matrix-core sweeps.  Workgroups are dealt to the 8
+     // XCDs round-robin by launch index, each XCD with its own L2.  All tiles of a front go to
+     // one XCD, so the front's right-hand rows, which every tile reads, are fetched into one
+     // L2 only.  Fronts are spread over the XCDs largest first onto the least-loaded one
+     // (load = the tiles' factor entries), and the XCDs' lists are interleaved at stride 8
+     // with (-1, 0) padding entries that exit at once.
     auto build = [&](int rows, int cols, std::vector<int64_t>& foff, std::vector<int64_t>& boff,
                      DevArray<int32_t>& dfw, DevArray<int32_t>& dbw) {
+      constexpr int kXcd = 8;
       std::vector<int32_t> fw, bw;
+      using Item = std::pair<int32_t, int32_t>;
+      auto deal = [&](const std::vector<std::pair<double, std::vector<Item>>>& per_front, std::vector<int32_t>& out) {
+        std::vector<std::vector<Item>> bins(kXcd);
+        std::vector<double> load(kXcd, 0.0);
+        std::vector<size_t> order(per_front.size());
+        for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](size_t a, size_t b) { return per_front[a].first > per_front[b].first; });
+        for (size_t k : order) {
+          const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+          load[x] += per_front[k].first;
+          bins[x].insert(bins[x].end(), per_front[k].second.begin(), per_front[k].second.end());
+        }
+        size_t mx = 0;
+        for (auto& b : bins) mx = std::max(mx, b.size());
+        for (size_t k = 0; k < mx; ++k)
+          for (int x = 0; x < kXcd; ++x) {
+            const Item it = k < bins[x].size() ? bins[x][k] : Item(-1, 0);
+            out.push_back(it.first);
+            out.push_back(it.second);
+          }
+      };
       for (const Level& L : d->levels) {
         foff.push_back((int64_t)fw.size() / 2);
         boff.push_back((int64_t)bw.size() / 2);
+        std::vector<std::pair<double, std::vector<Item>>> pf, pb;
         for (int32_t fi : L.fronts) {
           const Front& F = d->fronts[fi];
-          for (int64_t i0 = 0; i0 < F.f(); i0 += rows) {
-            fw.push_back(fi);
-            fw.push_back((int32_t)i0);
+          std::pair<double, std::vector<Item>> a, b;
+          for (int64_t i0 = 0; i0 < F.f(); i0 += rows) {  // a row tile reads columns [0, min(p, i0 + rows))
+            a.second.emplace_back(fi, (int32_t)i0);
+            a.first += (double)std::min<int64_t>(rows, F.f() - i0) * (double)(i0 < F.p ? std::min<int64_t>(F.p, i0 + rows) : F.p);
           }
-          for (int64_t j0 = 0; j0 < F.p; j0 += cols) {
-            bw.push_back(fi);
-            bw.push_back((int32_t)j0);
+          for (int64_t j0 = 0; j0 < F.p; j0 += cols) {  // a column tile reads rows [j0, f)
+            b.second.emplace_back(fi, (int32_t)j0);
+            b.first += (double)std::min<int64_t>(cols, F.p - j0) * (double)(F.f() - j0);
           }
+          pf.push_back(std::move(a));
+          pb.push_back(std::move(b));
         }
+        deal(pf, fw);
+        deal(pb, bw);
       }
       foff.push_back((int64_t)fw.size() / 2);
       boff.push_back((int64_t)bw.size() / 2);

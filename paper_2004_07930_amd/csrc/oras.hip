@@ -93,6 +93,7 @@ __global__ __launch_bounds__(256) void k_fwd_gemm(const int32_t* __restrict__ wo
   __shared__ cplx<T> Ft[JC][RT + 1];
   __shared__ cplx<T> Wt[JC][S];
   const int fid = work[2 * blockIdx.x];
+  if (fid < 0) return;  // padding entry of the XCD-interleaved worklist (block-uniform)
   const int64_t i0 = work[2 * blockIdx.x + 1];
   const FrontDesc F = fr[fid];
   const int64_t f = F.p + F.r;
@@ -151,6 +152,7 @@ __global__ __launch_bounds__(256) void k_bwd_gemm(const int32_t* __restrict__ wo
   __shared__ cplx<T> Ft[RC][CT + 1];
   __shared__ cplx<T> Ut[RC][S];
   const int fid = work[2 * blockIdx.x];
+  if (fid < 0) return;  // padding entry of the XCD-interleaved worklist (block-uniform)
   const int64_t j0 = work[2 * blockIdx.x + 1];
   const FrontDesc F = fr[fid];
   const int64_t f = F.p + F.r;
@@ -238,6 +240,7 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
   __shared__ c64 Ft[JC][RT + 1];
   __shared__ c64 Wt[JC][SC];
   const int fid = work[2 * blockIdx.x];
+  if (fid < 0) return;  // padding entry of the XCD-interleaved worklist (block-uniform)
   const int64_t i0 = work[2 * blockIdx.x + 1];
   const FrontDesc F = fr[fid];
   const int64_t f = F.p + F.r;
@@ -374,6 +377,7 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ wo
   __shared__ c64 Ft[RC][CT + 1];
   __shared__ c64 Ut[RC][SC];
   const int fid = work[2 * blockIdx.x];
+  if (fid < 0) return;  // padding entry of the XCD-interleaved worklist (block-uniform)
   const int64_t j0 = work[2 * blockIdx.x + 1];
   const FrontDesc F = fr[fid];
   const int64_t f = F.p + F.r;
