@@ -303,14 +303,15 @@ void lu_and_inverse(Ctx* ctx, int64_t nc, cplx<T>* E, int32_t* piv, cplx<T>* Ein
   HIP_CHECK(hipGetLastError());
 }
 
-// y[c][col] = sum_{i in Z^T row c} Z[i,c] v[i][col]  (fixed-order partial sums per column)
+// y[c][col] = sum_{i in Z^T row c} Z[i,c] v[i][col]  (fixed-order partial sums per column).
+// A coarse row holds thousands of fine dofs: 1024 threads per row keep enough gathers in flight.
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(int64_t nc, int s, const int64_t* __restrict__ ztptr,
-                                                  const int32_t* __restrict__ ztcol, const double* __restrict__ ztval,
-                                                  const c128* __restrict__ v, cplx<T>* __restrict__ y) {
-  __shared__ c128 part[256];
+__global__ __launch_bounds__(1024) void k_restrict(int64_t nc, int s, const int64_t* __restrict__ ztptr,
+                                                   const int32_t* __restrict__ ztcol, const double* __restrict__ ztval,
+                                                   const c128* __restrict__ v, cplx<T>* __restrict__ y) {
+  __shared__ c128 part[1024];
   const int64_t c = blockIdx.x;
-  const int groups = 256 / s;
+  const int groups = 1024 / s;
   const int g = threadIdx.x / s, col = threadIdx.x - (threadIdx.x / s) * s;
   c128 acc = cmk(0.0, 0.0);
   if (g < groups)
@@ -350,13 +351,14 @@ __global__ void k_dense_reduce(int nk, int64_t m, const cplx<T>* __restrict__ pa
   y2[e] = a;
 }
 
-// q = Z y2 ; t = v - AZ y2
+// q = Z y2 ; t = v - AZ y2 (v - AZ y2 formed in FP64, both stored in the coarse precision T:
+// the one-level apply reads t in T and the owner gather adds q)
 template <typename T>
 __global__ void k_prolong(int64_t n, int s, const int64_t* __restrict__ zptr, const int32_t* __restrict__ zcol,
                           const double* __restrict__ zval, const int64_t* __restrict__ azptr,
                           const int32_t* __restrict__ azcol, const cplx<T>* __restrict__ az,
-                          const cplx<T>* __restrict__ y2, const c128* __restrict__ v, c128* __restrict__ q,
-                          c128* __restrict__ t) {
+                          const cplx<T>* __restrict__ y2, const c128* __restrict__ v, cplx<T>* __restrict__ q,
+                          cplx<T>* __restrict__ t) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n * s) return;
   const int64_t i = k / s;
@@ -364,8 +366,9 @@ __global__ void k_prolong(int64_t n, int s, const int64_t* __restrict__ zptr, co
   cplx<T> qa = cmk((T)0, (T)0), ta = cmk((T)0, (T)0);
   for (int64_t e = zptr[i]; e < zptr[i + 1]; ++e) cfma(qa, cmk((T)zval[e], (T)0), y2[(int64_t)zcol[e] * s + col]);
   for (int64_t e = azptr[i]; e < azptr[i + 1]; ++e) cfma(ta, az[e], y2[(int64_t)azcol[e] * s + col]);
-  q[k] = cmk((double)qa.re, (double)qa.im);
-  t[k] = v[k] - cmk((double)ta.re, (double)ta.im);
+  q[k] = qa;
+  const c128 r = v[k] - cmk((double)ta.re, (double)ta.im);
+  t[k] = cmk((T)r.re, (T)r.im);
 }
 
 }  // namespace
@@ -428,7 +431,7 @@ void coarse_setup(Ctx* ctx, Ddm& d) {
 }
 
 template <typename T>
-static void coarse_apply_t(Ctx* ctx, Ddm& d, int s, const c128* v, c128* q, c128* t, const cplx<T>* Einv,
+static void coarse_apply_t(Ctx* ctx, Ddm& d, int s, const c128* v, cplx<T>* q, cplx<T>* t, const cplx<T>* Einv,
                            const cplx<T>* az) {
   CoarseSpace& cs = *d.coarse;
   hipStream_t st = ctx->stream;
@@ -443,7 +446,7 @@ static void coarse_apply_t(Ctx* ctx, Ddm& d, int s, const c128* v, c128* q, c128
   }
   cplx<T>* y = cs.w_y.as<cplx<T>>();
   cplx<T>* y2 = cs.w_y2.as<cplx<T>>();
-  hipLaunchKernelGGL(k_restrict<T>, dim3((unsigned)nc), dim3(256), 0, st, nc, s, cs.d_ztptr.ptr(), cs.d_ztcol.ptr(),
+  hipLaunchKernelGGL(k_restrict<T>, dim3((unsigned)nc), dim3(1024), 0, st, nc, s, cs.d_ztptr.ptr(), cs.d_ztcol.ptr(),
                      cs.d_ztval.ptr(), v, y);
   hipLaunchKernelGGL(k_dense_apply<T>, dim3((unsigned)((nc + 63) / 64), KS), dim3(256), 0, st, nc, s, kchunk, Einv, y,
                      cs.w_part.as<cplx<T>>());
@@ -454,11 +457,14 @@ static void coarse_apply_t(Ctx* ctx, Ddm& d, int s, const c128* v, c128* q, c128
   HIP_CHECK(hipGetLastError());
 }
 
+void coarse_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c64* q, c64* t) {
+  HZ_REQUIRE(d.precision == HZ_PREC_MIXED, HZ_ERR_STATE, "coarse correction: complex64 blocks need mixed precision");
+  coarse_apply_t<float>(ctx, d, s, v, q, t, d.coarse->d_E32.ptr(), d.coarse->d_az32.ptr());
+}
+
 void coarse_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c128* q, c128* t) {
-  if (d.precision == HZ_PREC_MIXED)
-    coarse_apply_t<float>(ctx, d, s, v, q, t, d.coarse->d_E32.ptr(), d.coarse->d_az32.ptr());
-  else
-    coarse_apply_t<double>(ctx, d, s, v, q, t, d.coarse->d_E.ptr(), d.coarse->d_az.ptr());
+  HZ_REQUIRE(d.precision != HZ_PREC_MIXED, HZ_ERR_STATE, "coarse correction: complex128 blocks need FP64");
+  coarse_apply_t<double>(ctx, d, s, v, q, t, d.coarse->d_E.ptr(), d.coarse->d_az.ptr());
 }
 
 }  // namespace hz

@@ -14,35 +14,37 @@
 
 namespace hz {
 
+// q = Z E^{-1} Z^T v and t = v - A q in the coarse precision (complex64 with mixed precision)
 void coarse_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c128* q, c128* t);
+void coarse_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c64* q, c64* t);
 
 namespace {
 
 constexpr int kNb = 32;
 constexpr int kThreads = 256;
 
-template <typename T>
-__global__ void k_gather_local(int64_t nloc, int s, const int32_t* __restrict__ gidx, const c128* __restrict__ src,
+template <typename T, typename TS>
+__global__ void k_gather_local(int64_t nloc, int s, const int32_t* __restrict__ gidx, const cplx<TS>* __restrict__ src,
                                cplx<T>* __restrict__ dst) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nloc * s) return;
   const int64_t q = k / s;
   const int c = (int)(k - q * s);
-  const c128 v = src[(int64_t)gidx[q] * s + c];
+  const cplx<TS> v = src[(int64_t)gidx[q] * s + c];
   dst[k] = cmk((T)v.re, (T)v.im);
 }
 
-// z = owner's local value (+ add), rounded to the output type TZ
-template <typename T, typename TZ>
+// z = owner's local value (+ add), summed in FP64 and rounded to the output type TZ
+template <typename T, typename TQ, typename TZ>
 __global__ void k_scatter_owner(int64_t n, int s, const int64_t* __restrict__ own, const cplx<T>* __restrict__ loc,
-                                const c128* __restrict__ add, cplx<TZ>* __restrict__ z) {
+                                const cplx<TQ>* __restrict__ add, cplx<TZ>* __restrict__ z) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n * s) return;
   const int64_t g = k / s;
   const int c = (int)(k - g * s);
   const cplx<T> v = loc[own[g] * s + c];
   c128 r = cmk((double)v.re, (double)v.im);
-  if (add) r = r + add[k];
+  if (add) r = r + cmk((double)add[k].re, (double)add[k].im);
   z[k] = cmk((TZ)r.re, (TZ)r.im);
 }
 
@@ -619,8 +621,8 @@ void sweep(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) 
     sweep_valu<T, S>(ctx, d, s, bin, bout, wbuf);
 }
 
-template <typename T, typename TZ>
-void one_level(Ctx* ctx, Ddm& d, int s, const c128* v, const c128* add, cplx<TZ>* z, DevBuf& bin, DevBuf& bout,
+template <typename T, typename TS, typename TQ, typename TZ>
+void one_level(Ctx* ctx, Ddm& d, int s, const cplx<TS>* v, const cplx<TQ>* add, cplx<TZ>* z, DevBuf& bin, DevBuf& bout,
                DevBuf& wbuf) {
   hipStream_t st = ctx->stream;
   const int64_t nl = d.n_local_total;
@@ -638,7 +640,7 @@ void one_level(Ctx* ctx, Ddm& d, int s, const c128* v, const c128* add, cplx<TZ>
   cplx<T>* bi = bin.as<cplx<T>>();
   cplx<T>* bo = bout.as<cplx<T>>();
   cplx<T>* wb = wbuf.as<cplx<T>>();
-  hipLaunchKernelGGL(k_gather_local<T>, dim3((unsigned)((nl * s + 255) / 256)), dim3(256), 0, st, nl, s,
+  hipLaunchKernelGGL((k_gather_local<T, TS>), dim3((unsigned)((nl * s + 255) / 256)), dim3(256), 0, st, nl, s,
                      d.d_gidx.ptr(), v, bi);
   if (s <= 1)
     sweep<T, 1>(ctx, d, s, bi, bo, wb);
@@ -654,7 +656,7 @@ void one_level(Ctx* ctx, Ddm& d, int s, const c128* v, const c128* add, cplx<TZ>
     sweep<T, 32>(ctx, d, s, bi, bo, wb);
   else
     fail(HZ_ERR_ARG, "preconditioner: at most 32 columns per block");
-  hipLaunchKernelGGL((k_scatter_owner<T, TZ>), dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, st, n, s,
+  hipLaunchKernelGGL((k_scatter_owner<T, TQ, TZ>), dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, st, n, s,
                      d.d_own_src.ptr(), bi, add, z);
   HIP_CHECK(hipGetLastError());
 }
@@ -669,24 +671,27 @@ template <typename TZ>
 void precond_apply_t(Ctx* ctx, Ddm& d, int s, const c128* v, cplx<TZ>* z) {
   PrecondWork& w = d.pw;
   const int64_t n = d.op->mesh->n;
-  const c128* rhs = v;
-  const c128* add = nullptr;
-  if (d.coarse) {
-    const size_t need = (size_t)(n * s) * sizeof(c128);
+  const bool mixed = d.precision == HZ_PREC_MIXED;
+  if (d.coarse) {  // q and t in the coarse precision
+    const size_t need = (size_t)(n * s) * (mixed ? sizeof(c64) : sizeof(c128));
     if (w.q.bytes < need) {
       w.q.release();
       w.t.release();
       w.q.alloc(ctx, need);
       w.t.alloc(ctx, need);
     }
-    coarse_apply(ctx, d, s, v, w.q.as<c128>(), w.t.as<c128>());
-    rhs = w.t.as<c128>();
-    add = w.q.as<c128>();
+    if (mixed) {
+      coarse_apply(ctx, d, s, v, w.q.as<c64>(), w.t.as<c64>());
+      one_level<float, float, float, TZ>(ctx, d, s, w.t.as<c64>(), w.q.as<c64>(), z, w.bin, w.bout, w.wbuf);
+    } else {
+      coarse_apply(ctx, d, s, v, w.q.as<c128>(), w.t.as<c128>());
+      one_level<double, double, double, TZ>(ctx, d, s, w.t.as<c128>(), w.q.as<c128>(), z, w.bin, w.bout, w.wbuf);
+    }
+  } else if (mixed) {
+    one_level<float, double, float, TZ>(ctx, d, s, v, (const c64*)nullptr, z, w.bin, w.bout, w.wbuf);
+  } else {
+    one_level<double, double, double, TZ>(ctx, d, s, v, (const c128*)nullptr, z, w.bin, w.bout, w.wbuf);
   }
-  if (d.precision == HZ_PREC_MIXED)
-    one_level<float, TZ>(ctx, d, s, rhs, add, z, w.bin, w.bout, w.wbuf);
-  else
-    one_level<double, TZ>(ctx, d, s, rhs, add, z, w.bin, w.bout, w.wbuf);
 }
 
 }  // namespace
