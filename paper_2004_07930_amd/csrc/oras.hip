@@ -49,14 +49,18 @@ __global__ void k_scatter_owner(int64_t n, int s, const int64_t* __restrict__ ow
 }
 
 // Forward, step 1 of a level: work block w = [b_p; 0] + extend-add of the children's
-// contributions, through the inverse maps (own, child 0, child 1: a fixed order).
+// contributions, through the inverse maps (own, child 0, child 1: a fixed order).  One block
+// per 64-row tile of a front (the forward worklist: tiles of one front on one XCD).
 template <typename T>
-__global__ __launch_bounds__(256) void k_fwd_assemble(const int32_t* __restrict__ lf, const FrontDesc* __restrict__ fr,
+__global__ __launch_bounds__(256) void k_fwd_assemble(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
                                                       const int32_t* __restrict__ imap, const cplx<T>* __restrict__ bin,
                                                       cplx<T>* __restrict__ wbuf, int s) {
-  const FrontDesc F = fr[lf[blockIdx.x]];
+  const int fid = work[2 * blockIdx.x];
+  if (fid < 0) return;  // padding entry of the XCD-interleaved worklist (block-uniform)
+  const int64_t i0 = work[2 * blockIdx.x + 1];
+  const FrontDesc F = fr[fid];
   const int64_t f = F.p + F.r;
-  const int64_t tot = f * s;
+  const int64_t tot = (min<int64_t>(f, i0 + 64) - i0) * s;
   const cplx<T>* w0 = nullptr;
   const cplx<T>* w1 = nullptr;
   if (F.child0 >= 0) {
@@ -69,9 +73,9 @@ __global__ __launch_bounds__(256) void k_fwd_assemble(const int32_t* __restrict_
   }
   const int32_t* m0 = imap + F.imap_off;
   const int32_t* m1 = m0 + f;
-  for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < tot; k += (int64_t)gridDim.y * blockDim.x) {
-    const int64_t i = k / s;
-    const int c = (int)(k - i * s);
+  for (int64_t k = threadIdx.x; k < tot; k += blockDim.x) {
+    const int64_t i = i0 + k / s;
+    const int c = (int)(k - (k / s) * s);
     cplx<T> v = i < F.p ? bin[(F.vec_off + F.pos0 + i) * s + c] : cmk((T)0, (T)0);
     if (w0) {
       const int32_t q = m0[i];
@@ -487,11 +491,9 @@ constexpr bool use_mfma() {
 
 template <typename T>
 void fwd_assemble(Ctx* ctx, Ddm& d, size_t lv, int s, const cplx<T>* bin, cplx<T>* wbuf) {
-  const int nf = (int)d.levels[lv].fronts.size();
-  const int64_t tot = d.levels[lv].max_f * s;
-  const unsigned gy = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 64));
-  hipLaunchKernelGGL((k_fwd_assemble<T>), dim3(nf, gy), dim3(256), 0, ctx->stream,
-                     d.d_level_fronts.ptr() + d.level_off[lv], d.d_fronts.ptr(), d.d_imap.ptr(), bin, wbuf, s);
+  const unsigned nb = (unsigned)(d.fwd_off[lv + 1] - d.fwd_off[lv]);  // 64-row tiles of the level
+  hipLaunchKernelGGL((k_fwd_assemble<T>), dim3(nb), dim3(256), 0, ctx->stream, d.d_fwd_work.ptr() + 2 * d.fwd_off[lv],
+                     d.d_fronts.ptr(), d.d_imap.ptr(), bin, wbuf, s);
 }
 
 // Vector-unit sweeps (complex128, and complex64 blocks narrower than 8 columns).
