@@ -112,13 +112,14 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // per row), RG groups per step, and are summed through LDS in a fixed order.
 template <int NCT, int GJ, int RG>
 __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int Jtot, const c128* __restrict__ V, int64_t ldv,
-                                                   const c128* __restrict__ W, c128* __restrict__ part, int64_t rpc) {
+                                                   const c128* __restrict__ W, c128* __restrict__ part, int64_t rpc,
+                                                   int jbase) {
   constexpr int S = 16 * NCT;
   __shared__ c128 red[GJ * 16][S];
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, lc = l & 15, q = l >> 4;
   const int64_t r0 = (int64_t)blockIdx.x * rpc;
   const int64_t r1 = min<int64_t>(n, r0 + rpc);
-  const int J0 = blockIdx.y * GJ * 16;
+  const int J0 = jbase + blockIdx.y * GJ * 16;
   f64x4 hre[GJ][NCT], him[GJ][NCT];
   const c128* vp[GJ];
   bool jv[GJ];
@@ -635,12 +636,23 @@ void KrylovKernels::gram(int nblk, const c128* V, int64_t ldv, const c128* W, c1
     // algorithmic traffic: the Jtot basis columns and W once; 8 flops per complex multiply-add
     // (the scope times the partial-product kernel alone, not the reduction below)
     ProfScope ps(ctx, HZ_K_CGS_GRAM, (double)n * (Jtot + s) * sizeof(c128), 8.0 * n * Jtot * s);
-    if (mfma) {
+    if (mfma && s == 16) {
+      // groups of 4 basis blocks, then one launch sized for the remaining 1..3 (so that no
+      // block multiplies zero padding: the single block of CholQR and of the first step)
+      const int full = nblk / 4, rem = nblk % 4;
+      if (full > 0)
+        hipLaunchKernelGGL((k_gram_mfma<1, 4, 2>), dim3((unsigned)nch, (unsigned)full), dim3(256), 0, ctx->stream, n,
+                           Jtot, V, ldv, W, part, rpc, 0);
+      const dim3 g1((unsigned)nch, 1);
+      if (rem == 1)
+        hipLaunchKernelGGL((k_gram_mfma<1, 1, 2>), g1, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc, 64 * full);
+      else if (rem == 2)
+        hipLaunchKernelGGL((k_gram_mfma<1, 2, 2>), g1, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc, 64 * full);
+      else if (rem == 3)
+        hipLaunchKernelGGL((k_gram_mfma<1, 3, 2>), g1, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc, 64 * full);
+    } else if (mfma) {
       const dim3 grid((unsigned)nch, (unsigned)jtiles);
-      if (s == 16)
-        hipLaunchKernelGGL((k_gram_mfma<1, 4, 2>), grid, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc);
-      else
-        hipLaunchKernelGGL((k_gram_mfma<2, 2, 2>), grid, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc);
+      hipLaunchKernelGGL((k_gram_mfma<2, 2, 2>), grid, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc, 0);
     } else if (s <= 4) {
       gram_t<4>(*this, Jtot, V, ldv, W, part, nch, rpc);
     } else if (s <= 8) {
