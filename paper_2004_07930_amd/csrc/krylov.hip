@@ -455,41 +455,90 @@ __global__ void k_set_identity(int s, c128* M) {
 // refl[step][2s][s] reflector vectors (v[0] = 1) and tau[step][s], G (ldg x s row-major).
 // Each column of the block is handled by a group of L lanes of one wavefront; dot
 // products reduce with cross-lane shuffles in a fixed order.
-__device__ __forceinline__ c128 group_sum(c128 v, int L) {
-  for (int m = L >> 1; m > 0; m >>= 1) {
-    v.re += __shfl_xor(v.re, m, 64);
-    v.im += __shfl_xor(v.im, m, 64);
-  }
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// sum over aligned groups of L lanes, the same value in every lane of a group: partner lanes
+// are paired symmetrically at each step (xor 1, xor 2 by quad permutes, then the half-row and
+// row mirrors on DPP; xor 16 and 32 by shuffles), and a + b == b + a exactly
+template <int L>
+__device__ __forceinline__ double group_sum_t(double v) {
+  if constexpr (L >= 2) v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  if constexpr (L >= 4) v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  if constexpr (L >= 8) v += dpp_move<0x141>(v);  // row_half_mirror
+  if constexpr (L >= 16) v += dpp_move<0x140>(v); // row_mirror
+  if constexpr (L >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (L >= 64) v += __shfl_xor(v, 32, 64);
   return v;
+}
+template <int L>
+__device__ __forceinline__ c128 group_sum_t(c128 v) {
+  return cmk(group_sum_t<L>(v.re), group_sum_t<L>(v.im));
 }
 
 // apply H^H = I - conj(tau) v v^H (v on rows [r0 + k, r0 + 2s), v[k] = 1) to column c of X
-__device__ __forceinline__ void apply_refl(c128* X, int s, int r0, int k, const c128* V, c128 tau, int c, int lane,
-                                           int L) {
+template <int L>
+__device__ __forceinline__ void apply_refl(c128* X, int s, int r0, int k, const c128* V, c128 tau, int c, int lane) {
   const int s2 = 2 * s;
   c128 w = cmk(0.0, 0.0);
   for (int r = k + lane; r < s2; r += L) cfma_conj(w, V[r * s + k], X[(int64_t)(r0 + r) * s + c]);
-  w = group_sum(w, L);
+  w = group_sum_t<L>(w);
   const c128 ct = conj(tau) * w;
   for (int r = k + lane; r < s2; r += L) cfms(X[(int64_t)(r0 + r) * s + c], V[r * s + k], ct);
 }
 
+// L lanes per column (L = min(64, 256 / s rounded up to a power of two)); s <= 32
+template <int L>
 __global__ __launch_bounds__(256) void k_lsq_step(int s, int jj, c128* __restrict__ Hc, c128* __restrict__ Rm,
                                                   int64_t ldr, c128* __restrict__ refl, c128* __restrict__ tau,
                                                   c128* __restrict__ G, double* __restrict__ res) {
-  int sp = 1;
-  while (sp < s) sp <<= 1;
-  const int L = min(64, 256 / sp);
   const int c = threadIdx.x / L, lane = threadIdx.x % L;
   const bool act = c < s;
   const int s2 = 2 * s;
   const int64_t base = (int64_t)jj * s;
-  // 1. previous reflectors, in order, on the new column block
-  if (act)
+  // 1. previous reflectors, in order, on the new column block.  Block i touches rows
+  //    [i s, i s + 2s) only, so the column block streams through an LDS window of 2s rows
+  //    (two halves used as a ring): after block i its first s rows are final and go back to
+  //    memory, and rows [(i+2)s, (i+3)s) come in.  A column's L lanes sit in one wavefront
+  //    and own that column of the window, so the reflectors of a block need no barrier.
+  if (jj > 0) {
+    __shared__ c128 win[2 * 32 * 32];  // [half][row][column]
+    __shared__ c128 Vs[64 * 32];       // block i's reflectors [row][k]
+    __shared__ c128 ts[32];
+    auto row_of = [&](int r, int ha) -> c128* {
+      return &win[((r < s ? ha : 1 - ha) * 32 + (r < s ? r : r - s)) * 32];
+    };
+    for (int e = threadIdx.x; e < s2 * s; e += blockDim.x) row_of(e / s, 0)[e % s] = Hc[e];
+    int ha = 0;
     for (int i = 0; i < jj; ++i) {
       const c128* Vi = refl + (int64_t)i * s2 * s;
-      for (int k = 0; k < s; ++k) apply_refl(Hc, s, i * s, k, Vi, tau[(int64_t)i * s + k], c, lane, L);
+      for (int e = threadIdx.x; e < s2 * s; e += blockDim.x) Vs[(e / s) * 32 + e % s] = Vi[e];
+      if (threadIdx.x < s) ts[threadIdx.x] = tau[(int64_t)i * s + threadIdx.x];
+      __syncthreads();
+      if (act)
+        for (int k = 0; k < s; ++k) {
+          c128 w = cmk(0.0, 0.0);
+          for (int r = k + lane; r < s2; r += L) cfma_conj(w, Vs[r * 32 + k], row_of(r, ha)[c]);
+          w = group_sum_t<L>(w);
+          const c128 ct = conj(ts[k]) * w;
+          for (int r = k + lane; r < s2; r += L) cfms(row_of(r, ha)[c], Vs[r * 32 + k], ct);
+        }
+      __syncthreads();
+      // rows [i s, i s + s) are final; rows [(i+2)s, (i+3)s) take their place in the ring
+      for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
+        c128& x = row_of(e / s, ha)[e % s];
+        Hc[(int64_t)i * s * s + e] = x;
+        x = Hc[(int64_t)(i + 2) * s * s + e];
+      }
+      __syncthreads();
+      ha = 1 - ha;
     }
+    for (int e = threadIdx.x; e < s2 * s; e += blockDim.x)  // the window holds rows [jj s, jj s + 2s)
+      Hc[(int64_t)jj * s * s + e] = row_of(e / s, ha)[e % s];
+  }
   __syncthreads();
   // 2. new reflectors on rows [jj s, jj s + 2s)
   c128* Vn = refl + (int64_t)jj * s2 * s;
@@ -502,7 +551,7 @@ __global__ __launch_bounds__(256) void k_lsq_step(int s, int jj, c128* __restric
         const c128 x = Hc[(base + r) * s + k];
         xn += x.re * x.re + x.im * x.im;
       }
-      for (int m = L >> 1; m > 0; m >>= 1) xn += __shfl_xor(xn, m, 64);
+      xn = group_sum_t<L>(xn);
       c128 t = cmk(0.0, 0.0), beta = alpha, sc = cmk(0.0, 0.0);
       const bool refl_needed = xn > 0 || alpha.im != 0;
       if (refl_needed) {
@@ -525,7 +574,7 @@ __global__ __launch_bounds__(256) void k_lsq_step(int s, int jj, c128* __restric
       for (int r = k + 1 + lane; r < s2; r += L) Hc[(base + r) * s + k] = cmk(0.0, 0.0);
     }
     __syncthreads();
-    if (act && c > k) apply_refl(Hc, s, (int)base, k, Vn, tn[k], c, lane, L);
+    if (act && c > k) apply_refl<L>(Hc, s, (int)base, k, Vn, tn[k], c, lane);
     __syncthreads();
   }
   // 3. R column block jj: rows 0 .. (jj+1)s-1
@@ -537,30 +586,78 @@ __global__ __launch_bounds__(256) void k_lsq_step(int s, int jj, c128* __restric
   }
   // 4. the new reflectors on G rows [jj s, jj s + 2s); residual estimates
   if (act) {
-    for (int k = 0; k < s; ++k) apply_refl(G, s, (int)base, k, Vn, tn[k], c, lane, L);
+    for (int k = 0; k < s; ++k) apply_refl<L>(G, s, (int)base, k, Vn, tn[k], c, lane);
     double q = 0;
     for (int r = lane; r < s; r += L) {
       const c128 g = G[(base + s + r) * s + c];
       q += g.re * g.re + g.im * g.im;
     }
-    for (int m = L >> 1; m > 0; m >>= 1) q += __shfl_xor(q, m, 64);
+    q = group_sum_t<L>(q);
     if (lane == 0) res[c] = sqrt(q);
   }
 }
 
-// Y = Rm[0:J, 0:J]^{-1} G[0:J]  (column-oriented back substitution, one block)
-__global__ __launch_bounds__(256) void k_lsq_solve(int s, int J, const c128* __restrict__ Rm, int64_t ldr,
-                                                   const c128* __restrict__ G, c128* __restrict__ Y) {
-  for (int e = threadIdx.x; e < J * s; e += blockDim.x) Y[e] = G[e];
-  __syncthreads();
-  for (int i = J - 1; i >= 0; --i) {
-    if (threadIdx.x < s) Y[(int64_t)i * s + threadIdx.x] = cdiv(Y[(int64_t)i * s + threadIdx.x], Rm[(int64_t)i * ldr + i]);
+// Y = Rm[0:J, 0:J]^{-1} G[0:J]: back substitution by blocks of 16 rows, one workgroup of NT
+// threads.  Every thread keeps its PER entries of Y in registers for the whole solve (J s <= NT
+// PER entries).  Per block: the block's rows go to LDS, one thread per column solves the 16 x 16
+// triangle in registers, and every entry above is updated by the solved block (the 16 values of
+// R it needs are loaded together).  The order of operations per entry is fixed.  Rm is
+// column-major with leading dimension ldr; G and Y are [J][s].
+template <int NT, int PER>
+__global__ __launch_bounds__(NT) void k_lsq_solve(int s, int J, const c128* __restrict__ Rm, int64_t ldr,
+                                                  const c128* __restrict__ G, c128* __restrict__ Y) {
+  constexpr int kLsqThreads = NT, kLsqPer = PER;
+  constexpr int B = 16;
+  __shared__ c128 Yb[B][32];
+  __shared__ c128 Rb[B][B];
+  const int tot = J * s;
+  c128 y[kLsqPer];
+#pragma unroll
+  for (int u = 0; u < kLsqPer; ++u) {
+    const int e = threadIdx.x + kLsqThreads * u;
+    y[u] = e < tot ? G[e] : cmk(0.0, 0.0);
+  }
+  for (int i0 = ((J - 1) / B) * B; i0 >= 0; i0 -= B) {
+    const int nb = min(B, J - i0);
+#pragma unroll
+    for (int u = 0; u < kLsqPer; ++u) {
+      const int e = threadIdx.x + kLsqThreads * u, r = e / s;
+      if (e < tot && r >= i0 && r < i0 + nb) Yb[r - i0][e - r * s] = y[u];
+    }
+    for (int e = threadIdx.x; e < nb * nb; e += kLsqThreads) Rb[e % nb][e / nb] = Rm[(int64_t)(i0 + e / nb) * ldr + i0 + e % nb];
     __syncthreads();
-    for (int e = threadIdx.x; e < i * s; e += blockDim.x) {
-      const int r = e / s, c = e % s;
-      cfms(Y[(int64_t)r * s + c], Rm[(int64_t)i * ldr + r], Y[(int64_t)i * s + c]);
+    if (threadIdx.x < s) {  // the block's columns are independent: one thread per column
+      const int c = threadIdx.x;
+      for (int i = nb - 1; i >= 0; --i) {
+        const c128 yi = cdiv(Yb[i][c], Rb[i][i]);
+        Yb[i][c] = yi;
+        for (int r = 0; r < i; ++r) cfms(Yb[r][c], Rb[r][i], yi);
+      }
     }
     __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kLsqPer; ++u) {
+      const int e = threadIdx.x + kLsqThreads * u, r = e / s, c = e - (e / s) * s;
+      if (e >= tot || r >= i0 + nb) continue;
+      if (r >= i0) {
+        y[u] = Yb[r - i0][c];
+      } else {
+#pragma unroll 1
+        for (int k0 = 0; k0 < B; k0 += 4) {
+          c128 rv[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) rv[k] = k0 + k < nb ? Rm[(int64_t)(i0 + k0 + k) * ldr + r] : cmk(0.0, 0.0);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) cfms(y[u], rv[k], Yb[k0 + k][c]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < kLsqPer; ++u) {
+    const int e = threadIdx.x + kLsqThreads * u;
+    if (e < tot) Y[e] = y[u];
   }
 }
 
@@ -749,12 +846,29 @@ void KrylovKernels::identity(c128* M) {
 }
 
 void KrylovKernels::lsq_step(int jj, c128* Hc, c128* Rm, int64_t ldr, c128* refl, c128* tau, c128* G, double* res) {
-  hipLaunchKernelGGL(k_lsq_step, dim3(1), dim3(256), 0, ctx->stream, s, jj, Hc, Rm, ldr, refl, tau, G, res);
+  int sp = 1;
+  while (sp < s) sp <<= 1;
+  const int L = std::min(64, 256 / sp);
+  auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(1), dim3(256), 0, ctx->stream, s, jj, Hc, Rm, ldr, refl, tau, G, res); };
+  if (L == 64)
+    go(k_lsq_step<64>);
+  else if (L == 32)
+    go(k_lsq_step<32>);
+  else if (L == 16)
+    go(k_lsq_step<16>);
+  else
+    go(k_lsq_step<8>);
   HIP_CHECK(hipGetLastError());
 }
 
 void KrylovKernels::lsq_solve(int J, const c128* Rm, int64_t ldr, const c128* G, c128* Y) {
-  hipLaunchKernelGGL(k_lsq_solve, dim3(1), dim3(256), 0, ctx->stream, s, J, Rm, ldr, G, Y);
+  const int64_t ent = (int64_t)J * s;
+  if (ent <= 1024 * 10)  // s = 16 up to restart 40
+    hipLaunchKernelGGL((k_lsq_solve<1024, 10>), dim3(1), dim3(1024), 0, ctx->stream, s, J, Rm, ldr, G, Y);
+  else if (ent <= 1024 * 40)  // s = 32 up to restart 40 (register spills: rare and short)
+    hipLaunchKernelGGL((k_lsq_solve<1024, 40>), dim3(1), dim3(1024), 0, ctx->stream, s, J, Rm, ldr, G, Y);
+  else
+    fail(HZ_ERR_ARG, "least squares: restart length times block size squared exceeds 40960");
   HIP_CHECK(hipGetLastError());
 }
 
