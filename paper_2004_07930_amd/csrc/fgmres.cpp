@@ -22,7 +22,7 @@ int64_t FgmresJob::bytes_needed(int64_t n, int s, int m, bool z32) {
   const int64_t ldr = (int64_t)(m + 1) * s;
   int64_t e = ((int64_t)m + 4) * ns;                      // V, W, Wt, R
   e += (int64_t)nchunk * (m + 1) * s * s;                 // partial sums
-  e += (int64_t)(2 * m + 3) * s * s + (int64_t)m * s * ldr + 2 * (int64_t)m * s * s + ldr * s + 8 * s * s;
+  e += (int64_t)(2 * m + 3) * s * s + (int64_t)m * s * ldr + 3 * (int64_t)m * s * s + ldr * s + 8 * s * s;
   return e * (int64_t)sizeof(c128) + (int64_t)m * ns * (int64_t)(z32 ? sizeof(c64) : sizeof(c128));  // + Z
 }
 
@@ -68,6 +68,7 @@ FgmresJob::FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c1
   Rm.alloc(ctx, (int64_t)m * s * ldr);
   refl.alloc(ctx, (int64_t)m * 2 * s * s);
   tau.alloc(ctx, (int64_t)m * s);
+  tmat.alloc(ctx, (int64_t)m * s * s);
   G.alloc(ctx, ldr * s);
   Y.alloc(ctx, (int64_t)m * s * s);
   Gs.alloc(ctx, s * s);
@@ -165,7 +166,7 @@ void FgmresJob::after_matvec() {
   cholqr2(W.ptr(), V.ptr() + (jj + 1) * ns);
   HIP_CHECK(hipMemcpyAsync(Hc.ptr() + (int64_t)(jj + 1) * s * s, Racc.ptr(), s * s * sizeof(c128),
                            hipMemcpyDeviceToDevice, st));
-  K.lsq_step(jj, Hc.ptr(), Rm.ptr(), ldr, refl.ptr(), tau.ptr(), G.ptr(), res.ptr());
+  K.lsq_step(jj, Hc.ptr(), Rm.ptr(), ldr, refl.ptr(), tau.ptr(), tmat.ptr(), G.ptr(), res.ptr());
   HIP_CHECK(hipMemcpyAsync(est.data(), res.ptr(), s * sizeof(double), hipMemcpyDeviceToHost, st));
 }
 

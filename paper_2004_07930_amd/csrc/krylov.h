@@ -25,7 +25,8 @@ struct KrylovKernels {
   // one CholQR pass: G = W^H W = R^H R, out = W R^{-1}, Racc = R Racc
   void cholqr_pass(const c128* W, c128* out, c128* part, c128* G, c128* R, c128* Rinv, c128* Racc, int* flag);
   void identity(c128* M);
-  void lsq_step(int jj, c128* Hc, c128* Rm, int64_t ldr, c128* refl, c128* tau, c128* G, double* res);
+  // block Hessenberg QR step jj: refl/tau/tmat hold each block's reflectors and its T factor
+  void lsq_step(int jj, c128* Hc, c128* Rm, int64_t ldr, c128* refl, c128* tau, c128* tmat, c128* G, double* res);
   void lsq_solve(int J, const c128* Rm, int64_t ldr, const c128* G, c128* Y);
   void colnorms(const c128* X, double* part, double* out);
 };
@@ -60,7 +61,7 @@ struct FgmresJob {
   int64_t n, ldr = 0;
   KrylovKernels K;
   bool z32;  // preconditioned blocks kept in complex64 (mixed-precision preconditioner)
-  DevArray<c128> V, Zb, W, Wt, R, part, Hc, Hp, Rm, refl, tau, G, Y, Gs, Rs, Ri, Racc;
+  DevArray<c128> V, Zb, W, Wt, R, part, Hc, Hp, Rm, refl, tau, tmat, G, Y, Gs, Rs, Ri, Racc;
   DevArray<c64> Zs;
   DevArray<double> res, npart, nrm;
   DevArray<int> flag;

@@ -490,46 +490,75 @@ __device__ __forceinline__ void apply_refl(c128* X, int s, int r0, int k, const 
   for (int r = k + lane; r < s2; r += L) cfms(X[(int64_t)(r0 + r) * s + c], V[r * s + k], ct);
 }
 
+// One step of the block Hessenberg QR (s <= 32, 256 threads, L lanes per column).
+// A block i of s Householder reflectors P_k = I - conj(tau_k) v_k v_k^H, applied in the order
+// k = 0 .. s-1, is the single update X <- X - V T^H V^H X, with V = [v_0 .. v_{s-1}] (2s x s,
+// unit lower trapezoidal) and T the upper triangular factor of P_0^H .. P_{s-1}^H = I - V T V^H
+// (T[k][k] = tau_k, T[0:k, k] = -tau_k T[0:k, 0:k] V[:, 0:k]^H v_k).  Each block's T is formed
+// once, when its reflectors are made, and kept beside them.
+
+// X (2s x s, in LDS through row(r)) <- X - V T^H V^H X; V, T and the work blocks in LDS
+template <typename RowFn>
+__device__ __forceinline__ void wy_apply(int s, RowFn row, const c128 (*Vs)[32], const c128 (*Ts)[32], c128 (*W1)[32],
+                                         c128 (*W2)[32]) {
+  const int s2 = 2 * s;
+  for (int e = threadIdx.x; e < s * s; e += blockDim.x) {  // W1 = V^H X
+    const int a = e / s, c = e - (e / s) * s;
+    c128 w = cmk(0.0, 0.0);
+    for (int r = a; r < s2; ++r) cfma_conj(w, Vs[r][a], row(r)[c]);
+    W1[a][c] = w;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < s * s; e += blockDim.x) {  // W2 = T^H W1
+    const int a = e / s, c = e - (e / s) * s;
+    c128 w = cmk(0.0, 0.0);
+    for (int b = 0; b <= a; ++b) cfma_conj(w, Ts[b][a], W1[b][c]);
+    W2[a][c] = w;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < s2 * s; e += blockDim.x) {  // X -= V W2
+    const int r = e / s, c = e - (e / s) * s;
+    c128 x = row(r)[c];
+    const int am = r < s ? r : s - 1;
+    for (int a = 0; a <= am; ++a) cfms(x, Vs[r][a], W2[a][c]);
+    row(r)[c] = x;
+  }
+  __syncthreads();
+}
+
 // L lanes per column (L = min(64, 256 / s rounded up to a power of two)); s <= 32
 template <int L>
 __global__ __launch_bounds__(256) void k_lsq_step(int s, int jj, c128* __restrict__ Hc, c128* __restrict__ Rm,
                                                   int64_t ldr, c128* __restrict__ refl, c128* __restrict__ tau,
-                                                  c128* __restrict__ G, double* __restrict__ res) {
+                                                  c128* __restrict__ tmat, c128* __restrict__ G,
+                                                  double* __restrict__ res) {
   const int c = threadIdx.x / L, lane = threadIdx.x % L;
   const bool act = c < s;
   const int s2 = 2 * s;
   const int64_t base = (int64_t)jj * s;
-  // 1. previous reflectors, in order, on the new column block.  Block i touches rows
-  //    [i s, i s + 2s) only, so the column block streams through an LDS window of 2s rows
-  //    (two halves used as a ring): after block i its first s rows are final and go back to
-  //    memory, and rows [(i+2)s, (i+3)s) come in.  A column's L lanes sit in one wavefront
-  //    and own that column of the window, so the reflectors of a block need no barrier.
+  __shared__ c128 win[2 * 32 * 32];  // [half][row][column]
+  __shared__ c128 Vs[64][32];
+  __shared__ c128 Ts[32][32];
+  __shared__ c128 W1[32][32];
+  __shared__ c128 W2[32][32];
+  // 1. previous blocks of reflectors, in order, on the new column block.  Block i touches rows
+  //    [i s, i s + 2s) only, so the column block streams through an LDS window of 2s rows (two
+  //    halves used as a ring): after block i its first s rows are final and go back to memory,
+  //    and rows [(i+2)s, (i+3)s) come in.
   if (jj > 0) {
-    __shared__ c128 win[2 * 32 * 32];  // [half][row][column]
-    __shared__ c128 Vs[64 * 32];       // block i's reflectors [row][k]
-    __shared__ c128 ts[32];
-    auto row_of = [&](int r, int ha) -> c128* {
-      return &win[((r < s ? ha : 1 - ha) * 32 + (r < s ? r : r - s)) * 32];
-    };
-    for (int e = threadIdx.x; e < s2 * s; e += blockDim.x) row_of(e / s, 0)[e % s] = Hc[e];
     int ha = 0;
+    auto row = [&](int r) -> c128* { return &win[((r < s ? ha : 1 - ha) * 32 + (r < s ? r : r - s)) * 32]; };
+    for (int e = threadIdx.x; e < s2 * s; e += blockDim.x) row(e / s)[e % s] = Hc[e];
     for (int i = 0; i < jj; ++i) {
       const c128* Vi = refl + (int64_t)i * s2 * s;
-      for (int e = threadIdx.x; e < s2 * s; e += blockDim.x) Vs[(e / s) * 32 + e % s] = Vi[e];
-      if (threadIdx.x < s) ts[threadIdx.x] = tau[(int64_t)i * s + threadIdx.x];
+      const c128* Ti = tmat + (int64_t)i * s * s;
+      for (int e = threadIdx.x; e < s2 * s; e += blockDim.x) Vs[e / s][e % s] = Vi[e];
+      for (int e = threadIdx.x; e < s * s; e += blockDim.x) Ts[e / s][e % s] = Ti[e];
       __syncthreads();
-      if (act)
-        for (int k = 0; k < s; ++k) {
-          c128 w = cmk(0.0, 0.0);
-          for (int r = k + lane; r < s2; r += L) cfma_conj(w, Vs[r * 32 + k], row_of(r, ha)[c]);
-          w = group_sum_t<L>(w);
-          const c128 ct = conj(ts[k]) * w;
-          for (int r = k + lane; r < s2; r += L) cfms(row_of(r, ha)[c], Vs[r * 32 + k], ct);
-        }
-      __syncthreads();
+      wy_apply(s, row, Vs, Ts, W1, W2);
       // rows [i s, i s + s) are final; rows [(i+2)s, (i+3)s) take their place in the ring
       for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
-        c128& x = row_of(e / s, ha)[e % s];
+        c128& x = row(e / s)[e % s];
         Hc[(int64_t)i * s * s + e] = x;
         x = Hc[(int64_t)(i + 2) * s * s + e];
       }
@@ -537,7 +566,7 @@ __global__ __launch_bounds__(256) void k_lsq_step(int s, int jj, c128* __restric
       ha = 1 - ha;
     }
     for (int e = threadIdx.x; e < s2 * s; e += blockDim.x)  // the window holds rows [jj s, jj s + 2s)
-      Hc[(int64_t)jj * s * s + e] = row_of(e / s, ha)[e % s];
+      Hc[(int64_t)jj * s * s + e] = row(e / s)[e % s];
   }
   __syncthreads();
   // 2. new reflectors on rows [jj s, jj s + 2s)
@@ -566,9 +595,11 @@ __global__ __launch_bounds__(256) void k_lsq_step(int s, int jj, c128* __restric
         if (r == k) v = cmk(1.0, 0.0);
         else if (r > k && refl_needed) v = Hc[(base + r) * s + k] * sc;
         Vn[r * s + k] = v;
+        Vs[r][k] = v;
       }
       if (lane == 0) {
         tn[k] = t;
+        Ts[k][k] = t;
         Hc[(base + k) * s + k] = beta;
       }
       for (int r = k + 1 + lane; r < s2; r += L) Hc[(base + r) * s + k] = cmk(0.0, 0.0);
@@ -577,6 +608,28 @@ __global__ __launch_bounds__(256) void k_lsq_step(int s, int jj, c128* __restric
     if (act && c > k) apply_refl<L>(Hc, s, (int)base, k, Vn, tn[k], c, lane);
     __syncthreads();
   }
+  // the block's T: W1 = V^H V, then column k of T from the columns before it
+  for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
+    const int a = e / s, k = e - (e / s) * s;
+    c128 w = cmk(0.0, 0.0);
+    if (a < k)
+      for (int r = k; r < s2; ++r) cfma_conj(w, Vs[r][a], Vs[r][k]);
+    W1[a][k] = w;
+    if (a > k) Ts[a][k] = cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int k = 1; k < s; ++k) {
+    for (int a = threadIdx.x; a < k; a += blockDim.x) {
+      c128 w = cmk(0.0, 0.0);
+      for (int b = a; b < k; ++b) cfma(w, Ts[a][b], W1[b][k]);
+      W2[a][0] = cmk(0.0, 0.0) - Ts[k][k] * w;
+    }
+    __syncthreads();
+    for (int a = threadIdx.x; a < k; a += blockDim.x) Ts[a][k] = W2[a][0];
+    __syncthreads();
+  }
+  c128* Tn = tmat + (int64_t)jj * s * s;
+  for (int e = threadIdx.x; e < s * s; e += blockDim.x) Tn[e] = Ts[e / s][e % s];
   // 3. R column block jj: rows 0 .. (jj+1)s-1
   const int64_t rows = (int64_t)(jj + 1) * s;
   for (int64_t e = threadIdx.x; e < rows * s; e += blockDim.x) {
@@ -584,24 +637,29 @@ __global__ __launch_bounds__(256) void k_lsq_step(int s, int jj, c128* __restric
     const int cc = (int)(e - r * s);
     Rm[(base + cc) * ldr + r] = Hc[r * s + cc];
   }
-  // 4. the new reflectors on G rows [jj s, jj s + 2s); residual estimates
-  if (act) {
-    for (int k = 0; k < s; ++k) apply_refl<L>(G, s, (int)base, k, Vn, tn[k], c, lane);
-    double q = 0;
-    for (int r = lane; r < s; r += L) {
-      const c128 g = G[(base + s + r) * s + c];
-      q += g.re * g.re + g.im * g.im;
+  // 4. the new block of reflectors on G rows [jj s, jj s + 2s); residual estimates
+  {
+    auto grow = [&](int r) -> c128* { return &win[r * 32]; };
+    for (int e = threadIdx.x; e < s2 * s; e += blockDim.x) grow(e / s)[e % s] = G[base * s + e];
+    __syncthreads();
+    wy_apply(s, grow, Vs, Ts, W1, W2);
+    for (int e = threadIdx.x; e < s2 * s; e += blockDim.x) G[base * s + e] = grow(e / s)[e % s];
+    if (act) {
+      double q = 0;
+      for (int r = lane; r < s; r += L) {
+        const c128 g = grow(s + r)[c];
+        q += g.re * g.re + g.im * g.im;
+      }
+      q = group_sum_t<L>(q);
+      if (lane == 0) res[c] = sqrt(q);
     }
-    q = group_sum_t<L>(q);
-    if (lane == 0) res[c] = sqrt(q);
   }
 }
 
 // Y = Rm[0:J, 0:J]^{-1} G[0:J]: back substitution by blocks of 16 rows, one workgroup of NT
 // threads.  Every thread keeps its PER entries of Y in registers for the whole solve (J s <= NT
 // PER entries).  Per block: the block's rows go to LDS, one thread per column solves the 16 x 16
-// triangle in registers, and every entry above is updated by the solved block (the 16 values of
-// R it needs are loaded together).  The order of operations per entry is fixed.  Rm is
+// triangle there, and every entry above is updated by the solved block.  The order of operations per entry is fixed.  Rm is
 // column-major with leading dimension ldr; G and Y are [J][s].
 template <int NT, int PER>
 __global__ __launch_bounds__(NT) void k_lsq_solve(int s, int J, const c128* __restrict__ Rm, int64_t ldr,
@@ -845,11 +903,14 @@ void KrylovKernels::identity(c128* M) {
   hipLaunchKernelGGL(k_set_identity, dim3(1), dim3(256), 0, ctx->stream, s, M);
 }
 
-void KrylovKernels::lsq_step(int jj, c128* Hc, c128* Rm, int64_t ldr, c128* refl, c128* tau, c128* G, double* res) {
+void KrylovKernels::lsq_step(int jj, c128* Hc, c128* Rm, int64_t ldr, c128* refl, c128* tau, c128* tmat, c128* G,
+                             double* res) {
   int sp = 1;
   while (sp < s) sp <<= 1;
   const int L = std::min(64, 256 / sp);
-  auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(1), dim3(256), 0, ctx->stream, s, jj, Hc, Rm, ldr, refl, tau, G, res); };
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(1), dim3(256), 0, ctx->stream, s, jj, Hc, Rm, ldr, refl, tau, tmat, G, res);
+  };
   if (L == 64)
     go(k_lsq_step<64>);
   else if (L == 32)
