@@ -364,8 +364,40 @@ __global__ void k_prolong(int64_t n, int s, const int64_t* __restrict__ zptr, co
   const int64_t i = k / s;
   const int col = (int)(k - i * s);
   cplx<T> qa = cmk((T)0, (T)0), ta = cmk((T)0, (T)0);
-  for (int64_t e = zptr[i]; e < zptr[i + 1]; ++e) cfma(qa, cmk((T)zval[e], (T)0), y2[(int64_t)zcol[e] * s + col]);
-  for (int64_t e = azptr[i]; e < azptr[i + 1]; ++e) cfma(ta, az[e], y2[(int64_t)azcol[e] * s + col]);
+  // Z rows hold at most 4 entries and AZ rows a few more: each batch loads its column
+  // indices and values together (clamped to a valid entry, the value zeroed past the row),
+  // then its gathers of y2, so a row costs a few memory round trips instead of one per entry
+  const int64_t z0 = zptr[i], z1 = zptr[i + 1], a0 = azptr[i], a1 = azptr[i + 1];
+  for (int64_t e = z0; e < z1; e += 4) {
+    int32_t jc[4];
+    T zv[4];
+    cplx<T> yv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool ok = e + u < z1;
+      jc[u] = zcol[ok ? e + u : e];
+      zv[u] = ok ? (T)zval[e + u] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) yv[u] = y2[(int64_t)jc[u] * s + col];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cfma(qa, cmk(zv[u], (T)0), yv[u]);
+  }
+  for (int64_t e = a0; e < a1; e += 8) {
+    int32_t jc[8];
+    cplx<T> av[8], yv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool ok = e + u < a1;
+      jc[u] = azcol[ok ? e + u : e];
+      const cplx<T> x = az[ok ? e + u : e];
+      av[u] = csel(ok, x, cmk((T)0, (T)0));
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) yv[u] = y2[(int64_t)jc[u] * s + col];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cfma(ta, av[u], yv[u]);
+  }
   q[k] = qa;
   const c128 r = v[k] - cmk((double)ta.re, (double)ta.im);
   t[k] = cmk((T)r.re, (T)r.im);
