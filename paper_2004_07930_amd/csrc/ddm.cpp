@@ -668,9 +668,8 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
       dbw.upload(ctx, bw);
     };
     build(64, 32, d->fwd_off, d->bwd_off, d->d_fwd_work, d->d_bwd_work);
-    if (precision == HZ_PREC_MIXED)
-      for (int t = 0; t < 2; ++t)
-        build(kFwdRowsMfma[t], kBwdColsMfma[t], d->fwdm_off[t], d->bwdm_off[t], d->d_fwdm_work[t], d->d_bwdm_work[t]);
+    for (int t = 0; t < 2; ++t)  // the matrix-core sweeps' tiles (both precisions)
+      build(kFwdRowsMfma[t], kBwdColsMfma[t], d->fwdm_off[t], d->bwdm_off[t], d->d_fwdm_work[t], d->d_bwdm_work[t]);
   }
   {
     std::vector<int64_t> rp, gp;

@@ -91,7 +91,7 @@ struct PrecondWork {
   DevBuf bin, bout, wbuf, q, t;
 };
 
-// tile sizes the complex64 matrix-core solve sweeps choose from (per tree level): forward
+// tile sizes the matrix-core solve sweeps choose from (per tree level): forward
 // rows per block, backward pivot columns per block
 constexpr int kFwdRowsMfma[2] = {64, 128};
 constexpr int kBwdColsMfma[2] = {64, 128};

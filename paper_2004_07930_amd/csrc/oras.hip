@@ -225,6 +225,34 @@ __device__ __forceinline__ void mfma_3m(c64 a, c64 b, f32x4& p1, f32x4& p2, f32x
   p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re + a.im, b.re + b.im, p3, 0, 0, 0);
 }
 
+// Complex accumulator of a 16 x 16 output tile on the matrix cores.  complex64: the three
+// products above.  complex128: the direct form, four v_mfma_f64_16x16x4f64 (same operand
+// layout, lane l: A[l%16][l/16], B[l/16][l%16]; D[l/16+4v][l%16]).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct CAcc;
+template <>
+struct CAcc<float> {
+  f32x4 p1, p2, p3;
+  __device__ __forceinline__ void zero() { p1 = p2 = p3 = f32x4{0.f, 0.f, 0.f, 0.f}; }
+  __device__ __forceinline__ void mac(c64 a, c64 b) { mfma_3m(a, b, p1, p2, p3); }
+  __device__ __forceinline__ c64 get(int v) const { return cmk(p1[v] - p2[v], p3[v] - p1[v] - p2[v]); }
+  static __device__ __forceinline__ int row(int lq, int v) { return 4 * lq + v; }
+};
+template <>
+struct CAcc<double> {
+  f64x4 re, im;
+  __device__ __forceinline__ void zero() { re = im = f64x4{0.0, 0.0, 0.0, 0.0}; }
+  __device__ __forceinline__ void mac(c128 a, c128 b) {
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, re, 0, 0, 0);
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, b.im, re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.im, im, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.re, im, 0, 0, 0);
+  }
+  __device__ __forceinline__ c128 get(int v) const { return cmk(re[v], im[v]); }
+  static __device__ __forceinline__ int row(int lq, int v) { return lq + 4 * v; }
+};
+
 // Forward rows [i0, i0 + 64 MT) (the k_fwd_gemm product on a wider tile): wavefront wv owns
 // MT tiles of 16 rows, NG groups of 16 columns.  Each thread stages a fixed share of the next
 // chunk in registers (loads from a clamped, always valid index, so they issue back to back)
@@ -236,15 +264,15 @@ __device__ __forceinline__ void mfma_3m(c64 a, c64 b, f32x4& p1, f32x4& p2, f32x
 // in the order of k_fwd_assemble (own, child 0, child 1), so the result is the same.  That
 // form saves the assembly pass where fronts have no children (the leaves); above them the
 // gathers through the child maps cost more than the pass.
-template <int NG, int MT, int JC, bool ASSEMBLED>
+template <typename T, int NG, int MT, int JC, bool ASSEMBLED>
 __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
-                                                  const c64* __restrict__ L, const int32_t* __restrict__ imap,
-                                                  const c64* __restrict__ bin, c64* __restrict__ wbuf,
-                                                  c64* __restrict__ bout, int s) {
+                                                  const cplx<T>* __restrict__ L, const int32_t* __restrict__ imap,
+                                                  const cplx<T>* __restrict__ bin, cplx<T>* __restrict__ wbuf,
+                                                  cplx<T>* __restrict__ bout, int s) {
   constexpr int RT = 64 * MT, SC = 16 * NG;
   constexpr int NF = JC * RT / 256, NW = JC * SC / 256;
-  __shared__ c64 Ft[JC][RT + 1];
-  __shared__ c64 Wt[JC][SC];
+  __shared__ cplx<T> Ft[JC][RT + 1];
+  __shared__ cplx<T> Wt[JC][SC];
   const int fid = work[2 * blockIdx.x];
   if (fid < 0) return;  // padding entry of the XCD-interleaved worklist (block-uniform)
   const int64_t i0 = work[2 * blockIdx.x + 1];
@@ -254,13 +282,13 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
   const int tid = threadIdx.x;
   const int wv = tid >> 6, l = tid & 63;
   const int lr = l & 15, lq = l >> 4;
-  const c64* Lf = L + F.L_off;
-  const c64* wp = wbuf + F.w_off * s;              // the assembled work block
-  const c64* bp = bin + (F.vec_off + F.pos0) * s;  // pivot rows of the right-hand side
+  const cplx<T>* Lf = L + F.L_off;
+  const cplx<T>* wp = wbuf + F.w_off * s;              // the assembled work block
+  const cplx<T>* bp = bin + (F.vec_off + F.pos0) * s;  // pivot rows of the right-hand side
   const int32_t* m0 = imap + F.imap_off;           // parent row -> child row (or -1), per child
   const int32_t* m1 = m0 + f;
-  const c64* w0 = nullptr;  // the children's update rows (only children that have some)
-  const c64* w1 = nullptr;
+  const cplx<T>* w0 = nullptr;  // the children's update rows (only children that have some)
+  const cplx<T>* w1 = nullptr;
   if (!ASSEMBLED && F.child0 >= 0) {
     const FrontDesc C = fr[F.child0];
     if (C.r > 0) w0 = wbuf + (C.w_off + C.p) * s;
@@ -269,8 +297,8 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
     const FrontDesc C = fr[F.child1];
     if (C.r > 0) w1 = wbuf + (C.w_off + C.p) * s;
   }
-  const c64 zero = cmk(0.f, 0.f);
-  c64 rf[NF], rb[NW], r0[NW], r1[NW];
+  const cplx<T> zero = cmk((T)0, (T)0);
+  cplx<T> rf[NF], rb[NW], r0[NW], r1[NW];
   int32_t q0[NW], q1[NW];
   auto fetch = [&](int64_t j) {
     const int jn = (int)min<int64_t>(JC, jend - j);
@@ -295,11 +323,11 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
       }
     }
   };
-  f32x4 p1[MT][NG], p2[MT][NG], p3[MT][NG];
+  CAcc<T> acc[MT][NG];
 #pragma unroll
   for (int m = 0; m < MT; ++m)
 #pragma unroll
-    for (int g = 0; g < NG; ++g) p1[m][g] = p2[m][g] = p3[m][g] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int g = 0; g < NG; ++g) acc[m][g].zero();
   fetch(0);
   for (int64_t j = 0; j < jend; j += JC) {
     const int jn = (int)min<int64_t>(JC, jend - j);
@@ -312,7 +340,7 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
 #pragma unroll
     for (int u = 0; u < NW; ++u) {
       const int e = tid + 256 * u, jj = e / SC, c = e - (e / SC) * SC;
-      c64 v = rb[u];
+      cplx<T> v = rb[u];
       if (w0) v = v + csel(q0[u] >= 0, r0[u], zero);
       if (w1) v = v + csel(q1[u] >= 0, r1[u], zero);
       Wt[jj][c] = csel(jj < jn && c < s, v, zero);
@@ -325,14 +353,14 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
 #pragma unroll 2
     for (int t = 0; t < steps; ++t) {
       const int kc = 4 * t + lq;
-      c64 wb[NG];
+      cplx<T> wb[NG];
 #pragma unroll
       for (int g = 0; g < NG; ++g) wb[g] = Wt[kc][16 * g + lr];
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
-        const c64 av = Ft[kc][16 * (wv * MT + m) + lr];
+        const cplx<T> av = Ft[kc][16 * (wv * MT + m) + lr];
 #pragma unroll
-        for (int g = 0; g < NG; ++g) mfma_3m(av, wb[g], p1[m][g], p2[m][g], p3[m][g]);
+        for (int g = 0; g < NG; ++g) acc[m][g].mac(av, wb[g]);
       }
     }
   }
@@ -344,16 +372,16 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
       if (c >= s) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t i = i0 + 16 * (wv * MT + m) + 4 * lq + v;
+        const int64_t i = i0 + 16 * (wv * MT + m) + CAcc<T>::row(lq, v);
         if (i >= f) continue;
-        const c64 val = cmk(p1[m][g][v] - p2[m][g][v], p3[m][g][v] - p1[m][g][v] - p2[m][g][v]);
+        const cplx<T> val = acc[m][g].get(v);
         if (i < F.p) {
           bout[(F.vec_off + F.pos0 + i) * s + c] = val;
         } else if (ASSEMBLED) {
-          c64* w = &wbuf[(F.w_off + i) * s + c];
+          cplx<T>* w = &wbuf[(F.w_off + i) * s + c];
           *w = *w - val;
         } else {  // update row: (0 + child 0 + child 1) - F_bot w_p
-          c64 wr = zero;
+          cplx<T> wr = zero;
           if (w0) {
             const int32_t q = m0[i];
             if (q >= 0) wr = wr + w0[(int64_t)q * s + c];
@@ -373,15 +401,15 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
 // forward kernel.  u rows below the pivot block are gathered through the update-row map;
 // the row indices are loaded first, so the factor loads stay in flight while the dependent
 // gathers wait for them.
-template <int NG, int NT, int RC>
+template <typename T, int NG, int NT, int RC>
 __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
-                                                  const c64* __restrict__ L, const int32_t* __restrict__ urows,
-                                                  const c64* __restrict__ dinv, const c64* __restrict__ bout,
-                                                  c64* __restrict__ bin, int s) {
+                                                  const cplx<T>* __restrict__ L, const int32_t* __restrict__ urows,
+                                                  const cplx<T>* __restrict__ dinv, const cplx<T>* __restrict__ bout,
+                                                  cplx<T>* __restrict__ bin, int s) {
   constexpr int CT = 64 * NT, SC = 16 * NG;
   constexpr int NF = RC * CT / 256, NU = RC * SC / 256;
-  __shared__ c64 Ft[RC][CT + 1];
-  __shared__ c64 Ut[RC][SC];
+  __shared__ cplx<T> Ft[RC][CT + 1];
+  __shared__ cplx<T> Ut[RC][SC];
   const int fid = work[2 * blockIdx.x];
   if (fid < 0) return;  // padding entry of the XCD-interleaved worklist (block-uniform)
   const int64_t j0 = work[2 * blockIdx.x + 1];
@@ -391,10 +419,10 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ wo
   const int tid = threadIdx.x;
   const int wv = tid >> 6, l = tid & 63;
   const int lr = l & 15, lq = l >> 4;
-  const c64* Lf = L + F.L_off;
+  const cplx<T>* Lf = L + F.L_off;
   const int64_t pbase = F.vec_off + F.pos0;  // first pivot position: a valid clamp target
-  const c64 zero = cmk(0.f, 0.f);
-  c64 rf[NF], rx[NU], rd[NU];
+  const cplx<T> zero = cmk((T)0, (T)0);
+  cplx<T> rf[NF], rx[NU], rd[NU];
   auto fetch = [&](int64_t i) {
     const int rn = (int)min<int64_t>(RC, f - i);
     // update-row indices from a clamped (valid) index; a front without update rows reads
@@ -427,11 +455,11 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ wo
       rd[u] = dinv[(ok && piv) ? pos : pbase];
     }
   };
-  f32x4 p1[NT][NG], p2[NT][NG], p3[NT][NG];
+  CAcc<T> acc[NT][NG];
 #pragma unroll
   for (int m = 0; m < NT; ++m)
 #pragma unroll
-    for (int g = 0; g < NG; ++g) p1[m][g] = p2[m][g] = p3[m][g] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int g = 0; g < NG; ++g) acc[m][g].zero();
   fetch(j0);
   for (int64_t i = j0; i < f; i += RC) {
     const int rn = (int)min<int64_t>(RC, f - i);
@@ -446,7 +474,7 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ wo
       const int e = tid + 256 * u, rr = e / SC, c = e - (e / SC) * SC;
       const bool ok = rr < rn && c < s;
       const bool piv = i + rr < F.p;
-      const c64 x = rx[u];
+      const cplx<T> x = rx[u];
       Ut[rr][c] = csel(ok, csel(piv, x * rd[u], cmk(-x.re, -x.im)), zero);
     }
     __syncthreads();
@@ -455,14 +483,14 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ wo
 #pragma unroll 2
     for (int t = 0; t < steps; ++t) {
       const int rr = 4 * t + lq;
-      c64 ub[NG];
+      cplx<T> ub[NG];
 #pragma unroll
       for (int g = 0; g < NG; ++g) ub[g] = Ut[rr][16 * g + lr];
 #pragma unroll
       for (int m = 0; m < NT; ++m) {
-        const c64 av = Ft[rr][16 * (wv * NT + m) + lr];
+        const cplx<T> av = Ft[rr][16 * (wv * NT + m) + lr];
 #pragma unroll
-        for (int g = 0; g < NG; ++g) mfma_3m(av, ub[g], p1[m][g], p2[m][g], p3[m][g]);
+        for (int g = 0; g < NG; ++g) acc[m][g].mac(av, ub[g]);
       }
     }
   }
@@ -474,19 +502,17 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ wo
       if (c >= s) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int jj = 16 * (wv * NT + m) + 4 * lq + v;
-        if (jj < nj)
-          bin[(F.vec_off + F.pos0 + j0 + jj) * s + c] =
-              cmk(p1[m][g][v] - p2[m][g][v], p3[m][g][v] - p1[m][g][v] - p2[m][g][v]);
+        const int jj = 16 * (wv * NT + m) + CAcc<T>::row(lq, v);
+        if (jj < nj) bin[(F.vec_off + F.pos0 + j0 + jj) * s + c] = acc[m][g].get(v);
       }
     }
 }
 
-// Matrix-core sweeps serve complex64 blocks of at least 8 columns; narrower blocks (and
-// complex128) stay on the vector-unit kernels.
+// Matrix-core sweeps serve blocks of at least 8 columns (complex64 in the three-product form,
+// complex128 in the direct form); narrower blocks stay on the vector-unit kernels.
 template <typename T, int S>
 constexpr bool use_mfma() {
-  return std::is_same<T, float>::value && S >= 8;
+  return S >= 8;
 }
 
 template <typename T>
@@ -522,16 +548,17 @@ void sweep_valu(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* w
   HIP_CHECK(hipGetLastError());
 }
 
-// Matrix-core sweeps (complex64, 8..32 columns).  The tile of each level and direction is one
+// Matrix-core sweeps (8..32 columns; complex64 or complex128).  The tile of each level and direction is one
 // of two sizes; the first apply for a column-group width times both on every level (all tile
 // sizes give bit-identical results, and every timed launch is repeated exactly as the real
 // one: a forward level above the leaves re-assembles its work block before each try) and
 // keeps the faster one.
-template <int S>
-void sweep_mfma(Ctx* ctx, Ddm& d, int s, c64* bin, c64* bout, c64* wbuf) {
+template <typename T, int S>
+void sweep_mfma(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) {
   constexpr int NG = (S + 15) / 16;
   hipStream_t st = ctx->stream;
-  const c64* L = d.d_factor.as<c64>();
+  const cplx<T>* L = d.d_factor.as<cplx<T>>();
+  const double esz = (double)sizeof(cplx<T>);
   const size_t nl = d.levels.size();
   const int gi = NG - 1;
   const bool tune = d.tile_fwd[gi].size() != nl;
@@ -540,40 +567,40 @@ void sweep_mfma(Ctx* ctx, Ddm& d, int s, c64* bin, c64* bout, c64* wbuf) {
     const int32_t* wl = d.d_fwdm_work[t].ptr() + 2 * d.fwdm_off[t][lv];
     const bool kids = lv > 0;  // leaves form their work block themselves
     if (t == 0 && kids)
-      hipLaunchKernelGGL((k_fwd_mfma<NG, kFwdRowsMfma[0] / 64, 32, true>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(),
+      hipLaunchKernelGGL((k_fwd_mfma<T, NG, kFwdRowsMfma[0] / 64, 32, true>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(),
                          L, d.d_imap.ptr(), bin, wbuf, bout, s);
     else if (t == 0)
-      hipLaunchKernelGGL((k_fwd_mfma<NG, kFwdRowsMfma[0] / 64, 32, false>), grid, dim3(256), 0, st, wl,
+      hipLaunchKernelGGL((k_fwd_mfma<T, NG, kFwdRowsMfma[0] / 64, 32, false>), grid, dim3(256), 0, st, wl,
                          d.d_fronts.ptr(), L, d.d_imap.ptr(), bin, wbuf, bout, s);
     else if (kids)
-      hipLaunchKernelGGL((k_fwd_mfma<NG, kFwdRowsMfma[1] / 64, 32, true>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(),
+      hipLaunchKernelGGL((k_fwd_mfma<T, NG, kFwdRowsMfma[1] / 64, 32, true>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(),
                          L, d.d_imap.ptr(), bin, wbuf, bout, s);
     else
-      hipLaunchKernelGGL((k_fwd_mfma<NG, kFwdRowsMfma[1] / 64, 32, false>), grid, dim3(256), 0, st, wl,
+      hipLaunchKernelGGL((k_fwd_mfma<T, NG, kFwdRowsMfma[1] / 64, 32, false>), grid, dim3(256), 0, st, wl,
                          d.d_fronts.ptr(), L, d.d_imap.ptr(), bin, wbuf, bout, s);
   };
   auto bwd = [&](size_t lv, int t) {
     const dim3 grid((unsigned)(d.bwdm_off[t][lv + 1] - d.bwdm_off[t][lv]));
     const int32_t* wl = d.d_bwdm_work[t].ptr() + 2 * d.bwdm_off[t][lv];
     if (t == 0)
-      hipLaunchKernelGGL((k_bwd_mfma<NG, kBwdColsMfma[0] / 64, 32>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(), L,
-                         d.d_urows.ptr(), d.d_dinv.as<c64>(), bout, bin, s);
+      hipLaunchKernelGGL((k_bwd_mfma<T, NG, kBwdColsMfma[0] / 64, 32>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(), L,
+                         d.d_urows.ptr(), d.d_dinv.as<cplx<T>>(), bout, bin, s);
     else
-      hipLaunchKernelGGL((k_bwd_mfma<NG, kBwdColsMfma[1] / 64, 32>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(), L,
-                         d.d_urows.ptr(), d.d_dinv.as<c64>(), bout, bin, s);
+      hipLaunchKernelGGL((k_bwd_mfma<T, NG, kBwdColsMfma[1] / 64, 32>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(), L,
+                         d.d_urows.ptr(), d.d_dinv.as<cplx<T>>(), bout, bin, s);
   };
   if (!tune) {
     for (size_t lv = 0; lv < nl; ++lv) {
-      if (lv > 0) fwd_assemble<float>(ctx, d, lv, s, bin, wbuf);
+      if (lv > 0) fwd_assemble<T>(ctx, d, lv, s, bin, wbuf);
       const Level& Lv = d.levels[lv];
       // algorithmic traffic: the level's stored factor once, its work rows read and written once
-      ProfScope ps(ctx, HZ_K_ORAS_FWD, 8.0 * ((double)Lv.useful + 2.0 * (double)Lv.sum_f * s),
+      ProfScope ps(ctx, HZ_K_ORAS_FWD, esz * ((double)Lv.useful + 2.0 * (double)Lv.sum_f * s),
                    8.0 * (double)Lv.useful * s);
       fwd(lv, d.tile_fwd[gi][lv]);
     }
     for (size_t lv = nl; lv-- > 0;) {
       const Level& Lv = d.levels[lv];
-      ProfScope ps(ctx, HZ_K_ORAS_BWD, 8.0 * ((double)Lv.useful + (double)(Lv.sum_f + Lv.sum_p) * s),
+      ProfScope ps(ctx, HZ_K_ORAS_BWD, esz * ((double)Lv.useful + (double)(Lv.sum_f + Lv.sum_p) * s),
                    8.0 * (double)Lv.useful * s);
       bwd(lv, d.tile_bwd[gi][lv]);
     }
@@ -588,7 +615,7 @@ void sweep_mfma(Ctx* ctx, Ddm& d, int s, c64* bin, c64* bout, c64* wbuf) {
   for (size_t lv = 0; lv < nl; ++lv)
     for (int rep = 0; rep < 2; ++rep)
       for (int t = 0; t < 2; ++t) {
-        if (lv > 0) fwd_assemble<float>(ctx, d, lv, s, bin, wbuf);
+        if (lv > 0) fwd_assemble<T>(ctx, d, lv, s, bin, wbuf);
         if (rep) HIP_CHECK(hipEventRecord(at(0, lv, t, 0), st));
         fwd(lv, t);
         if (rep) HIP_CHECK(hipEventRecord(at(0, lv, t, 1), st));
@@ -618,7 +645,7 @@ void sweep_mfma(Ctx* ctx, Ddm& d, int s, c64* bin, c64* bout, c64* wbuf) {
 template <typename T, int S>
 void sweep(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) {
   if constexpr (use_mfma<T, S>())
-    sweep_mfma<S>(ctx, d, s, bin, bout, wbuf);
+    sweep_mfma<T, S>(ctx, d, s, bin, bout, wbuf);
   else
     sweep_valu<T, S>(ctx, d, s, bin, bout, wbuf);
 }
