@@ -220,6 +220,30 @@ def test_fgmres_fixed_iterations_c128(case, ddm_case, ctx):
             np.testing.assert_allclose([i["rel_residual"] for i in info], io["rel_residual"], rtol=1e-8)
 
 
+def test_fgmres_fixed_iterations_wide_block(ctx):
+    """12 steps of a 32-column block (a least-squares problem of 384 x 384 blocks of 32, over
+    the 10240 entries of the small register layout of the back substitution) on a problem that
+    is still far from converged after them (cube 6 at 8 Hz, no overlap, so no column becomes
+    dependent): FP64 parity 1e-10 and equal residual estimates."""
+    p = w.unit_cube_problem(6, freq=8.0, parts=(2, 2, 2), overlap=0)
+    om = fem.Mesh(p.tets, p.coords, p.face_bc)
+    A = fem.assemble_operator(om, p.velocity, p.freq, p.quality)
+    gm = ctx.mesh(p.tets, p.coords, p.face_bc)
+    gop = ctx.assemble(gm, p.velocity, p.freq, p.quality)
+    d = ctx.setup_ddm(gop, p.partition, p.n_sub, p.overlap)
+    subs, own = odd.build_subdomains(om, p.velocity, p.freq, p.quality, p.partition, p.n_sub, p.overlap)
+    odd.factor_subdomains(subs)
+    P = odd.ORAS(A, subs)
+    rng = np.random.default_rng(21)
+    B = rng.standard_normal((32, om.n)) + 1j * rng.standard_normal((32, om.n))
+    X, info = ctx.solve(d, B, fixed_iters=12, restart=12)
+    Xo, io = krylov.block_fgmres(lambda x: A @ x, B.T, P.apply, fixed_iters=12, m=12)
+    assert min(io["rel_residual"]) > 1e-3  # not converged: every Arnoldi block has full rank
+    assert _rel(X, Xo.T) <= 1e-10, _rel(X, Xo.T)
+    np.testing.assert_allclose([i["rel_residual"] for i in info], io["rel_residual"], rtol=1e-8)
+    ctx.release(d)
+
+
 def test_solve_to_tolerance_matches_direct(ctx):
     """cube 4, 8 subdomains: ORAS-FGMRES to 1e-12 equals the dense direct solve to 1e-9."""
     p = w.unit_cube_problem(4, freq=1.0, parts=(2, 2, 2), overlap=1)
