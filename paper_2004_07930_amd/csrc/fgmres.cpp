@@ -134,11 +134,17 @@ void FgmresJob::start() {
   total = 0;
   restarts = 0;
   start_cycle();
+  HIP_CHECK(hipMemcpyAsync(&hflag, flag.ptr(), sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  HZ_REQUIRE(hflag == 0, HZ_ERR_ARG,
+             "hz_solve: the right-hand-side block is numerically rank deficient (dependent columns): "
+             "solve such columns in separate blocks");
 }
 
 void FgmresJob::start_cycle() {
   hipStream_t st = ctx->stream;
   const c128 one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
+  HIP_CHECK(hipMemsetAsync(flag.ptr(), 0, sizeof(int), st));
   if (total == 0)
     HIP_CHECK(hipMemcpyAsync(R.ptr(), B, n * s * sizeof(c128), hipMemcpyDeviceToDevice, st));
   else
@@ -168,6 +174,7 @@ void FgmresJob::after_matvec() {
                            hipMemcpyDeviceToDevice, st));
   K.lsq_step(jj, Hc.ptr(), Rm.ptr(), ldr, refl.ptr(), tau.ptr(), tmat.ptr(), G.ptr(), res.ptr());
   HIP_CHECK(hipMemcpyAsync(est.data(), res.ptr(), s * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(&hflag, flag.ptr(), sizeof(int), hipMemcpyDeviceToHost, st));
 }
 
 bool FgmresJob::cycle_done() {
@@ -175,7 +182,10 @@ bool FgmresJob::cycle_done() {
   ++total;
   bool conv = true;
   for (int c = 0; c < s; ++c) conv = conv && (est[c] / bnorm[c] <= o.tol);
-  const bool end = o.fixed_iters > 0 ? jj + 1 >= o.fixed_iters : (conv || total >= o.max_iter || jj + 1 >= m);
+  // a CholQR breakdown (the new block is numerically dependent on the basis: the Krylov
+  // space is exhausted for some column) ends the cycle at this step
+  const bool brk = hflag != 0;
+  const bool end = brk || (o.fixed_iters > 0 ? jj + 1 >= o.fixed_iters : (conv || total >= o.max_iter || jj + 1 >= m));
   if (!end) ++jj;
   return end;
 }
@@ -199,19 +209,23 @@ bool FgmresJob::end_cycle() {
     rel[c] = rn[c] / bnorm[c];
     conv = conv && rel[c] <= o.tol;
   }
-  if (o.fixed_iters > 0 || conv || total >= o.max_iter) {
-    info.assign(s, ColInfo{});
-    for (int c = 0; c < s; ++c) {
-      info[c].iters = total;
-      info[c].restarts = restarts;
-      info[c].rel_residual = rel[c];
-      info[c].status = (o.fixed_iters > 0 || rel[c] <= o.tol) ? HZ_OK : HZ_ERR_NOT_CONVERGED;
-    }
-    return true;
+  if (!(o.fixed_iters > 0 || conv || total >= o.max_iter)) {
+    ++restarts;
+    start_cycle();
+    HIP_CHECK(hipMemcpyAsync(&hflag, flag.ptr(), sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    if (hflag == 0) return false;
+    // the new residual block is numerically rank deficient: no further cycle can start, and
+    // the columns are reported as they stand
   }
-  ++restarts;
-  start_cycle();
-  return false;
+  info.assign(s, ColInfo{});
+  for (int c = 0; c < s; ++c) {
+    info[c].iters = total;
+    info[c].restarts = restarts;
+    info[c].rel_residual = rel[c];
+    info[c].status = (o.fixed_iters > 0 || rel[c] <= o.tol) ? HZ_OK : HZ_ERR_NOT_CONVERGED;
+  }
+  return true;
 }
 
 void fgmres(Ctx* ctx, std::shared_ptr<Ddm> d, int s, const c128* B, c128* X, const SolveOptions& o,

@@ -67,6 +67,7 @@ struct FgmresJob {
   DevArray<int> flag;
   std::vector<double> bnorm, est, rel;
   int total = 0, restarts = 0, jj = 0;
+  int hflag = 0;  // host copy of the CholQR breakdown flag (a numerically dependent block)
   std::vector<ColInfo> info;
 
   FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c128* X_, const SolveOptions& o_, int m_);

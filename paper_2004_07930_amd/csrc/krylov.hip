@@ -363,7 +363,7 @@ __global__ void k_right_mult(int64_t n, int s, const c128* __restrict__ W, const
 }
 
 // Cholesky G = R^H R (upper R, real positive diagonal), Rinv = R^{-1}; Racc = R * Racc.
-// flag[0] = 1 on breakdown (non-positive pivot).  One block, s <= 32.
+// flag[0] = 1 on breakdown (a pivot below 1e-14 of its diagonal entry).  One block, s <= 32.
 __global__ __launch_bounds__(256) void k_chol_small(int s, const c128* __restrict__ G, c128* __restrict__ R,
                                                     c128* __restrict__ Rinv, c128* __restrict__ Racc,
                                                     int* __restrict__ flag) {
@@ -382,9 +382,11 @@ __global__ __launch_bounds__(256) void k_chol_small(int s, const c128* __restric
     if (t == 0) {
       double d = A[k][k].re;
       const double scale = fabs(G[k * s + k].re) + 1e-300;
-      if (!(d > 1e-28 * scale) || !isfinite(d)) {
+      // breakdown: the column's part orthogonal to the ones before it is below 1e-7 of its
+      // norm (d / G_kk < 1e-14), where CholQR can no longer recover orthogonality
+      if (!(d > 1e-14 * scale) || !isfinite(d)) {
         flag[0] = 1;
-        d = fmax(d, 1e-28 * scale);
+        d = fmax(d, 1e-14 * scale);
       }
       Rs[k][k] = cmk(sqrt(d), 0.0);
     }

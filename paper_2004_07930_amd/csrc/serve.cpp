@@ -60,7 +60,7 @@ struct Ticket {
   int admitted = 0;      // parts admitted by the scheduler
   int finished = 0;      // parts done
   int64_t held = 0;      // memory reserved for the admitted parts (and the host copies)
-  bool oom = false;      // a part could not be allocated even with nothing else running
+  bool oom = false;      // a part could not start: no memory even alone, or a dependent block
   DevArray<c128> Bu;     // device copy of the rhs in user layout (host requests only)
   struct Part {
     int c0 = 0, s = 0;
@@ -284,7 +284,7 @@ static void scheduler(Serve* S) {
         try {
           start_part(*S, *t, k);
         } catch (const Error& e) {
-          if (e.code != HZ_ERR_OOM) throw;
+          if (e.code != HZ_ERR_OOM && e.code != HZ_ERR_ARG) throw;
           std::lock_guard<std::mutex> lk(S->mu);
           // undo this and every later admission of this round, latest first (FIFO order)
           for (size_t b = admit.size(); b-- > a;) {
@@ -296,8 +296,8 @@ static void scheduler(Serve* S) {
             --tb->admitted;
             if (S->queue.empty() || S->queue.front() != tb) S->queue.push_front(tb);
           }
-          if (S->active_parts == 0) {  // the part cannot fit even alone: the request fails
-            t->status = HZ_ERR_OOM;
+          if (e.code == HZ_ERR_ARG || S->active_parts == 0) {  // bad block, or it cannot fit even alone:
+            t->status = e.code;                                  // the request fails
             t->oom = true;
           }
           break;

@@ -343,7 +343,9 @@ def test_mixed_precision_reaches_tolerance(ctx):
 
 def test_solve_failure_paths(ctx):
     """Non-finite right-hand side -> HZ_ERR_ARG; max_iter reached -> HZ_ERR_NOT_CONVERGED with
-    the best iterate and its residual returned (the residual is that of the returned x)."""
+    the best iterate and its residual returned (the residual is that of the returned x); a
+    block with dependent columns -> HZ_ERR_ARG; a block that becomes dependent while iterating
+    (every column converged to rounding) ends its cycle instead of breaking down."""
     from paper_2004_07930_amd import hz
 
     p = w.unit_cube_problem(3, freq=1.5, parts=(2, 2, 1), overlap=1)
@@ -368,6 +370,19 @@ def test_solve_failure_paths(ctx):
     res = np.linalg.norm(B.T - A @ X.T, axis=0) / np.linalg.norm(B, axis=1)
     np.testing.assert_allclose(res, [i["rel_residual"] for i in info], rtol=1e-8)
     assert res.max() < 1.0  # one preconditioned step already reduces the residual
+    # dependent columns (block CholQR breakdown at the start) -> HZ_ERR_ARG, nothing solved
+    with pytest.raises(hz.HzError) as e:
+        ctx.solve(d, np.stack([B[0], B[1], 2j * B[0]]))
+    assert e.value.code == hz.HZ_ERR_ARG and "rank deficient" in str(e.value)
+    # iterating on past convergence: the Krylov block becomes dependent, the cycle ends at
+    # that step and the solution is returned converged and finite (no breakdown NaN)
+    B32 = rng.standard_normal((32, om.n)) + 1j * rng.standard_normal((32, om.n))
+    X, info = ctx.solve(d, B32, fixed_iters=12, restart=12)
+    assert np.isfinite(X).all()
+    res = np.linalg.norm(B32.T - A @ X.T, axis=0) / np.linalg.norm(B32, axis=1)
+    assert res.max() <= 1e-8 and info[0]["iters"] <= 12, (res.max(), info[0]["iters"])
+    np.testing.assert_allclose(res, [i["rel_residual"] for i in info], rtol=1e-3, atol=1e-13)
+    ctx.release(d)
 
 
 def test_sweep_tile_tuning(case, ctx):
