@@ -118,3 +118,28 @@ def test_serve_parts_admitted_one_at_a_time(setup):
     assert all(i["rel_residual"] <= 1e-6 for i in info1 + info2)
     assert _rel(x1, alone1) <= 1e-5 and _rel(x2, alone2) <= 1e-5
     assert st["completed"] == 2 and st["rejected"] == 0
+
+
+def test_serve_dependent_block_fails_alone(setup):
+    """A request whose columns are dependent fails with HZ_ERR_ARG (its part cannot start);
+    the scheduler keeps serving, and a request submitted beside it converges as if alone."""
+    from paper_2004_07930_amd import hz
+
+    ctx, ops = setup
+    p, d, F = ops[1]
+    bad = np.stack([F[0], F[1], 3.0 * F[0]])
+    good = F[2:5]
+    alone = ctx.solve(d, good, tol=1e-6)[0]
+    ctx.serve_start(max_slots=4)
+    try:
+        tb = ctx.submit(d, bad, tol=1e-6)
+        tg = ctx.submit(d, good, tol=1e-6)
+        _, _, sb = ctx.wait(tb)
+        xg, info, sg = ctx.wait(tg)
+        st = ctx.serve_stats()
+    finally:
+        ctx.serve_stop()
+    assert sb == hz.HZ_ERR_ARG
+    assert sg == 0 and all(i["rel_residual"] <= 1e-6 for i in info)
+    assert _rel(xg, alone) <= 1e-5
+    assert st["completed"] == 1 and st["rejected"] == 1
