@@ -158,8 +158,12 @@ typedef struct {
  * applied twice, CholQR2 block normalisation, Householder least squares, all FP64.
  *   rhs [n_rhs][n_dofs] complex128, x same layout (may not alias rhs)
  * Returns HZ_ERR_NOT_CONVERGED (x = best iterate, info filled) when max_iter is hit;
- * HZ_ERR_ARG for a non-finite entry in rhs, a negative or non-finite tol, n_rhs < 1 or null
- * x / info (x is then not written).
+ * HZ_ERR_ARG for a non-finite entry in rhs, a zero column, a block whose columns are
+ * numerically dependent (CholQR pivot below 1e-14 of its diagonal entry: solve such columns
+ * in separate blocks), a negative or non-finite tol, n_rhs < 1 or null x / info (x is then
+ * not written).  A step whose new block becomes dependent (every direction of some column
+ * exhausted) ends its restart cycle there; a residual block that is dependent at a restart
+ * ends the solve with the columns' status as they stand.
  */
 hz_status hz_solve(hz_ctx* ctx, hz_handle ddm, int64_t n_rhs, const void* rhs, int rhs_mem,
                    double tol, int32_t max_iter, void* x, int x_mem, hz_col_info* info);
@@ -282,9 +286,10 @@ typedef struct {
  *   (struct_size), HZ_ERR_BUSY (fits at no restart length >= 8: never admissible),
  *   HZ_ERR_STATE (not serving, or the scheduler failed).
  * hz_serve_poll: *done = 1 once the ticket completed.  hz_serve_wait: blocks until then,
- *   returns the request's status in *status (nullable; HZ_OK, HZ_ERR_NOT_CONVERGED, or
+ *   returns the request's status in *status (nullable; HZ_OK, HZ_ERR_NOT_CONVERGED,
  *   HZ_ERR_OOM when the allocator could not give one part its memory even with nothing else
- *   running; x is then undefined) and retires the ticket.  A part whose allocation fails
+ *   running, or HZ_ERR_ARG when a part's block is dependent or has a zero column; x is then
+ *   undefined) and retires the ticket.  A part whose allocation fails
  *   while others run waits for their memory.  Both: HZ_ERR_ARG for an unknown ticket.
  * hz_serve_stats_get: p50 / p99 of the submit-to-completion latency of completed requests,
  *   sources per second from the first submission to the last completion, counts.
