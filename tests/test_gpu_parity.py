@@ -152,10 +152,13 @@ def test_precond_one_level_c128(case, ddm_case, ctx):
     odd.factor_subdomains(subs)
     P = odd.ORAS(A, subs)
     rng = np.random.default_rng(11)
-    V = rng.standard_normal((4, om.n)) + 1j * rng.standard_normal((4, om.n))
-    Z = ctx.precond(d, V)
-    Zo = P.apply(V.T).T
-    assert _rel(Z, Zo) <= 1e-10, _rel(Z, Zo)
+    # 1 and 4 columns: vector-unit sweeps; 8..32: FP64 matrix-core sweeps (partial column
+    # groups at 8, 21; the first apply of each group width also times both tile sizes)
+    for s in (1, 4, 8, 16, 21, 32):
+        V = rng.standard_normal((s, om.n)) + 1j * rng.standard_normal((s, om.n))
+        Z = ctx.precond(d, V)
+        Zo = P.apply(V.T).T
+        assert _rel(Z, Zo) <= 1e-10, (s, _rel(Z, Zo))
     st = ctx.ddm_stats(d)
     assert st["static_pivots"] == 0
 
@@ -385,21 +388,23 @@ def test_solve_failure_paths(ctx):
     ctx.release(d)
 
 
-def test_sweep_tile_tuning(case, ctx):
-    """The first complex64 apply times both tile sizes on every level and keeps the faster;
+@pytest.mark.parametrize("prec", ["mixed", "c128"])
+def test_sweep_tile_tuning(case, ctx, prec):
+    """The first matrix-core apply times both tile sizes on every level and keeps the faster;
     tile sizes do not change results, so the tuning apply (which ends on the larger tiles) and
-    the tuned apply agree bit for bit."""
+    the tuned apply agree bit for bit (complex64 and complex128 sweeps)."""
     from paper_2004_07930_amd import hz
 
     name, p, om, gm, A, gop = case
-    d32 = ctx.setup_ddm(gop, p.partition, p.n_sub, p.overlap, precision=hz.HZ_PREC_MIXED)
-    assert all(l["fwd_tile_rows"] == 0 and l["bwd_tile_cols"] == 0 for l in ctx.ddm_levels(d32))
+    pr = hz.HZ_PREC_MIXED if prec == "mixed" else hz.HZ_PREC_C128
+    dd = ctx.setup_ddm(gop, p.partition, p.n_sub, p.overlap, precision=pr)
+    assert all(l["fwd_tile_rows"] == 0 and l["bwd_tile_cols"] == 0 for l in ctx.ddm_levels(dd))
     rng = np.random.default_rng(17)
     V = rng.standard_normal((16, om.n)) + 1j * rng.standard_normal((16, om.n))
-    Z1 = ctx.precond(d32, V)
-    lv = ctx.ddm_levels(d32)
-    print(name, "tiles", [(l["fwd_tile_rows"], l["bwd_tile_cols"]) for l in lv])
+    Z1 = ctx.precond(dd, V)
+    lv = ctx.ddm_levels(dd)
+    print(name, prec, "tiles", [(l["fwd_tile_rows"], l["bwd_tile_cols"]) for l in lv])
     assert all(l["fwd_tile_rows"] in (64, 128) and l["bwd_tile_cols"] in (64, 128) for l in lv)
-    Z2 = ctx.precond(d32, V)
+    Z2 = ctx.precond(dd, V)
     assert np.array_equal(Z1, Z2)
-    ctx.release(d32)
+    ctx.release(dd)
