@@ -54,13 +54,15 @@ __global__ void k_scatter_owner(int64_t n, int s, const int64_t* __restrict__ ow
 template <typename T>
 __global__ __launch_bounds__(256) void k_fwd_assemble(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
                                                       const int32_t* __restrict__ imap, const cplx<T>* __restrict__ bin,
-                                                      cplx<T>* __restrict__ wbuf, int s) {
+                                                      cplx<T>* __restrict__ wbuf, int s, int pivots_only) {
   const int fid = work[2 * blockIdx.x];
   if (fid < 0) return;  // padding entry of the XCD-interleaved worklist (block-uniform)
   const int64_t i0 = work[2 * blockIdx.x + 1];
   const FrontDesc F = fr[fid];
   const int64_t f = F.p + F.r;
-  const int64_t tot = (min<int64_t>(f, i0 + 64) - i0) * s;
+  const int64_t iend = pivots_only ? F.p : f;  // the matrix-core sweeps form update rows themselves
+  if (i0 >= iend) return;
+  const int64_t tot = (min<int64_t>(iend, i0 + 64) - i0) * s;
   const cplx<T>* w0 = nullptr;
   const cplx<T>* w1 = nullptr;
   if (F.child0 >= 0) {
@@ -258,12 +260,12 @@ struct CAcc<double> {
 // chunk in registers (loads from a clamped, always valid index, so they issue back to back)
 // while the current chunk is multiplied out of LDS; the bounds predicate is applied when the
 // registers are written to LDS, so the loads stay in flight across the products.
-// ASSEMBLED: w was formed by k_fwd_assemble (its pivot rows are read, its update rows
-// updated in place).  Otherwise w = [b_p; 0] + the children's update contributions is never
-// stored: the pivot rows are summed as they are staged and the update rows in the epilogue,
-// in the order of k_fwd_assemble (own, child 0, child 1), so the result is the same.  That
-// form saves the assembly pass where fronts have no children (the leaves); above them the
-// gathers through the child maps cost more than the pass.
+// The update rows of w = [b_p; 0] + the children's update contributions are formed in the
+// epilogue, where each is read once, in the order of k_fwd_assemble (own, child 0, child 1).
+// The pivot rows, which every row tile multiplies, are read from the pass k_fwd_assemble
+// made of them (ASSEMBLED, fronts with children) or summed as they are staged (the leaves,
+// whose pivot rows are b_p alone): above the leaves, summing them in every tile would cost
+// more than the pass.
 template <typename T, int NG, int MT, int JC, bool ASSEMBLED>
 __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
                                                   const cplx<T>* __restrict__ L, const int32_t* __restrict__ imap,
@@ -289,11 +291,11 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
   const int32_t* m1 = m0 + f;
   const cplx<T>* w0 = nullptr;  // the children's update rows (only children that have some)
   const cplx<T>* w1 = nullptr;
-  if (!ASSEMBLED && F.child0 >= 0) {
+  if (F.child0 >= 0) {
     const FrontDesc C = fr[F.child0];
     if (C.r > 0) w0 = wbuf + (C.w_off + C.p) * s;
   }
-  if (!ASSEMBLED && F.child1 >= 0) {
+  if (F.child1 >= 0) {
     const FrontDesc C = fr[F.child1];
     if (C.r > 0) w1 = wbuf + (C.w_off + C.p) * s;
   }
@@ -313,11 +315,11 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
       const bool ok = jj < jn && c < s;
       const int64_t row = ok ? j + jj : 0, cc = ok ? c : 0;
       rb[u] = ASSEMBLED ? wp[row * s + cc] : bp[row * s + cc];
-      if (w0) {  // block-uniform tests
+      if (!ASSEMBLED && w0) {  // block-uniform tests
         q0[u] = m0[row];
         r0[u] = w0[(int64_t)max(q0[u], 0) * s + cc];
       }
-      if (w1) {
+      if (!ASSEMBLED && w1) {
         q1[u] = m1[row];
         r1[u] = w1[(int64_t)max(q1[u], 0) * s + cc];
       }
@@ -341,8 +343,8 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
     for (int u = 0; u < NW; ++u) {
       const int e = tid + 256 * u, jj = e / SC, c = e - (e / SC) * SC;
       cplx<T> v = rb[u];
-      if (w0) v = v + csel(q0[u] >= 0, r0[u], zero);
-      if (w1) v = v + csel(q1[u] >= 0, r1[u], zero);
+      if (!ASSEMBLED && w0) v = v + csel(q0[u] >= 0, r0[u], zero);
+      if (!ASSEMBLED && w1) v = v + csel(q1[u] >= 0, r1[u], zero);
       Wt[jj][c] = csel(jj < jn && c < s, v, zero);
     }
     __syncthreads();
@@ -377,9 +379,6 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
         const cplx<T> val = acc[m][g].get(v);
         if (i < F.p) {
           bout[(F.vec_off + F.pos0 + i) * s + c] = val;
-        } else if (ASSEMBLED) {
-          cplx<T>* w = &wbuf[(F.w_off + i) * s + c];
-          *w = *w - val;
         } else {  // update row: (0 + child 0 + child 1) - F_bot w_p
           cplx<T> wr = zero;
           if (w0) {
@@ -516,10 +515,10 @@ constexpr bool use_mfma() {
 }
 
 template <typename T>
-void fwd_assemble(Ctx* ctx, Ddm& d, size_t lv, int s, const cplx<T>* bin, cplx<T>* wbuf) {
+void fwd_assemble(Ctx* ctx, Ddm& d, size_t lv, int s, const cplx<T>* bin, cplx<T>* wbuf, bool pivots_only) {
   const unsigned nb = (unsigned)(d.fwd_off[lv + 1] - d.fwd_off[lv]);  // 64-row tiles of the level
   hipLaunchKernelGGL((k_fwd_assemble<T>), dim3(nb), dim3(256), 0, ctx->stream, d.d_fwd_work.ptr() + 2 * d.fwd_off[lv],
-                     d.d_fronts.ptr(), d.d_imap.ptr(), bin, wbuf, s);
+                     d.d_fronts.ptr(), d.d_imap.ptr(), bin, wbuf, s, pivots_only ? 1 : 0);
 }
 
 // Vector-unit sweeps (complex128, and complex64 blocks narrower than 8 columns).
@@ -529,7 +528,7 @@ void sweep_valu(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* w
   const cplx<T>* L = d.d_factor.as<cplx<T>>();
   const double esz = (double)sizeof(cplx<T>);
   for (size_t lv = 0; lv < d.levels.size(); ++lv) {
-    fwd_assemble<T>(ctx, d, lv, s, bin, wbuf);
+    fwd_assemble<T>(ctx, d, lv, s, bin, wbuf, false);
     const Level& Lv = d.levels[lv];
     // algorithmic traffic: the level's stored factor once, its work rows read and written once
     ProfScope ps(ctx, HZ_K_ORAS_FWD, esz * ((double)Lv.useful + 2.0 * (double)Lv.sum_f * s),
@@ -591,7 +590,7 @@ void sweep_mfma(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* w
   };
   if (!tune) {
     for (size_t lv = 0; lv < nl; ++lv) {
-      if (lv > 0) fwd_assemble<T>(ctx, d, lv, s, bin, wbuf);
+      if (lv > 0) fwd_assemble<T>(ctx, d, lv, s, bin, wbuf, true);
       const Level& Lv = d.levels[lv];
       // algorithmic traffic: the level's stored factor once, its work rows read and written once
       ProfScope ps(ctx, HZ_K_ORAS_FWD, esz * ((double)Lv.useful + 2.0 * (double)Lv.sum_f * s),
@@ -615,7 +614,7 @@ void sweep_mfma(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* w
   for (size_t lv = 0; lv < nl; ++lv)
     for (int rep = 0; rep < 2; ++rep)
       for (int t = 0; t < 2; ++t) {
-        if (lv > 0) fwd_assemble<T>(ctx, d, lv, s, bin, wbuf);
+        if (lv > 0) fwd_assemble<T>(ctx, d, lv, s, bin, wbuf, true);
         if (rep) HIP_CHECK(hipEventRecord(at(0, lv, t, 0), st));
         fwd(lv, t);
         if (rep) HIP_CHECK(hipEventRecord(at(0, lv, t, 1), st));
