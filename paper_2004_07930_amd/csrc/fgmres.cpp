@@ -1,13 +1,22 @@
 // Block FGMRES(m) as a resumable job (host control flow; all arithmetic in krylov.hip /
 // spmm.hip / oras.hip kernels).  One Arnoldi process per right-hand-side block:
 //   cycle:  R = B - A X ; [V_1, S] = CholQR2(R) ; G = [S; 0]
-//   step j: Z_j = M^{-1} V_j (stored in complex64 with the mixed-precision preconditioner:
-//           the flexible method multiplies and combines exactly the stored Z_j) ; W = A Z_j ; two passes of H = V^H W, W -= V H (CGS2) ;
-//           [V_{j+1}, H_{j+1,j}] = CholQR2(W) ; Householder update of the block Hessenberg
-//           QR applied to G ; per-column residual estimate |G_{j+1}| / |b|
+//   step j: Z_j = M^{-1} V~_j (stored in complex64 with the mixed-precision preconditioner:
+//           the flexible method multiplies and combines exactly the stored Z_j) ; W = A Z_j ;
+//           orthogonalisation of W against the basis ; Householder update of the block
+//           Hessenberg QR applied to G ; per-column residual estimate |G_{j+1}| / |b|
 //   end:    Y = R^{-1} G ; X += Z Y ; explicit residual decides restart.
+// Orthogonalisation, 16 columns: delayed reorthogonalisation (DCGS2).  W is projected once
+// (W' = W - V V^H W); W' is the block V~_{j+1} that the next step preconditions, and that
+// step projects it again and normalises it (V_{j+1}) in the same passes over the basis that
+// project its own product.  So each step reads the basis twice (one Gram product, one
+// update) instead of four times, and column j of the Hessenberg matrix is complete one step
+// later: the convergence test of column j runs at step j + 1, and the step known to be the
+// cycle's last finishes its own column with one more Gram product.  The flexible method
+// accepts Z_j = M^{-1} V~_j: A Z = V H holds for any Z, and x = Z y.
+// Other widths: two passes of H = V^H W, W -= V H (CGS2), then [V_{j+1}, H_{j+1,j}] = CholQR2(W).
 // hz_solve drives a job step by step; the serving scheduler interleaves many jobs and
-// packs their Z_j = M^{-1} V_j and W = A Z_j products into shared launches.
+// packs their Z_j = M^{-1} V~_j and W = A Z_j products into shared launches.
 #include <algorithm>
 #include <cmath>
 
@@ -20,9 +29,11 @@ int64_t FgmresJob::bytes_needed(int64_t n, int s, int m, bool z32) {
   const int64_t ns = n * s;
   const int nchunk = (int)((n + 4095) / 4096);
   const int64_t ldr = (int64_t)(m + 1) * s;
+  const int64_t pw = delayed(s) ? 2 : 1;                  // Gram products of width 2s
   int64_t e = ((int64_t)m + 4) * ns;                      // V, W, Wt, R
-  e += (int64_t)nchunk * (m + 1) * s * s;                 // partial sums
+  e += (int64_t)nchunk * (m + 2) * s * s * pw;            // partial sums
   e += (int64_t)(2 * m + 3) * s * s + (int64_t)m * s * ldr + 3 * (int64_t)m * s * s + ldr * s + 8 * s * s;
+  if (delayed(s)) e += (int64_t)(m + 2) * s * s + 2 * (int64_t)(m + 2) * s * 2 * s;  // Hc2, Gm, Cm
   return e * (int64_t)sizeof(c128) + (int64_t)m * ns * (int64_t)(z32 ? sizeof(c64) : sizeof(c128));  // + Z
 }
 
@@ -50,7 +61,8 @@ FgmresJob::FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c1
       m(m_),
       n(d->op->mesh->n),
       K(c, d->op->mesh->n, s_),
-      z32(d->precision == HZ_PREC_MIXED) {
+      z32(d->precision == HZ_PREC_MIXED),
+      dcgs(delayed(s_)) {
   HZ_REQUIRE(s >= 1 && s <= 32, HZ_ERR_ARG, "fgmres: block size must be 1..32");
   const int64_t ns = n * s;
   ldr = (int64_t)(m + 1) * s;
@@ -62,9 +74,15 @@ FgmresJob::FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c1
   W.alloc(ctx, ns);
   Wt.alloc(ctx, ns);
   R.alloc(ctx, ns);
-  part.alloc(ctx, (int64_t)K.nchunk * (m + 1) * s * s);
+  part.alloc(ctx, (int64_t)K.nchunk * (m + 2) * s * s * (dcgs ? 2 : 1));
   Hc.alloc(ctx, (int64_t)(m + 2) * s * s);
-  Hp.alloc(ctx, (int64_t)(m + 1) * s * s);
+  if (dcgs) {
+    Hc2.alloc(ctx, (int64_t)(m + 2) * s * s);
+    Gm.alloc(ctx, (int64_t)(m + 2) * s * 2 * s);
+    Cm.alloc(ctx, (int64_t)(m + 2) * s * 2 * s);
+  } else {
+    Hp.alloc(ctx, (int64_t)(m + 1) * s * s);
+  }
   Rm.alloc(ctx, (int64_t)m * s * ldr);
   refl.alloc(ctx, (int64_t)m * 2 * s * s);
   tau.alloc(ctx, (int64_t)m * s);
@@ -132,6 +150,7 @@ void FgmresJob::start() {
   }
   HIP_CHECK(hipMemsetAsync(X, 0, n * s * sizeof(c128), st));
   total = 0;
+  base = 0;
   restarts = 0;
   start_cycle();
   HIP_CHECK(hipMemcpyAsync(&hflag, flag.ptr(), sizeof(int), hipMemcpyDeviceToHost, st));
@@ -153,52 +172,88 @@ void FgmresJob::start_cycle() {
   HIP_CHECK(hipMemsetAsync(G.ptr(), 0, ldr * s * sizeof(c128), st));
   HIP_CHECK(hipMemcpyAsync(G.ptr(), Racc.ptr(), s * s * sizeof(c128), hipMemcpyDeviceToDevice, st));
   jj = 0;
+  base = total;
 }
 
-c128* FgmresJob::v_cur() { return V.ptr() + jj * n * s; }
+// delayed reorthogonalisation: step j >= 1 preconditions V~_j, the once-projected product of
+// step j - 1, kept in W (j even) or Wt (j odd); A Z_j goes to the other one and is projected
+// in place, becoming V~_{j+1}
+c128* FgmresJob::v_cur() {
+  if (dcgs && jj > 0) return (jj & 1) ? Wt.ptr() : W.ptr();
+  return V.ptr() + jj * n * s;
+}
+c128* FgmresJob::h_col(int j) { return (dcgs && (j & 1)) ? Hc2.ptr() : Hc.ptr(); }
 c128* FgmresJob::z_cur() { return z32 ? nullptr : Zb.ptr() + jj * n * s; }
 c64* FgmresJob::z32_cur() { return z32 ? Zs.ptr() + jj * n * s : nullptr; }
-c128* FgmresJob::w_cur() { return W.ptr(); }
+c128* FgmresJob::w_cur() { return (dcgs && !(jj & 1)) ? Wt.ptr() : W.ptr(); }
 
 void FgmresJob::after_matvec() {
   hipStream_t st = ctx->stream;
   const int64_t ns = n * s;
-  // CGS2
-  K.gram(jj + 1, V.ptr(), ns, W.ptr(), part.ptr(), Hc.ptr(), false);
-  K.block_axpy(jj + 1, V.ptr(), ns, Hc.ptr(), -1.0, W.ptr(), W.ptr());
-  K.gram(jj + 1, V.ptr(), ns, W.ptr(), part.ptr(), Hp.ptr(), false, Hc.ptr());
-  K.block_axpy(jj + 1, V.ptr(), ns, Hp.ptr(), -1.0, W.ptr(), W.ptr());
-  // V_{j+1} R = W
-  cholqr2(W.ptr(), V.ptr() + (jj + 1) * ns);
-  HIP_CHECK(hipMemcpyAsync(Hc.ptr() + (int64_t)(jj + 1) * s * s, Racc.ptr(), s * s * sizeof(c128),
-                           hipMemcpyDeviceToDevice, st));
-  K.lsq_step(jj, Hc.ptr(), Rm.ptr(), ldr, refl.ptr(), tau.ptr(), tmat.ptr(), G.ptr(), res.ptr());
+  last = jj + 1 >= m || (o.fixed_iters > 0 ? jj + 1 >= o.fixed_iters : base + jj + 1 >= o.max_iter);
+  if (!dcgs) {
+    // CGS2
+    K.gram(jj + 1, V.ptr(), ns, W.ptr(), part.ptr(), Hc.ptr(), false);
+    K.block_axpy(jj + 1, V.ptr(), ns, Hc.ptr(), -1.0, W.ptr(), W.ptr());
+    K.gram(jj + 1, V.ptr(), ns, W.ptr(), part.ptr(), Hp.ptr(), false, Hc.ptr());
+    K.block_axpy(jj + 1, V.ptr(), ns, Hp.ptr(), -1.0, W.ptr(), W.ptr());
+    // V_{j+1} R = W
+    cholqr2(W.ptr(), V.ptr() + (jj + 1) * ns);
+    HIP_CHECK(hipMemcpyAsync(Hc.ptr() + (int64_t)(jj + 1) * s * s, Racc.ptr(), s * s * sizeof(c128),
+                             hipMemcpyDeviceToDevice, st));
+    K.lsq_step(jj, Hc.ptr(), Rm.ptr(), ldr, refl.ptr(), tau.ptr(), tmat.ptr(), G.ptr(), res.ptr());
+  } else {
+    c128* w = w_cur();
+    c128* hn = h_col(jj);
+    if (jj == 0) {  // V_0 is final (CholQR2 of the residual): one projection
+      K.gram(1, V.ptr(), ns, w, part.ptr(), hn, false);
+      K.block_axpy(1, V.ptr(), ns, hn, -1.0, w, w);
+    } else {
+      // [V_<j, V~_j]^H [V~_j, W], the coefficients, then V_j and W' in one update
+      c128* vt = v_cur();
+      c128* hp = h_col(jj - 1);
+      K.gram_ext(jj + 1, V.ptr(), ns, jj, vt, vt, w, part.ptr(), Gm.ptr(), false);
+      K.dcgs_coef(jj * s, Gm.ptr(), Cm.ptr(), hp, hn, flag.ptr());
+      K.update_split(jj, V.ptr(), ns, vt, Cm.ptr(), V.ptr() + jj * ns, w, w);
+      K.lsq_step(jj - 1, hp, Rm.ptr(), ldr, refl.ptr(), tau.ptr(), tmat.ptr(), G.ptr(), res.ptr());
+    }
+    if (last) {  // finish column j: [V_<=j, W']^H W'
+      K.gram_ext(jj + 2, V.ptr(), ns, jj + 1, w, w, nullptr, part.ptr(), Gm.ptr(), false);
+      K.dcgs_coef((jj + 1) * s, Gm.ptr(), nullptr, nullptr, hn, flag.ptr());
+      K.lsq_step(jj, hn, Rm.ptr(), ldr, refl.ptr(), tau.ptr(), tmat.ptr(), G.ptr(), res.ptr());
+    }
+  }
   HIP_CHECK(hipMemcpyAsync(est.data(), res.ptr(), s * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipMemcpyAsync(&hflag, flag.ptr(), sizeof(int), hipMemcpyDeviceToHost, st));
 }
 
 bool FgmresJob::cycle_done() {
   // the caller has synchronised the stream since after_matvec()
-  ++total;
-  bool conv = true;
+  // Hessenberg columns complete in this cycle (the estimate refers to the last of them)
+  const int done = dcgs ? (last ? jj + 1 : jj) : jj + 1;
+  total = base + done;
+  bool conv = done > 0;
   for (int c = 0; c < s; ++c) conv = conv && (est[c] / bnorm[c] <= o.tol);
-  // a CholQR breakdown (the new block is numerically dependent on the basis: the Krylov
-  // space is exhausted for some column) ends the cycle at this step
+  // a CholQR breakdown (a new block numerically dependent on the basis: the Krylov space is
+  // exhausted for some column) ends the cycle at the column it completes
   const bool brk = hflag != 0;
-  const bool end = brk || (o.fixed_iters > 0 ? jj + 1 >= o.fixed_iters : (conv || total >= o.max_iter || jj + 1 >= m));
-  if (!end) ++jj;
+  const bool end = brk || last || (o.fixed_iters <= 0 && conv);
+  if (end)
+    ncols = done;
+  else
+    ++jj;
   return end;
 }
 
 bool FgmresJob::end_cycle() {
   hipStream_t st = ctx->stream;
   const c128 one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
-  const int J = (jj + 1) * s;
+  const int J = ncols * s;
   K.lsq_solve(J, Rm.ptr(), ldr, G.ptr(), Y.ptr());
   if (z32)
-    K.block_axpy(jj + 1, Zs.ptr(), n * s, Y.ptr(), 1.0, X, X);
+    K.block_axpy(ncols, Zs.ptr(), n * s, Y.ptr(), 1.0, X, X);
   else
-    K.block_axpy(jj + 1, Zb.ptr(), n * s, Y.ptr(), 1.0, X, X);
+    K.block_axpy(ncols, Zb.ptr(), n * s, Y.ptr(), 1.0, X, X);
   spmm(X, R.ptr(), mone, one, B);
   K.colnorms(R.ptr(), npart.ptr(), nrm.ptr());
   std::vector<double> rn(s);
@@ -233,7 +288,8 @@ void fgmres(Ctx* ctx, std::shared_ptr<Ddm> d, int s, const c128* B, c128* X, con
   const int m = FgmresJob::restart_for(ctx, d->op->mesh->n, s, o.restart, o.fixed_iters, d->precision == HZ_PREC_MIXED);
   FgmresJob job(ctx, d, s, B, X, o, m);
   job.start();
-  const int limit = (o.fixed_iters > 0 ? o.fixed_iters : o.max_iter) + 1;
+  // each cycle completes at least one column with at most one step more than it completes
+  const int limit = 2 * (o.fixed_iters > 0 ? o.fixed_iters : o.max_iter) + 1;
   for (int it = 0;; ++it) {
     HZ_REQUIRE(it <= limit, HZ_ERR_STATE, "fgmres: iteration bookkeeping error");
     job.matvec();

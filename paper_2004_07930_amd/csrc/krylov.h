@@ -18,6 +18,16 @@ struct KrylovKernels {
   // if H2 is given the same sums are also added into it
   void gram(int nblk, const c128* V, int64_t ldv, const c128* W, c128* part, c128* H, bool accumulate,
             c128* H2 = nullptr);
+  // the same with the basis blocks b < nvb at V + b ldv and block nvb at Vx (Jtot = (nblk) s
+  // columns in all), and a right operand of two blocks [W0, W1] when W1 is given (H then has
+  // 2s columns); split operands need s = 16
+  void gram_ext(int nblk, const c128* V, int64_t ldv, int nvb, const c128* Vx, const c128* W0, const c128* W1,
+                c128* part, c128* H, bool accumulate, c128* H2 = nullptr);
+  // [Y0, Y1] = [0, Yin1] + [V_0 .. V_{nvb-1}, Vx] C, C ((nvb + 1) s x 2s); s = 16
+  void update_split(int nvb, const c128* V, int64_t ldv, const c128* Vx, const c128* C, c128* Y0, const c128* Yin1,
+                    c128* Y1);
+  // delayed-reorthogonalisation coefficients (k_dcgs_coef): C null finishes a column
+  void dcgs_coef(int nb, const c128* G, c128* C, c128* Hp, c128* Hn, int* flag);
   // Y = Yin + beta * sum_J V_J H[J][:]
   void block_axpy(int nblk, const c128* V, int64_t ldv, const c128* H, double beta, const c128* Yin, c128* Y);
   // the same with complex64 basis blocks (widened exactly)
@@ -60,18 +70,23 @@ struct FgmresJob {
   int m;
   int64_t n, ldr = 0;
   KrylovKernels K;
-  bool z32;  // preconditioned blocks kept in complex64 (mixed-precision preconditioner)
-  DevArray<c128> V, Zb, W, Wt, R, part, Hc, Hp, Rm, refl, tau, tmat, G, Y, Gs, Rs, Ri, Racc;
+  bool z32;   // preconditioned blocks kept in complex64 (mixed-precision preconditioner)
+  bool dcgs;  // delayed reorthogonalisation (16 columns); CGS2 + CholQR2 otherwise
+  DevArray<c128> V, Zb, W, Wt, R, part, Hc, Hp, Hc2, Gm, Cm, Rm, refl, tau, tmat, G, Y, Gs, Rs, Ri, Racc;
   DevArray<c64> Zs;
   DevArray<double> res, npart, nrm;
   DevArray<int> flag;
   std::vector<double> bnorm, est, rel;
   int total = 0, restarts = 0, jj = 0;
+  int base = 0;        // Hessenberg columns completed before this cycle
+  int ncols = 0;       // columns of this cycle that end_cycle() combines
+  bool last = false;   // this step is the cycle's last (restart length, fixed count, max_iter)
   int hflag = 0;  // host copy of the CholQR breakdown flag (a numerically dependent block)
   std::vector<ColInfo> info;
 
   FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c128* X_, const SolveOptions& o_, int m_);
   static int64_t bytes_needed(int64_t n, int s, int m, bool z32);
+  static bool delayed(int s) { return s == 16; }
   static int restart_for(Ctx* ctx, int64_t n, int s, int want, int fixed, bool z32);
   void start();                 // norms of B (synchronises), X = 0, first cycle
   c128* v_cur();                // block to precondition this step
@@ -80,7 +95,7 @@ struct FgmresJob {
   c128* w_cur();                // where A z goes
   void matvec();                // z_cur() = M^{-1} v_cur(), w_cur() = A z_cur()
   void spmm_z(const c64* z, c128* w);  // w = A z, z complex64 widened exactly
-  void after_matvec();          // CGS2, CholQR2, least-squares step; estimates copied to host (async)
+  void after_matvec();          // orthogonalisation, least-squares step; estimates copied to host (async)
   bool cycle_done();            // after a synchronisation: end of this cycle?
   bool end_cycle();             // X update and explicit residual (synchronises); true when finished
   void spmm(const c128* x, c128* y, c128 alpha, c128 beta, const c128* yin);
@@ -88,6 +103,7 @@ struct FgmresJob {
  private:
   void start_cycle();
   void cholqr2(const c128* in, c128* out);
+  c128* h_col(int j);  // Hessenberg column buffer of step j (two alternate with delayed reorthogonalisation)
 };
 
 // Solve A X = B for a node-major block B [n][s] (device, c128).  X (device) receives the

@@ -106,62 +106,68 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, int s, int Jtot, const 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 #define HZ_MFMA64 __builtin_amdgcn_mfma_f64_16x16x4f64
 
-// Partial sums of H = V^H W over one chunk of rows, s = 16 NCT columns.  A wavefront holds
-// GJ tiles of 16 basis columns; the block's 4 wavefronts take interleaved groups of 4 rows
-// (lane l reads row 4 (wave) + l/16 of each group of 16, column l%16: 256 contiguous bytes
-// per row), RG groups per step, and are summed through LDS in a fixed order.
-template <int NCT, int GJ, int RG>
+// Partial sums of H = V^H W over one chunk of rows.  The left operand is Jtot basis columns
+// in blocks of S = 16 NCT (block b < nvb at V + b ldv, block nvb at Vx); the right operand is
+// NRB blocks of S columns (W0, then W1), so H has NRB S columns.  A wavefront holds GJ tiles
+// of 16 basis columns; the block's 4 wavefronts take interleaved groups of 4 rows (lane l
+// reads row 4 (wave) + l/16 of each group of 16, column l%16: 256 contiguous bytes per row),
+// RG groups per step, and are summed through LDS in a fixed order.
+template <int NCT, int NRB, int GJ, int RG>
 __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int Jtot, const c128* __restrict__ V, int64_t ldv,
-                                                   const c128* __restrict__ W, c128* __restrict__ part, int64_t rpc,
+                                                   int nvb, const c128* __restrict__ Vx, const c128* __restrict__ W0,
+                                                   const c128* __restrict__ W1, c128* __restrict__ part, int64_t rpc,
                                                    int jbase) {
-  constexpr int S = 16 * NCT;
-  __shared__ c128 red[GJ * 16][S];
+  constexpr int S = 16 * NCT, NC = NRB * NCT, SO = NRB * S;
+  __shared__ c128 red[GJ * 16][SO];
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, lc = l & 15, q = l >> 4;
   const int64_t r0 = (int64_t)blockIdx.x * rpc;
   const int64_t r1 = min<int64_t>(n, r0 + rpc);
   const int J0 = jbase + blockIdx.y * GJ * 16;
-  f64x4 hre[GJ][NCT], him[GJ][NCT];
+  f64x4 hre[GJ][NC], him[GJ][NC];
   const c128* vp[GJ];
+  const c128* wp[NC];
   bool jv[GJ];
 #pragma unroll
   for (int g = 0; g < GJ; ++g) {
     const int J = J0 + 16 * g;
     jv[g] = J < Jtot;
     const int b = J / S, jc = J - (J / S) * S;
-    vp[g] = jv[g] ? V + (int64_t)b * ldv + jc + lc : V;
+    vp[g] = jv[g] ? (b < nvb ? V + (int64_t)b * ldv : Vx) + jc + lc : V;
 #pragma unroll
-    for (int ct = 0; ct < NCT; ++ct) hre[g][ct] = him[g][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int ct = 0; ct < NC; ++ct) hre[g][ct] = him[g][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
-  auto load = [&](int64_t rb, c128 (&w)[RG][NCT], c128 (&a)[RG][GJ]) {
+#pragma unroll
+  for (int ct = 0; ct < NC; ++ct) wp[ct] = (ct < NCT ? W0 : W1) + 16 * (ct % NCT) + lc;
+  auto load = [&](int64_t rb, c128 (&w)[RG][NC], c128 (&a)[RG][GJ]) {
 #pragma unroll
     for (int u = 0; u < RG; ++u) {
       const int64_t r = rb + 16 * u + q;
       const bool ok = r < r1;
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct) w[u][ct] = ok ? W[r * S + 16 * ct + lc] : cmk(0.0, 0.0);
+      for (int ct = 0; ct < NC; ++ct) w[u][ct] = ok ? wp[ct][r * S] : cmk(0.0, 0.0);
 #pragma unroll
       for (int g = 0; g < GJ; ++g) a[u][g] = (ok && jv[g]) ? vp[g][r * S] : cmk(0.0, 0.0);
     }
   };
-  c128 wc[RG][NCT], ac[RG][GJ];
+  c128 wc[RG][NC], ac[RG][GJ];
   int64_t rb = r0 + 4 * wv;
   load(rb, wc, ac);
   for (; rb < r1; rb += 16 * RG) {
-    c128 wn[RG][NCT], an[RG][GJ];
+    c128 wn[RG][NC], an[RG][GJ];
     load(rb + 16 * RG, wn, an);
 #pragma unroll
     for (int u = 0; u < RG; ++u) {
 #pragma unroll
       for (int g = 0; g < GJ; ++g)
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
+        for (int ct = 0; ct < NC; ++ct) {
           hre[g][ct] = HZ_MFMA64(ac[u][g].re, wc[u][ct].re, hre[g][ct], 0, 0, 0);
           him[g][ct] = HZ_MFMA64(ac[u][g].re, wc[u][ct].im, him[g][ct], 0, 0, 0);
         }
 #pragma unroll
       for (int g = 0; g < GJ; ++g)
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
+        for (int ct = 0; ct < NC; ++ct) {
           hre[g][ct] = HZ_MFMA64(ac[u][g].im, wc[u][ct].im, hre[g][ct], 0, 0, 0);
           him[g][ct] = HZ_MFMA64(ac[u][g].im, -wc[u][ct].re, him[g][ct], 0, 0, 0);
         }
@@ -169,7 +175,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int Jtot, const c1
 #pragma unroll
     for (int u = 0; u < RG; ++u) {
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct) wc[u][ct] = wn[u][ct];
+      for (int ct = 0; ct < NC; ++ct) wc[u][ct] = wn[u][ct];
 #pragma unroll
       for (int g = 0; g < GJ; ++g) ac[u][g] = an[u][g];
     }
@@ -179,7 +185,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int Jtot, const c1
 #pragma unroll
       for (int g = 0; g < GJ; ++g)
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct)
+        for (int ct = 0; ct < NC; ++ct)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             c128& d = red[16 * g + q + 4 * v][16 * ct + lc];
@@ -189,39 +195,42 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int Jtot, const c1
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < GJ * 16 * S; e += 256) {
-    const int j = e / S, c = e - (e / S) * S;
-    if (J0 + j < Jtot) part[((int64_t)blockIdx.x * Jtot + J0 + j) * S + c] = red[j][c];
+  for (int e = threadIdx.x; e < GJ * 16 * SO; e += 256) {
+    const int j = e / SO, c = e - (e / SO) * SO;
+    if (J0 + j < Jtot) part[((int64_t)blockIdx.x * Jtot + J0 + j) * SO + c] = red[j][c];
   }
 }
 
-// Y = Yin + beta V H, s = 16 NCT columns.  A wavefront holds RT tiles of 16 rows; the basis
-// columns go 16 at a time, lane l taking columns 4 (l/16) .. 4 (l/16) + 3 of row l%16 of
-// each tile (64 contiguous bytes) for eight consecutive k steps.
-template <typename TV, int NCT, int RT>
+// Y = Yin + beta V H.  V is Jtot basis columns in blocks of S = 16 NCT (block b < nvb at
+// V + b ldv, block nvb at Vx); Y is NRB blocks of S columns (Y0, Y1, each with its own Yin,
+// which may be null or equal to its Y), H has NRB S columns.  A wavefront holds RT tiles of
+// 16 rows; the basis columns go 16 at a time, lane l taking columns 4 (l/16) .. 4 (l/16) + 3
+// of row l%16 of each tile (64 contiguous bytes) for eight consecutive k steps.
+template <typename TV, int NCT, int NRB, int RT>
 __global__ __launch_bounds__(256) void k_axpy_mfma(int64_t n, int Jtot, const cplx<TV>* __restrict__ V, int64_t ldv,
-                                                   const c128* __restrict__ H, double beta,
-                                                   const c128* __restrict__ Yin, c128* __restrict__ Y) {
-  constexpr int S = 16 * NCT;
+                                                   int nvb, const cplx<TV>* __restrict__ Vx,
+                                                   const c128* __restrict__ H, double beta, const c128* Yin0, c128* Y0,
+                                                   const c128* Yin1, c128* Y1) {
+  constexpr int S = 16 * NCT, NC = NRB * NCT, SH = NRB * S;
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, lc = l & 15, q = l >> 4;
   const int64_t rbase = ((int64_t)blockIdx.x * 4 + wv) * (16 * RT);
-  f64x4 cre[RT][NCT], cim[RT][NCT];
+  f64x4 cre[RT][NC], cim[RT][NC];
   int64_t row[RT];
 #pragma unroll
   for (int t = 0; t < RT; ++t) {
     row[t] = rbase + 16 * t + lc;
 #pragma unroll
-    for (int ct = 0; ct < NCT; ++ct) cre[t][ct] = cim[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int ct = 0; ct < NC; ++ct) cre[t][ct] = cim[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
-  auto load = [&](int J, c128 (&h)[4][NCT], c128 (&a)[RT][4]) {
+  auto load = [&](int J, c128 (&h)[4][NC], c128 (&a)[RT][4]) {
     const bool jok = J < Jtot;
     const int b = J / S, jc = J - (J / S) * S;
-    const cplx<TV>* vb = V + (int64_t)b * ldv + jc + 4 * q;
+    const cplx<TV>* vb = (b < nvb ? V + (int64_t)b * ldv : Vx) + jc + 4 * q;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct)
-        h[k][ct] = jok ? H[(int64_t)(J + 4 * q + k) * S + 16 * ct + lc] : cmk(0.0, 0.0);
+      for (int ct = 0; ct < NC; ++ct)
+        h[k][ct] = jok ? H[(int64_t)(J + 4 * q + k) * SH + 16 * ct + lc] : cmk(0.0, 0.0);
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -230,24 +239,24 @@ __global__ __launch_bounds__(256) void k_axpy_mfma(int64_t n, int Jtot, const cp
         a[t][k] = cmk((double)v.re, (double)v.im);
       }
   };
-  c128 hc[4][NCT], ac[RT][4];
+  c128 hc[4][NC], ac[RT][4];
   load(0, hc, ac);
   for (int J = 0; J < Jtot; J += 16) {
-    c128 hn[4][NCT], an[RT][4];
+    c128 hn[4][NC], an[RT][4];
     load(J + 16, hn, an);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
 #pragma unroll
       for (int t = 0; t < RT; ++t)
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
+        for (int ct = 0; ct < NC; ++ct) {
           cre[t][ct] = HZ_MFMA64(ac[t][k].re, hc[k][ct].re, cre[t][ct], 0, 0, 0);
           cim[t][ct] = HZ_MFMA64(ac[t][k].re, hc[k][ct].im, cim[t][ct], 0, 0, 0);
         }
 #pragma unroll
       for (int t = 0; t < RT; ++t)
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
+        for (int ct = 0; ct < NC; ++ct) {
           cre[t][ct] = HZ_MFMA64(ac[t][k].im, -hc[k][ct].im, cre[t][ct], 0, 0, 0);
           cim[t][ct] = HZ_MFMA64(ac[t][k].im, hc[k][ct].re, cim[t][ct], 0, 0, 0);
         }
@@ -255,7 +264,7 @@ __global__ __launch_bounds__(256) void k_axpy_mfma(int64_t n, int Jtot, const cp
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct) hc[k][ct] = hn[k][ct];
+      for (int ct = 0; ct < NC; ++ct) hc[k][ct] = hn[k][ct];
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -264,14 +273,17 @@ __global__ __launch_bounds__(256) void k_axpy_mfma(int64_t n, int Jtot, const cp
 #pragma unroll
   for (int t = 0; t < RT; ++t)
 #pragma unroll
-    for (int ct = 0; ct < NCT; ++ct)
+    for (int ct = 0; ct < NC; ++ct) {
+      const c128* yin = ct < NCT ? Yin0 : Yin1;
+      c128* y = ct < NCT ? Y0 : Y1;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t r = rbase + 16 * t + q + 4 * v;
         if (r >= n) continue;
-        const int64_t k = r * S + 16 * ct + lc;
-        Y[k] = (Yin ? Yin[k] : cmk(0.0, 0.0)) + cmk(beta * cre[t][ct][v], beta * cim[t][ct][v]);
+        const int64_t k = r * S + 16 * (ct % NCT) + lc;
+        y[k] = (yin ? yin[k] : cmk(0.0, 0.0)) + cmk(beta * cre[t][ct][v], beta * cim[t][ct][v]);
       }
+    }
 }
 
 // out[e] (+)= sum over chunks of part[chunk][e]: 4 groups of 64 threads take every fourth
@@ -429,6 +441,129 @@ __global__ __launch_bounds__(256) void k_chol_small(int s, const c128* __restric
     __syncthreads();
     cnt = 0;
     for (int e = t; e < s * s; e += 256, ++cnt) Racc[e] = v[cnt];
+  }
+}
+
+// Delayed reorthogonalisation (DCGS2, one pass over the basis per product): the block Vt
+// that was projected once at the previous step is projected again and normalised in the
+// same pass that projects the new product W once.  With V = [V_0 .. V_{j-1}] orthonormal and
+// G = [V, Vt]^H [Vt, W] ((nb + s) x 2s, nb = j s; a = V^H Vt, c = V^H W, b = Vt^H Vt,
+// d = Vt^H W):
+//   R^H R = b - a^H a (Cholesky of the Gram matrix of Vt - V a), v_j = (Vt - V a) R^{-1},
+//   h = v_j^H W = R^{-H} (d - a^H c), W' = W - V c - v_j h, written as one product
+//   [v_j, W'] = [0, W] + [V, Vt] C,  C = [[-a Ri, a T - c], [Ri, -T]],  Ri = R^{-1}, T = Ri h.
+// Vt = V a + v_j R completes the Hessenberg column of the previous step (Hp: += a on rows
+// < nb, R on rows nb .. nb + s); the new column (Hn) holds c, h until the next step adds its
+// own correction.  Finishing (C null): G = [V, W]^H W ((nb + s) x s, V = [V_0 .. V_j]);
+// Hn += a on rows < nb and R on rows nb .. nb + s.  flag[0] = 1 when a pivot of R^H R falls
+// below 1e-14 of its diagonal entry of b (a numerically dependent block), as in CholQR.
+// One block of 1024 threads; s a power of two <= 32.
+__global__ __launch_bounds__(1024) void k_dcgs_coef(int s, int nb, const c128* __restrict__ G,
+                                                    c128* __restrict__ C, c128* __restrict__ Hp,
+                                                    c128* __restrict__ Hn, int* __restrict__ flag) {
+  __shared__ c128 A[32][33];   // b - a^H a, eliminated in place
+  __shared__ c128 Rs[32][33];  // R
+  __shared__ c128 Xs[32][33];  // Ri
+  __shared__ c128 Qs[32][33];  // d - a^H c, then h
+  __shared__ c128 Ts[32][33];  // T = Ri h
+  __shared__ c128 red[1024];
+  const int t = threadIdx.x;
+  const bool fused = C != nullptr;
+  const int so = fused ? 2 * s : s;
+  const int ss = s * s, ng = 1024 / ss;
+  auto Gat = [&](int i, int c) { return G[(int64_t)i * so + c]; };
+  // P = b - a^H a and Q = d - a^H c: ng groups of threads take every ng-th basis row, then
+  // the group sums are added in a fixed order
+  for (int pass = 0; pass < (fused ? 2 : 1); ++pass) {
+    const int e = t % ss, g = t / ss, k = e / s, l = e % s;
+    c128 acc = cmk(0.0, 0.0);
+    if (g < ng)
+      for (int i = g; i < nb; i += ng) cfma_conj(acc, Gat(i, k), Gat(i, pass * s + l));
+    red[t] = acc;
+    __syncthreads();
+    if (t < ss) {
+      c128 sum = red[t];
+      for (int q = 1; q < ng; ++q) sum = sum + red[q * ss + t];
+      const c128 v = Gat(nb + k, pass * s + l) - sum;
+      if (pass == 0)
+        A[k][l] = v;
+      else
+        Qs[k][l] = v;
+      if (pass == 0) {
+        Rs[k][l] = cmk(0.0, 0.0);
+        Xs[k][l] = cmk(0.0, 0.0);
+      }
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k < s; ++k) {
+    if (t == 0) {
+      double d = A[k][k].re;
+      const double scale = fabs(Gat(nb + k, k).re) + 1e-300;
+      if (!(d > 1e-14 * scale) || !isfinite(d)) {
+        flag[0] = 1;
+        d = fmax(d, 1e-14 * scale);
+      }
+      Rs[k][k] = cmk(sqrt(d), 0.0);
+    }
+    __syncthreads();
+    const double rk = Rs[k][k].re;
+    if (t > k && t < s) Rs[k][t] = cmk(A[k][t].re / rk, A[k][t].im / rk);
+    __syncthreads();
+    if (t < ss) {
+      const int i = t / s, j = t % s;
+      if (i > k && j >= i) cfma_conj(A[i][j], cmk(-Rs[k][i].re, -Rs[k][i].im), Rs[k][j]);
+    }
+    __syncthreads();
+  }
+  if (t < s) {  // Ri: column c by thread c (back substitution)
+    const int c = t;
+    for (int i = c; i >= 0; --i) {
+      c128 v = cmk(i == c ? 1.0 : 0.0, 0.0);
+      for (int l = i + 1; l <= c; ++l) cfms(v, Rs[i][l], Xs[l][c]);
+      Xs[i][c] = cmk(v.re / Rs[i][i].re, v.im / Rs[i][i].re);
+    }
+  }
+  __syncthreads();
+  if (!fused) {
+    for (int e = t; e < nb * s; e += 1024) Hn[e] = Hn[e] + G[e];  // rows < nb of G are a (width s)
+    if (t < ss) Hn[(int64_t)nb * s + t] = Rs[t / s][t % s];
+    return;
+  }
+  c128 hv = cmk(0.0, 0.0);
+  if (t < ss) {  // h = Ri^H Q (Ri upper triangular)
+    const int k = t / s, l = t % s;
+    for (int m = 0; m <= k; ++m) cfma_conj(hv, Xs[m][k], Qs[m][l]);
+  }
+  __syncthreads();
+  if (t < ss) Qs[t / s][t % s] = hv;
+  __syncthreads();
+  if (t < ss) {  // T = Ri h
+    const int k = t / s, l = t % s;
+    c128 v = cmk(0.0, 0.0);
+    for (int m = k; m < s; ++m) cfma(v, Xs[k][m], Qs[m][l]);
+    Ts[k][l] = v;
+  }
+  __syncthreads();
+  for (int e = t; e < nb * s; e += 1024) {
+    const int i = e / s, l = e % s;
+    c128 x = cmk(0.0, 0.0), y = cmk(0.0, 0.0) - Gat(i, s + l);
+    for (int m = 0; m < s; ++m) {
+      const c128 am = Gat(i, m);
+      if (m <= l) cfms(x, am, Xs[m][l]);
+      cfma(y, am, Ts[m][l]);
+    }
+    C[(int64_t)i * 2 * s + l] = x;
+    C[(int64_t)i * 2 * s + s + l] = y;
+    Hp[e] = Hp[e] + Gat(i, l);
+    Hn[e] = Gat(i, s + l);
+  }
+  if (t < ss) {
+    const int k = t / s, l = t % s;
+    C[(int64_t)(nb + k) * 2 * s + l] = Xs[k][l];
+    C[(int64_t)(nb + k) * 2 * s + s + l] = cmk(0.0, 0.0) - Ts[k][l];
+    Hp[(int64_t)nb * s + t] = Rs[k][l];
+    Hn[(int64_t)nb * s + t] = Qs[k][l];
   }
 }
 
@@ -779,8 +914,15 @@ static void gram_t(KrylovKernels& k, int Jtot, const c128* V, int64_t ldv, const
 
 void KrylovKernels::gram(int nblk, const c128* V, int64_t ldv, const c128* W, c128* part, c128* H, bool accumulate,
                          c128* H2) {
+  gram_ext(nblk, V, ldv, nblk, nullptr, W, nullptr, part, H, accumulate, H2);
+}
+
+void KrylovKernels::gram_ext(int nblk, const c128* V, int64_t ldv, int nvb, const c128* Vx, const c128* W0,
+                             const c128* W1, c128* part, c128* H, bool accumulate, c128* H2) {
   const int Jtot = nblk * s;
+  const int nrb = W1 ? 2 : 1;
   const bool mfma = s == 16 || s == 32;
+  HZ_REQUIRE((nvb == nblk && nrb == 1) || s == 16, HZ_ERR_STATE, "gram: split operands need 16 columns");
   // about 2048 blocks in total: fewer, longer row chunks when there are many basis tiles
   // (never more chunks than `nchunk`: the partial-sum workspace is sized for nchunk)
   const int jper = s == 16 ? 64 : s == 32 ? 32 : kJT;
@@ -792,35 +934,41 @@ void KrylovKernels::gram(int nblk, const c128* V, int64_t ldv, const c128* W, c1
   {
     // algorithmic traffic: the Jtot basis columns and W once; 8 flops per complex multiply-add
     // (the scope times the partial-product kernel alone, not the reduction below)
-    ProfScope ps(ctx, HZ_K_CGS_GRAM, (double)n * (Jtot + s) * sizeof(c128), 8.0 * n * Jtot * s);
+    ProfScope ps(ctx, HZ_K_CGS_GRAM, (double)n * (Jtot + nrb * s) * sizeof(c128), 8.0 * n * Jtot * nrb * s);
     if (mfma && s == 16) {
       // groups of 4 basis blocks, then one launch sized for the remaining 1..3 (so that no
       // block multiplies zero padding: the single block of CholQR and of the first step)
       const int full = nblk / 4, rem = nblk % 4;
-      if (full > 0)
-        hipLaunchKernelGGL((k_gram_mfma<1, 4, 2>), dim3((unsigned)nch, (unsigned)full), dim3(256), 0, ctx->stream, n,
-                           Jtot, V, ldv, W, part, rpc, 0);
+      auto go = [&](auto kern, dim3 grid, int jbase) {
+        hipLaunchKernelGGL(kern, grid, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, nvb, Vx, W0, W1, part, rpc, jbase);
+      };
       const dim3 g1((unsigned)nch, 1);
-      if (rem == 1)
-        hipLaunchKernelGGL((k_gram_mfma<1, 1, 2>), g1, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc, 64 * full);
-      else if (rem == 2)
-        hipLaunchKernelGGL((k_gram_mfma<1, 2, 2>), g1, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc, 64 * full);
-      else if (rem == 3)
-        hipLaunchKernelGGL((k_gram_mfma<1, 3, 2>), g1, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc, 64 * full);
+      if (nrb == 1) {
+        if (full > 0) go(k_gram_mfma<1, 1, 4, 2>, dim3((unsigned)nch, (unsigned)full), 0);
+        if (rem == 1) go(k_gram_mfma<1, 1, 1, 2>, g1, 64 * full);
+        if (rem == 2) go(k_gram_mfma<1, 1, 2, 2>, g1, 64 * full);
+        if (rem == 3) go(k_gram_mfma<1, 1, 3, 2>, g1, 64 * full);
+      } else {
+        if (full > 0) go(k_gram_mfma<1, 2, 4, 2>, dim3((unsigned)nch, (unsigned)full), 0);
+        if (rem == 1) go(k_gram_mfma<1, 2, 1, 2>, g1, 64 * full);
+        if (rem == 2) go(k_gram_mfma<1, 2, 2, 2>, g1, 64 * full);
+        if (rem == 3) go(k_gram_mfma<1, 2, 3, 2>, g1, 64 * full);
+      }
     } else if (mfma) {
       const dim3 grid((unsigned)nch, (unsigned)jtiles);
-      hipLaunchKernelGGL((k_gram_mfma<2, 2, 2>), grid, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, W, part, rpc, 0);
+      hipLaunchKernelGGL((k_gram_mfma<2, 1, 2, 2>), grid, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, nblk,
+                         (const c128*)nullptr, W0, (const c128*)nullptr, part, rpc, 0);
     } else if (s <= 4) {
-      gram_t<4>(*this, Jtot, V, ldv, W, part, nch, rpc);
+      gram_t<4>(*this, Jtot, V, ldv, W0, part, nch, rpc);
     } else if (s <= 8) {
-      gram_t<8>(*this, Jtot, V, ldv, W, part, nch, rpc);
+      gram_t<8>(*this, Jtot, V, ldv, W0, part, nch, rpc);
     } else if (s <= 16) {
-      gram_t<16>(*this, Jtot, V, ldv, W, part, nch, rpc);
+      gram_t<16>(*this, Jtot, V, ldv, W0, part, nch, rpc);
     } else {
-      gram_t<32>(*this, Jtot, V, ldv, W, part, nch, rpc);
+      gram_t<32>(*this, Jtot, V, ldv, W0, part, nch, rpc);
     }
   }
-  const int64_t m = (int64_t)Jtot * s;
+  const int64_t m = (int64_t)Jtot * nrb * s;
   hipLaunchKernelGGL(k_reduce_part, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, ctx->stream, nch, m, part, H,
                      accumulate ? 1 : 0);
   if (H2)
@@ -844,12 +992,13 @@ static void block_axpy_t(KrylovKernels& k, int nblk, const cplx<TV>* V, int64_t 
   ProfScope ps(k.ctx, HZ_K_CGS_UPDATE, (double)n * Jtot * sizeof(cplx<TV>) + (double)n * (Yin ? 2 : 1) * s * sizeof(c128),
                8.0 * n * Jtot * s);
   hipStream_t st = k.ctx->stream;
+  const cplx<TV>* none = nullptr;
   if (s == 16)  // 4 wavefronts x 2 tiles of 16 rows per block
-    hipLaunchKernelGGL((k_axpy_mfma<TV, 1, 2>), dim3((unsigned)((n + 127) / 128)), dim3(256), 0, st, n, Jtot, V, ldv, H,
-                       beta, Yin, Y);
+    hipLaunchKernelGGL((k_axpy_mfma<TV, 1, 1, 2>), dim3((unsigned)((n + 127) / 128)), dim3(256), 0, st, n, Jtot, V, ldv,
+                       nblk, none, H, beta, Yin, Y, (const c128*)nullptr, (c128*)nullptr);
   else if (s == 32)  // 4 wavefronts x 1 tile of 16 rows per block
-    hipLaunchKernelGGL((k_axpy_mfma<TV, 2, 1>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, n, Jtot, V, ldv, H,
-                       beta, Yin, Y);
+    hipLaunchKernelGGL((k_axpy_mfma<TV, 2, 1, 1>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, n, Jtot, V, ldv,
+                       nblk, none, H, beta, Yin, Y, (const c128*)nullptr, (c128*)nullptr);
   else if (s == 1)
     axpy_t<TV, 1>(k, Jtot, V, ldv, H, beta, Yin, Y);
   else if (s == 2)
@@ -873,6 +1022,25 @@ void KrylovKernels::block_axpy(int nblk, const c128* V, int64_t ldv, const c128*
 void KrylovKernels::block_axpy(int nblk, const c64* V, int64_t ldv, const c128* H, double beta, const c128* Yin,
                                c128* Y) {
   block_axpy_t<float>(*this, nblk, V, ldv, H, beta, Yin, Y);
+}
+
+void KrylovKernels::update_split(int nvb, const c128* V, int64_t ldv, const c128* Vx, const c128* C, c128* Y0,
+                                 const c128* Yin1, c128* Y1) {
+  HZ_REQUIRE(s == 16, HZ_ERR_STATE, "update_split: needs 16 columns");
+  const int Jtot = (nvb + 1) * s;
+  // algorithmic traffic: the Jtot basis columns and Yin1 once, Y0 and Y1 written once
+  ProfScope ps(ctx, HZ_K_CGS_UPDATE, (double)n * (Jtot + 3 * s) * sizeof(c128), 8.0 * n * Jtot * 2 * s);
+  // 4 wavefronts x 1 tile of 16 rows per block
+  hipLaunchKernelGGL((k_axpy_mfma<double, 1, 2, 1>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, ctx->stream, n,
+                     Jtot, V, ldv, nvb, Vx, C, 1.0, (const c128*)nullptr, Y0, Yin1, Y1);
+  HIP_CHECK(hipGetLastError());
+}
+
+void KrylovKernels::dcgs_coef(int nb, const c128* G, c128* C, c128* Hp, c128* Hn, int* flag) {
+  HZ_REQUIRE(s == 1 || s == 2 || s == 4 || s == 8 || s == 16 || s == 32, HZ_ERR_STATE,
+             "dcgs_coef: block size must be a power of two");
+  hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(1024), 0, ctx->stream, s, nb, G, C, Hp, Hn, flag);
+  HIP_CHECK(hipGetLastError());
 }
 
 void KrylovKernels::cholqr_pass(const c128* W, c128* out, c128* part, c128* G, c128* R, c128* Rinv, c128* Racc,
