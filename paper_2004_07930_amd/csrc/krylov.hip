@@ -111,9 +111,10 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // NRB blocks of S columns (W0, then W1), so H has NRB S columns.  A wavefront holds GJ tiles
 // of 16 basis columns; the block's 4 wavefronts take interleaved groups of 4 rows (lane l
 // reads row 4 (wave) + l/16 of each group of 16, column l%16: 256 contiguous bytes per row),
-// RG groups per step, and are summed through LDS in a fixed order.
+// RG groups per step, and are summed through LDS in a fixed order.  Two wavefronts per SIMD
+// (register budget 256): with one, the loads of the next step do not cover the memory latency.
 template <int NCT, int NRB, int GJ, int RG>
-__global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int Jtot, const c128* __restrict__ V, int64_t ldv,
+__global__ __launch_bounds__(256, 2) void k_gram_mfma(int64_t n, int Jtot, const c128* __restrict__ V, int64_t ldv,
                                                    int nvb, const c128* __restrict__ Vx, const c128* __restrict__ W0,
                                                    const c128* __restrict__ W1, c128* __restrict__ part, int64_t rpc,
                                                    int jbase) {
@@ -206,21 +207,24 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, int Jtot, const c1
 // which may be null or equal to its Y), H has NRB S columns.  A wavefront holds RT tiles of
 // 16 rows; the basis columns go 16 at a time, lane l taking columns 4 (l/16) .. 4 (l/16) + 3
 // of row l%16 of each tile (64 contiguous bytes) for eight consecutive k steps.
-template <typename TV, int NCT, int NRB, int RT>
-__global__ __launch_bounds__(256) void k_axpy_mfma(int64_t n, int Jtot, const cplx<TV>* __restrict__ V, int64_t ldv,
+// M3: three real products per complex one (where the matrix cores bound the kernel):
+//   P1 = a_re b_re, P2 = a_im b_im, P3 = (a_re + a_im)(b_re + b_im);  a b = (P1 - P2) + i (P3 - P1 - P2)
+// Three wavefronts per SIMD (register budget 168).
+template <typename TV, int NCT, int NRB, int RT, bool M3 = false>
+__global__ __launch_bounds__(256, 3) void k_axpy_mfma(int64_t n, int Jtot, const cplx<TV>* __restrict__ V, int64_t ldv,
                                                    int nvb, const cplx<TV>* __restrict__ Vx,
                                                    const c128* __restrict__ H, double beta, const c128* Yin0, c128* Y0,
                                                    const c128* Yin1, c128* Y1) {
   constexpr int S = 16 * NCT, NC = NRB * NCT, SH = NRB * S;
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, lc = l & 15, q = l >> 4;
   const int64_t rbase = ((int64_t)blockIdx.x * 4 + wv) * (16 * RT);
-  f64x4 cre[RT][NC], cim[RT][NC];
+  f64x4 cre[RT][NC], cim[RT][NC], c3[RT][NC];
   int64_t row[RT];
 #pragma unroll
   for (int t = 0; t < RT; ++t) {
     row[t] = rbase + 16 * t + lc;
 #pragma unroll
-    for (int ct = 0; ct < NC; ++ct) cre[t][ct] = cim[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int ct = 0; ct < NC; ++ct) cre[t][ct] = cim[t][ct] = c3[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
   auto load = [&](int J, c128 (&h)[4][NC], c128 (&a)[RT][4]) {
     const bool jok = J < Jtot;
@@ -246,20 +250,36 @@ __global__ __launch_bounds__(256) void k_axpy_mfma(int64_t n, int Jtot, const cp
     load(J + 16, hn, an);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
+      if constexpr (M3) {  // cre = P1, cim = P2, c3 = P3
+        double sa[RT], sh[NC];
 #pragma unroll
-      for (int t = 0; t < RT; ++t)
+        for (int t = 0; t < RT; ++t) sa[t] = ac[t][k].re + ac[t][k].im;
 #pragma unroll
-        for (int ct = 0; ct < NC; ++ct) {
-          cre[t][ct] = HZ_MFMA64(ac[t][k].re, hc[k][ct].re, cre[t][ct], 0, 0, 0);
-          cim[t][ct] = HZ_MFMA64(ac[t][k].re, hc[k][ct].im, cim[t][ct], 0, 0, 0);
-        }
+        for (int ct = 0; ct < NC; ++ct) sh[ct] = hc[k][ct].re + hc[k][ct].im;
 #pragma unroll
-      for (int t = 0; t < RT; ++t)
+        for (int t = 0; t < RT; ++t)
 #pragma unroll
-        for (int ct = 0; ct < NC; ++ct) {
-          cre[t][ct] = HZ_MFMA64(ac[t][k].im, -hc[k][ct].im, cre[t][ct], 0, 0, 0);
-          cim[t][ct] = HZ_MFMA64(ac[t][k].im, hc[k][ct].re, cim[t][ct], 0, 0, 0);
-        }
+          for (int ct = 0; ct < NC; ++ct) {
+            cre[t][ct] = HZ_MFMA64(ac[t][k].re, hc[k][ct].re, cre[t][ct], 0, 0, 0);
+            cim[t][ct] = HZ_MFMA64(ac[t][k].im, hc[k][ct].im, cim[t][ct], 0, 0, 0);
+            c3[t][ct] = HZ_MFMA64(sa[t], sh[ct], c3[t][ct], 0, 0, 0);
+          }
+      } else {
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int ct = 0; ct < NC; ++ct) {
+            cre[t][ct] = HZ_MFMA64(ac[t][k].re, hc[k][ct].re, cre[t][ct], 0, 0, 0);
+            cim[t][ct] = HZ_MFMA64(ac[t][k].re, hc[k][ct].im, cim[t][ct], 0, 0, 0);
+          }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int ct = 0; ct < NC; ++ct) {
+            cre[t][ct] = HZ_MFMA64(ac[t][k].im, -hc[k][ct].im, cre[t][ct], 0, 0, 0);
+            cim[t][ct] = HZ_MFMA64(ac[t][k].im, hc[k][ct].re, cim[t][ct], 0, 0, 0);
+          }
+      }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -281,7 +301,9 @@ __global__ __launch_bounds__(256) void k_axpy_mfma(int64_t n, int Jtot, const cp
         const int64_t r = rbase + 16 * t + q + 4 * v;
         if (r >= n) continue;
         const int64_t k = r * S + 16 * (ct % NCT) + lc;
-        y[k] = (yin ? yin[k] : cmk(0.0, 0.0)) + cmk(beta * cre[t][ct][v], beta * cim[t][ct][v]);
+        const double pr = M3 ? cre[t][ct][v] - cim[t][ct][v] : cre[t][ct][v];
+        const double pi = M3 ? c3[t][ct][v] - cre[t][ct][v] - cim[t][ct][v] : cim[t][ct][v];
+        y[k] = (yin ? yin[k] : cmk(0.0, 0.0)) + cmk(beta * pr, beta * pi);
       }
     }
 }
@@ -1031,7 +1053,7 @@ void KrylovKernels::update_split(int nvb, const c128* V, int64_t ldv, const c128
   // algorithmic traffic: the Jtot basis columns and Yin1 once, Y0 and Y1 written once
   ProfScope ps(ctx, HZ_K_CGS_UPDATE, (double)n * (Jtot + 3 * s) * sizeof(c128), 8.0 * n * Jtot * 2 * s);
   // 4 wavefronts x 1 tile of 16 rows per block
-  hipLaunchKernelGGL((k_axpy_mfma<double, 1, 2, 1>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, ctx->stream, n,
+  hipLaunchKernelGGL((k_axpy_mfma<double, 1, 2, 1, true>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, ctx->stream, n,
                      Jtot, V, ldv, nvb, Vx, C, 1.0, (const c128*)nullptr, Y0, Yin1, Y1);
   HIP_CHECK(hipGetLastError());
 }
