@@ -113,7 +113,10 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // reads row 4 (wave) + l/16 of each group of 16, column l%16: 256 contiguous bytes per row),
 // RG groups per step, and are summed through LDS in a fixed order.  Two wavefronts per SIMD
 // (register budget 256): with one, the loads of the next step do not cover the memory latency.
-template <int NCT, int NRB, int GJ, int RG>
+// M3: three real products per complex one (where the matrix cores bound the kernel):
+//   P1 = a_re b_re, P2 = a_im b_im, P3 = (a_re + a_im)(b_im - b_re);
+//   conj(a) b = (P1 + P2) + i (P3 + P1 - P2)
+template <int NCT, int NRB, int GJ, int RG, bool M3 = false>
 __global__ __launch_bounds__(256, 2) void k_gram_mfma(int64_t n, int Jtot, const c128* __restrict__ V, int64_t ldv,
                                                    int nvb, const c128* __restrict__ Vx, const c128* __restrict__ W0,
                                                    const c128* __restrict__ W1, c128* __restrict__ part, int64_t rpc,
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(int64_t n, int Jtot, const
   const int64_t r0 = (int64_t)blockIdx.x * rpc;
   const int64_t r1 = min<int64_t>(n, r0 + rpc);
   const int J0 = jbase + blockIdx.y * GJ * 16;
-  f64x4 hre[GJ][NC], him[GJ][NC];
+  f64x4 hre[GJ][NC], him[GJ][NC], h3[GJ][NC];
   const c128* vp[GJ];
   const c128* wp[NC];
   bool jv[GJ];
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(int64_t n, int Jtot, const
     const int b = J / S, jc = J - (J / S) * S;
     vp[g] = jv[g] ? (b < nvb ? V + (int64_t)b * ldv : Vx) + jc + lc : V;
 #pragma unroll
-    for (int ct = 0; ct < NC; ++ct) hre[g][ct] = him[g][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int ct = 0; ct < NC; ++ct) hre[g][ct] = him[g][ct] = h3[g][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
 #pragma unroll
   for (int ct = 0; ct < NC; ++ct) wp[ct] = (ct < NCT ? W0 : W1) + 16 * (ct % NCT) + lc;
@@ -158,20 +161,36 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(int64_t n, int Jtot, const
     load(rb + 16 * RG, wn, an);
 #pragma unroll
     for (int u = 0; u < RG; ++u) {
+      if constexpr (M3) {  // hre = P1, him = P2, h3 = P3
+        double sa[GJ], sw[NC];
 #pragma unroll
-      for (int g = 0; g < GJ; ++g)
+        for (int g = 0; g < GJ; ++g) sa[g] = ac[u][g].re + ac[u][g].im;
 #pragma unroll
-        for (int ct = 0; ct < NC; ++ct) {
-          hre[g][ct] = HZ_MFMA64(ac[u][g].re, wc[u][ct].re, hre[g][ct], 0, 0, 0);
-          him[g][ct] = HZ_MFMA64(ac[u][g].re, wc[u][ct].im, him[g][ct], 0, 0, 0);
-        }
+        for (int ct = 0; ct < NC; ++ct) sw[ct] = wc[u][ct].im - wc[u][ct].re;
 #pragma unroll
-      for (int g = 0; g < GJ; ++g)
+        for (int g = 0; g < GJ; ++g)
 #pragma unroll
-        for (int ct = 0; ct < NC; ++ct) {
-          hre[g][ct] = HZ_MFMA64(ac[u][g].im, wc[u][ct].im, hre[g][ct], 0, 0, 0);
-          him[g][ct] = HZ_MFMA64(ac[u][g].im, -wc[u][ct].re, him[g][ct], 0, 0, 0);
-        }
+          for (int ct = 0; ct < NC; ++ct) {
+            hre[g][ct] = HZ_MFMA64(ac[u][g].re, wc[u][ct].re, hre[g][ct], 0, 0, 0);
+            him[g][ct] = HZ_MFMA64(ac[u][g].im, wc[u][ct].im, him[g][ct], 0, 0, 0);
+            h3[g][ct] = HZ_MFMA64(sa[g], sw[ct], h3[g][ct], 0, 0, 0);
+          }
+      } else {
+#pragma unroll
+        for (int g = 0; g < GJ; ++g)
+#pragma unroll
+          for (int ct = 0; ct < NC; ++ct) {
+            hre[g][ct] = HZ_MFMA64(ac[u][g].re, wc[u][ct].re, hre[g][ct], 0, 0, 0);
+            him[g][ct] = HZ_MFMA64(ac[u][g].re, wc[u][ct].im, him[g][ct], 0, 0, 0);
+          }
+#pragma unroll
+        for (int g = 0; g < GJ; ++g)
+#pragma unroll
+          for (int ct = 0; ct < NC; ++ct) {
+            hre[g][ct] = HZ_MFMA64(ac[u][g].im, wc[u][ct].im, hre[g][ct], 0, 0, 0);
+            him[g][ct] = HZ_MFMA64(ac[u][g].im, -wc[u][ct].re, him[g][ct], 0, 0, 0);
+          }
+      }
     }
 #pragma unroll
     for (int u = 0; u < RG; ++u) {
@@ -190,7 +209,8 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(int64_t n, int Jtot, const
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             c128& d = red[16 * g + q + 4 * v][16 * ct + lc];
-            const c128 x = cmk(hre[g][ct][v], him[g][ct][v]);
+            const c128 x = M3 ? cmk(hre[g][ct][v] + him[g][ct][v], h3[g][ct][v] + hre[g][ct][v] - him[g][ct][v])
+                              : cmk(hre[g][ct][v], him[g][ct][v]);
             d = w == 0 ? x : d + x;
           }
     }
@@ -947,7 +967,7 @@ void KrylovKernels::gram_ext(int nblk, const c128* V, int64_t ldv, int nvb, cons
   HZ_REQUIRE((nvb == nblk && nrb == 1) || s == 16, HZ_ERR_STATE, "gram: split operands need 16 columns");
   // about 2048 blocks in total: fewer, longer row chunks when there are many basis tiles
   // (never more chunks than `nchunk`: the partial-sum workspace is sized for nchunk)
-  const int jper = s == 16 ? 64 : s == 32 ? 32 : kJT;
+  const int jper = s == 16 ? (nrb == 2 ? 48 : 64) : s == 32 ? 32 : kJT;
   const int jtiles = (Jtot + jper - 1) / jper;
   int nch = std::min(nchunk, std::max(16, 2048 / jtiles));
   int64_t rpc = ((n + nch - 1) / nch + 15) / 16 * 16;
@@ -971,10 +991,11 @@ void KrylovKernels::gram_ext(int nblk, const c128* V, int64_t ldv, int nvb, cons
         if (rem == 2) go(k_gram_mfma<1, 1, 2, 2>, g1, 64 * full);
         if (rem == 3) go(k_gram_mfma<1, 1, 3, 2>, g1, 64 * full);
       } else {
-        if (full > 0) go(k_gram_mfma<1, 2, 4, 2>, dim3((unsigned)nch, (unsigned)full), 0);
-        if (rem == 1) go(k_gram_mfma<1, 2, 1, 2>, g1, 64 * full);
-        if (rem == 2) go(k_gram_mfma<1, 2, 2, 2>, g1, 64 * full);
-        if (rem == 3) go(k_gram_mfma<1, 2, 3, 2>, g1, 64 * full);
+        // 32 right-hand columns, 3M form: groups of 3 basis blocks fit two wavefronts per SIMD
+        const int f3 = nblk / 3, r3 = nblk % 3;
+        if (f3 > 0) go(k_gram_mfma<1, 2, 3, 2, true>, dim3((unsigned)nch, (unsigned)f3), 0);
+        if (r3 == 1) go(k_gram_mfma<1, 2, 1, 2, true>, g1, 48 * f3);
+        if (r3 == 2) go(k_gram_mfma<1, 2, 2, 2, true>, g1, 48 * f3);
       }
     } else if (mfma) {
       const dim3 grid((unsigned)nch, (unsigned)jtiles);
