@@ -51,6 +51,19 @@ __global__ void k_scatter_owner(int64_t n, int s, const int64_t* __restrict__ ow
 // Forward, step 1 of a level: work block w = [b_p; 0] + extend-add of the children's
 // contributions, through the inverse maps (own, child 0, child 1: a fixed order).  One block
 // per 64-row tile of a front (the forward worklist: tiles of one front on one XCD).
+
+// streamed load (the factor is read once per sweep): non-temporal hint
+__device__ __forceinline__ cplx<float> ld_stream(const cplx<float>* p) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  const f2 v = __builtin_nontemporal_load(reinterpret_cast<const f2*>(p));
+  return cmk(v.x, v.y);
+}
+__device__ __forceinline__ cplx<double> ld_stream(const cplx<double>* p) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const d2 v = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p));
+  return cmk(v.x, v.y);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_fwd_assemble(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
                                                       const int32_t* __restrict__ imap, const cplx<T>* __restrict__ bin,
@@ -307,7 +320,7 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
 #pragma unroll
     for (int u = 0; u < NF; ++u) {
       const int e = tid + 256 * u, jj = e / RT, rr = e - (e / RT) * RT;  // element e of [JC][RT]
-      rf[u] = Lf[(jj < jn && i0 + rr < f) ? (j + jj) * F.ld + i0 + rr : 0];
+      rf[u] = ld_stream(&Lf[(jj < jn && i0 + rr < f) ? (j + jj) * F.ld + i0 + rr : 0]);
     }
 #pragma unroll
     for (int u = 0; u < NW; ++u) {
@@ -441,7 +454,7 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ wo
 #pragma unroll
     for (int u = 0; u < NF; ++u) {
       const int e = tid + 256 * u, cc = e / RC, rr = e - (e / RC) * RC;  // element e of [CT][RC]
-      rf[u] = Lf[(rr < rn && cc < nj) ? (j0 + cc) * F.ld + i + rr : 0];
+      rf[u] = ld_stream(&Lf[(rr < rn && cc < nj) ? (j0 + cc) * F.ld + i + rr : 0]);
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
