@@ -33,7 +33,7 @@ int64_t FgmresJob::bytes_needed(int64_t n, int s, int m, bool z32) {
   int64_t e = ((int64_t)m + 4) * ns;                      // V, W, Wt, R
   e += (int64_t)nchunk * (m + 2) * s * s * pw;            // partial sums
   e += (int64_t)(2 * m + 3) * s * s + (int64_t)m * s * ldr + 3 * (int64_t)m * s * s + ldr * s + 8 * s * s;
-  if (delayed(s)) e += (int64_t)(m + 2) * s * s + 2 * (int64_t)(m + 2) * s * 2 * s;  // Hc2, Gm, Cm
+  if (delayed(s)) e += (int64_t)(m + 3) * s * s + 2 * (int64_t)(m + 2) * s * 2 * s;  // Hc2, Rprev, Gm, Cm
   return e * (int64_t)sizeof(c128) + (int64_t)m * ns * (int64_t)(z32 ? sizeof(c64) : sizeof(c128));  // + Z
 }
 
@@ -80,6 +80,7 @@ FgmresJob::FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c1
     Hc2.alloc(ctx, (int64_t)(m + 2) * s * s);
     Gm.alloc(ctx, (int64_t)(m + 2) * s * 2 * s);
     Cm.alloc(ctx, (int64_t)(m + 2) * s * 2 * s);
+    Rprev.alloc(ctx, (int64_t)s * s);
   } else {
     Hp.alloc(ctx, (int64_t)(m + 1) * s * s);
   }
@@ -205,21 +206,23 @@ void FgmresJob::after_matvec() {
   } else {
     c128* w = w_cur();
     c128* hn = h_col(jj);
-    if (jj == 0) {  // V_0 is final (CholQR2 of the residual): one projection
+    if (jj == 0) {  // V_0 is final (CholQR2 of the residual): one projection, V~_1 = W'
+      K.identity(Rprev.ptr());
       K.gram(1, V.ptr(), ns, w, part.ptr(), hn, false);
       K.block_axpy(1, V.ptr(), ns, hn, -1.0, w, w);
     } else {
-      // [V_<j, V~_j]^H [V~_j, W], the coefficients, then V_j and W' in one update
+      // [V_<j, V~_j]^H [V~_j, W], the coefficients, then V_j and V~_{j+1} = W' R_j^{-1} in one
+      // update (written over W)
       c128* vt = v_cur();
       c128* hp = h_col(jj - 1);
       K.gram_ext(jj + 1, V.ptr(), ns, jj, vt, vt, w, part.ptr(), Gm.ptr(), false);
-      K.dcgs_coef(jj * s, Gm.ptr(), Cm.ptr(), hp, hn, flag.ptr());
-      K.update_split(jj, V.ptr(), ns, vt, Cm.ptr(), V.ptr() + jj * ns, w, w);
+      K.dcgs_coef(jj * s, Gm.ptr(), Cm.ptr(), hp, hn, Rprev.ptr(), flag.ptr());
+      K.update_split(jj, V.ptr(), ns, vt, w, Cm.ptr(), V.ptr() + jj * ns, w);
       K.lsq_step(jj - 1, hp, Rm.ptr(), ldr, refl.ptr(), tau.ptr(), tmat.ptr(), G.ptr(), res.ptr());
     }
-    if (last) {  // finish column j: [V_<=j, W']^H W'
+    if (last) {  // finish column j: [V_<=j, V~_{j+1}]^H V~_{j+1}
       K.gram_ext(jj + 2, V.ptr(), ns, jj + 1, w, w, nullptr, part.ptr(), Gm.ptr(), false);
-      K.dcgs_coef((jj + 1) * s, Gm.ptr(), nullptr, nullptr, hn, flag.ptr());
+      K.dcgs_coef((jj + 1) * s, Gm.ptr(), nullptr, nullptr, hn, Rprev.ptr(), flag.ptr());
       K.lsq_step(jj, hn, Rm.ptr(), ldr, refl.ptr(), tau.ptr(), tmat.ptr(), G.ptr(), res.ptr());
     }
   }

@@ -23,11 +23,12 @@ struct KrylovKernels {
   // 2s columns); split operands need s = 16
   void gram_ext(int nblk, const c128* V, int64_t ldv, int nvb, const c128* Vx, const c128* W0, const c128* W1,
                 c128* part, c128* H, bool accumulate, c128* H2 = nullptr);
-  // [Y0, Y1] = [0, Yin1] + [V_0 .. V_{nvb-1}, Vx] C, C ((nvb + 1) s x 2s); s = 16
-  void update_split(int nvb, const c128* V, int64_t ldv, const c128* Vx, const c128* C, c128* Y0, const c128* Yin1,
+  // [Y0, Y1] = [V_0 .. V_{nvb-1}, Vx, Vx2] C, C ((nvb + 2) s x 2s); Y1 may be Vx2; s = 16
+  void update_split(int nvb, const c128* V, int64_t ldv, const c128* Vx, const c128* Vx2, const c128* C, c128* Y0,
                     c128* Y1);
-  // delayed-reorthogonalisation coefficients (k_dcgs_coef): C null finishes a column
-  void dcgs_coef(int nb, const c128* G, c128* C, c128* Hp, c128* Hn, int* flag);
+  // delayed-reorthogonalisation coefficients (k_dcgs_coef): C null finishes a column; Rprev is
+  // the triangular factor that scaled the block being completed (updated by the fused form)
+  void dcgs_coef(int nb, const c128* G, c128* C, c128* Hp, c128* Hn, c128* Rprev, int* flag);
   // Y = Yin + beta * sum_J V_J H[J][:]
   void block_axpy(int nblk, const c128* V, int64_t ldv, const c128* H, double beta, const c128* Yin, c128* Y);
   // the same with complex64 basis blocks (widened exactly)
@@ -72,7 +73,7 @@ struct FgmresJob {
   KrylovKernels K;
   bool z32;   // preconditioned blocks kept in complex64 (mixed-precision preconditioner)
   bool dcgs;  // delayed reorthogonalisation (16 columns); CGS2 + CholQR2 otherwise
-  DevArray<c128> V, Zb, W, Wt, R, part, Hc, Hp, Hc2, Gm, Cm, Rm, refl, tau, tmat, G, Y, Gs, Rs, Ri, Racc;
+  DevArray<c128> V, Zb, W, Wt, R, part, Hc, Hp, Hc2, Gm, Cm, Rprev, Rm, refl, tau, tmat, G, Y, Gs, Rs, Ri, Racc;
   DevArray<c64> Zs;
   DevArray<double> res, npart, nrm;
   DevArray<int> flag;

@@ -223,18 +223,20 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(int64_t n, int Jtot, const
 }
 
 // Y = Yin + beta V H.  V is Jtot basis columns in blocks of S = 16 NCT (block b < nvb at
-// V + b ldv, block nvb at Vx); Y is NRB blocks of S columns (Y0, Y1, each with its own Yin,
-// which may be null or equal to its Y), H has NRB S columns.  A wavefront holds RT tiles of
+// V + b ldv, block nvb at Vx, block nvb + 1 at Vx2); Y is NRB blocks of S columns (Y0, Y1, each
+// with its own Yin, which may be null or equal to its Y), H has NRB S columns.  A Y block may
+// also be one of the V blocks: every row of Y is written by the wavefront that read that row
+// of every V block, after its last read.  A wavefront holds RT tiles of
 // 16 rows; the basis columns go 16 at a time, lane l taking columns 4 (l/16) .. 4 (l/16) + 3
 // of row l%16 of each tile (64 contiguous bytes) for eight consecutive k steps.
 // M3: three real products per complex one (where the matrix cores bound the kernel):
 //   P1 = a_re b_re, P2 = a_im b_im, P3 = (a_re + a_im)(b_re + b_im);  a b = (P1 - P2) + i (P3 - P1 - P2)
 // Three wavefronts per SIMD (register budget 168).
 template <typename TV, int NCT, int NRB, int RT, bool M3 = false>
-__global__ __launch_bounds__(256, 3) void k_axpy_mfma(int64_t n, int Jtot, const cplx<TV>* __restrict__ V, int64_t ldv,
-                                                   int nvb, const cplx<TV>* __restrict__ Vx,
-                                                   const c128* __restrict__ H, double beta, const c128* Yin0, c128* Y0,
-                                                   const c128* Yin1, c128* Y1) {
+__global__ __launch_bounds__(256, 3) void k_axpy_mfma(int64_t n, int Jtot, const cplx<TV>* V, int64_t ldv, int nvb,
+                                                      const cplx<TV>* Vx, const cplx<TV>* Vx2,
+                                                      const c128* __restrict__ H, double beta, const c128* Yin0,
+                                                      c128* Y0, const c128* Yin1, c128* Y1) {
   constexpr int S = 16 * NCT, NC = NRB * NCT, SH = NRB * S;
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, lc = l & 15, q = l >> 4;
   const int64_t rbase = ((int64_t)blockIdx.x * 4 + wv) * (16 * RT);
@@ -249,7 +251,7 @@ __global__ __launch_bounds__(256, 3) void k_axpy_mfma(int64_t n, int Jtot, const
   auto load = [&](int J, c128 (&h)[4][NC], c128 (&a)[RT][4]) {
     const bool jok = J < Jtot;
     const int b = J / S, jc = J - (J / S) * S;
-    const cplx<TV>* vb = (b < nvb ? V + (int64_t)b * ldv : Vx) + jc + 4 * q;
+    const cplx<TV>* vb = (b < nvb ? V + (int64_t)b * ldv : b == nvb ? Vx : Vx2) + jc + 4 * q;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -491,29 +493,36 @@ __global__ __launch_bounds__(256) void k_chol_small(int s, const c128* __restric
 // same pass that projects the new product W once.  With V = [V_0 .. V_{j-1}] orthonormal and
 // G = [V, Vt]^H [Vt, W] ((nb + s) x 2s, nb = j s; a = V^H Vt, c = V^H W, b = Vt^H Vt,
 // d = Vt^H W):
-//   R^H R = b - a^H a (Cholesky of the Gram matrix of Vt - V a), v_j = (Vt - V a) R^{-1},
-//   h = v_j^H W = R^{-H} (d - a^H c), W' = W - V c - v_j h, written as one product
-//   [v_j, W'] = [0, W] + [V, Vt] C,  C = [[-a Ri, a T - c], [Ri, -T]],  Ri = R^{-1}, T = Ri h.
-// Vt = V a + v_j R completes the Hessenberg column of the previous step (Hp: += a on rows
-// < nb, R on rows nb .. nb + s); the new column (Hn) holds c, h until the next step adds its
-// own correction.  Finishing (C null): G = [V, W]^H W ((nb + s) x s, V = [V_0 .. V_j]);
-// Hn += a on rows < nb and R on rows nb .. nb + s.  flag[0] = 1 when a pivot of R^H R falls
-// below 1e-14 of its diagonal entry of b (a numerically dependent block), as in CholQR.
+//   R^H R = b - a^H a (Cholesky of the Gram matrix of Vt - V a), v_j = (Vt - V a) Ri, Ri = R^{-1},
+//   h = v_j^H W = R^{-H} (d - a^H c), W' = W - V c - v_j h.
+// The next block is Vt' = W' Ri: it then carries the scale of a normalised step instead of
+// the product of every earlier step's scale (which underflows once a column has converged).
+// One product writes both: [v_j, Vt'] = [V, Vt, W] C with T = Ri h, U = T Ri,
+//   C = [[-a Ri, a U - c Ri], [Ri, -U], [0, Ri]].
+// Vt = V a + v_j R completes the Hessenberg column of the previous step, whose block was
+// scaled by Rprev^{-1} (Hp: += a Rprev on rows < nb, R Rprev on rows nb .. nb + s); the new
+// column (Hn) holds c, h until the next step adds its own part; Rprev becomes R.
+// Finishing (C null): G = [V, Vt]^H Vt ((nb + s) x s, V = [V_0 .. V_j]): Hn += a Rprev on rows
+// < nb and R Rprev on rows nb .. nb + s.  flag[0] = 1 when a pivot of R^H R falls below 1e-14 of
+// its diagonal entry of b (a numerically dependent block), as in CholQR.
 // One block of 1024 threads; s a power of two <= 32.
 __global__ __launch_bounds__(1024) void k_dcgs_coef(int s, int nb, const c128* __restrict__ G,
                                                     c128* __restrict__ C, c128* __restrict__ Hp,
-                                                    c128* __restrict__ Hn, int* __restrict__ flag) {
+                                                    c128* __restrict__ Hn, c128* __restrict__ Rprev,
+                                                    int* __restrict__ flag) {
   __shared__ c128 A[32][33];   // b - a^H a, eliminated in place
   __shared__ c128 Rs[32][33];  // R
   __shared__ c128 Xs[32][33];  // Ri
   __shared__ c128 Qs[32][33];  // d - a^H c, then h
-  __shared__ c128 Ts[32][33];  // T = Ri h
+  __shared__ c128 Ts[32][33];  // T = Ri h, then U = T Ri
+  __shared__ c128 Ps[32][33];  // Rprev
   __shared__ c128 red[1024];
   const int t = threadIdx.x;
   const bool fused = C != nullptr;
   const int so = fused ? 2 * s : s;
   const int ss = s * s, ng = 1024 / ss;
   auto Gat = [&](int i, int c) { return G[(int64_t)i * so + c]; };
+  if (t < ss) Ps[t / s][t % s] = Rprev[t];
   // P = b - a^H a and Q = d - a^H c: ng groups of threads take every ng-th basis row, then
   // the group sums are added in a fixed order
   for (int pass = 0; pass < (fused ? 2 : 1); ++pass) {
@@ -527,13 +536,12 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int s, int nb, const c128* _
       c128 sum = red[t];
       for (int q = 1; q < ng; ++q) sum = sum + red[q * ss + t];
       const c128 v = Gat(nb + k, pass * s + l) - sum;
-      if (pass == 0)
-        A[k][l] = v;
-      else
-        Qs[k][l] = v;
       if (pass == 0) {
+        A[k][l] = v;
         Rs[k][l] = cmk(0.0, 0.0);
         Xs[k][l] = cmk(0.0, 0.0);
+      } else {
+        Qs[k][l] = v;
       }
     }
     __syncthreads();
@@ -567,11 +575,20 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int s, int nb, const c128* _
     }
   }
   __syncthreads();
-  if (!fused) {
-    for (int e = t; e < nb * s; e += 1024) Hn[e] = Hn[e] + G[e];  // rows < nb of G are a (width s)
-    if (t < ss) Hn[(int64_t)nb * s + t] = Rs[t / s][t % s];
-    return;
+  c128* Hc = fused ? Hp : Hn;  // the column this call completes
+  for (int e = t; e < nb * s; e += 1024) {  // rows < nb: += a Rprev (Rprev upper triangular)
+    const int i = e / s, l = e % s;
+    c128 v = Hc[e];
+    for (int m = 0; m <= l; ++m) cfma(v, Gat(i, m), Ps[m][l]);
+    Hc[e] = v;
   }
+  if (t < ss) {  // subdiagonal block R Rprev
+    const int k = t / s, l = t % s;
+    c128 v = cmk(0.0, 0.0);
+    for (int m = k; m <= l; ++m) cfma(v, Rs[k][m], Ps[m][l]);
+    Hc[(int64_t)nb * s + t] = v;
+  }
+  if (!fused) return;
   c128 hv = cmk(0.0, 0.0);
   if (t < ss) {  // h = Ri^H Q (Ri upper triangular)
     const int k = t / s, l = t % s;
@@ -580,32 +597,44 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int s, int nb, const c128* _
   __syncthreads();
   if (t < ss) Qs[t / s][t % s] = hv;
   __syncthreads();
+  c128 tv = cmk(0.0, 0.0);
   if (t < ss) {  // T = Ri h
     const int k = t / s, l = t % s;
-    c128 v = cmk(0.0, 0.0);
-    for (int m = k; m < s; ++m) cfma(v, Xs[k][m], Qs[m][l]);
-    Ts[k][l] = v;
+    for (int m = k; m < s; ++m) cfma(tv, Xs[k][m], Qs[m][l]);
+    Ts[k][l] = tv;
   }
+  __syncthreads();
+  c128 uv = cmk(0.0, 0.0);
+  if (t < ss) {  // U = T Ri
+    const int k = t / s, l = t % s;
+    for (int m = 0; m <= l; ++m) cfma(uv, Ts[k][m], Xs[m][l]);
+  }
+  __syncthreads();
+  if (t < ss) Ts[t / s][t % s] = uv;
   __syncthreads();
   for (int e = t; e < nb * s; e += 1024) {
     const int i = e / s, l = e % s;
-    c128 x = cmk(0.0, 0.0), y = cmk(0.0, 0.0) - Gat(i, s + l);
+    c128 x = cmk(0.0, 0.0), y = cmk(0.0, 0.0);
     for (int m = 0; m < s; ++m) {
       const c128 am = Gat(i, m);
-      if (m <= l) cfms(x, am, Xs[m][l]);
+      if (m <= l) {
+        cfms(x, am, Xs[m][l]);
+        cfms(y, Gat(i, s + m), Xs[m][l]);
+      }
       cfma(y, am, Ts[m][l]);
     }
     C[(int64_t)i * 2 * s + l] = x;
     C[(int64_t)i * 2 * s + s + l] = y;
-    Hp[e] = Hp[e] + Gat(i, l);
     Hn[e] = Gat(i, s + l);
   }
   if (t < ss) {
     const int k = t / s, l = t % s;
     C[(int64_t)(nb + k) * 2 * s + l] = Xs[k][l];
     C[(int64_t)(nb + k) * 2 * s + s + l] = cmk(0.0, 0.0) - Ts[k][l];
-    Hp[(int64_t)nb * s + t] = Rs[k][l];
+    C[(int64_t)(nb + s + k) * 2 * s + l] = cmk(0.0, 0.0);
+    C[(int64_t)(nb + s + k) * 2 * s + s + l] = Xs[k][l];
     Hn[(int64_t)nb * s + t] = Qs[k][l];
+    Rprev[t] = Rs[k][l];
   }
 }
 
@@ -1038,10 +1067,10 @@ static void block_axpy_t(KrylovKernels& k, int nblk, const cplx<TV>* V, int64_t 
   const cplx<TV>* none = nullptr;
   if (s == 16)  // 4 wavefronts x 2 tiles of 16 rows per block
     hipLaunchKernelGGL((k_axpy_mfma<TV, 1, 1, 2>), dim3((unsigned)((n + 127) / 128)), dim3(256), 0, st, n, Jtot, V, ldv,
-                       nblk, none, H, beta, Yin, Y, (const c128*)nullptr, (c128*)nullptr);
+                       nblk, none, none, H, beta, Yin, Y, (const c128*)nullptr, (c128*)nullptr);
   else if (s == 32)  // 4 wavefronts x 1 tile of 16 rows per block
     hipLaunchKernelGGL((k_axpy_mfma<TV, 2, 1, 1>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, n, Jtot, V, ldv,
-                       nblk, none, H, beta, Yin, Y, (const c128*)nullptr, (c128*)nullptr);
+                       nblk, none, none, H, beta, Yin, Y, (const c128*)nullptr, (c128*)nullptr);
   else if (s == 1)
     axpy_t<TV, 1>(k, Jtot, V, ldv, H, beta, Yin, Y);
   else if (s == 2)
@@ -1067,22 +1096,22 @@ void KrylovKernels::block_axpy(int nblk, const c64* V, int64_t ldv, const c128* 
   block_axpy_t<float>(*this, nblk, V, ldv, H, beta, Yin, Y);
 }
 
-void KrylovKernels::update_split(int nvb, const c128* V, int64_t ldv, const c128* Vx, const c128* C, c128* Y0,
-                                 const c128* Yin1, c128* Y1) {
+void KrylovKernels::update_split(int nvb, const c128* V, int64_t ldv, const c128* Vx, const c128* Vx2, const c128* C,
+                                 c128* Y0, c128* Y1) {
   HZ_REQUIRE(s == 16, HZ_ERR_STATE, "update_split: needs 16 columns");
-  const int Jtot = (nvb + 1) * s;
-  // algorithmic traffic: the Jtot basis columns and Yin1 once, Y0 and Y1 written once
-  ProfScope ps(ctx, HZ_K_CGS_UPDATE, (double)n * (Jtot + 3 * s) * sizeof(c128), 8.0 * n * Jtot * 2 * s);
+  const int Jtot = (nvb + 2) * s;
+  // algorithmic traffic: the Jtot basis columns once, Y0 and Y1 written once
+  ProfScope ps(ctx, HZ_K_CGS_UPDATE, (double)n * (Jtot + 2 * s) * sizeof(c128), 8.0 * n * Jtot * 2 * s);
   // 4 wavefronts x 1 tile of 16 rows per block
   hipLaunchKernelGGL((k_axpy_mfma<double, 1, 2, 1, true>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, ctx->stream, n,
-                     Jtot, V, ldv, nvb, Vx, C, 1.0, (const c128*)nullptr, Y0, Yin1, Y1);
+                     Jtot, V, ldv, nvb, Vx, Vx2, C, 1.0, (const c128*)nullptr, Y0, (const c128*)nullptr, Y1);
   HIP_CHECK(hipGetLastError());
 }
 
-void KrylovKernels::dcgs_coef(int nb, const c128* G, c128* C, c128* Hp, c128* Hn, int* flag) {
+void KrylovKernels::dcgs_coef(int nb, const c128* G, c128* C, c128* Hp, c128* Hn, c128* Rprev, int* flag) {
   HZ_REQUIRE(s == 1 || s == 2 || s == 4 || s == 8 || s == 16 || s == 32, HZ_ERR_STATE,
              "dcgs_coef: block size must be a power of two");
-  hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(1024), 0, ctx->stream, s, nb, G, C, Hp, Hn, flag);
+  hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(1024), 0, ctx->stream, s, nb, G, C, Hp, Hn, Rprev, flag);
   HIP_CHECK(hipGetLastError());
 }
 

@@ -263,6 +263,48 @@ def test_solve_to_tolerance_matches_direct(ctx):
     assert _rel(X, Xd) <= 1e-9
 
 
+def test_delayed_reorthogonalisation_restarts_and_convergence(ctx):
+    """16-column blocks take the delayed-reorthogonalisation path, whose Hessenberg columns
+    complete one step late: restarted cycles (restart 3) that end on the tolerance must stop
+    after the same number of steps as the CGS2 oracle, with the same restarts and the same
+    iterate; and a block iterated on past convergence (its Krylov blocks become dependent)
+    must end its cycle with a finite, converged result."""
+    p = w.unit_cube_problem(4, freq=1.0, parts=(2, 2, 2), overlap=1)
+    om = fem.Mesh(p.tets, p.coords, p.face_bc)
+    A = fem.assemble_operator(om, p.velocity, p.freq)
+    gm = ctx.mesh(p.tets, p.coords, p.face_bc)
+    gop = ctx.assemble(gm, p.velocity, p.freq)
+    d = ctx.setup_ddm(gop, p.partition, p.n_sub, p.overlap)
+    subs, own = odd.build_subdomains(om, p.velocity, p.freq, None, p.partition, p.n_sub, p.overlap)
+    odd.factor_subdomains(subs)
+    P = odd.ORAS(A, subs)
+    rng = np.random.default_rng(33)
+    B = rng.standard_normal((16, om.n)) + 1j * rng.standard_normal((16, om.n))
+    for m, tol in ((3, 1e-9), (40, 1e-10)):
+        X, info = ctx.solve(d, B, tol=tol, max_iter=200, restart=m)
+        Xo, io = krylov.block_fgmres(lambda x: A @ x, B.T, P.apply, tol=tol, m=m, max_iter=200)
+        print(f"restart {m}: GPU {info[0]['iters']} steps, {info[0]['restarts']} restarts; "
+              f"oracle {io['iters']}, {io['restarts']}; iterate difference {_rel(X, Xo.T):.2e}")
+        assert info[0]["iters"] == io["iters"] and info[0]["restarts"] == io["restarts"]
+        assert all(i["rel_residual"] <= tol for i in info)
+        assert _rel(X, Xo.T) <= 1e-8, _rel(X, Xo.T)
+    # past convergence: cube 3 at 1.5 Hz converges to rounding in a few steps of 16 columns
+    p = w.unit_cube_problem(3, freq=1.5, parts=(2, 2, 1), overlap=1)
+    om = fem.Mesh(p.tets, p.coords, p.face_bc)
+    A = fem.assemble_operator(om, p.velocity, p.freq)
+    gm = ctx.mesh(p.tets, p.coords, p.face_bc)
+    gop = ctx.assemble(gm, p.velocity, p.freq)
+    d2 = ctx.setup_ddm(gop, p.partition, p.n_sub, p.overlap)
+    B16 = rng.standard_normal((16, om.n)) + 1j * rng.standard_normal((16, om.n))
+    X, info = ctx.solve(d2, B16, fixed_iters=12, restart=12)
+    assert np.isfinite(X).all()
+    res = np.linalg.norm(B16.T - A @ X.T, axis=0) / np.linalg.norm(B16, axis=1)
+    assert res.max() <= 1e-8 and info[0]["iters"] <= 12, (res.max(), info[0]["iters"])
+    np.testing.assert_allclose(res, [i["rel_residual"] for i in info], rtol=1e-3, atol=1e-13)
+    ctx.release(d)
+    ctx.release(d2)
+
+
 def test_config1_plane_wave(ctx):
     """Unit cube 8^3 (15,625 dofs), k = 8 pi, impedance everywhere, 8 subdomains, overlap 1,
     one-level ORAS, c128, tol 1e-8: same iteration count as the oracle and the iterate at
