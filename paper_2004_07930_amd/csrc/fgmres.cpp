@@ -6,10 +6,11 @@
 //           orthogonalisation of W against the basis ; Householder update of the block
 //           Hessenberg QR applied to G ; per-column residual estimate |G_{j+1}| / |b|
 //   end:    Y = R^{-1} G ; X += Z Y ; explicit residual decides restart.
-// Orthogonalisation, 16 columns: delayed reorthogonalisation (DCGS2).  W is projected once
-// (W' = W - V V^H W); W' is the block V~_{j+1} that the next step preconditions, and that
-// step projects it again and normalises it (V_{j+1}) in the same passes over the basis that
-// project its own product.  So each step reads the basis twice (one Gram product, one
+// Orthogonalisation, 16 or 32 columns: delayed reorthogonalisation (DCGS2).  W is projected once
+// (W' = W - V V^H W); W' scaled by diag(R_j)^{-1} (R_j: the triangular factor that normalised
+// V_j; the scale of each step's block then does not compound) is the block V~_{j+1} that the
+// next step preconditions, and that step projects it again and normalises it (V_{j+1}) in the
+// same passes over the basis that project its own product.  So each step reads the basis twice (one Gram product, one
 // update) instead of four times, and column j of the Hessenberg matrix is complete one step
 // later: the convergence test of column j runs at step j + 1, and the step known to be the
 // cycle's last finishes its own column with one more Gram product.  The flexible method
@@ -97,7 +98,7 @@ FgmresJob::FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c1
   res.alloc(ctx, s);
   npart.alloc(ctx, (int64_t)K.nchunk * s);
   nrm.alloc(ctx, s);
-  flag.alloc(ctx, 1);
+  flag.alloc(ctx, 2);
   bnorm.assign(s, 0.0);
   est.assign(s, 0.0);
   rel.assign(s, 0.0);
@@ -141,7 +142,7 @@ void FgmresJob::cholqr2(const c128* in, c128* out) {
 
 void FgmresJob::start() {
   hipStream_t st = ctx->stream;
-  HIP_CHECK(hipMemsetAsync(flag.ptr(), 0, sizeof(int), st));
+  HIP_CHECK(hipMemsetAsync(flag.ptr(), 0, 2 * sizeof(int), st));
   K.colnorms(B, npart.ptr(), nrm.ptr());
   HIP_CHECK(hipMemcpyAsync(bnorm.data(), nrm.ptr(), s * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
@@ -154,9 +155,9 @@ void FgmresJob::start() {
   base = 0;
   restarts = 0;
   start_cycle();
-  HIP_CHECK(hipMemcpyAsync(&hflag, flag.ptr(), sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(hflags, flag.ptr(), sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
-  HZ_REQUIRE(hflag == 0, HZ_ERR_ARG,
+  HZ_REQUIRE(hflags[0] == 0, HZ_ERR_ARG,
              "hz_solve: the right-hand-side block is numerically rank deficient (dependent columns): "
              "solve such columns in separate blocks");
 }
@@ -164,7 +165,7 @@ void FgmresJob::start() {
 void FgmresJob::start_cycle() {
   hipStream_t st = ctx->stream;
   const c128 one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
-  HIP_CHECK(hipMemsetAsync(flag.ptr(), 0, sizeof(int), st));
+  HIP_CHECK(hipMemsetAsync(flag.ptr(), 0, 2 * sizeof(int), st));
   if (total == 0)
     HIP_CHECK(hipMemcpyAsync(R.ptr(), B, n * s * sizeof(c128), hipMemcpyDeviceToDevice, st));
   else
@@ -211,8 +212,8 @@ void FgmresJob::after_matvec() {
       K.gram(1, V.ptr(), ns, w, part.ptr(), hn, false);
       K.block_axpy(1, V.ptr(), ns, hn, -1.0, w, w);
     } else {
-      // [V_<j, V~_j]^H [V~_j, W], the coefficients, then V_j and V~_{j+1} = W' R_j^{-1} in one
-      // update (written over W)
+      // [V_<j, V~_j]^H [V~_j, W], the coefficients, then V_j and V~_{j+1} = W' diag(R_j)^{-1} in
+      // one update (written over W)
       c128* vt = v_cur();
       c128* hp = h_col(jj - 1);
       K.gram_ext(jj + 1, V.ptr(), ns, jj, vt, vt, w, part.ptr(), Gm.ptr(), false);
@@ -222,25 +223,27 @@ void FgmresJob::after_matvec() {
     }
     if (last) {  // finish column j: [V_<=j, V~_{j+1}]^H V~_{j+1}
       K.gram_ext(jj + 2, V.ptr(), ns, jj + 1, w, w, nullptr, part.ptr(), Gm.ptr(), false);
-      K.dcgs_coef((jj + 1) * s, Gm.ptr(), nullptr, nullptr, hn, Rprev.ptr(), flag.ptr());
+      K.dcgs_coef((jj + 1) * s, Gm.ptr(), nullptr, nullptr, hn, Rprev.ptr(), flag.ptr() + 1);
       K.lsq_step(jj, hn, Rm.ptr(), ldr, refl.ptr(), tau.ptr(), tmat.ptr(), G.ptr(), res.ptr());
     }
   }
   HIP_CHECK(hipMemcpyAsync(est.data(), res.ptr(), s * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipMemcpyAsync(&hflag, flag.ptr(), sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(hflags, flag.ptr(), 2 * sizeof(int), hipMemcpyDeviceToHost, st));
 }
 
 bool FgmresJob::cycle_done() {
   // the caller has synchronised the stream since after_matvec()
+  // a breakdown (a new block numerically dependent on the basis: the Krylov space is exhausted
+  // for some column) ends the cycle at the column whose subdiagonal block it gives: with CGS2
+  // and the finishing pass that is column j; with the delayed form's step j it is column j - 1,
+  // and column j (built from the dependent block) is dropped
+  const bool brk = hflags[0] != 0, brk_fin = hflags[1] != 0;
   // Hessenberg columns complete in this cycle (the estimate refers to the last of them)
-  const int done = dcgs ? (last ? jj + 1 : jj) : jj + 1;
+  const int done = !dcgs ? jj + 1 : brk ? jj : last ? jj + 1 : jj;
   total = base + done;
   bool conv = done > 0;
   for (int c = 0; c < s; ++c) conv = conv && (est[c] / bnorm[c] <= o.tol);
-  // a CholQR breakdown (a new block numerically dependent on the basis: the Krylov space is
-  // exhausted for some column) ends the cycle at the column it completes
-  const bool brk = hflag != 0;
-  const bool end = brk || last || (o.fixed_iters <= 0 && conv);
+  const bool end = brk || brk_fin || last || (o.fixed_iters <= 0 && conv);
   if (end)
     ncols = done;
   else
@@ -270,9 +273,9 @@ bool FgmresJob::end_cycle() {
   if (!(o.fixed_iters > 0 || conv || total >= o.max_iter)) {
     ++restarts;
     start_cycle();
-    HIP_CHECK(hipMemcpyAsync(&hflag, flag.ptr(), sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(hflags, flag.ptr(), sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
-    if (hflag == 0) return false;
+    if (hflags[0] == 0) return false;
     // the new residual block is numerically rank deficient: no further cycle can start, and
     // the columns are reported as they stand
   }

@@ -20,10 +20,10 @@ struct KrylovKernels {
             c128* H2 = nullptr);
   // the same with the basis blocks b < nvb at V + b ldv and block nvb at Vx (Jtot = (nblk) s
   // columns in all), and a right operand of two blocks [W0, W1] when W1 is given (H then has
-  // 2s columns); split operands need s = 16
+  // 2s columns); split operands need s = 16 or 32
   void gram_ext(int nblk, const c128* V, int64_t ldv, int nvb, const c128* Vx, const c128* W0, const c128* W1,
                 c128* part, c128* H, bool accumulate, c128* H2 = nullptr);
-  // [Y0, Y1] = [V_0 .. V_{nvb-1}, Vx, Vx2] C, C ((nvb + 2) s x 2s); Y1 may be Vx2; s = 16
+  // [Y0, Y1] = [V_0 .. V_{nvb-1}, Vx, Vx2] C, C ((nvb + 2) s x 2s); Y1 may be Vx2; s = 16 or 32
   void update_split(int nvb, const c128* V, int64_t ldv, const c128* Vx, const c128* Vx2, const c128* C, c128* Y0,
                     c128* Y1);
   // delayed-reorthogonalisation coefficients (k_dcgs_coef): C null finishes a column; Rprev is
@@ -72,7 +72,7 @@ struct FgmresJob {
   int64_t n, ldr = 0;
   KrylovKernels K;
   bool z32;   // preconditioned blocks kept in complex64 (mixed-precision preconditioner)
-  bool dcgs;  // delayed reorthogonalisation (16 columns); CGS2 + CholQR2 otherwise
+  bool dcgs;  // delayed reorthogonalisation (16 or 32 columns); CGS2 + CholQR2 otherwise
   DevArray<c128> V, Zb, W, Wt, R, part, Hc, Hp, Hc2, Gm, Cm, Rprev, Rm, refl, tau, tmat, G, Y, Gs, Rs, Ri, Racc;
   DevArray<c64> Zs;
   DevArray<double> res, npart, nrm;
@@ -82,12 +82,14 @@ struct FgmresJob {
   int base = 0;        // Hessenberg columns completed before this cycle
   int ncols = 0;       // columns of this cycle that end_cycle() combines
   bool last = false;   // this step is the cycle's last (restart length, fixed count, max_iter)
-  int hflag = 0;  // host copy of the CholQR breakdown flag (a numerically dependent block)
+  // host copies of the breakdown flags (a numerically dependent block): [0] CholQR, or the
+  // delayed form's step (column j - 1); [1] the delayed form's finishing pass (column j)
+  int hflags[2] = {0, 0};
   std::vector<ColInfo> info;
 
   FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c128* X_, const SolveOptions& o_, int m_);
   static int64_t bytes_needed(int64_t n, int s, int m, bool z32);
-  static bool delayed(int s) { return s == 16; }
+  static bool delayed(int s) { return s == 16 || s == 32; }
   static int restart_for(Ctx* ctx, int64_t n, int s, int want, int fixed, bool z32);
   void start();                 // norms of B (synchronises), X = 0, first cycle
   c128* v_cur();                // block to precondition this step

@@ -231,9 +231,9 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(int64_t n, int Jtot, const
 // of row l%16 of each tile (64 contiguous bytes) for eight consecutive k steps.
 // M3: three real products per complex one (where the matrix cores bound the kernel):
 //   P1 = a_re b_re, P2 = a_im b_im, P3 = (a_re + a_im)(b_re + b_im);  a b = (P1 - P2) + i (P3 - P1 - P2)
-// Three wavefronts per SIMD (register budget 168).
+// Three wavefronts per SIMD (register budget 168); two with four column tiles.
 template <typename TV, int NCT, int NRB, int RT, bool M3 = false>
-__global__ __launch_bounds__(256, 3) void k_axpy_mfma(int64_t n, int Jtot, const cplx<TV>* V, int64_t ldv, int nvb,
+__global__ __launch_bounds__(256, NCT * NRB > 2 ? 2 : 3) void k_axpy_mfma(int64_t n, int Jtot, const cplx<TV>* V, int64_t ldv, int nvb,
                                                       const cplx<TV>* Vx, const cplx<TV>* Vx2,
                                                       const c128* __restrict__ H, double beta, const c128* Yin0,
                                                       c128* Y0, const c128* Yin1, c128* Y1) {
@@ -495,13 +495,15 @@ __global__ __launch_bounds__(256) void k_chol_small(int s, const c128* __restric
 // d = Vt^H W):
 //   R^H R = b - a^H a (Cholesky of the Gram matrix of Vt - V a), v_j = (Vt - V a) Ri, Ri = R^{-1},
 //   h = v_j^H W = R^{-H} (d - a^H c), W' = W - V c - v_j h.
-// The next block is Vt' = W' Ri: it then carries the scale of a normalised step instead of
-// the product of every earlier step's scale (which underflows once a column has converged).
-// One product writes both: [v_j, Vt'] = [V, Vt, W] C with T = Ri h, U = T Ri,
-//   C = [[-a Ri, a U - c Ri], [Ri, -U], [0, Ri]].
+// The next block is Vt' = W' D, D = diag(1 / R_kk): each column then carries the scale of a
+// normalised step instead of the product of every earlier step's scale (which underflows once
+// a column has converged).  A diagonal keeps the products as well conditioned as W' itself;
+// scaling by Ri would multiply the cancellation in W' by the condition number of R again.
+// One product writes both: [v_j, Vt'] = [V, Vt, W] C with T = Ri h,
+//   C = [[-a Ri, (a T - c) D], [Ri, -T D], [0, D]].
 // Vt = V a + v_j R completes the Hessenberg column of the previous step, whose block was
 // scaled by Rprev^{-1} (Hp: += a Rprev on rows < nb, R Rprev on rows nb .. nb + s); the new
-// column (Hn) holds c, h until the next step adds its own part; Rprev becomes R.
+// column (Hn) holds c, h until the next step adds its own part; Rprev becomes D^{-1}.
 // Finishing (C null): G = [V, Vt]^H Vt ((nb + s) x s, V = [V_0 .. V_j]): Hn += a Rprev on rows
 // < nb and R Rprev on rows nb .. nb + s.  flag[0] = 1 when a pivot of R^H R falls below 1e-14 of
 // its diagonal entry of b (a numerically dependent block), as in CholQR.
@@ -514,7 +516,7 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int s, int nb, const c128* _
   __shared__ c128 Rs[32][33];  // R
   __shared__ c128 Xs[32][33];  // Ri
   __shared__ c128 Qs[32][33];  // d - a^H c, then h
-  __shared__ c128 Ts[32][33];  // T = Ri h, then U = T Ri
+  __shared__ c128 Ts[32][33];  // T = Ri h
   __shared__ c128 Ps[32][33];  // Rprev
   __shared__ c128 red[1024];
   const int t = threadIdx.x;
@@ -604,37 +606,28 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int s, int nb, const c128* _
     Ts[k][l] = tv;
   }
   __syncthreads();
-  c128 uv = cmk(0.0, 0.0);
-  if (t < ss) {  // U = T Ri
-    const int k = t / s, l = t % s;
-    for (int m = 0; m <= l; ++m) cfma(uv, Ts[k][m], Xs[m][l]);
-  }
-  __syncthreads();
-  if (t < ss) Ts[t / s][t % s] = uv;
-  __syncthreads();
   for (int e = t; e < nb * s; e += 1024) {
     const int i = e / s, l = e % s;
-    c128 x = cmk(0.0, 0.0), y = cmk(0.0, 0.0);
+    c128 x = cmk(0.0, 0.0), y = cmk(0.0, 0.0) - Gat(i, s + l);
     for (int m = 0; m < s; ++m) {
       const c128 am = Gat(i, m);
-      if (m <= l) {
-        cfms(x, am, Xs[m][l]);
-        cfms(y, Gat(i, s + m), Xs[m][l]);
-      }
+      if (m <= l) cfms(x, am, Xs[m][l]);
       cfma(y, am, Ts[m][l]);
     }
+    const double dl = 1.0 / Rs[l][l].re;
     C[(int64_t)i * 2 * s + l] = x;
-    C[(int64_t)i * 2 * s + s + l] = y;
+    C[(int64_t)i * 2 * s + s + l] = cmk(y.re * dl, y.im * dl);
     Hn[e] = Gat(i, s + l);
   }
   if (t < ss) {
     const int k = t / s, l = t % s;
+    const double dl = 1.0 / Rs[l][l].re;
     C[(int64_t)(nb + k) * 2 * s + l] = Xs[k][l];
-    C[(int64_t)(nb + k) * 2 * s + s + l] = cmk(0.0, 0.0) - Ts[k][l];
+    C[(int64_t)(nb + k) * 2 * s + s + l] = cmk(-Ts[k][l].re * dl, -Ts[k][l].im * dl);
     C[(int64_t)(nb + s + k) * 2 * s + l] = cmk(0.0, 0.0);
-    C[(int64_t)(nb + s + k) * 2 * s + s + l] = Xs[k][l];
+    C[(int64_t)(nb + s + k) * 2 * s + s + l] = cmk(k == l ? dl : 0.0, 0.0);
     Hn[(int64_t)nb * s + t] = Qs[k][l];
-    Rprev[t] = Rs[k][l];
+    Rprev[t] = k == l ? Rs[k][k] : cmk(0.0, 0.0);
   }
 }
 
@@ -993,7 +986,7 @@ void KrylovKernels::gram_ext(int nblk, const c128* V, int64_t ldv, int nvb, cons
   const int Jtot = nblk * s;
   const int nrb = W1 ? 2 : 1;
   const bool mfma = s == 16 || s == 32;
-  HZ_REQUIRE((nvb == nblk && nrb == 1) || s == 16, HZ_ERR_STATE, "gram: split operands need 16 columns");
+  HZ_REQUIRE((nvb == nblk && nrb == 1) || s == 16 || s == 32, HZ_ERR_STATE, "gram: split operands need 16 or 32 columns");
   // about 2048 blocks in total: fewer, longer row chunks when there are many basis tiles
   // (never more chunks than `nchunk`: the partial-sum workspace is sized for nchunk)
   const int jper = s == 16 ? (nrb == 2 ? 48 : 64) : s == 32 ? 32 : kJT;
@@ -1026,10 +1019,15 @@ void KrylovKernels::gram_ext(int nblk, const c128* V, int64_t ldv, int nvb, cons
         if (r3 == 1) go(k_gram_mfma<1, 2, 1, 2, true>, g1, 48 * f3);
         if (r3 == 2) go(k_gram_mfma<1, 2, 2, 2, true>, g1, 48 * f3);
       }
-    } else if (mfma) {
+    } else if (mfma && nrb == 1) {
       const dim3 grid((unsigned)nch, (unsigned)jtiles);
-      hipLaunchKernelGGL((k_gram_mfma<2, 1, 2, 2>), grid, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, nblk,
-                         (const c128*)nullptr, W0, (const c128*)nullptr, part, rpc, 0);
+      hipLaunchKernelGGL((k_gram_mfma<2, 1, 2, 2>), grid, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, nvb, Vx, W0,
+                         (const c128*)nullptr, part, rpc, 0);
+    } else if (mfma) {  // 32 columns, right operand [W0, W1]: one basis block per group (the
+      // 3M form does not fit two wavefronts per SIMD at this width)
+      const dim3 grid((unsigned)nch, (unsigned)nblk);
+      hipLaunchKernelGGL((k_gram_mfma<2, 2, 2, 2>), grid, dim3(256), 0, ctx->stream, n, Jtot, V, ldv, nvb, Vx, W0, W1,
+                         part, rpc, 0);
     } else if (s <= 4) {
       gram_t<4>(*this, Jtot, V, ldv, W0, part, nch, rpc);
     } else if (s <= 8) {
@@ -1098,13 +1096,17 @@ void KrylovKernels::block_axpy(int nblk, const c64* V, int64_t ldv, const c128* 
 
 void KrylovKernels::update_split(int nvb, const c128* V, int64_t ldv, const c128* Vx, const c128* Vx2, const c128* C,
                                  c128* Y0, c128* Y1) {
-  HZ_REQUIRE(s == 16, HZ_ERR_STATE, "update_split: needs 16 columns");
+  HZ_REQUIRE(s == 16 || s == 32, HZ_ERR_STATE, "update_split: needs 16 or 32 columns");
   const int Jtot = (nvb + 2) * s;
   // algorithmic traffic: the Jtot basis columns once, Y0 and Y1 written once
   ProfScope ps(ctx, HZ_K_CGS_UPDATE, (double)n * (Jtot + 2 * s) * sizeof(c128), 8.0 * n * Jtot * 2 * s);
   // 4 wavefronts x 1 tile of 16 rows per block
-  hipLaunchKernelGGL((k_axpy_mfma<double, 1, 2, 1, true>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, ctx->stream, n,
-                     Jtot, V, ldv, nvb, Vx, Vx2, C, 1.0, (const c128*)nullptr, Y0, (const c128*)nullptr, Y1);
+  if (s == 16)
+    hipLaunchKernelGGL((k_axpy_mfma<double, 1, 2, 1, true>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, ctx->stream,
+                       n, Jtot, V, ldv, nvb, Vx, Vx2, C, 1.0, (const c128*)nullptr, Y0, (const c128*)nullptr, Y1);
+  else  // direct form: the 3M form spills at four column tiles
+    hipLaunchKernelGGL((k_axpy_mfma<double, 2, 2, 1>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, ctx->stream, n,
+                       Jtot, V, ldv, nvb, Vx, Vx2, C, 1.0, (const c128*)nullptr, Y0, (const c128*)nullptr, Y1);
   HIP_CHECK(hipGetLastError());
 }
 
