@@ -154,8 +154,11 @@ typedef struct {
 /*
  * hz_solve -- right-preconditioned block FGMRES(m) with two-level ORAS, x0 = 0.
  * Paper: section "Domain decomposition preconditioner" (GMRES with M^{-1}, eq. 2lvl) and
- * the stopping test ||A u - b|| / ||b|| <= eps of the FE section.  Classical Gram-Schmidt
- * applied twice, CholQR2 block normalisation, Householder least squares, all FP64.
+ * the stopping test ||A u - b|| / ||b|| <= eps of the FE section.  Blocks of 16 or 32
+ * columns are orthogonalised by classical Gram-Schmidt with delayed reorthogonalisation (one
+ * Gram product and one update over the basis per step; each column of the Hessenberg matrix
+ * is complete one step later), other widths by classical Gram-Schmidt applied twice with
+ * CholQR2 block normalisation; Householder least squares; all FP64.
  *   rhs [n_rhs][n_dofs] complex128, x same layout (may not alias rhs)
  * Returns HZ_ERR_NOT_CONVERGED (x = best iterate, info filled) when max_iter is hit;
  * HZ_ERR_ARG for a non-finite entry in rhs, a zero column, a block whose columns are
@@ -236,8 +239,8 @@ hz_status hz_ddm_levels(hz_ctx* ctx, hz_handle ddm, hz_ddm_level* out, int32_t m
  *   HZ_K_SPMM        multi-RHS operator product (FP64 CSR)
  *   HZ_K_ORAS_FWD    forward multifrontal sweep, one launch per tree level
  *   HZ_K_ORAS_BWD    backward multifrontal sweep, one launch per tree level
- *   HZ_K_CGS_GRAM    V^H W partial products of classical Gram-Schmidt
- *   HZ_K_CGS_UPDATE  W -= V H (and X += Z Y) block updates
+ *   HZ_K_CGS_GRAM    V^H W partial products of classical Gram-Schmidt (both forms)
+ *   HZ_K_CGS_UPDATE  W -= V H, the delayed form's [v_j, next block] update, X += Z Y
  * hz_profile_enable(ctx, 1) clears and starts recording, (ctx, 0) stops.
  * hz_profile_get synchronises the stream and returns the totals of one class.
  */
