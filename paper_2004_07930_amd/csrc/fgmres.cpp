@@ -100,7 +100,8 @@ FgmresJob::FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c1
   nrm.alloc(ctx, s);
   flag.alloc(ctx, 2);
   bnorm.assign(s, 0.0);
-  est.assign(s, 0.0);
+  est.alloc(s);
+  hflags.alloc(2);
   rel.assign(s, 0.0);
 }
 
@@ -155,7 +156,7 @@ void FgmresJob::start() {
   base = 0;
   restarts = 0;
   start_cycle();
-  HIP_CHECK(hipMemcpyAsync(hflags, flag.ptr(), sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(hflags.p, flag.ptr(), sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   HZ_REQUIRE(hflags[0] == 0, HZ_ERR_ARG,
              "hz_solve: the right-hand-side block is numerically rank deficient (dependent columns): "
@@ -227,8 +228,8 @@ void FgmresJob::after_matvec() {
       K.lsq_step(jj, hn, Rm.ptr(), ldr, refl.ptr(), tau.ptr(), tmat.ptr(), G.ptr(), res.ptr());
     }
   }
-  HIP_CHECK(hipMemcpyAsync(est.data(), res.ptr(), s * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipMemcpyAsync(hflags, flag.ptr(), 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(est.p, res.ptr(), s * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(hflags.p, flag.ptr(), 2 * sizeof(int), hipMemcpyDeviceToHost, st));
 }
 
 bool FgmresJob::cycle_done() {
@@ -273,7 +274,7 @@ bool FgmresJob::end_cycle() {
   if (!(o.fixed_iters > 0 || conv || total >= o.max_iter)) {
     ++restarts;
     start_cycle();
-    HIP_CHECK(hipMemcpyAsync(hflags, flag.ptr(), sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(hflags.p, flag.ptr(), sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
     if (hflags[0] == 0) return false;
     // the new residual block is numerically rank deficient: no further cycle can start, and

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <cstring>
@@ -104,6 +105,25 @@ __host__ __device__ __forceinline__ cplx<T> cdiv(cplx<T> a, cplx<T> b) {
 // ---------------------------------------------------------------- device memory
 
 struct Ctx;
+
+// Page-locked host array (hipHostMalloc) for small results copied to the host every step:
+// the copies are direct DMA transfers instead of staged ones.
+template <typename T>
+struct HostPinned {
+  T* p = nullptr;
+  HostPinned() = default;
+  HostPinned(const HostPinned&) = delete;
+  HostPinned& operator=(const HostPinned&) = delete;
+  ~HostPinned() {
+    if (p) (void)hipHostFree(p);
+  }
+  void alloc(size_t count) {
+    HIP_CHECK(hipHostMalloc((void**)&p, std::max<size_t>(1, count) * sizeof(T), hipHostMallocDefault));
+    for (size_t i = 0; i < count; ++i) p[i] = T{};
+  }
+  T& operator[](size_t i) { return p[i]; }
+  const T& operator[](size_t i) const { return p[i]; }
+};
 
 // Owning device allocation (the context's allocator, else hipMalloc / hipFree); the bytes
 // are charged to the context.

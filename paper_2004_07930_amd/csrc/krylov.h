@@ -77,14 +77,15 @@ struct FgmresJob {
   DevArray<c64> Zs;
   DevArray<double> res, npart, nrm;
   DevArray<int> flag;
-  std::vector<double> bnorm, est, rel;
+  std::vector<double> bnorm, rel;
+  HostPinned<double> est;  // per-column residual estimates of the latest least-squares step
   int total = 0, restarts = 0, jj = 0;
   int base = 0;        // Hessenberg columns completed before this cycle
   int ncols = 0;       // columns of this cycle that end_cycle() combines
   bool last = false;   // this step is the cycle's last (restart length, fixed count, max_iter)
   // host copies of the breakdown flags (a numerically dependent block): [0] CholQR, or the
   // delayed form's step (column j - 1); [1] the delayed form's finishing pass (column j)
-  int hflags[2] = {0, 0};
+  HostPinned<int> hflags;
   std::vector<ColInfo> info;
 
   FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c128* X_, const SolveOptions& o_, int m_);
