@@ -103,6 +103,20 @@ FgmresJob::FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c1
   est.alloc(s);
   hflags.alloc(2);
   rel.assign(s, 0.0);
+  if (dcgs) {
+    HIP_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    HIP_CHECK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  }
+}
+
+FgmresJob::~FgmresJob() {
+  if (side) {
+    (void)hipStreamSynchronize(side);
+    (void)hipStreamDestroy(side);
+  }
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
 }
 
 void FgmresJob::spmm(const c128* x, c128* y, c128 alpha, c128 beta, const c128* yin) {
@@ -219,8 +233,13 @@ void FgmresJob::after_matvec() {
       c128* hp = h_col(jj - 1);
       K.gram_ext(jj + 1, V.ptr(), ns, jj, vt, vt, w, part.ptr(), Gm.ptr(), false);
       K.dcgs_coef(jj * s, Gm.ptr(), Cm.ptr(), hp, hn, Rprev.ptr(), flag.ptr());
+      // column j - 1 is complete: its least-squares step runs beside the update
+      HIP_CHECK(hipEventRecord(ev_fork, st));
+      HIP_CHECK(hipStreamWaitEvent(side, ev_fork, 0));
+      K.lsq_step(jj - 1, hp, Rm.ptr(), ldr, refl.ptr(), tau.ptr(), tmat.ptr(), G.ptr(), res.ptr(), side);
+      HIP_CHECK(hipEventRecord(ev_join, side));
       K.update_split(jj, V.ptr(), ns, vt, w, Cm.ptr(), V.ptr() + jj * ns, w);
-      K.lsq_step(jj - 1, hp, Rm.ptr(), ldr, refl.ptr(), tau.ptr(), tmat.ptr(), G.ptr(), res.ptr());
+      HIP_CHECK(hipStreamWaitEvent(st, ev_join, 0));
     }
     if (last) {  // finish column j: [V_<=j, V~_{j+1}]^H V~_{j+1}
       K.gram_ext(jj + 2, V.ptr(), ns, jj + 1, w, w, nullptr, part.ptr(), Gm.ptr(), false);

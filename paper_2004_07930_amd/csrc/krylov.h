@@ -37,7 +37,9 @@ struct KrylovKernels {
   void cholqr_pass(const c128* W, c128* out, c128* part, c128* G, c128* R, c128* Rinv, c128* Racc, int* flag);
   void identity(c128* M);
   // block Hessenberg QR step jj: refl/tau/tmat hold each block's reflectors and its T factor
-  void lsq_step(int jj, c128* Hc, c128* Rm, int64_t ldr, c128* refl, c128* tau, c128* tmat, c128* G, double* res);
+  // (on `stream` when given, else the context's stream)
+  void lsq_step(int jj, c128* Hc, c128* Rm, int64_t ldr, c128* refl, c128* tau, c128* tmat, c128* G, double* res,
+                hipStream_t stream = nullptr);
   void lsq_solve(int J, const c128* Rm, int64_t ldr, const c128* G, c128* Y);
   void colnorms(const c128* X, double* part, double* out);
 };
@@ -88,7 +90,15 @@ struct FgmresJob {
   HostPinned<int> hflags;
   std::vector<ColInfo> info;
 
+  // delayed form: the least-squares step of column j - 1 runs on a second stream (default
+  // priority) beside the update of the same step, which does not depend on it
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
   FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c128* X_, const SolveOptions& o_, int m_);
+  ~FgmresJob();
+  FgmresJob(const FgmresJob&) = delete;
+  FgmresJob& operator=(const FgmresJob&) = delete;
   static int64_t bytes_needed(int64_t n, int s, int m, bool z32);
   static bool delayed(int s) { return s == 16 || s == 32; }
   static int restart_for(Ctx* ctx, int64_t n, int s, int want, int fixed, bool z32);

@@ -1148,12 +1148,13 @@ void KrylovKernels::identity(c128* M) {
 }
 
 void KrylovKernels::lsq_step(int jj, c128* Hc, c128* Rm, int64_t ldr, c128* refl, c128* tau, c128* tmat, c128* G,
-                             double* res) {
+                             double* res, hipStream_t stream) {
   int sp = 1;
   while (sp < s) sp <<= 1;
   const int L = std::min(64, 256 / sp);
+  hipStream_t st = stream ? stream : ctx->stream;
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(1), dim3(256), 0, ctx->stream, s, jj, Hc, Rm, ldr, refl, tau, tmat, G, res);
+    hipLaunchKernelGGL(kern, dim3(1), dim3(256), 0, st, s, jj, Hc, Rm, ldr, refl, tau, tmat, G, res);
   };
   if (L == 64)
     go(k_lsq_step<64>);
