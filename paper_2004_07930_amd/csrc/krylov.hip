@@ -507,11 +507,13 @@ __global__ __launch_bounds__(256) void k_chol_small(int s, const c128* __restric
 // Finishing (C null): G = [V, Vt]^H Vt ((nb + s) x s, V = [V_0 .. V_j]): Hn += a Rprev on rows
 // < nb and R Rprev on rows nb .. nb + s.  flag[0] = 1 when a pivot of R^H R falls below 1e-14 of
 // its diagonal entry of b (a numerically dependent block), as in CholQR.
-// One block of 1024 threads; s a power of two <= 32.
-__global__ __launch_bounds__(1024) void k_dcgs_coef(int s, int nb, const c128* __restrict__ G,
-                                                    c128* __restrict__ C, c128* __restrict__ Hp,
-                                                    c128* __restrict__ Hn, c128* __restrict__ Rprev,
-                                                    int* __restrict__ flag) {
+// One block of 1024 threads; S (the block size) a power of two <= 32, a template parameter
+// so that the loops over a row of the Gram block unroll and their loads issue together.
+template <int S>
+__global__ __launch_bounds__(1024) void k_dcgs_coef(int nb, const c128* __restrict__ G, c128* __restrict__ C,
+                                                    c128* __restrict__ Hp, c128* __restrict__ Hn,
+                                                    c128* __restrict__ Rprev, int* __restrict__ flag) {
+  constexpr int s = S;
   __shared__ c128 A[32][33];   // b - a^H a, eliminated in place
   __shared__ c128 Rs[32][33];  // R
   __shared__ c128 Xs[32][33];  // Ri
@@ -530,8 +532,10 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int s, int nb, const c128* _
   for (int pass = 0; pass < (fused ? 2 : 1); ++pass) {
     const int e = t % ss, g = t / ss, k = e / s, l = e % s;
     c128 acc = cmk(0.0, 0.0);
-    if (g < ng)
+    if (g < ng) {
+#pragma unroll 4
       for (int i = g; i < nb; i += ng) cfma_conj(acc, Gat(i, k), Gat(i, pass * s + l));
+    }
     red[t] = acc;
     __syncthreads();
     if (t < ss) {
@@ -609,6 +613,7 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int s, int nb, const c128* _
   for (int e = t; e < nb * s; e += 1024) {
     const int i = e / s, l = e % s;
     c128 x = cmk(0.0, 0.0), y = cmk(0.0, 0.0) - Gat(i, s + l);
+#pragma unroll 4
     for (int m = 0; m < s; ++m) {
       const c128 am = Gat(i, m);
       if (m <= l) cfms(x, am, Xs[m][l]);
@@ -1113,7 +1118,15 @@ void KrylovKernels::update_split(int nvb, const c128* V, int64_t ldv, const c128
 void KrylovKernels::dcgs_coef(int nb, const c128* G, c128* C, c128* Hp, c128* Hn, c128* Rprev, int* flag) {
   HZ_REQUIRE(s == 1 || s == 2 || s == 4 || s == 8 || s == 16 || s == 32, HZ_ERR_STATE,
              "dcgs_coef: block size must be a power of two");
-  hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(1024), 0, ctx->stream, s, nb, G, C, Hp, Hn, Rprev, flag);
+  auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(1), dim3(1024), 0, ctx->stream, nb, G, C, Hp, Hn, Rprev, flag); };
+  switch (s) {
+    case 1: go(k_dcgs_coef<1>); break;
+    case 2: go(k_dcgs_coef<2>); break;
+    case 4: go(k_dcgs_coef<4>); break;
+    case 8: go(k_dcgs_coef<8>); break;
+    case 16: go(k_dcgs_coef<16>); break;
+    default: go(k_dcgs_coef<32>); break;
+  }
   HIP_CHECK(hipGetLastError());
 }
 
