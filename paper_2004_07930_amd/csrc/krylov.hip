@@ -552,19 +552,21 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int nb, const c128* __restri
     }
     __syncthreads();
   }
+  // a pivot below 1e-14 of its diagonal entry of b is a numerically dependent direction: its
+  // row of R (and of Ri, and its scaling) is zero, so that the column this call completes gets
+  // no subdiagonal part from it and nothing overflows (clamping it instead made Ri grow by
+  // 1e7 per dependent direction)
   for (int k = 0; k < s; ++k) {
     if (t == 0) {
-      double d = A[k][k].re;
-      const double scale = fabs(Gat(nb + k, k).re) + 1e-300;
-      if (!(d > 1e-14 * scale) || !isfinite(d)) {
-        flag[0] = 1;
-        d = fmax(d, 1e-14 * scale);
-      }
-      Rs[k][k] = cmk(sqrt(d), 0.0);
+      const double d = A[k][k].re;
+      const double scale = fabs(Gat(nb + k, k).re);
+      const bool dep = !(d > 1e-14 * scale) || !isfinite(d);
+      if (dep) flag[0] = 1;
+      Rs[k][k] = cmk(dep ? 0.0 : sqrt(d), 0.0);
     }
     __syncthreads();
     const double rk = Rs[k][k].re;
-    if (t > k && t < s) Rs[k][t] = cmk(A[k][t].re / rk, A[k][t].im / rk);
+    if (t > k && t < s) Rs[k][t] = rk > 0.0 ? cmk(A[k][t].re / rk, A[k][t].im / rk) : cmk(0.0, 0.0);
     __syncthreads();
     if (t < ss) {
       const int i = t / s, j = t % s;
@@ -572,12 +574,13 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int nb, const c128* __restri
     }
     __syncthreads();
   }
-  if (t < s) {  // Ri: column c by thread c (back substitution)
+  if (t < s) {  // Ri: column c by thread c (back substitution; dependent rows stay zero)
     const int c = t;
     for (int i = c; i >= 0; --i) {
       c128 v = cmk(i == c ? 1.0 : 0.0, 0.0);
       for (int l = i + 1; l <= c; ++l) cfms(v, Rs[i][l], Xs[l][c]);
-      Xs[i][c] = cmk(v.re / Rs[i][i].re, v.im / Rs[i][i].re);
+      const double ri = Rs[i][i].re;
+      Xs[i][c] = ri > 0.0 ? cmk(v.re / ri, v.im / ri) : cmk(0.0, 0.0);
     }
   }
   __syncthreads();
@@ -619,14 +622,14 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int nb, const c128* __restri
       if (m <= l) cfms(x, am, Xs[m][l]);
       cfma(y, am, Ts[m][l]);
     }
-    const double dl = 1.0 / Rs[l][l].re;
+    const double dl = Rs[l][l].re > 0.0 ? 1.0 / Rs[l][l].re : 0.0;
     C[(int64_t)i * 2 * s + l] = x;
     C[(int64_t)i * 2 * s + s + l] = cmk(y.re * dl, y.im * dl);
     Hn[e] = Gat(i, s + l);
   }
   if (t < ss) {
     const int k = t / s, l = t % s;
-    const double dl = 1.0 / Rs[l][l].re;
+    const double dl = Rs[l][l].re > 0.0 ? 1.0 / Rs[l][l].re : 0.0;
     C[(int64_t)(nb + k) * 2 * s + l] = Xs[k][l];
     C[(int64_t)(nb + k) * 2 * s + s + l] = cmk(-Ts[k][l].re * dl, -Ts[k][l].im * dl);
     C[(int64_t)(nb + s + k) * 2 * s + l] = cmk(0.0, 0.0);

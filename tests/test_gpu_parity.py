@@ -264,11 +264,11 @@ def test_solve_to_tolerance_matches_direct(ctx):
 
 
 def test_delayed_reorthogonalisation_restarts_and_convergence(ctx):
-    """16-column blocks take the delayed-reorthogonalisation path, whose Hessenberg columns
-    complete one step late: restarted cycles (restart 3) that end on the tolerance must stop
-    after the same number of steps as the CGS2 oracle, with the same restarts and the same
+    """16- and 32-column blocks take the delayed-reorthogonalisation path, whose Hessenberg
+    columns complete one step late: restarted cycles (restart 3) that end on the tolerance must
+    stop after the same number of steps as the CGS2 oracle, with the same restarts and the same
     iterate; and a block iterated on past convergence (its Krylov blocks become dependent)
-    must end its cycle with a finite, converged result."""
+    must end its cycle with a finite, converged result (32 columns: test_solve_failure_paths)."""
     p = w.unit_cube_problem(4, freq=1.0, parts=(2, 2, 2), overlap=1)
     om = fem.Mesh(p.tets, p.coords, p.face_bc)
     A = fem.assemble_operator(om, p.velocity, p.freq)
@@ -279,11 +279,11 @@ def test_delayed_reorthogonalisation_restarts_and_convergence(ctx):
     odd.factor_subdomains(subs)
     P = odd.ORAS(A, subs)
     rng = np.random.default_rng(33)
-    B = rng.standard_normal((16, om.n)) + 1j * rng.standard_normal((16, om.n))
-    for m, tol in ((3, 1e-9), (40, 1e-10)):
+    for s, m, tol in ((16, 3, 1e-9), (16, 40, 1e-10), (32, 3, 1e-9)):
+        B = rng.standard_normal((s, om.n)) + 1j * rng.standard_normal((s, om.n))
         X, info = ctx.solve(d, B, tol=tol, max_iter=200, restart=m)
         Xo, io = krylov.block_fgmres(lambda x: A @ x, B.T, P.apply, tol=tol, m=m, max_iter=200)
-        print(f"restart {m}: GPU {info[0]['iters']} steps, {info[0]['restarts']} restarts; "
+        print(f"{s} columns, restart {m}: GPU {info[0]['iters']} steps, {info[0]['restarts']} restarts; "
               f"oracle {io['iters']}, {io['restarts']}; iterate difference {_rel(X, Xo.T):.2e}")
         assert info[0]["iters"] == io["iters"] and info[0]["restarts"] == io["restarts"]
         assert all(i["rel_residual"] <= tol for i in info)
@@ -303,6 +303,32 @@ def test_delayed_reorthogonalisation_restarts_and_convergence(ctx):
     np.testing.assert_allclose(res, [i["rel_residual"] for i in info], rtol=1e-3, atol=1e-13)
     ctx.release(d)
     ctx.release(d2)
+
+
+def test_delayed_reorthogonalisation_past_convergence_seeds(ctx):
+    """Blocks iterated far past convergence make the once-projected block rounding noise,
+    whose Gram matrix has many dependent directions: over several right-hand sides, 16 and
+    32 columns and both precisions, every solve ends finite, converged, and with the reported
+    residual equal to the true one."""
+    from paper_2004_07930_amd import hz
+
+    p = w.unit_cube_problem(3, freq=1.5, parts=(2, 2, 1), overlap=1)
+    om = fem.Mesh(p.tets, p.coords, p.face_bc)
+    A = fem.assemble_operator(om, p.velocity, p.freq)
+    gm = ctx.mesh(p.tets, p.coords, p.face_bc)
+    gop = ctx.assemble(gm, p.velocity, p.freq)
+    for prec, tol in ((hz.HZ_PREC_C128, 1e-8), (hz.HZ_PREC_MIXED, 1e-5)):
+        d = ctx.setup_ddm(gop, p.partition, p.n_sub, p.overlap, precision=prec)
+        for seed in (1, 2, 3, 4):
+            rng = np.random.default_rng(seed)
+            for s in (16, 32):
+                B = rng.standard_normal((s, om.n)) + 1j * rng.standard_normal((s, om.n))
+                X, info = ctx.solve(d, B, fixed_iters=12, restart=12)
+                assert np.isfinite(X).all(), (prec, seed, s)
+                res = np.linalg.norm(B.T - A @ X.T, axis=0) / np.linalg.norm(B, axis=1)
+                assert res.max() <= tol, (prec, seed, s, res.max())
+                np.testing.assert_allclose(res, [i["rel_residual"] for i in info], rtol=1e-3, atol=1e-13)
+        ctx.release(d)
 
 
 def test_config1_plane_wave(ctx):
