@@ -23,17 +23,6 @@ namespace {
 constexpr int kNb = 32;
 constexpr int kThreads = 256;
 
-template <typename T, typename TS>
-__global__ void k_gather_local(int64_t nloc, int s, const int32_t* __restrict__ gidx, const cplx<TS>* __restrict__ src,
-                               cplx<T>* __restrict__ dst) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nloc * s) return;
-  const int64_t q = k / s;
-  const int c = (int)(k - q * s);
-  const cplx<TS> v = src[(int64_t)gidx[q] * s + c];
-  dst[k] = cmk((T)v.re, (T)v.im);
-}
-
 // z = owner's local value (+ add), summed in FP64 and rounded to the output type TZ
 template <typename T, typename TQ, typename TZ>
 __global__ void k_scatter_owner(int64_t n, int s, const int64_t* __restrict__ own, const cplx<T>* __restrict__ loc,
@@ -64,10 +53,16 @@ __device__ __forceinline__ cplx<double> ld_stream(const cplx<double>* p) {
   return cmk(v.x, v.y);
 }
 
-template <typename T>
+// Forward, step 1: the work block of a front, w = [b_p; 0] + the children's update rows, in a
+// fixed order (own, child 0, child 1).  b_p is read from the global right-hand side through
+// the local-to-global map of the front's pivots (rounded to the factor precision), so no
+// local copy of the right-hand side is made.
+template <typename T, typename TS>
 __global__ __launch_bounds__(256) void k_fwd_assemble(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
-                                                      const int32_t* __restrict__ imap, const cplx<T>* __restrict__ bin,
-                                                      cplx<T>* __restrict__ wbuf, int s, int pivots_only) {
+                                                      const int32_t* __restrict__ imap,
+                                                      const int32_t* __restrict__ gidx,
+                                                      const cplx<TS>* __restrict__ src, cplx<T>* __restrict__ wbuf,
+                                                      int s, int pivots_only) {
   const int fid = work[2 * blockIdx.x];
   if (fid < 0) return;  // padding entry of the XCD-interleaved worklist (block-uniform)
   const int64_t i0 = work[2 * blockIdx.x + 1];
@@ -91,7 +86,11 @@ __global__ __launch_bounds__(256) void k_fwd_assemble(const int32_t* __restrict_
   for (int64_t k = threadIdx.x; k < tot; k += blockDim.x) {
     const int64_t i = i0 + k / s;
     const int c = (int)(k - (k / s) * s);
-    cplx<T> v = i < F.p ? bin[(F.vec_off + F.pos0 + i) * s + c] : cmk((T)0, (T)0);
+    cplx<T> v = cmk((T)0, (T)0);
+    if (i < F.p) {
+      const cplx<TS> b = src[(int64_t)gidx[F.vec_off + F.pos0 + i] * s + c];
+      v = cmk((T)b.re, (T)b.im);
+    }
     if (w0) {
       const int32_t q = m0[i];
       if (q >= 0) v = v + w0[(int64_t)q * s + c];
@@ -273,17 +272,14 @@ struct CAcc<double> {
 // chunk in registers (loads from a clamped, always valid index, so they issue back to back)
 // while the current chunk is multiplied out of LDS; the bounds predicate is applied when the
 // registers are written to LDS, so the loads stay in flight across the products.
-// The update rows of w = [b_p; 0] + the children's update contributions are formed in the
-// epilogue, where each is read once, in the order of k_fwd_assemble (own, child 0, child 1).
-// The pivot rows, which every row tile multiplies, are read from the pass k_fwd_assemble
-// made of them (ASSEMBLED, fronts with children) or summed as they are staged (the leaves,
-// whose pivot rows are b_p alone): above the leaves, summing them in every tile would cost
-// more than the pass.
-template <typename T, int NG, int MT, int JC, bool ASSEMBLED>
+// The pivot rows of w, which every row tile multiplies, are read from the pass k_fwd_assemble
+// made of them; the update rows of w = [b_p; 0] + the children's update contributions are
+// formed in the epilogue, where each is read once, in the order of k_fwd_assemble (own,
+// child 0, child 1).
+template <typename T, int NG, int MT, int JC>
 __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
                                                   const cplx<T>* __restrict__ L, const int32_t* __restrict__ imap,
-                                                  const cplx<T>* __restrict__ bin, cplx<T>* __restrict__ wbuf,
-                                                  cplx<T>* __restrict__ bout, int s) {
+                                                  cplx<T>* __restrict__ wbuf, cplx<T>* __restrict__ bout, int s) {
   constexpr int RT = 64 * MT, SC = 16 * NG;
   constexpr int NF = JC * RT / 256, NW = JC * SC / 256;
   __shared__ cplx<T> Ft[JC][RT + 1];
@@ -298,8 +294,7 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
   const int wv = tid >> 6, l = tid & 63;
   const int lr = l & 15, lq = l >> 4;
   const cplx<T>* Lf = L + F.L_off;
-  const cplx<T>* wp = wbuf + F.w_off * s;              // the assembled work block
-  const cplx<T>* bp = bin + (F.vec_off + F.pos0) * s;  // pivot rows of the right-hand side
+  const cplx<T>* wp = wbuf + F.w_off * s;          // the assembled work block
   const int32_t* m0 = imap + F.imap_off;           // parent row -> child row (or -1), per child
   const int32_t* m1 = m0 + f;
   const cplx<T>* w0 = nullptr;  // the children's update rows (only children that have some)
@@ -313,8 +308,7 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
     if (C.r > 0) w1 = wbuf + (C.w_off + C.p) * s;
   }
   const cplx<T> zero = cmk((T)0, (T)0);
-  cplx<T> rf[NF], rb[NW], r0[NW], r1[NW];
-  int32_t q0[NW], q1[NW];
+  cplx<T> rf[NF], rb[NW];
   auto fetch = [&](int64_t j) {
     const int jn = (int)min<int64_t>(JC, jend - j);
 #pragma unroll
@@ -327,15 +321,7 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
       const int e = tid + 256 * u, jj = e / SC, c = e - (e / SC) * SC;
       const bool ok = jj < jn && c < s;
       const int64_t row = ok ? j + jj : 0, cc = ok ? c : 0;
-      rb[u] = ASSEMBLED ? wp[row * s + cc] : bp[row * s + cc];
-      if (!ASSEMBLED && w0) {  // block-uniform tests
-        q0[u] = m0[row];
-        r0[u] = w0[(int64_t)max(q0[u], 0) * s + cc];
-      }
-      if (!ASSEMBLED && w1) {
-        q1[u] = m1[row];
-        r1[u] = w1[(int64_t)max(q1[u], 0) * s + cc];
-      }
+      rb[u] = wp[row * s + cc];
     }
   };
   CAcc<T> acc[MT][NG];
@@ -355,10 +341,7 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
 #pragma unroll
     for (int u = 0; u < NW; ++u) {
       const int e = tid + 256 * u, jj = e / SC, c = e - (e / SC) * SC;
-      cplx<T> v = rb[u];
-      if (!ASSEMBLED && w0) v = v + csel(q0[u] >= 0, r0[u], zero);
-      if (!ASSEMBLED && w1) v = v + csel(q1[u] >= 0, r1[u], zero);
-      Wt[jj][c] = csel(jj < jn && c < s, v, zero);
+      Wt[jj][c] = csel(jj < jn && c < s, rb[u], zero);
     }
     __syncthreads();
     if (j + JC < jend) fetch(j + JC);
@@ -527,21 +510,22 @@ constexpr bool use_mfma() {
   return S >= 8;
 }
 
-template <typename T>
-void fwd_assemble(Ctx* ctx, Ddm& d, size_t lv, int s, const cplx<T>* bin, cplx<T>* wbuf, bool pivots_only) {
+template <typename T, typename TS>
+void fwd_assemble(Ctx* ctx, Ddm& d, size_t lv, int s, const cplx<TS>* src, cplx<T>* wbuf, bool pivots_only) {
   const unsigned nb = (unsigned)(d.fwd_off[lv + 1] - d.fwd_off[lv]);  // 64-row tiles of the level
-  hipLaunchKernelGGL((k_fwd_assemble<T>), dim3(nb), dim3(256), 0, ctx->stream, d.d_fwd_work.ptr() + 2 * d.fwd_off[lv],
-                     d.d_fronts.ptr(), d.d_imap.ptr(), bin, wbuf, s, pivots_only ? 1 : 0);
+  hipLaunchKernelGGL((k_fwd_assemble<T, TS>), dim3(nb), dim3(256), 0, ctx->stream,
+                     d.d_fwd_work.ptr() + 2 * d.fwd_off[lv], d.d_fronts.ptr(), d.d_imap.ptr(), d.d_gidx.ptr(), src,
+                     wbuf, s, pivots_only ? 1 : 0);
 }
 
 // Vector-unit sweeps (complex128, and complex64 blocks narrower than 8 columns).
-template <typename T, int S>
-void sweep_valu(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) {
+template <typename T, int S, typename TS>
+void sweep_valu(Ctx* ctx, Ddm& d, int s, const cplx<TS>* src, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) {
   hipStream_t st = ctx->stream;
   const cplx<T>* L = d.d_factor.as<cplx<T>>();
   const double esz = (double)sizeof(cplx<T>);
   for (size_t lv = 0; lv < d.levels.size(); ++lv) {
-    fwd_assemble<T>(ctx, d, lv, s, bin, wbuf, false);
+    fwd_assemble<T, TS>(ctx, d, lv, s, src, wbuf, false);
     const Level& Lv = d.levels[lv];
     // algorithmic traffic: the level's stored factor once, its work rows read and written once
     ProfScope ps(ctx, HZ_K_ORAS_FWD, esz * ((double)Lv.useful + 2.0 * (double)Lv.sum_f * s),
@@ -563,10 +547,10 @@ void sweep_valu(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* w
 // Matrix-core sweeps (8..32 columns; complex64 or complex128).  The tile of each level and direction is one
 // of two sizes; the first apply for a column-group width times both on every level (all tile
 // sizes give bit-identical results, and every timed launch is repeated exactly as the real
-// one: a forward level above the leaves re-assembles its work block before each try) and
+// one: a forward level re-assembles the pivot rows of its work block before each try) and
 // keeps the faster one.
-template <typename T, int S>
-void sweep_mfma(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) {
+template <typename T, int S, typename TS>
+void sweep_mfma(Ctx* ctx, Ddm& d, int s, const cplx<TS>* src, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) {
   constexpr int NG = (S + 15) / 16;
   hipStream_t st = ctx->stream;
   const cplx<T>* L = d.d_factor.as<cplx<T>>();
@@ -577,19 +561,12 @@ void sweep_mfma(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* w
   auto fwd = [&](size_t lv, int t) {
     const dim3 grid((unsigned)(d.fwdm_off[t][lv + 1] - d.fwdm_off[t][lv]));
     const int32_t* wl = d.d_fwdm_work[t].ptr() + 2 * d.fwdm_off[t][lv];
-    const bool kids = lv > 0;  // leaves form their work block themselves
-    if (t == 0 && kids)
-      hipLaunchKernelGGL((k_fwd_mfma<T, NG, kFwdRowsMfma[0] / 64, 32, true>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(),
-                         L, d.d_imap.ptr(), bin, wbuf, bout, s);
-    else if (t == 0)
-      hipLaunchKernelGGL((k_fwd_mfma<T, NG, kFwdRowsMfma[0] / 64, 32, false>), grid, dim3(256), 0, st, wl,
-                         d.d_fronts.ptr(), L, d.d_imap.ptr(), bin, wbuf, bout, s);
-    else if (kids)
-      hipLaunchKernelGGL((k_fwd_mfma<T, NG, kFwdRowsMfma[1] / 64, 32, true>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(),
-                         L, d.d_imap.ptr(), bin, wbuf, bout, s);
+    if (t == 0)
+      hipLaunchKernelGGL((k_fwd_mfma<T, NG, kFwdRowsMfma[0] / 64, 32>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(), L,
+                         d.d_imap.ptr(), wbuf, bout, s);
     else
-      hipLaunchKernelGGL((k_fwd_mfma<T, NG, kFwdRowsMfma[1] / 64, 32, false>), grid, dim3(256), 0, st, wl,
-                         d.d_fronts.ptr(), L, d.d_imap.ptr(), bin, wbuf, bout, s);
+      hipLaunchKernelGGL((k_fwd_mfma<T, NG, kFwdRowsMfma[1] / 64, 32>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(), L,
+                         d.d_imap.ptr(), wbuf, bout, s);
   };
   auto bwd = [&](size_t lv, int t) {
     const dim3 grid((unsigned)(d.bwdm_off[t][lv + 1] - d.bwdm_off[t][lv]));
@@ -603,7 +580,7 @@ void sweep_mfma(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* w
   };
   if (!tune) {
     for (size_t lv = 0; lv < nl; ++lv) {
-      if (lv > 0) fwd_assemble<T>(ctx, d, lv, s, bin, wbuf, true);
+      fwd_assemble<T, TS>(ctx, d, lv, s, src, wbuf, true);
       const Level& Lv = d.levels[lv];
       // algorithmic traffic: the level's stored factor once, its work rows read and written once
       ProfScope ps(ctx, HZ_K_ORAS_FWD, esz * ((double)Lv.useful + 2.0 * (double)Lv.sum_f * s),
@@ -627,7 +604,7 @@ void sweep_mfma(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* w
   for (size_t lv = 0; lv < nl; ++lv)
     for (int rep = 0; rep < 2; ++rep)
       for (int t = 0; t < 2; ++t) {
-        if (lv > 0) fwd_assemble<T>(ctx, d, lv, s, bin, wbuf, true);
+        fwd_assemble<T, TS>(ctx, d, lv, s, src, wbuf, true);
         if (rep) HIP_CHECK(hipEventRecord(at(0, lv, t, 0), st));
         fwd(lv, t);
         if (rep) HIP_CHECK(hipEventRecord(at(0, lv, t, 1), st));
@@ -654,12 +631,14 @@ void sweep_mfma(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* w
   d.tile_bwd[gi] = cb;
 }
 
-template <typename T, int S>
-void sweep(Ctx* ctx, Ddm& d, int s, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) {
+// src: the global right-hand side (the forward sweep reads its pivot rows through the
+// local-to-global map); bin: the local solution, written by the backward sweep
+template <typename T, int S, typename TS>
+void sweep(Ctx* ctx, Ddm& d, int s, const cplx<TS>* src, cplx<T>* bin, cplx<T>* bout, cplx<T>* wbuf) {
   if constexpr (use_mfma<T, S>())
-    sweep_mfma<T, S>(ctx, d, s, bin, bout, wbuf);
+    sweep_mfma<T, S, TS>(ctx, d, s, src, bin, bout, wbuf);
   else
-    sweep_valu<T, S>(ctx, d, s, bin, bout, wbuf);
+    sweep_valu<T, S, TS>(ctx, d, s, src, bin, bout, wbuf);
 }
 
 template <typename T, typename TS, typename TQ, typename TZ>
@@ -681,20 +660,18 @@ void one_level(Ctx* ctx, Ddm& d, int s, const cplx<TS>* v, const cplx<TQ>* add, 
   cplx<T>* bi = bin.as<cplx<T>>();
   cplx<T>* bo = bout.as<cplx<T>>();
   cplx<T>* wb = wbuf.as<cplx<T>>();
-  hipLaunchKernelGGL((k_gather_local<T, TS>), dim3((unsigned)((nl * s + 255) / 256)), dim3(256), 0, st, nl, s,
-                     d.d_gidx.ptr(), v, bi);
   if (s <= 1)
-    sweep<T, 1>(ctx, d, s, bi, bo, wb);
+    sweep<T, 1, TS>(ctx, d, s, v, bi, bo, wb);
   else if (s <= 2)
-    sweep<T, 2>(ctx, d, s, bi, bo, wb);
+    sweep<T, 2, TS>(ctx, d, s, v, bi, bo, wb);
   else if (s <= 4)
-    sweep<T, 4>(ctx, d, s, bi, bo, wb);
+    sweep<T, 4, TS>(ctx, d, s, v, bi, bo, wb);
   else if (s <= 8)
-    sweep<T, 8>(ctx, d, s, bi, bo, wb);
+    sweep<T, 8, TS>(ctx, d, s, v, bi, bo, wb);
   else if (s <= 16)
-    sweep<T, 16>(ctx, d, s, bi, bo, wb);
+    sweep<T, 16, TS>(ctx, d, s, v, bi, bo, wb);
   else if (s <= 32)
-    sweep<T, 32>(ctx, d, s, bi, bo, wb);
+    sweep<T, 32, TS>(ctx, d, s, v, bi, bo, wb);
   else
     fail(HZ_ERR_ARG, "preconditioner: at most 32 columns per block");
   hipLaunchKernelGGL((k_scatter_owner<T, TQ, TZ>), dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, st, n, s,
