@@ -239,8 +239,8 @@ __device__ __forceinline__ void mfma_3m(c64 a, c64 b, f32x4& p1, f32x4& p2, f32x
   p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re + a.im, b.re + b.im, p3, 0, 0, 0);
 }
 
-// Complex accumulator of a 16 x 16 output tile on the matrix cores.  complex64: the three
-// products above.  complex128: the direct form, four v_mfma_f64_16x16x4f64 (same operand
+// Complex accumulator of a 16 x 16 output tile on the matrix cores: the three products above,
+// on v_mfma_f32_16x16x4f32 (complex64) or v_mfma_f64_16x16x4f64 (complex128: same operand
 // layout, lane l: A[l%16][l/16], B[l/16][l%16]; D[l/16+4v][l%16]).
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <typename T>
@@ -255,15 +255,14 @@ struct CAcc<float> {
 };
 template <>
 struct CAcc<double> {
-  f64x4 re, im;
-  __device__ __forceinline__ void zero() { re = im = f64x4{0.0, 0.0, 0.0, 0.0}; }
+  f64x4 p1, p2, p3;
+  __device__ __forceinline__ void zero() { p1 = p2 = p3 = f64x4{0.0, 0.0, 0.0, 0.0}; }
   __device__ __forceinline__ void mac(c128 a, c128 b) {
-    re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, re, 0, 0, 0);
-    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, b.im, re, 0, 0, 0);
-    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.im, im, 0, 0, 0);
-    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.re, im, 0, 0, 0);
+    p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, p1, 0, 0, 0);
+    p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.im, p2, 0, 0, 0);
+    p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re + a.im, b.re + b.im, p3, 0, 0, 0);
   }
-  __device__ __forceinline__ c128 get(int v) const { return cmk(re[v], im[v]); }
+  __device__ __forceinline__ c128 get(int v) const { return cmk(p1[v] - p2[v], p3[v] - p1[v] - p2[v]); }
   static __device__ __forceinline__ int row(int lq, int v) { return lq + 4 * v; }
 };
 
@@ -503,8 +502,8 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ wo
     }
 }
 
-// Matrix-core sweeps serve blocks of at least 8 columns (complex64 in the three-product form,
-// complex128 in the direct form); narrower blocks stay on the vector-unit kernels.
+// Matrix-core sweeps serve blocks of at least 8 columns (both precisions in the three-product
+// form); narrower blocks stay on the vector-unit kernels.
 template <typename T, int S>
 constexpr bool use_mfma() {
   return S >= 8;
