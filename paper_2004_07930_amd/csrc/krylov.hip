@@ -1,5 +1,6 @@
-// Block FGMRES(m) in FP64 on the GPU: classical Gram-Schmidt twice (CGS2) as tall-skinny
-// products, CholQR2 block normalisation, Householder QR of the block Hessenberg matrix and
+// Block FGMRES(m) in FP64 on the GPU: classical Gram-Schmidt as tall-skinny products (with
+// delayed reorthogonalisation for 16- and 32-column blocks, twice (CGS2) with CholQR2 block
+// normalisation otherwise), Householder QR of the block Hessenberg matrix and
 // the least-squares update in one workgroup.
 //
 // The paper solves A u = b with GMRES preconditioned by the two-level ORAS operator and

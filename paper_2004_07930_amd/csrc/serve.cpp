@@ -9,7 +9,7 @@
 // scheduler tick advances every active job by one Arnoldi step: the blocks M^{-1} v of all
 // jobs on the same operator are packed column-wise into shared launches of the
 // preconditioner and of the SpMM (so the factors and the matrix are read once for all of
-// them), then each job does its own CGS2 / CholQR2 / least-squares step.  A finished job
+// them), then each job does its own orthogonalisation and least-squares step.  A finished job
 // frees its Krylov memory at once; a request completes when all its parts have.
 #include <algorithm>
 #include <chrono>
