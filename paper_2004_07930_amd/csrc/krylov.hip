@@ -125,9 +125,19 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(int64_t n, int Jtot, const
   constexpr int S = 16 * NCT, NC = NRB * NCT, SO = NRB * S;
   __shared__ c128 red[GJ * 16][SO];
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, lc = l & 15, q = l >> 4;
-  const int64_t r0 = (int64_t)blockIdx.x * rpc;
+  // the basis groups of one row chunk run one after another on one XCD (blocks are dealt to
+  // the 8 XCDs in turn), so the chunk's right-operand rows they all read are shared in its L2
+  int bx = blockIdx.x, by = blockIdx.y;
+  if (NRB == 2) {
+    const int64_t nb = (int64_t)gridDim.x * gridDim.y, b = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+    const int64_t qd = nb / 8, rm = nb % 8, x = b % 8, k = b / 8;
+    const int64_t lg = x * qd + (x < rm ? x : rm) + k;
+    bx = (int)(lg / gridDim.y);
+    by = (int)(lg % gridDim.y);
+  }
+  const int64_t r0 = (int64_t)bx * rpc;
   const int64_t r1 = min<int64_t>(n, r0 + rpc);
-  const int J0 = jbase + blockIdx.y * GJ * 16;
+  const int J0 = jbase + by * GJ * 16;
   f64x4 hre[GJ][NC], him[GJ][NC], h3[GJ][NC];
   const c128* vp[GJ];
   const c128* wp[NC];
@@ -219,7 +229,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(int64_t n, int Jtot, const
   }
   for (int e = threadIdx.x; e < GJ * 16 * SO; e += 256) {
     const int j = e / SO, c = e - (e / SO) * SO;
-    if (J0 + j < Jtot) part[((int64_t)blockIdx.x * Jtot + J0 + j) * SO + c] = red[j][c];
+    if (J0 + j < Jtot) part[((int64_t)bx * Jtot + J0 + j) * SO + c] = red[j][c];
   }
 }
 
