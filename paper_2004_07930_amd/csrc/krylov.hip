@@ -242,9 +242,10 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(int64_t n, int Jtot, const
 // of row l%16 of each tile (64 contiguous bytes) for eight consecutive k steps.
 // M3: three real products per complex one (where the matrix cores bound the kernel):
 //   P1 = a_re b_re, P2 = a_im b_im, P3 = (a_re + a_im)(b_re + b_im);  a b = (P1 - P2) + i (P3 - P1 - P2)
-// Three wavefronts per SIMD (register budget 168); two with four column tiles.
+// Three wavefronts per SIMD (register budget 168); two with four column tiles or with two row
+// tiles of the split form.
 template <typename TV, int NCT, int NRB, int RT, bool M3 = false>
-__global__ __launch_bounds__(256, NCT * NRB > 2 ? 2 : 3) void k_axpy_mfma(int64_t n, int Jtot, const cplx<TV>* V, int64_t ldv, int nvb,
+__global__ __launch_bounds__(256, (NCT * NRB > 2 || (NRB == 2 && RT > 1)) ? 2 : 3) void k_axpy_mfma(int64_t n, int Jtot, const cplx<TV>* V, int64_t ldv, int nvb,
                                                       const cplx<TV>* Vx, const cplx<TV>* Vx2,
                                                       const c128* __restrict__ H, double beta, const c128* Yin0,
                                                       c128* Y0, const c128* Yin1, c128* Y1) {
@@ -1119,11 +1120,11 @@ void KrylovKernels::update_split(int nvb, const c128* V, int64_t ldv, const c128
   const int Jtot = (nvb + 2) * s;
   // algorithmic traffic: the Jtot basis columns once, Y0 and Y1 written once
   ProfScope ps(ctx, HZ_K_CGS_UPDATE, (double)n * (Jtot + 2 * s) * sizeof(c128), 8.0 * n * Jtot * 2 * s);
-  // 4 wavefronts x 1 tile of 16 rows per block
-  if (s == 16)
-    hipLaunchKernelGGL((k_axpy_mfma<double, 1, 2, 1, true>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, ctx->stream,
-                       n, Jtot, V, ldv, nvb, Vx, Vx2, C, 1.0, (const c128*)nullptr, Y0, (const c128*)nullptr, Y1);
-  else  // direct form: the 3M form spills at four column tiles
+  if (s == 16)  // 4 wavefronts x 2 tiles of 16 rows per block: each coefficient load feeds both tiles
+    hipLaunchKernelGGL((k_axpy_mfma<double, 1, 2, 2, true>), dim3((unsigned)((n + 127) / 128)), dim3(256), 0,
+                       ctx->stream, n, Jtot, V, ldv, nvb, Vx, Vx2, C, 1.0, (const c128*)nullptr, Y0,
+                       (const c128*)nullptr, Y1);
+  else  // 4 wavefronts x 1 tile; direct form: the 3M form spills at four column tiles
     hipLaunchKernelGGL((k_axpy_mfma<double, 2, 2, 1>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, ctx->stream, n,
                        Jtot, V, ldv, nvb, Vx, Vx2, C, 1.0, (const c128*)nullptr, Y0, (const c128*)nullptr, Y1);
   HIP_CHECK(hipGetLastError());
