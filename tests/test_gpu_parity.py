@@ -72,7 +72,8 @@ def test_csr_pattern_bit_exact_values_close(case, ctx):
     assert abs(G - G.T).max() == 0
 
 
-SPMM_WIDTHS = (1, 3, 8, 12, 16, 17, 31, 32, 40)  # both kernels, partial column groups, odd widths, two chunks
+# both kernels, partial column groups, odd and even widths, blocks split into 32-column chunks
+SPMM_WIDTHS = (1, 3, 8, 12, 16, 17, 31, 32, 40, 57, 64, 70)
 
 
 def test_spmm_matches(case, ctx):
@@ -180,9 +181,9 @@ def test_ddm_levels_consistent(case, ddm_case, ctx):
 
 def test_precond_one_level_mixed(case, ddm_case, ctx):
     """complex64 factors and sweeps (vector kernels below 8 columns, matrix-core kernels from
-    8 on, 16-column groups with a ragged last group): each column within 1e-4 of the FP64
-    oracle's ORAS application, and a column's result independent of the block it sits in
-    (to single-precision rounding)."""
+    8 on, 16-column groups with a ragged last group, wider blocks in 32-column chunks): each
+    column within 1e-4 of the FP64 oracle's ORAS application, and a column's result
+    independent of the block it sits in (to single-precision rounding)."""
     from paper_2004_07930_amd import hz
 
     name, p, om, gm, A, gop = case
@@ -192,15 +193,18 @@ def test_precond_one_level_mixed(case, ddm_case, ctx):
     P = odd.ORAS(A, subs)
     d32 = ctx.setup_ddm(gop, p.partition, p.n_sub, p.overlap, precision=hz.HZ_PREC_MIXED)
     rng = np.random.default_rng(13)
-    V = rng.standard_normal((32, om.n)) + 1j * rng.standard_normal((32, om.n))
+    V = rng.standard_normal((64, om.n)) + 1j * rng.standard_normal((64, om.n))
     Zo = P.apply(V.T).T
     Z1 = ctx.precond(d32, V[:1])
-    for s in (1, 3, 8, 16, 21, 32):
+    for s in (1, 3, 8, 16, 21, 32, 45, 64):
         Z = ctx.precond(d32, V[:s])
         errs = [_rel(Z[c], Zo[c]) for c in range(s)]
         print(f"{name} s={s}: max column error vs FP64 oracle {max(errs):.2e}")
         assert max(errs) <= 1e-4, (s, max(errs))
         assert _rel(Z[0], Z1[0]) <= 1e-5, (s, _rel(Z[0], Z1[0]))
+    # the second chunk of a 64-column block against the same columns applied alone
+    Zh = ctx.precond(d32, V[32:])
+    assert max(_rel(Z[32 + c], Zh[c]) for c in range(32)) <= 1e-5
     ctx.release(d32)
 
 

@@ -69,6 +69,30 @@ def test_serve_results_same_alone_and_in_mix(setup):
     assert st["sources_per_s"] > 0
 
 
+def test_serve_packing_past_32_columns(setup):
+    """Parts on one operator whose columns add up past 32 (20 + 9 + 12 here) are packed in
+    order into launches of at most 32 columns (20 + 9 together, 12 in a launch of its own,
+    regrouped as parts finish); each result matches its request solved alone."""
+    ctx, ops = setup
+    p, d, F = ops[0]
+    rng = np.random.default_rng(9)
+    reqs = []
+    for ns in (20, 9, 12):
+        cols = rng.choice(F.shape[0], size=ns, replace=True)
+        reqs.append(F[cols] + 0.1 * (rng.standard_normal((ns, F.shape[1])) + 1j * rng.standard_normal((ns, F.shape[1]))))
+    alone = [ctx.solve(d, B, tol=1e-6)[0] for B in reqs]
+    ctx.serve_start(max_slots=8)
+    try:
+        tickets = [ctx.submit(d, B, tol=1e-6) for B in reqs]
+        outs = [ctx.wait(t) for t in tickets]
+    finally:
+        ctx.serve_stop()
+    for x1, (x2, info, status) in zip(alone, outs):
+        assert status == 0
+        assert all(i["rel_residual"] <= 1e-6 for i in info)
+        assert _rel(x2, x1) <= 1e-5, _rel(x2, x1)
+
+
 def test_serve_admission_refuses_impossible_request():
     import torch
     from paper_2004_07930_amd import hz
