@@ -351,56 +351,134 @@ __global__ void k_dense_reduce(int nk, int64_t m, const cplx<T>* __restrict__ pa
   y2[e] = a;
 }
 
+// lane L of each 16-lane row of a wavefront, in every lane of that row (DPP row broadcast)
+template <int L>
+__device__ __forceinline__ int row_bcast(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + L, 0xF, 0xF, false);
+}
+template <int L>
+__device__ __forceinline__ float row_bcast(float v) {
+  return __int_as_float(row_bcast<L>(__float_as_int(v)));
+}
+template <int L>
+__device__ __forceinline__ double row_bcast(double v) {
+  return __hiloint2double(row_bcast<L>(__double2hiint(v)), row_bcast<L>(__double2loint(v)));
+}
+// out[j] = lane B + j of the row, j < N
+template <int B, int N, typename V>
+__device__ __forceinline__ void row_lanes(V v, V* out) {
+  if constexpr (N > 0) {
+    out[0] = row_bcast<B>(v);
+    row_lanes<B + 1, N - 1>(v, out + 1);
+  }
+}
+
 // q = Z y2 ; t = v - AZ y2 (v - AZ y2 formed in FP64, both stored in the coarse precision T:
-// the one-level apply reads t in T and the owner gather adds q)
+// the one-level apply reads t in T and the owner gather adds q).  One 16-lane row of a
+// wavefront per fine row: lane u loads entry u of the row's Z part (rows hold at most 4) and
+// of its first 16 AZ entries (rows hold about 5) once, the row's lanes receive each entry by
+// a DPP broadcast, and lane u forms columns u, u + 16, ...  Entries are taken in batches
+// (Z: 4, AZ: 8) whose gathers of y2 go out together; past the row an entry has weight zero
+// and gathers from coarse row 0.  Longer rows continue with direct loads.
 template <typename T>
-__global__ void k_prolong(int64_t n, int s, const int64_t* __restrict__ zptr, const int32_t* __restrict__ zcol,
-                          const double* __restrict__ zval, const int64_t* __restrict__ azptr,
-                          const int32_t* __restrict__ azcol, const cplx<T>* __restrict__ az,
-                          const cplx<T>* __restrict__ y2, const c128* __restrict__ v, cplx<T>* __restrict__ q,
-                          cplx<T>* __restrict__ t) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n * s) return;
-  const int64_t i = k / s;
-  const int col = (int)(k - i * s);
-  cplx<T> qa = cmk((T)0, (T)0), ta = cmk((T)0, (T)0);
-  // Z rows hold at most 4 entries and AZ rows a few more: each batch loads its column
-  // indices and values together (clamped to a valid entry, the value zeroed past the row),
-  // then its gathers of y2, so a row costs a few memory round trips instead of one per entry
+__global__ __launch_bounds__(256) void k_prolong(int64_t n, int s, const int64_t* __restrict__ zptr,
+                                                 const int32_t* __restrict__ zcol, const double* __restrict__ zval,
+                                                 const int64_t* __restrict__ azptr, const int32_t* __restrict__ azcol,
+                                                 const cplx<T>* __restrict__ az, const cplx<T>* __restrict__ y2,
+                                                 const c128* __restrict__ v, cplx<T>* __restrict__ q,
+                                                 cplx<T>* __restrict__ t) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int u = threadIdx.x & 15;
+  if (i >= n) return;  // the 16 lanes of a fine row leave together
   const int64_t z0 = zptr[i], z1 = zptr[i + 1], a0 = azptr[i], a1 = azptr[i + 1];
-  for (int64_t e = z0; e < z1; e += 4) {
-    int32_t jc[4];
-    T zv[4];
-    cplx<T> yv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const bool ok = e + u < z1;
-      jc[u] = zcol[ok ? e + u : e];
-      zv[u] = ok ? (T)zval[e + u] : (T)0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) yv[u] = y2[(int64_t)jc[u] * s + col];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) cfma(qa, cmk(zv[u], (T)0), yv[u]);
+  int32_t zc = 0, ac = 0;
+  T zw = 0, ar = 0, ai = 0;
+  if (u < 4 && z0 + u < z1) {
+    zc = zcol[z0 + u];
+    zw = (T)zval[z0 + u];
   }
-  for (int64_t e = a0; e < a1; e += 8) {
-    int32_t jc[8];
-    cplx<T> av[8], yv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const bool ok = e + u < a1;
-      jc[u] = azcol[ok ? e + u : e];
-      const cplx<T> x = az[ok ? e + u : e];
-      av[u] = csel(ok, x, cmk((T)0, (T)0));
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) yv[u] = y2[(int64_t)jc[u] * s + col];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) cfma(ta, av[u], yv[u]);
+  if (a0 + u < a1) {
+    ac = azcol[a0 + u];
+    const cplx<T> x = az[a0 + u];
+    ar = x.re;
+    ai = x.im;
   }
-  q[k] = qa;
-  const c128 r = v[k] - cmk((double)ta.re, (double)ta.im);
-  t[k] = cmk((T)r.re, (T)r.im);
+  for (int c0 = 0; c0 < s; c0 += 16) {
+    const int col = c0 + u;
+    const int cl = col < s ? col : s - 1;  // lanes past the last column repeat it, store nothing
+    const c128 vk = v[i * s + cl];
+    cplx<T> qa = cmk((T)0, (T)0), ta = cmk((T)0, (T)0);
+    {
+      int32_t jc[4];
+      T w[4];
+      cplx<T> y[4];
+      row_lanes<0, 4>(zc, jc);
+      row_lanes<0, 4>(zw, w);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) y[e] = y2[(int64_t)jc[e] * s + cl];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cfma(qa, cmk(w[e], (T)0), y[e]);
+    }
+    {
+      int32_t jc[8];
+      T wr[8], wi[8];
+      cplx<T> y[8];
+      row_lanes<0, 8>(ac, jc);
+      row_lanes<0, 8>(ar, wr);
+      row_lanes<0, 8>(ai, wi);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) y[e] = y2[(int64_t)jc[e] * s + cl];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) cfma(ta, cmk(wr[e], wi[e]), y[e]);
+    }
+    if (a1 - a0 > 8) {  // the same for every lane of the row
+      int32_t jc[8];
+      T wr[8], wi[8];
+      cplx<T> y[8];
+      row_lanes<8, 8>(ac, jc);
+      row_lanes<8, 8>(ar, wr);
+      row_lanes<8, 8>(ai, wi);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) y[e] = y2[(int64_t)jc[e] * s + cl];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) cfma(ta, cmk(wr[e], wi[e]), y[e]);
+    }
+    for (int64_t e = z0 + 4; e < z1; e += 4) {
+      int32_t jc[4];
+      T zv[4];
+      cplx<T> yv[4];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const bool ok = e + w < z1;
+        jc[w] = zcol[ok ? e + w : e];
+        zv[w] = ok ? (T)zval[e + w] : (T)0;
+      }
+#pragma unroll
+      for (int w = 0; w < 4; ++w) yv[w] = y2[(int64_t)jc[w] * s + cl];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) cfma(qa, cmk(zv[w], (T)0), yv[w]);
+    }
+    for (int64_t e = a0 + 16; e < a1; e += 8) {
+      int32_t jc[8];
+      cplx<T> av[8], yv[8];
+#pragma unroll
+      for (int w = 0; w < 8; ++w) {
+        const bool ok = e + w < a1;
+        jc[w] = azcol[ok ? e + w : e];
+        const cplx<T> x = az[ok ? e + w : e];
+        av[w] = csel(ok, x, cmk((T)0, (T)0));
+      }
+#pragma unroll
+      for (int w = 0; w < 8; ++w) yv[w] = y2[(int64_t)jc[w] * s + cl];
+#pragma unroll
+      for (int w = 0; w < 8; ++w) cfma(ta, av[w], yv[w]);
+    }
+    if (col < s) {
+      q[i * s + col] = qa;
+      const c128 r = vk - cmk((double)ta.re, (double)ta.im);
+      t[i * s + col] = cmk((T)r.re, (T)r.im);
+    }
+  }
 }
 
 }  // namespace
@@ -484,7 +562,7 @@ static void coarse_apply_t(Ctx* ctx, Ddm& d, int s, const c128* v, cplx<T>* q, c
                      cs.w_part.as<cplx<T>>());
   hipLaunchKernelGGL(k_dense_reduce<T>, dim3((unsigned)((nc * s + 255) / 256)), dim3(256), 0, st, KS, nc * s,
                      cs.w_part.as<cplx<T>>(), y2);
-  hipLaunchKernelGGL(k_prolong<T>, dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, st, n, s, cs.d_zptr.ptr(),
+  hipLaunchKernelGGL(k_prolong<T>, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, st, n, s, cs.d_zptr.ptr(),
                      cs.d_zcol.ptr(), cs.d_zval.ptr(), cs.d_azptr.ptr(), cs.d_azcol.ptr(), az, y2, v, q, t);
   HIP_CHECK(hipGetLastError());
 }

@@ -83,23 +83,43 @@ __global__ __launch_bounds__(256) void k_fwd_assemble(const int32_t* __restrict_
   }
   const int32_t* m0 = imap + F.imap_off;
   const int32_t* m1 = m0 + f;
-  for (int64_t k = threadIdx.x; k < tot; k += blockDim.x) {
-    const int64_t i = i0 + k / s;
-    const int c = (int)(k - (k / s) * s);
-    cplx<T> v = cmk((T)0, (T)0);
-    if (i < F.p) {
-      const cplx<TS> b = src[(int64_t)gidx[F.vec_off + F.pos0 + i] * s + c];
-      v = cmk((T)b.re, (T)b.im);
+  // four elements per thread and pass: their index loads go out together, then their
+  // gathers, then the sums (in the order own, child 0, child 1) and the stores
+  constexpr int U = 4;
+  const cplx<T> zero = cmk((T)0, (T)0);
+  for (int64_t kb = threadIdx.x; kb < tot; kb += U * (int64_t)blockDim.x) {
+    int64_t ii[U];
+    int cc[U];
+    int32_t g[U], q0[U], q1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t k = kb + u * (int64_t)blockDim.x;
+      const int kk = k < tot ? (int)k : 0;  // past the tile: the tile's first element, not stored
+      ii[u] = i0 + kk / s;                  // a tile holds at most 64 s elements: 32-bit division
+      cc[u] = kk - (kk / s) * s;
+      g[u] = ii[u] < F.p ? gidx[F.vec_off + F.pos0 + ii[u]] : 0;
+      q0[u] = w0 ? m0[ii[u]] : -1;
+      q1[u] = w1 ? m1[ii[u]] : -1;
     }
-    if (w0) {
-      const int32_t q = m0[i];
-      if (q >= 0) v = v + w0[(int64_t)q * s + c];
+    cplx<T> b[U], x0[U], x1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (ii[u] < F.p) {
+        const cplx<TS> bs = src[(int64_t)g[u] * s + cc[u]];
+        b[u] = cmk((T)bs.re, (T)bs.im);
+      } else {
+        b[u] = zero;
+      }
+      x0[u] = q0[u] >= 0 ? w0[(int64_t)q0[u] * s + cc[u]] : zero;
+      x1[u] = q1[u] >= 0 ? w1[(int64_t)q1[u] * s + cc[u]] : zero;
     }
-    if (w1) {
-      const int32_t q = m1[i];
-      if (q >= 0) v = v + w1[(int64_t)q * s + c];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      cplx<T> v = b[u];
+      if (q0[u] >= 0) v = v + x0[u];
+      if (q1[u] >= 0) v = v + x1[u];
+      if (kb + u * (int64_t)blockDim.x < tot) wbuf[(F.w_off + ii[u]) * s + cc[u]] = v;
     }
-    wbuf[(F.w_off + i) * s + c] = v;
   }
 }
 
