@@ -7,9 +7,10 @@
 // Each request's restart length is the largest up to 40 with which one of its parts fits
 // next to the resident objects (requests that fit at no useful length are refused).  Each
 // scheduler tick advances every active job by one Arnoldi step: the blocks M^{-1} v of all
-// jobs on the same operator are packed column-wise into shared launches of the
-// preconditioner and of the SpMM (so the factors and the matrix are read once for all of
-// them), then each job does its own orthogonalisation and least-squares step.  A finished job
+// jobs on the same operator are packed column-wise (first-fit decreasing, at most 32 columns
+// a launch) into shared launches of the preconditioner and of the SpMM (so the factors and the
+// matrix are read once for all of them), then each job does its own orthogonalisation and
+// least-squares step.  A finished job
 // frees its Krylov memory at once; a request completes when all its parts have.
 #include <algorithm>
 #include <chrono>
@@ -166,6 +167,27 @@ static void finish_ticket(Serve& S, Ticket& t) {
   t.status = st;
 }
 
+// Shared launches for the jobs of one operator: first-fit decreasing into launches of at most
+// 32 columns (the widest job first, each into the first launch with room), so that as few
+// passes over the factors as possible serve them all.  Ties keep admission order.
+static std::vector<std::vector<FgmresJob*>> pack_launches(const std::vector<FgmresJob*>& jobs) {
+  std::vector<FgmresJob*> order(jobs);
+  std::stable_sort(order.begin(), order.end(), [](const FgmresJob* x, const FgmresJob* y) { return x->s > y->s; });
+  std::vector<std::vector<FgmresJob*>> bins;
+  std::vector<int> width;
+  for (FgmresJob* j : order) {
+    size_t b = 0;
+    while (b < bins.size() && width[b] + j->s > 32) ++b;
+    if (b == bins.size()) {
+      bins.emplace_back();
+      width.push_back(0);
+    }
+    bins[b].push_back(j);
+    width[b] += j->s;
+  }
+  return bins;
+}
+
 static void tick(Serve& S) {
   Ctx* ctx = S.ctx;
   hipStream_t st = ctx->stream;
@@ -175,14 +197,12 @@ static void tick(Serve& S) {
     for (auto& p : t->parts)
       if (!p->done) groups[t->ddm.get()].push_back(p->job.get());
   for (auto& [dp, jobs] : groups) {
-    size_t a = 0;
-    while (a < jobs.size()) {
+    for (const std::vector<FgmresJob*>& bin : pack_launches(jobs)) {
       int cols = 0;
-      size_t b = a;
-      while (b < jobs.size() && cols + jobs[b]->s <= 32) cols += jobs[b++]->s;
+      for (FgmresJob* j : bin) cols += j->s;
       const int64_t n = dp->op->mesh->n;
-      if (b - a == 1) {  // a single job needs no packing
-        jobs[a]->matvec();
+      if (bin.size() == 1) {  // a single job needs no packing
+        bin[0]->matvec();
       } else {
         const bool z32 = dp->precision == HZ_PREC_MIXED;
         const int64_t need = n * 32;
@@ -193,8 +213,7 @@ static void tick(Serve& S) {
         if (z32 && (int64_t)S.packZ32.n < need) S.packZ32.alloc(ctx, need);
         if (!z32 && (int64_t)S.packZ.n < need) S.packZ.alloc(ctx, need);
         int off = 0;
-        for (size_t q = a; q < b; ++q) {
-          FgmresJob* j = jobs[q];
+        for (FgmresJob* j : bin) {
           hipLaunchKernelGGL(k_pack_cols, dim3((unsigned)((n * j->s + 255) / 256)), dim3(256), 0, st, n, j->s, cols, off,
                              j->v_cur(), S.packV.ptr());
           off += j->s;
@@ -212,8 +231,7 @@ static void tick(Serve& S) {
                               cmk(0.0, 0.0), nullptr);
         }
         off = 0;
-        for (size_t q = a; q < b; ++q) {
-          FgmresJob* j = jobs[q];
+        for (FgmresJob* j : bin) {
           const dim3 grid((unsigned)((n * j->s + 255) / 256));
           if (z32)
             hipLaunchKernelGGL(k_unpack_cols<float>, grid, dim3(256), 0, st, n, j->s, cols, off, S.packZ32.ptr(),
@@ -227,7 +245,6 @@ static void tick(Serve& S) {
         }
         HIP_CHECK(hipGetLastError());
       }
-      a = b;
     }
     for (FgmresJob* j : jobs) j->after_matvec();
   }

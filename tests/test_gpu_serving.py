@@ -70,9 +70,9 @@ def test_serve_results_same_alone_and_in_mix(setup):
 
 
 def test_serve_packing_past_32_columns(setup):
-    """Parts on one operator whose columns add up past 32 (20 + 9 + 12 here) are packed in
-    order into launches of at most 32 columns (20 + 9 together, 12 in a launch of its own,
-    regrouped as parts finish); each result matches its request solved alone."""
+    """Parts on one operator whose columns add up past 32 (20 + 9 + 12 here) are packed first
+    fit decreasing into launches of at most 32 columns (20 + 12 together, 9 in a launch of
+    its own, regrouped as parts finish); each result matches its request solved alone."""
     ctx, ops = setup
     p, d, F = ops[0]
     rng = np.random.default_rng(9)
