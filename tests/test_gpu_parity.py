@@ -375,9 +375,20 @@ def test_coarse_space_and_two_level(ctx):
     P = odd.build_preconditioner(om, A, p.velocity, p.freq, None, p.partition, p.n_sub, p.overlap,
                                  p.coarse_tets, p.coarse_coords)
     rng = np.random.default_rng(5)
-    V = rng.standard_normal((3, om.n)) + 1j * rng.standard_normal((3, om.n))
-    Zg = ctx.precond(d, V)
-    assert _rel(Zg, P.apply(V.T).T) <= 1e-10
+    V = rng.standard_normal((32, om.n)) + 1j * rng.standard_normal((32, om.n))
+    Zo = P.apply(V.T).T
+    # blocks of 1..32 columns: the prolongation takes a fine row's columns 16 at a time (one
+    # ragged chunk, one full chunk, two chunks)
+    for s in (1, 3, 16, 17, 32):
+        assert _rel(ctx.precond(d, V[:s]), Zo[:s]) <= 1e-10, s
+    from paper_2004_07930_amd import hz
+
+    d32 = ctx.setup_ddm(gop, p.partition, p.n_sub, p.overlap, coarse=(p.coarse_tets, p.coarse_coords),
+                        precision=hz.HZ_PREC_MIXED)
+    for s in (1, 3, 16, 17, 32):
+        Z = ctx.precond(d32, V[:s])
+        assert max(_rel(Z[c], Zo[c]) for c in range(s)) <= 1e-4, s
+    ctx.release(d32)
     F = ctx.point_sources(gm, p.sources)
     X, info = ctx.solve(d, F, fixed_iters=5, restart=5)
     Xo, io = krylov.block_fgmres(lambda x: A @ x, F.T, P.apply, fixed_iters=5, m=5)
