@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define HZ_ABI_VERSION 1
+#define HZ_ABI_VERSION 2
 
 typedef enum {
   HZ_OK = 0,
@@ -140,15 +140,17 @@ typedef struct {
   int32_t restarts;
   double rel_residual;  /* explicit ||b - A x|| / ||b|| in FP64 */
   int32_t status;       /* HZ_OK or HZ_ERR_NOT_CONVERGED */
+  int32_t restart_len;  /* restart length m the column's block ran with */
+  int32_t block;        /* width of the column's Arnoldi block */
 } hz_col_info;
 
 typedef struct {
   size_t struct_size;   /* sizeof(hz_solve_opts) */
   double tol;           /* per-column relative residual target (paper: backward error) */
   int32_t max_iter;     /* total inner iterations allowed */
-  int32_t restart;      /* FGMRES restart length m (0 = default 40, capped by memory) */
+  int32_t restart;      /* FGMRES restart length m (0 = default 40) */
   int32_t fixed_iters;  /* > 0: run exactly this many steps in one cycle, ignore tol */
-  int32_t block;        /* max right-hand sides per Arnoldi block (0 = all, max 32) */
+  int32_t block;        /* right-hand sides per Arnoldi block (0 = automatic, max 32) */
 } hz_solve_opts;
 
 /*
@@ -160,6 +162,16 @@ typedef struct {
  * is complete one step later), other widths by classical Gram-Schmidt applied twice with
  * CholQR2 block normalisation; Householder least squares; all FP64.
  *   rhs [n_rhs][n_dofs] complex128, x same layout (may not alias rhs)
+ * Memory: the Krylov basis of a block of s columns at restart m takes about
+ * (m + 1) n s complex128 entries plus m n s preconditioned entries (complex64 with
+ * HZ_PREC_MIXED).  With block = 0 the block is the widest of min(n_rhs, 32) columns and its
+ * successive halvings whose basis at the requested m fits in 80% of the free device memory;
+ * only if one column does not fit is m shortened, down to 8 at the least (below that:
+ * HZ_ERR_OOM).  An explicit block keeps its width and shortens m the same way.  The
+ * m and width used are reported per column (hz_col_info.restart_len, .block).  With
+ * fixed_iters, m is at least fixed_iters and is never shortened (HZ_ERR_OOM instead).
+ * Setting the environment variable HZ_TRACE=1 before hz_init prints one line per Arnoldi
+ * step (largest residual estimate) and per restart cycle (explicit residuals) to stderr.
  * Returns HZ_ERR_NOT_CONVERGED (x = best iterate, info filled) when max_iter is hit;
  * HZ_ERR_ARG for a non-finite entry in rhs, a zero column, a block whose columns are
  * numerically dependent (CholQR pivot below 1e-14 of its diagonal entry: solve such columns
@@ -197,6 +209,7 @@ hz_status hz_point_sources(hz_ctx* ctx, hz_handle mesh, int64_t n_src, const dou
 hz_status hz_spmm(hz_ctx* ctx, hz_handle op, int64_t n_rhs, const void* x, int x_mem, void* y, int y_mem);
 hz_status hz_spmm_c64x(hz_ctx* ctx, hz_handle op, int64_t n_rhs, const void* x, int x_mem, void* y, int y_mem);
 hz_status hz_precond(hz_ctx* ctx, hz_handle ddm, int64_t n_rhs, const void* v, int v_mem, void* z, int z_mem);
+
 
 typedef struct {
   int64_t n_dofs, nnz, n_sub;

@@ -191,6 +191,8 @@ hz_status hz_init(hz_ctx** out, const hz_init_opts* opts) {
     size_t fr = 0, tot = 0;
     HIP_CHECK(hipMemGetInfo(&fr, &tot));
     c->hbm_budget = (opts && opts->hbm_budget) ? opts->hbm_budget : (size_t)(0.9 * (double)fr);
+    const char* tr = std::getenv("HZ_TRACE");
+    c->trace = tr && tr[0] && tr[0] != '0';
     p3_upload_tables(c);
   });
   if (st != HZ_OK) {
@@ -327,12 +329,33 @@ hz_status hz_solve_ex(hz_ctx* c, hz_handle ddm, int64_t n_rhs, const void* rhs, 
     HZ_REQUIRE(count_nonfinite(c, B.ptr, n_rhs * n) == 0, HZ_ERR_ARG, "hz_solve: non-finite right-hand side");
     DevArray<c128> Xd;
     Xd.alloc(c, n_rhs * n);
-    const int blk = std::min<int64_t>(n_rhs, opts->block > 0 ? std::min(opts->block, 32) : 32);
     SolveOptions so;
     so.tol = opts->tol;
     so.max_iter = opts->max_iter > 0 ? opts->max_iter : 500;
     so.restart = opts->restart > 0 ? opts->restart : 40;
     so.fixed_iters = opts->fixed_iters;
+    const bool z32 = d->precision == HZ_PREC_MIXED;
+    // block width and restart length: a short memory supply narrows the block (automatic width)
+    // before it shortens the restart, which changes the iteration
+    const int want = so.fixed_iters > 0 ? std::max(so.restart, so.fixed_iters) : so.restart;
+    int blk = (int)std::min<int64_t>(n_rhs, opts->block > 0 ? std::min(opts->block, 32) : 32);
+    // the block's node-major right-hand side and solution (2 n b complex128) come on top
+    int m = 0;
+    if (opts->block <= 0) {
+      for (int b = blk; b >= 1; b = b > 1 ? b / 2 : 0) {
+        const int mb = FgmresJob::restart_fit(c, n, b, want, so.fixed_iters, z32, 2 * n * b * (int64_t)sizeof(c128));
+        if (mb == want || b == 1) {
+          blk = b;
+          m = mb;
+          break;
+        }
+      }
+    } else {
+      m = FgmresJob::restart_fit(c, n, blk, want, so.fixed_iters, z32, 2 * n * blk * (int64_t)sizeof(c128));
+    }
+    HZ_REQUIRE(m > 0, HZ_ERR_OOM,
+               so.fixed_iters > 0 ? "hz_solve: the Krylov basis for fixed_iters steps does not fit in device memory"
+                                  : "hz_solve: not even a restart length of 8 fits in device memory");
     bool all_ok = true;
     DevArray<c128> Bn, Xn;
     for (int64_t c0 = 0; c0 < n_rhs; c0 += blk) {
@@ -342,13 +365,15 @@ hz_status hz_solve_ex(hz_ctx* c, hz_handle ddm, int64_t n_rhs, const void* rhs, 
       KrylovKernels K(c, n, s);
       K.to_node(B.ptr + c0 * n, Bn.ptr());
       std::vector<ColInfo> ci;
-      fgmres(c, d, s, Bn.ptr(), Xn.ptr(), so, ci);
+      fgmres(c, d, s, Bn.ptr(), Xn.ptr(), so, m, ci);
       K.from_node(Xn.ptr(), Xd.ptr() + c0 * n);
       for (int k = 0; k < s; ++k) {
         info[c0 + k].iters = ci[k].iters;
         info[c0 + k].restarts = ci[k].restarts;
         info[c0 + k].rel_residual = ci[k].rel_residual;
         info[c0 + k].status = ci[k].status;
+        info[c0 + k].restart_len = ci[k].m;
+        info[c0 + k].block = ci[k].block;
         all_ok = all_ok && ci[k].status == HZ_OK;
       }
     }

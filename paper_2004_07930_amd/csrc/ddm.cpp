@@ -11,6 +11,7 @@
 //    sum_i R_i^T D_i R_i = I and the prolongation is a pure gather;
 //  * A_i: the tets of the overlapped subdomain, the physical boundary conditions, and the
 //    first-order absorbing (Robin) term on every face whose neighbour tet is outside.
+#include <cstdio>
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -342,7 +343,7 @@ int64_t Ddm::device_bytes() const {
   int64_t b = 0;
   b += d_fronts.bytes() + d_urows.bytes() + d_emap.bytes() + d_gidx.bytes() + d_orig_src.bytes() +
        d_orig_dst.bytes() + d_own_src.bytes() + d_lrowptr.bytes() + d_lgptr.bytes() + d_lcol.bytes() +
-       d_lgsrc.bytes() + d_ldir.bytes() + d_lval.bytes() + d_level_fronts.bytes();
+       d_lgsrc.bytes() + d_ldir.bytes() + d_lval.bytes() + d_level_fronts.bytes() + d_flf.bytes();
   b += d_factor.bytes + d_update.bytes + d_dinv.bytes;
   b += d_fwd_work.bytes() + d_bwd_work.bytes() + d_imap.bytes();
   for (int t = 0; t < 2; ++t) b += d_fwdm_work[t].bytes() + d_bwdm_work[t].bytes();
@@ -410,6 +411,10 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     for (auto& t : th) t.join();
     for (auto& e : errs) HZ_REQUIRE(e.empty(), HZ_ERR_STATE, "hz_setup_ddm: " + e);
   }
+  auto phase = [&](const char* what) {
+    if (ctx->trace) std::fprintf(stderr, "hz: setup %-34s %8.2f s\n", what, wall_time() - t0);
+  };
+  phase("subdomains, nested dissection, symbolic");
   // --- concatenate fronts, offsets
   int64_t vec = 0, csr = 0, rows = 0, Loff = 0, Uoff = 0, urow = 0, orig = 0;
   int max_level = 0;
@@ -447,33 +452,68 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   d->urows_total = urow;
   d->urows.resize(urow);
   d->emap.assign(urow, 0);
-  // update rows, extend-add maps and original-entry scatter lists
-  for (int32_t i = 0; i < n_sub; ++i) {
-    Subdomain& S = d->subs[i];
-    SubSym& sy = syms[i];
-    for (size_t fi = 0; fi < sy.fronts.size(); ++fi) {
+  // update rows, extend-add maps and original-entry scatter lists, one subdomain per task:
+  // count each front's original entries, place them by a prefix sum (subdomain, then front
+  // order), then fill every list at its offset
+  auto each_sub = [&](const std::function<void(int32_t)>& body) {
+    const int nt = std::max(1, std::min<int>(n_sub, std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
+    std::atomic<int32_t> next{0};
+    std::vector<std::string> errs(nt);
+    std::vector<std::thread> th;
+    for (int w = 0; w < nt; ++w)
+      th.emplace_back([&, w] {
+        try {
+          for (int32_t i; (i = next.fetch_add(1)) < n_sub;) body(i);
+        } catch (const std::exception& e) {
+          errs[w] = e.what();
+        }
+      });
+    for (auto& t : th) t.join();
+    for (auto& e : errs) HZ_REQUIRE(e.empty(), HZ_ERR_STATE, "hz_setup_ddm: " + e);
+  };
+  each_sub([&](int32_t i) {
+    const Subdomain& S = d->subs[i];
+    for (size_t fi = 0; fi < S.fronts.size(); ++fi) {
       Front& F = d->fronts[S.fronts[fi]];
+      int64_t cnt = 0;
+      for (int64_t q = F.pos0; q < F.pos0 + F.p; ++q) {
+        const int32_t v = S.perm[q];
+        for (int64_t k = S.rowptr[v]; k < S.rowptr[v + 1]; ++k) cnt += S.ipos[S.col[k]] >= q;
+      }
+      F.orig_cnt = cnt;
+    }
+  });
+  for (Front& F : d->fronts) {
+    F.orig_off = orig;
+    orig += F.orig_cnt;
+  }
+  d->orig_src.resize(orig);
+  d->orig_dst.resize(orig);
+  each_sub([&](int32_t i) {
+    const Subdomain& S = d->subs[i];
+    const SubSym& sy = syms[i];
+    for (size_t fi = 0; fi < sy.fronts.size(); ++fi) {
+      const Front& F = d->fronts[S.fronts[fi]];
       std::copy(sy.U[fi].begin(), sy.U[fi].end(), d->urows.begin() + F.rows_off);
       if (F.parent >= 0) {
         const Front& P = d->fronts[F.parent];
         const auto& UP = sy.U[(size_t)(F.parent - S.fronts[0])];
         for (int64_t k = 0; k < F.r; ++k) d->emap[F.emap_off + k] = (int32_t)front_index(P, UP, sy.U[fi][k]);
       }
-      F.orig_off = orig;
       const int64_t ld = F.ld();
+      int64_t o = F.orig_off;
       for (int64_t q = F.pos0; q < F.pos0 + F.p; ++q) {
         const int32_t v = S.perm[q];
         for (int64_t k = S.rowptr[v]; k < S.rowptr[v + 1]; ++k) {
           const int64_t pc = S.ipos[S.col[k]];
           if (pc < q) continue;
-          d->orig_src.push_back(S.csr_off + k);
-          d->orig_dst.push_back((q - F.pos0) * ld + front_index(F, sy.U[fi], pc));
+          d->orig_src[o] = S.csr_off + k;
+          d->orig_dst[o] = (q - F.pos0) * ld + front_index(F, sy.U[fi], pc);
+          ++o;
         }
       }
-      F.orig_cnt = (int64_t)d->orig_src.size() - orig;
-      orig = (int64_t)d->orig_src.size();
     }
-  }
+  });
   d->orig_total = orig;
   // levels
   d->levels.assign(max_level + 1, Level{});
@@ -498,8 +538,11 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   // Update (Schur) blocks live from their front's level until their parent's level has
   // absorbed them.  Place them in one arena with a first-fit allocator over those lifetimes:
   // at each level the new blocks are placed while the children being absorbed at that level
-  // are still held, and only then are those children released.
-  {
+  // are still held, and only then are those children released.  The subdomains are factored
+  // in groups of consecutive ids, one group after the other, each group packed from offset 0:
+  // the arena then holds one group's blocks at a time.  A front's arithmetic does not depend
+  // on the fronts it shares a launch with, so the grouping changes memory, not results.
+  auto pack_arena = [&](int32_t s0, int32_t s1) -> int64_t {
     std::map<int64_t, int64_t> holes;  // offset -> length
     int64_t arena = 0;
     auto take = [&](int64_t len) {
@@ -538,19 +581,57 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     for (const Level& L : d->levels) {
       for (int32_t fi : L.fronts) {
         Front& F = d->fronts[fi];
+        if (F.sub < s0 || F.sub >= s1) continue;
         F.U_off = F.r > 0 ? take(F.r * F.r) : 0;
         peak = std::max(peak, arena);
       }
       for (int32_t fi : L.fronts) {
         const Front& F = d->fronts[fi];
+        if (F.sub < s0 || F.sub >= s1) continue;
         for (int k = 0; k < F.nchild; ++k) {
           const Front& C = d->fronts[F.child[k]];
           if (C.r > 0) give(C.U_off, C.r * C.r);
         }
       }
     }
-    d->update_entries = peak;
+    return peak;
+  };
+  {
+    // group count: the smallest power of two whose arena fits next to the factor and the
+    // local operators in the free device memory (HZ_FACTOR_GROUPS overrides)
+    const int64_t elem = precision == HZ_PREC_MIXED ? (int64_t)sizeof(c64) : (int64_t)sizeof(c128);
+    size_t fr = 0, tot = 0;
+    HIP_CHECK(hipMemGetInfo(&fr, &tot));
+    const double fixed = (double)d->factor_entries * elem + (double)csr * sizeof(c128) +
+                         (double)d->orig_total * 16.0 + (double)vec * (elem + 16.0);
+    const double budget = 0.85 * (double)fr - fixed;
+    const int forced = env_int("HZ_FACTOR_GROUPS", 0);
+    int G = forced > 0 ? std::min<int>(forced, n_sub) : 1;
+    for (;;) {
+      int64_t peak = 0;
+      d->fgroup_off.clear();
+      for (int g = 0; g <= G; ++g) d->fgroup_off.push_back((int32_t)((int64_t)n_sub * g / G));
+      for (int g = 0; g < G; ++g) peak = std::max(peak, pack_arena(d->fgroup_off[g], d->fgroup_off[g + 1]));
+      d->update_entries = peak;
+      if (forced > 0 || G >= n_sub || (double)peak * elem <= budget) break;
+      G = std::min<int>(2 * G, n_sub);
+    }
+    // factor launches: the fronts of each (group, level), p descending
+    d->flf.clear();
+    d->flf_off.clear();
+    for (int g = 0; g < G; ++g)
+      for (const Level& L : d->levels) {
+        d->flf_off.push_back((int64_t)d->flf.size());
+        for (int32_t fi : L.fronts)
+          if (d->fronts[fi].sub >= d->fgroup_off[g] && d->fronts[fi].sub < d->fgroup_off[g + 1]) d->flf.push_back(fi);
+      }
+    d->flf_off.push_back((int64_t)d->flf.size());
   }
+  phase("fronts, levels, arena");
+  if (ctx->trace)
+    std::fprintf(stderr, "hz: setup factor %lld entries, arena %lld entries in %zu groups, %zu fronts, %zu levels\n",
+                 (long long)d->factor_entries, (long long)d->update_entries, d->fgroup_off.size() - 1,
+                 d->fronts.size(), d->levels.size());
   // local vector <-> global maps
   d->gidx.resize(vec);
   d->own_src.assign(m.n, -1);
@@ -606,6 +687,7 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   d->d_orig_src.upload(ctx, d->orig_src);
   d->d_orig_dst.upload(ctx, d->orig_dst);
   d->d_level_fronts.upload(ctx, lf);
+  d->d_flf.upload(ctx, d->flf);
   d->w_total = wrows;
   d->d_imap.upload(ctx, imap);
   {  // solve worklists: forward row tiles of 64, backward column tiles of 32 (vector-unit
@@ -672,23 +754,22 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
       build(kFwdRowsMfma[t], kBwdColsMfma[t], d->fwdm_off[t], d->bwdm_off[t], d->d_fwdm_work[t], d->d_bwdm_work[t]);
   }
   {
-    std::vector<int64_t> rp, gp;
-    std::vector<int32_t> cl;
-    std::vector<uint32_t> gs;
-    std::vector<uint8_t> dr;
-    rp.reserve(rows);
-    cl.reserve(csr);
-    int64_t gbase = 0;
-    for (int32_t i = 0; i < n_sub; ++i) {
+    // concatenated local CSR patterns, gather maps and Dirichlet flags (one subdomain per task)
+    std::vector<int64_t> goff(n_sub + 1, 0);
+    for (int32_t i = 0; i < n_sub; ++i) goff[i + 1] = goff[i] + d->subs[i].gm.ptr.back();
+    std::vector<int64_t> rp(rows), gp(csr + 1);
+    std::vector<int32_t> cl(csr);
+    std::vector<uint32_t> gs(goff[n_sub]);
+    std::vector<uint8_t> dr(vec);
+    each_sub([&](int32_t i) {
       const Subdomain& S = d->subs[i];
-      for (int64_t k = 0; k <= S.n; ++k) rp.push_back(S.rowptr[k]);
-      cl.insert(cl.end(), S.col.begin(), S.col.end());
-      for (size_t k = 0; k + 1 < S.gm.ptr.size(); ++k) gp.push_back(S.gm.ptr[k] + gbase);
-      gbase += S.gm.ptr.back();
-      gs.insert(gs.end(), S.gm.src.begin(), S.gm.src.end());
-      dr.insert(dr.end(), S.dir.begin(), S.dir.end());
-    }
-    gp.push_back(gbase);
+      std::copy(S.rowptr.begin(), S.rowptr.begin() + S.n + 1, rp.begin() + S.row_off);
+      std::copy(S.col.begin(), S.col.end(), cl.begin() + S.csr_off);
+      for (size_t k = 0; k + 1 < S.gm.ptr.size(); ++k) gp[S.csr_off + k] = S.gm.ptr[k] + goff[i];
+      std::copy(S.gm.src.begin(), S.gm.src.end(), gs.begin() + goff[i]);
+      std::copy(S.dir.begin(), S.dir.end(), dr.begin() + S.vec_off);
+    });
+    gp[csr] = goff[n_sub];
     d->d_lrowptr.upload(ctx, rp);
     d->d_lcol.upload(ctx, cl);
     d->d_lgptr.upload(ctx, gp);
@@ -708,15 +789,20 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   HIP_CHECK(hipStreamSynchronize(ctx->stream));
   d->d_lgptr = DevArray<int64_t>();
   d->d_lgsrc = DevArray<uint32_t>();
+  phase("device maps, local operators");
   // --- numeric factorisation
   factor_all(ctx, *d);
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  phase("numeric factorisation");
   // --- coarse space
   if (coarse) {
     d->coarse = std::make_unique<CoarseSpace>();
     build_coarse_host(m, coarse, *d->coarse);
+    phase("coarse space (host)");
     coarse_setup(ctx, *d);
   }
   HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  phase("coarse space (device)");
   d->setup_seconds = wall_time() - t0;
   return d;
 }

@@ -104,7 +104,7 @@ struct Ddm {
   std::vector<Front> fronts;
   std::vector<Level> levels;
   int64_t n_local_total = 0;      // sum of n_i
-  int64_t factor_entries = 0, update_entries = 0, urows_total = 0, orig_total = 0;
+  int64_t factor_entries = 0, update_entries = 0, urows_total = 0, orig_total = 0;  // update: per group
   int64_t max_front = 0;
   int64_t static_pivots = 0;
   double setup_seconds = 0;
@@ -129,6 +129,13 @@ struct Ddm {
   DevArray<c128> d_lval;          // local operator values (FP64), concatenated
   DevArray<int32_t> d_level_fronts;  // fronts of every level, concatenated
   std::vector<int64_t> level_off;    // offsets into d_level_fronts
+  // numeric factorisation in groups of consecutive subdomains (the update arena holds one
+  // group's Schur blocks at a time): group g is subdomains [fgroup_off[g], fgroup_off[g+1]);
+  // flf lists the fronts of each (group, level) by p descending, at flf_off[g * levels + lv]
+  std::vector<int32_t> fgroup_off;
+  std::vector<int32_t> flf;
+  std::vector<int64_t> flf_off;
+  DevArray<int32_t> d_flf;
   DevBuf d_factor;                // c128 or c64 L blocks
   DevBuf d_update;                // update workspace
   DevBuf d_dinv;                  // inverse pivots per local position (factor precision)

@@ -397,19 +397,26 @@ void factor_typed(Ctx* ctx, Ddm& d) {
   d.d_npiv.alloc(ctx, 1);
   HIP_CHECK(hipMemsetAsync(d.d_npiv.ptr(), 0, sizeof(unsigned long long), st));
   const FrontDesc* fr = d.d_fronts.ptr();
-  for (size_t lv = 0; lv < d.levels.size(); ++lv) {
-    const Level& Lv = d.levels[lv];
-    const int nf = (int)Lv.fronts.size();
-    const int32_t* lf = d.d_level_fronts.ptr() + d.level_off[lv];
-    int64_t max_orig = 1, max_child_u = 1;
-    for (int32_t fi : Lv.fronts) {
+  const size_t nlev = d.levels.size();
+  const size_t ngroups = d.fgroup_off.size() - 1;
+  for (size_t gl = 0; gl < ngroups * nlev; ++gl) {
+    const size_t lv = gl % nlev;
+    const int nf = (int)(d.flf_off[gl + 1] - d.flf_off[gl]);
+    if (nf == 0) continue;
+    const int32_t* lfh = d.flf.data() + d.flf_off[gl];  // host copy: p descending
+    const int32_t* lf = d.d_flf.ptr() + d.flf_off[gl];
+    int64_t max_orig = 1, max_child_u = 1, lv_max_r = 0, lv_max_p = 0;
+    for (int k = 0; k < nf; ++k) {
+      const int32_t fi = lfh[k];
+      lv_max_r = std::max(lv_max_r, d.fronts[fi].r);
+      lv_max_p = std::max(lv_max_p, d.fronts[fi].p);
       max_orig = std::max(max_orig, d.fronts[fi].orig_cnt);
       for (int k = 0; k < d.fronts[fi].nchild; ++k)
         max_child_u = std::max(max_child_u, d.fronts[d.fronts[fi].child[k]].r * d.fronts[d.fronts[fi].child[k]].r);
     }
     const unsigned gy_o = (unsigned)std::min<int64_t>((max_orig + 255) / 256, 1024);
-    if (Lv.max_r > 0) {
-      const unsigned gy_z = (unsigned)std::min<int64_t>((Lv.max_r * Lv.max_r + 255) / 256, 4096);
+    if (lv_max_r > 0) {
+      const unsigned gy_z = (unsigned)std::min<int64_t>((lv_max_r * lv_max_r + 255) / 256, 4096);
       hipLaunchKernelGGL(k_zero_update<T>, dim3(nf, gy_z), dim3(256), 0, st, lf, fr, U);
     }
     hipLaunchKernelGGL(k_scatter_orig<T>, dim3(nf, gy_o), dim3(256), 0, st, lf, nf, fr, d.d_orig_src.ptr(),
@@ -422,11 +429,11 @@ void factor_typed(Ctx* ctx, Ddm& d) {
         HIP_CHECK(hipGetLastError());
       }
     }
-    for (int64_t k0 = 0; k0 < Lv.max_p; k0 += kNb) {
+    for (int64_t k0 = 0; k0 < lv_max_p; k0 += kNb) {
       int cnt = 0;  // fronts sorted by p descending: active prefix
       int64_t max_f = 0;
-      while (cnt < nf && d.fronts[Lv.fronts[cnt]].p > k0) {
-        max_f = std::max(max_f, d.fronts[Lv.fronts[cnt]].f());
+      while (cnt < nf && d.fronts[lfh[cnt]].p > k0) {
+        max_f = std::max(max_f, d.fronts[lfh[cnt]].f());
         ++cnt;
       }
       hipLaunchKernelGGL(k_diag_block<T>, dim3(cnt), dim3(256), 0, st, lf, fr, (int)k0, L, d_tau.ptr(), d_fsub.ptr(),

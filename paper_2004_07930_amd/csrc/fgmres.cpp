@@ -20,6 +20,7 @@
 // packs their Z_j = M^{-1} V~_j and W = A Z_j products into shared launches.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 
 #include "krylov.h"
 #include "prof.h"
@@ -38,18 +39,16 @@ int64_t FgmresJob::bytes_needed(int64_t n, int s, int m, bool z32) {
   return e * (int64_t)sizeof(c128) + (int64_t)m * ns * (int64_t)(z32 ? sizeof(c64) : sizeof(c128));  // + Z
 }
 
-int FgmresJob::restart_for(Ctx* ctx, int64_t n, int s, int want, int fixed, bool z32) {
+int FgmresJob::restart_fit(Ctx* ctx, int64_t n, int s, int want, int fixed, bool z32, int64_t extra) {
   int m = std::max(1, want);
   if (fixed > 0) m = std::max(m, fixed);
   size_t fr = 0, tot = 0;
   HIP_CHECK(hipMemGetInfo(&fr, &tot));
-  // each step keeps one V block (complex128) and one Z block; four more blocks are fixed
-  const double blk = (double)n * s;
-  const double per_step = blk * (sizeof(c128) + (z32 ? sizeof(c64) : sizeof(c128)));
-  const int mcap = (int)std::floor((0.8 * (double)fr - 4.0 * blk * sizeof(c128)) / per_step);
-  HZ_REQUIRE(mcap >= 1, HZ_ERR_OOM, "fgmres: not enough device memory for one Krylov step");
-  if (fixed > 0) HZ_REQUIRE(mcap >= fixed, HZ_ERR_OOM, "fgmres: fixed_iters exceeds memory");
-  return std::min(m, mcap);
+  const double avail = 0.8 * (double)fr;
+  const int floor_m = fixed > 0 ? m : std::min(m, kMinRestart);
+  for (int k = m; k >= floor_m; --k)
+    if ((double)(bytes_needed(n, s, k, z32) + extra) <= avail) return k;
+  return 0;
 }
 
 FgmresJob::FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c128* X_, const SolveOptions& o_, int m_)
@@ -271,6 +270,14 @@ bool FgmresJob::cycle_done() {
   return end;
 }
 
+void FgmresJob::trace_step() const {
+  // est[] refers to the latest completed Hessenberg column (one step late in the delayed form)
+  double mx = 0;
+  for (int c = 0; c < s; ++c) mx = std::max(mx, est[c] / bnorm[c]);
+  std::fprintf(stderr, "hz: step  n=%lld s=%d m=%d cycle-step=%d completed=%d est max rel residual %.3e%s\n",
+               (long long)n, s, m, jj, total, mx, (hflags[0] || hflags[1]) ? " (breakdown)" : "");
+}
+
 bool FgmresJob::end_cycle() {
   hipStream_t st = ctx->stream;
   const c128 one = cmk(1.0, 0.0), mone = cmk(-1.0, 0.0);
@@ -299,8 +306,16 @@ bool FgmresJob::end_cycle() {
     // the new residual block is numerically rank deficient: no further cycle can start, and
     // the columns are reported as they stand
   }
+  if (ctx->trace) {
+    double mx = 0;
+    for (int c = 0; c < s; ++c) mx = std::max(mx, rel[c]);
+    std::fprintf(stderr, "hz: cycle end  n=%lld s=%d m=%d iters=%d restarts=%d explicit max rel residual %.3e\n",
+                 (long long)n, s, m, total, restarts, mx);
+  }
   info.assign(s, ColInfo{});
   for (int c = 0; c < s; ++c) {
+    info[c].m = m;
+    info[c].block = s;
     info[c].iters = total;
     info[c].restarts = restarts;
     info[c].rel_residual = rel[c];
@@ -309,9 +324,8 @@ bool FgmresJob::end_cycle() {
   return true;
 }
 
-void fgmres(Ctx* ctx, std::shared_ptr<Ddm> d, int s, const c128* B, c128* X, const SolveOptions& o,
+void fgmres(Ctx* ctx, std::shared_ptr<Ddm> d, int s, const c128* B, c128* X, const SolveOptions& o, int m,
             std::vector<ColInfo>& info) {
-  const int m = FgmresJob::restart_for(ctx, d->op->mesh->n, s, o.restart, o.fixed_iters, d->precision == HZ_PREC_MIXED);
   FgmresJob job(ctx, d, s, B, X, o, m);
   job.start();
   // each cycle completes at least one column with at most one step more than it completes
@@ -321,7 +335,9 @@ void fgmres(Ctx* ctx, std::shared_ptr<Ddm> d, int s, const c128* B, c128* X, con
     job.matvec();
     job.after_matvec();
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
-    if (job.cycle_done() && job.end_cycle()) break;
+    const bool cyc = job.cycle_done();
+    if (ctx->trace) job.trace_step();
+    if (cyc && job.end_cycle()) break;
   }
   info = job.info;
 }

@@ -229,6 +229,7 @@ struct Ctx {
   struct Serve* serve = nullptr;
   std::atomic<bool> serving{false};  // a scheduler thread owns the stream: only hz_serve_* calls
   struct Prof* prof = nullptr;  // live kernel accounting (hz_profile_*)
+  bool trace = false;           // HZ_TRACE=1 at hz_init: per-step solver lines on stderr
 };
 
 // reference element tables (host), see p3ref.cpp

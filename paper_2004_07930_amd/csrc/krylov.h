@@ -57,6 +57,7 @@ struct SolveOptions {
 struct ColInfo {
   int iters = 0, restarts = 0, status = 0;
   double rel_residual = 0;
+  int m = 0, block = 0;  // restart length and Arnoldi block width the column ran with
 };
 
 // One block FGMRES(m) solve as a resumable state machine.  Driver protocol:
@@ -101,7 +102,10 @@ struct FgmresJob {
   FgmresJob& operator=(const FgmresJob&) = delete;
   static int64_t bytes_needed(int64_t n, int s, int m, bool z32);
   static bool delayed(int s) { return s == 16 || s == 32; }
-  static int restart_for(Ctx* ctx, int64_t n, int s, int want, int fixed, bool z32);
+  // largest restart length <= want (>= fixed) whose Krylov memory for an s-column block, plus
+  // `extra` bytes, fits in 80% of the free device memory; 0 if not even kMinRestart (or fixed) fits
+  static int restart_fit(Ctx* ctx, int64_t n, int s, int want, int fixed, bool z32, int64_t extra = 0);
+  static constexpr int kMinRestart = 8;
   void start();                 // norms of B (synchronises), X = 0, first cycle
   c128* v_cur();                // block to precondition this step
   c128* z_cur();                // where M^{-1} v goes (kept for the update of X); FP64 jobs
@@ -112,6 +116,7 @@ struct FgmresJob {
   void after_matvec();          // orthogonalisation, least-squares step; estimates copied to host (async)
   bool cycle_done();            // after a synchronisation: end of this cycle?
   bool end_cycle();             // X update and explicit residual (synchronises); true when finished
+  void trace_step() const;      // one stderr line: step, completed columns, largest estimate
   void spmm(const c128* x, c128* y, c128 alpha, c128 beta, const c128* yin);
 
  private:
@@ -120,9 +125,10 @@ struct FgmresJob {
   c128* h_col(int j);  // Hessenberg column buffer of step j (two alternate with delayed reorthogonalisation)
 };
 
-// Solve A X = B for a node-major block B [n][s] (device, c128).  X (device) receives the
-// solution.  Returns per-column info; status HZ_ERR_NOT_CONVERGED if max_iter is hit.
-void fgmres(Ctx* ctx, std::shared_ptr<Ddm> d, int s, const c128* B, c128* X, const SolveOptions& o,
+// Solve A X = B for a node-major block B [n][s] (device, c128) with restart length m.  X
+// (device) receives the solution.  Returns per-column info; status HZ_ERR_NOT_CONVERGED if
+// max_iter is hit.
+void fgmres(Ctx* ctx, std::shared_ptr<Ddm> d, int s, const c128* B, c128* X, const SolveOptions& o, int m,
             std::vector<ColInfo>& info);
 
 }  // namespace hz

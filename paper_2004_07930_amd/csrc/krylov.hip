@@ -878,32 +878,23 @@ __global__ __launch_bounds__(256) void k_lsq_step(int s, int jj, c128* __restric
 }
 
 // Y = Rm[0:J, 0:J]^{-1} G[0:J]: back substitution by blocks of 16 rows, one workgroup of NT
-// threads.  Every thread keeps its PER entries of Y in registers for the whole solve (J s <= NT
-// PER entries).  Per block: the block's rows go to LDS, one thread per column solves the 16 x 16
-// triangle there, and every entry above is updated by the solved block.  The order of operations per entry is fixed.  Rm is
-// column-major with leading dimension ldr; G and Y are [J][s].
-template <int NT, int PER>
+// threads, Y kept in global memory (any J s).  Per block: the block's rows go to LDS, one
+// thread per column solves the 16 x 16 triangle there, and every entry above is updated by the
+// solved block.  The order of operations per entry is fixed.  Rm is column-major with leading
+// dimension ldr; G and Y are [J][s] (Y may not alias G).
+template <int NT>
 __global__ __launch_bounds__(NT) void k_lsq_solve(int s, int J, const c128* __restrict__ Rm, int64_t ldr,
                                                   const c128* __restrict__ G, c128* __restrict__ Y) {
-  constexpr int kLsqThreads = NT, kLsqPer = PER;
   constexpr int B = 16;
   __shared__ c128 Yb[B][32];
   __shared__ c128 Rb[B][B];
   const int tot = J * s;
-  c128 y[kLsqPer];
-#pragma unroll
-  for (int u = 0; u < kLsqPer; ++u) {
-    const int e = threadIdx.x + kLsqThreads * u;
-    y[u] = e < tot ? G[e] : cmk(0.0, 0.0);
-  }
+  for (int e = threadIdx.x; e < tot; e += NT) Y[e] = G[e];
+  __syncthreads();
   for (int i0 = ((J - 1) / B) * B; i0 >= 0; i0 -= B) {
     const int nb = min(B, J - i0);
-#pragma unroll
-    for (int u = 0; u < kLsqPer; ++u) {
-      const int e = threadIdx.x + kLsqThreads * u, r = e / s;
-      if (e < tot && r >= i0 && r < i0 + nb) Yb[r - i0][e - r * s] = y[u];
-    }
-    for (int e = threadIdx.x; e < nb * nb; e += kLsqThreads) Rb[e % nb][e / nb] = Rm[(int64_t)(i0 + e / nb) * ldr + i0 + e % nb];
+    for (int e = threadIdx.x; e < B * s; e += NT) Yb[e / s][e % s] = e < nb * s ? Y[(int64_t)i0 * s + e] : cmk(0.0, 0.0);
+    for (int e = threadIdx.x; e < nb * nb; e += NT) Rb[e % nb][e / nb] = Rm[(int64_t)(i0 + e / nb) * ldr + i0 + e % nb];
     __syncthreads();
     if (threadIdx.x < s) {  // the block's columns are independent: one thread per column
       const int c = threadIdx.x;
@@ -914,29 +905,22 @@ __global__ __launch_bounds__(NT) void k_lsq_solve(int s, int J, const c128* __re
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kLsqPer; ++u) {
-      const int e = threadIdx.x + kLsqThreads * u, r = e / s, c = e - (e / s) * s;
-      if (e >= tot || r >= i0 + nb) continue;
-      if (r >= i0) {
-        y[u] = Yb[r - i0][c];
-      } else {
+    for (int e = threadIdx.x; e < nb * s; e += NT) Y[(int64_t)i0 * s + e] = Yb[e / s][e % s];
+    // rows above the block: y_r -= sum_k R[r][i0 + k] y_{i0 + k}, k ascending
+    for (int e = threadIdx.x; e < i0 * s; e += NT) {
+      const int r = e / s, c = e - r * s;
+      c128 y = Y[e];
 #pragma unroll 1
-        for (int k0 = 0; k0 < B; k0 += 4) {
-          c128 rv[4];
+      for (int k0 = 0; k0 < B; k0 += 4) {
+        c128 rv[4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) rv[k] = k0 + k < nb ? Rm[(int64_t)(i0 + k0 + k) * ldr + r] : cmk(0.0, 0.0);
+        for (int k = 0; k < 4; ++k) rv[k] = k0 + k < nb ? Rm[(int64_t)(i0 + k0 + k) * ldr + r] : cmk(0.0, 0.0);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) cfms(y[u], rv[k], Yb[k0 + k][c]);
-        }
+        for (int k = 0; k < 4; ++k) cfms(y, rv[k], Yb[k0 + k][c]);
       }
+      Y[e] = y;
     }
     __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < kLsqPer; ++u) {
-    const int e = threadIdx.x + kLsqThreads * u;
-    if (e < tot) Y[e] = y[u];
   }
 }
 
@@ -1196,13 +1180,7 @@ void KrylovKernels::lsq_step(int jj, c128* Hc, c128* Rm, int64_t ldr, c128* refl
 }
 
 void KrylovKernels::lsq_solve(int J, const c128* Rm, int64_t ldr, const c128* G, c128* Y) {
-  const int64_t ent = (int64_t)J * s;
-  if (ent <= 1024 * 10)  // s = 16 up to restart 40
-    hipLaunchKernelGGL((k_lsq_solve<1024, 10>), dim3(1), dim3(1024), 0, ctx->stream, s, J, Rm, ldr, G, Y);
-  else if (ent <= 1024 * 40)  // s = 32 up to restart 40 (register spills: rare and short)
-    hipLaunchKernelGGL((k_lsq_solve<1024, 40>), dim3(1), dim3(1024), 0, ctx->stream, s, J, Rm, ldr, G, Y);
-  else
-    fail(HZ_ERR_ARG, "least squares: restart length times block size squared exceeds 40960");
+  hipLaunchKernelGGL((k_lsq_solve<1024>), dim3(1), dim3(1024), 0, ctx->stream, s, J, Rm, ldr, G, Y);
   HIP_CHECK(hipGetLastError());
 }
 

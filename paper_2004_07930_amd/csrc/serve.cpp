@@ -155,6 +155,8 @@ static void finish_ticket(Serve& S, Ticket& t) {
         hi.restarts = ci.restarts;
         hi.rel_residual = ci.rel_residual;
         hi.status = ci.status;
+        hi.restart_len = ci.m;
+        hi.block = ci.block;
       }
       if (ci.status != HZ_OK) st = HZ_ERR_NOT_CONVERGED;
     }

@@ -58,7 +58,13 @@ class CoarseMesh(C.Structure):
 
 
 class ColInfo(C.Structure):
-    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("rel_residual", C.c_double), ("status", C.c_int32)]
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("rel_residual", C.c_double), ("status", C.c_int32),
+                ("restart_len", C.c_int32), ("block", C.c_int32)]
+
+
+def _info_dicts(arr):
+    return [dict(iters=i.iters, restarts=i.restarts, rel_residual=i.rel_residual, status=i.status,
+                 restart_len=i.restart_len, block=i.block) for i in arr]
 
 
 class SolveOpts(C.Structure):
@@ -233,6 +239,7 @@ class Context:
     def __init__(self, device=0, stream=None, hbm_budget=0, allocator="torch"):
         self.lib = load()
         self.h = None
+        self._alloc_cbs = None
         o = InitOpts()
         o.struct_size, o.device, o.hbm_budget = C.sizeof(InitOpts), device, hbm_budget
         if stream is not None:
@@ -296,8 +303,15 @@ class Context:
             keep += [ct, cc]
             cm = CoarseMesh(ct.shape[0], ct.ctypes.data, cc.shape[0], cc.ctypes.data)
         h = C.c_uint64()
-        self._check(self.lib.hz_setup_ddm(self.h, op.handle, _np_ptr(p), int(n_sub), int(overlap),
-                                          None if cm is None else C.byref(cm), int(precision), C.byref(h)))
+        st = self.lib.hz_setup_ddm(self.h, op.handle, _np_ptr(p), int(n_sub), int(overlap),
+                                   None if cm is None else C.byref(cm), int(precision), C.byref(h))
+        if self._alloc_cbs is not None:
+            # the factorisation's transient buffers went back to torch's cache: hand them back to
+            # the device, where the library's free-memory queries (Krylov sizing) see them
+            import torch
+
+            torch.cuda.empty_cache()
+        self._check(st)
         return Ddm(self, h.value, op, precision)
 
     # ---------------------------------------------------------------- compute
@@ -318,8 +332,7 @@ class Context:
         o = SolveOpts(C.sizeof(SolveOpts), float(tol), int(max_iter), int(restart), int(fixed_iters), int(block))
         st = self.lib.hz_solve_ex(self.h, ddm.handle, s, rp, rm, C.byref(o), xp, xm, info)
         self._check(st, allow=() if raise_on_not_converged else (HZ_ERR_NOT_CONVERGED,))
-        return out, [dict(iters=i.iters, restarts=i.restarts, rel_residual=i.rel_residual, status=i.status)
-                     for i in info]
+        return out, _info_dicts(info)
 
     def point_sources(self, mesh, xyz, amp=None, out=None):
         x = np.ascontiguousarray(xyz, np.float64).reshape(-1, 3)
@@ -403,9 +416,7 @@ class Context:
     def wait(self, ticket):
         st = C.c_int32()
         self._check(self.lib.hz_serve_wait(self.h, ticket["id"], C.byref(st)))
-        info = [dict(iters=i.iters, restarts=i.restarts, rel_residual=i.rel_residual, status=i.status)
-                for i in ticket["info"]]
-        return ticket["out"], info, st.value
+        return ticket["out"], _info_dicts(ticket["info"]), st.value
 
     def serve_stats(self):
         s = ServeStats()

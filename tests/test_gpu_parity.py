@@ -251,6 +251,31 @@ def test_fgmres_fixed_iterations_wide_block(ctx):
     ctx.release(d)
 
 
+def test_fgmres_long_restart_wide_block(ctx):
+    """A 32-column block at restart 48, run for 42 steps: the least-squares problem (43 x 42
+    blocks of 32, 43,008 entries of Y) is past the 40,960 entries a register-resident back
+    substitution could hold, and the restart length is used as asked (no shortening): FP64
+    parity 1e-10 with the oracle at the same step count, reported m and block width (the block
+    reaches residuals near 1e-10 by then)."""
+    p = w.unit_cube_problem(6, freq=8.0, parts=(2, 2, 2), overlap=0)
+    om = fem.Mesh(p.tets, p.coords, p.face_bc)
+    A = fem.assemble_operator(om, p.velocity, p.freq, p.quality)
+    gm = ctx.mesh(p.tets, p.coords, p.face_bc)
+    gop = ctx.assemble(gm, p.velocity, p.freq, p.quality)
+    d = ctx.setup_ddm(gop, p.partition, p.n_sub, p.overlap)
+    subs, own = odd.build_subdomains(om, p.velocity, p.freq, p.quality, p.partition, p.n_sub, p.overlap)
+    odd.factor_subdomains(subs)
+    P = odd.ORAS(A, subs)
+    B = w.seeded_rhs_block(om.n, 32, 22)
+    X, info = ctx.solve(d, B, fixed_iters=42, restart=48, block=32)
+    assert all(i["restart_len"] == 48 and i["block"] == 32 and i["iters"] == 42 for i in info)
+    Xo, io = krylov.block_fgmres(lambda x: A @ x, B.T, P.apply, fixed_iters=42, m=48)
+    assert _rel(X, Xo.T) <= 1e-10, _rel(X, Xo.T)
+    # residuals near 1e-10 after 42 steps: equal to rounding (absolute floor 1e-14)
+    np.testing.assert_allclose([i["rel_residual"] for i in info], io["rel_residual"], rtol=1e-3, atol=1e-14)
+    ctx.release(d)
+
+
 def test_solve_to_tolerance_matches_direct(ctx):
     """cube 4, 8 subdomains: ORAS-FGMRES to 1e-12 equals the dense direct solve to 1e-9."""
     p = w.unit_cube_problem(4, freq=1.0, parts=(2, 2, 2), overlap=1)

@@ -3,12 +3,15 @@
 Requests of different sizes and on two different operators are submitted together; the
 scheduler packs their preconditioner and SpMM products into shared launches while each
 keeps its own Arnoldi process.  Each result must match the same request solved alone
-(hz_solve) within the stated tolerance, reach its residual, and the statistics must
-account for every request."""
+(hz_solve) within the stated tolerance and the oracle's direct solution (SuperLU on the
+oracle's operator) within 1e-5, reach its residual recomputed with the oracle's operator,
+and the statistics must account for every request."""
 import numpy as np
 import pytest
+import scipy.sparse.linalg as spla
 
 import workloads as w
+from oracle import fem
 
 pytestmark = pytest.mark.gpu
 
@@ -31,9 +34,23 @@ def setup():
         d = ctx.setup_ddm(op, p.partition, p.n_sub, p.overlap, coarse=(p.coarse_tets, p.coarse_coords),
                           precision=hz.HZ_PREC_MIXED)
         F = ctx.point_sources(mesh, p.sources)
-        ops.append((p, d, F))
+        A = fem.assemble_operator(fem.Mesh(p.tets, p.coords, p.face_bc), p.velocity, p.freq)
+        ops.append((p, d, F, A, spla.splu(A.tocsc())))
     yield ctx, ops
     ctx.close()
+
+
+def _check_against_oracle(A, lu, B, X, info):
+    """Residual of every column recomputed with the oracle's operator (equal to the reported
+    one) and the error against the direct solution."""
+    B, X = np.asarray(B), np.asarray(X)
+    res = np.linalg.norm(B.T - A @ X.T, axis=0) / np.linalg.norm(B.T, axis=0)
+    np.testing.assert_allclose(res, [i["rel_residual"] for i in info], rtol=1e-4)
+    assert res.max() <= 1.0001e-6, res.max()
+    Xd = lu.solve(B.T).T
+    err = max(_rel(X[c], Xd[c]) for c in range(B.shape[0]))
+    assert err <= 1e-5, err
+    return err
 
 
 def test_serve_results_same_alone_and_in_mix(setup):
@@ -43,27 +60,29 @@ def test_serve_results_same_alone_and_in_mix(setup):
     rng = np.random.default_rng(4)
     reqs = []
     for k, ns in enumerate([1, 4, 2, 9, 3, 5]):
-        p, d, F = ops[k % 2]
+        p, d, F, A, lu = ops[k % 2]
         cols = rng.choice(F.shape[0], size=ns, replace=ns > F.shape[0])
         B = F[cols] + 0.1 * (rng.standard_normal((ns, F.shape[1])) + 1j * rng.standard_normal((ns, F.shape[1])))
-        reqs.append((d, B))
-    alone = [ctx.solve(d, B, tol=1e-6)[0] for d, B in reqs]
+        reqs.append((d, B, A, lu))
+    alone = [ctx.solve(d, B, tol=1e-6)[0] for d, B, _, _ in reqs]
     ctx.serve_start(max_slots=8)
     try:
         # host and device requests mixed
         tickets = []
-        for k, (d, B) in enumerate(reqs):
+        for k, (d, B, _, _) in enumerate(reqs):
             rhs = torch.from_numpy(B).cuda() if k % 2 else B
             tickets.append(ctx.submit(d, rhs, tol=1e-6))
         outs = [ctx.wait(t) for t in tickets]
         st = ctx.serve_stats()
     finally:
         ctx.serve_stop()
-    for (d, B), x1, (x2, info, status) in zip(reqs, alone, outs):
+    for (d, B, A, lu), x1, (x2, info, status) in zip(reqs, alone, outs):
         x2 = x2.cpu().numpy() if hasattr(x2, "cpu") else x2
         assert status == 0
         assert all(i["rel_residual"] <= 1e-6 for i in info)
         assert _rel(x2, x1) <= 1e-5, _rel(x2, x1)
+        err = _check_against_oracle(A, lu, B, x2, info)
+        print(f"served request of {B.shape[0]} sources: worst column error vs the direct solution {err:.2e}")
     assert st["completed"] == len(reqs)
     assert 0 < st["p50_s"] <= st["p99_s"]
     assert st["sources_per_s"] > 0
@@ -74,7 +93,7 @@ def test_serve_packing_past_32_columns(setup):
     fit decreasing into launches of at most 32 columns (20 + 12 together, 9 in a launch of
     its own, regrouped as parts finish); each result matches its request solved alone."""
     ctx, ops = setup
-    p, d, F = ops[0]
+    p, d, F, A, lu = ops[0]
     rng = np.random.default_rng(9)
     reqs = []
     for ns in (20, 9, 12):
@@ -87,10 +106,11 @@ def test_serve_packing_past_32_columns(setup):
         outs = [ctx.wait(t) for t in tickets]
     finally:
         ctx.serve_stop()
-    for x1, (x2, info, status) in zip(alone, outs):
+    for B, x1, (x2, info, status) in zip(reqs, alone, outs):
         assert status == 0
         assert all(i["rel_residual"] <= 1e-6 for i in info)
         assert _rel(x2, x1) <= 1e-5, _rel(x2, x1)
+        _check_against_oracle(A, lu, B, x2, info)
 
 
 def test_serve_admission_refuses_impossible_request():
@@ -122,7 +142,7 @@ def test_serve_parts_admitted_one_at_a_time(setup):
     second admitted when the first has finished and released its Krylov memory); a request
     behind it waits its turn.  Results match hz_solve, which splits the same blocks of 32."""
     ctx, ops = setup
-    p, d, F = ops[0]
+    p, d, F, A, lu = ops[0]
     rng = np.random.default_rng(9)
     noise = rng.standard_normal((40, F.shape[1])) + 1j * rng.standard_normal((40, F.shape[1]))
     B1 = F[rng.integers(0, F.shape[0], 40)] + 0.1 * noise  # full column rank
@@ -141,6 +161,8 @@ def test_serve_parts_admitted_one_at_a_time(setup):
     assert s1 == 0 and s2 == 0
     assert all(i["rel_residual"] <= 1e-6 for i in info1 + info2)
     assert _rel(x1, alone1) <= 1e-5 and _rel(x2, alone2) <= 1e-5
+    _check_against_oracle(A, lu, B1, x1, info1)
+    _check_against_oracle(A, lu, B2, x2, info2)
     assert st["completed"] == 2 and st["rejected"] == 0
 
 
@@ -150,7 +172,7 @@ def test_serve_dependent_block_fails_alone(setup):
     from paper_2004_07930_amd import hz
 
     ctx, ops = setup
-    p, d, F = ops[1]
+    p, d, F, A, lu = ops[1]
     bad = np.stack([F[0], F[1], 3.0 * F[0]])
     good = F[2:5]
     alone = ctx.solve(d, good, tol=1e-6)[0]
@@ -166,4 +188,5 @@ def test_serve_dependent_block_fails_alone(setup):
     assert sb == hz.HZ_ERR_ARG
     assert sg == 0 and all(i["rel_residual"] <= 1e-6 for i in info)
     assert _rel(xg, alone) <= 1e-5
+    _check_against_oracle(A, lu, good, xg, info)
     assert st["completed"] == 1 and st["rejected"] == 1
