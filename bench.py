@@ -1,22 +1,31 @@
 """Benchmark: sources solved per second at a 1e-6 relative residual, mixed vs FP64.
 
-Workload (default): the layered synthetic stand-in for the Overthrust box of the paper --
-20 x 20 x 4.65 km, v(z) = 2200 + 3800 z / 4.65 m/s with 12 seeded Gaussian anomalies and
-3 dipping step layers, 2.5 Hz, graded Kuhn tets (72 x 72 x 12 cubes, 1,742,293 P3 dofs),
-free surface on top and absorbing elsewhere, 64 subdomains (8 x 8 columns) with overlap 2,
-P1 coarse space on a 4x coarser grid, 16 point sources on a 4 x 4 grid at 500 m depth.
+Workload (default, the configuration the metric is quoted on): the layered synthetic stand-in
+for the Overthrust box of the paper -- 20 x 20 x 4.65 km, v(z) = 2200 + 3800 z / 4.65 m/s with
+12 seeded Gaussian anomalies and 3 dipping step layers -- at 5 Hz on graded Kuhn tets
+(144 x 144 x 20 cubes, 11,436,829 P3 dofs), free surface on top and absorbing elsewhere,
+256 subdomains of uneven size (8 x 8 x 4 boxes cut at equal depth, so the finely graded top
+boxes hold about 2.7x the tets of the bottom ones), overlap 1, one-level ORAS, 128 point
+sources on a 16 x 8 grid at 500 m depth.  The P1 coarse space on the 4x coarser grid (0.7
+vertices per minimum wavelength at 5 Hz) makes the iteration stagnate there, so this workload
+runs without it; the 2.5 Hz workload keeps it (--workload layered-2.5hz).
 
-A step is one hz_solve of the 16-source block to 1e-6 with the operator and factors
-resident in HBM (set-up is timed separately).  The headline value uses the mixed
-precision preconditioner (complex64 factors, ORAS and coarse solve inside FP64 FGMRES);
-the FP64 solve is timed the same way and reported beside it.
+A step is one 16-source sub-block of the 128 sources (steps cycle over the 8 sub-blocks):
+its point-source loads are formed on the GPU and it is solved to 1e-6 with the operator and
+the factors resident in HBM (set-up is timed separately).  The headline value uses the mixed
+precision preconditioner (complex64 factors and ORAS inside FP64 FGMRES); the FP64 solve
+(complex128 factors) of the same sub-blocks is timed beside it on --fp64-steps steps, and the
+relative difference of the two solutions of the first sub-block is stated.
 
-The roofline object is computed live: the library brackets every launch of its main
-kernel classes with HIP events on the solve stream during the timed steps and sums each
-launch's algorithmic bytes (hz_profile_*); the class with the largest time is reported.
+The roofline object is computed live: the library brackets every launch of its main kernel
+classes with HIP events on the solve stream during the timed steps and sums each launch's
+algorithmic bytes (hz_profile_*); the class with the largest time is reported, with the
+achieved rate under two byte counts (the survey's: factor read once plus two right-hand-side
+passes over the pivot rows; the kernels' own, which adds the multifrontal update rows).
 
-The CPU baseline times the oracle (NumPy / SciPy, one thread) on a bounded sample of the
-same workload -- one overlapped subdomain -- and scales it to sources per second.
+The CPU baseline times the oracle (NumPy / SciPy) on a bounded sample of the same workload --
+one overlapped subdomain factored and solved by each of P worker processes at once -- and
+extrapolates it to sources per second.
 
 Prints ONE JSON line.  More than one GPU is not supported.
 """
@@ -25,6 +34,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -36,22 +46,39 @@ sys.path.insert(0, ROOT)
 METRIC = "sources solved/s at 1e-6 rel. residual, mixed vs FP64; p50/p99 solve latency"
 HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
 
+# per workload: problem, whether the P1 coarse space is used, solver block / restart, sources per step
+WORKLOADS = {
+    "layered-5hz": dict(
+        problem=dict(freq=5.0, r=1.4, parts=(8, 8, 4), overlap=1, n_sources=(16, 8), src_depth=0.5,
+                     equal_depth_zcuts=True),
+        coarse=False, block=16, restart=24, step_sources=16,
+        desc="layered 20x20x4.65 km, 5 Hz, Kuhn P3 %dx%dx%d cubes, 256 subdomains (8x8x4 boxes cut at equal "
+             "depth, uneven), overlap 1, one-level ORAS, 128 point sources at 0.5 km in 16-source steps, tol 1e-6"),
+    "layered-2.5hz": dict(
+        problem=dict(freq=2.5, r=1.4, parts=(8, 8, 1), overlap=2, n_sources=(4, 4), src_depth=0.5),
+        coarse=True, block=16, restart=40, step_sources=16,
+        desc="layered 20x20x4.65 km, 2.5 Hz, Kuhn P3 %dx%dx%d cubes, 64 subdomains, overlap 2, "
+             "P1 coarse (4x coarser), 16 point sources at 0.5 km, tol 1e-6"),
+    "layered-1hz": dict(
+        problem=dict(freq=1.0, r=1.4, parts=(4, 4, 1), overlap=2, n_sources=(4, 4), src_depth=0.5),
+        coarse=True, block=16, restart=40, step_sources=16,
+        desc="layered 20x20x4.65 km, 1 Hz, %dx%dx%d cubes, 16 subdomains, overlap 2, P1 coarse, 16 sources"),
+}
+
 
 def build_workload(name):
     import workloads as w
 
-    if name == "layered-2.5hz":
-        p = w.layered_problem(freq=2.5, r=1.4, parts=(8, 8, 1), overlap=2, n_sources=(4, 4), src_depth=0.5)
-        desc = ("layered 20x20x4.65 km, 2.5 Hz, Kuhn P3 %dx%dx%d cubes, 64 subdomains, overlap 2, "
-                "P1 coarse (4x coarser), 16 point sources at 0.5 km, tol 1e-6" % p.grid)
-        return p, desc
     if name == "cube8":
         p = w.unit_cube_problem(8)
-        return p, "unit cube 8^3 x 6 tets, k = 8 pi, impedance, 8 subdomains, overlap 1, tol 1e-8"
-    if name == "layered-1hz":
-        p = w.layered_problem(freq=1.0, r=1.4, parts=(4, 4, 1), overlap=2, n_sources=(4, 4), src_depth=0.5)
-        return p, "layered 20x20x4.65 km, 1 Hz, %dx%dx%d cubes, 16 subdomains, overlap 2, P1 coarse" % p.grid
-    raise SystemExit(f"unknown workload {name}")
+        return p, dict(coarse=False, block=0, restart=40, step_sources=1,
+                       desc="unit cube 8^3 x 6 tets, k = 8 pi, impedance, 8 subdomains, overlap 1, tol 1e-8")
+    if name not in WORKLOADS:
+        raise SystemExit(f"unknown workload {name}")
+    spec = dict(WORKLOADS[name])
+    p = w.layered_problem(**spec["problem"])
+    spec["desc"] = spec["desc"] % p.grid
+    return p, spec
 
 
 def counter_traffic(kernel_class, workload):
@@ -72,60 +99,107 @@ def counter_traffic(kernel_class, workload):
     return rec["traffic_bytes_per_launch"] / 1e9  # GB per launch, same unit basis as "achieved"
 
 
-def cpu_baseline(p, n_global, iters, s):
-    """Oracle on one overlapped subdomain of the workload, scaled to sources/s.
-
-    The sample is the corner column of the partition with its overlap (the tets of
-    11 x 11 cubes over the full depth) as a standalone mesh: assembly, SuperLU factor,
-    one s-RHS local solve, one local SpMM and one CGS pass against 20 s-blocks.  A full
-    oracle iteration is then n_sub local solves plus (n / n_i) times the local SpMM and
-    four CGS passes; a source block needs `iters` iterations (the GPU's count for the
-    same algorithm)."""
-    import scipy.sparse.linalg as spla
+def _oracle_subdomain_sample(args):
+    """One worker of the CPU baseline: the tets of one overlapped box of the partition (the box
+    grown by `overlap` cubes) as a standalone mesh, assembled by the oracle, factored by SuperLU
+    and solved for s right-hand sides, single-threaded.  Returns (dofs, factor s, solve s)."""
+    tets, coords, vel, freq, s = args
     from threadpoolctl import threadpool_limits
+    import scipy.sparse.linalg as spla
 
     import workloads as w
     from oracle import fem
 
-    nx, ny, nz = p.grid
-    ex = p.overlap + (nx // int(round(np.sqrt(p.n_sub))))
-    cubes = np.arange(p.tets.shape[0]) // 6
-    ci, cj = cubes % nx, (cubes // nx) % ny
-    sel = np.nonzero((ci < ex) & (cj < ex))[0]
-    used, inv = np.unique(p.tets[sel].ravel(), return_inverse=True)
-    lt = inv.reshape(-1, 4).astype(np.int32)
-    lc = p.coords[used]
-    t0 = time.perf_counter()
     with threadpool_limits(1):
-        m = fem.Mesh(lt, lc, w.face_bc_tags(lt, lc, dirichlet_top=True))
-        A = fem.assemble_operator(m, p.velocity[sel], p.freq, None if p.quality is None else p.quality[sel])
+        m = fem.Mesh(tets, coords, w.face_bc_tags(tets, coords, dirichlet_top=True))
+        A = fem.assemble_operator(m, vel, freq)
         t1 = time.perf_counter()
         lu = spla.splu(A.tocsc(), permc_spec="MMD_AT_PLUS_A")
         t2 = time.perf_counter()
         rng = np.random.default_rng(0)
-        B = rng.standard_normal((m.n, s)) + 1j * rng.standard_normal((m.n, s))
-        lu.solve(B)
+        lu.solve(rng.standard_normal((m.n, s)) + 1j * rng.standard_normal((m.n, s)))
         t3 = time.perf_counter()
-        A @ B
-        t4 = time.perf_counter()
+    return m.n, t2 - t1, t3 - t2
+
+
+def cpu_baseline_sample(p, s):
+    """Times the oracle on a bounded sample of the workload, before the GPU is touched (the
+    sample forks worker processes).  P = min(16, CPUs) workers each factor and solve one of the
+    smallest overlapped subdomains (the boxes of the deepest layer) at the same time; the global
+    SpMM and one CGS pass are timed on a slice of the mesh and scaled to its size.  Returns the
+    per-iteration and set-up estimates; sources/s follow once the GPU's iteration count is
+    known (cpu_baseline_result).  The smallest subdomains make this an upper bound on the
+    oracle's speed."""
+    import multiprocessing as mp
+    import platform
+
+    import scipy.sparse as sp
+
+    import workloads as w
+    from oracle import fem
+
+    t0 = time.perf_counter()
+    cores = max(1, min(16, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1))
+    nx, ny, nz = p.grid
+    px, py, pz = p.extra.get("parts", (1, 1, 1))
+    cubes = np.arange(p.tets.shape[0]) // 6
+    ci, cj, ck = cubes % nx, (cubes // nx) % ny, cubes // (nx * ny)
+    part_cube = p.partition[::6]
+    # deepest boxes first (smallest: the bottom layers are the thickest cells)
+    boxes = sorted(range(p.n_sub), key=lambda i: (-(i // (px * py)), i))[:cores]
+    jobs = []
+    for i in boxes:
+        mine = np.nonzero(part_cube == i)[0]
+        lo = np.array([ci[6 * mine].min(), cj[6 * mine].min(), ck[6 * mine].min()]) - p.overlap
+        hi = np.array([ci[6 * mine].max(), cj[6 * mine].max(), ck[6 * mine].max()]) + p.overlap
+        sel = np.nonzero((ci >= lo[0]) & (ci <= hi[0]) & (cj >= lo[1]) & (cj <= hi[1]) & (ck >= lo[2]) & (ck <= hi[2]))[0]
+        used, inv = np.unique(p.tets[sel].ravel(), return_inverse=True)
+        jobs.append((inv.reshape(-1, 4).astype(np.int32), p.coords[used], p.velocity[sel], p.freq, s))
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_subdomain_sample, jobs)
+    t_par = time.perf_counter() - t0
+    # global SpMM and one CGS pass (20 blocks) on a slice of full-depth columns, scaled by dofs
+    from threadpoolctl import threadpool_limits
+
+    with threadpool_limits(cores):
+        sel = np.nonzero(ci < max(2, nx // 32))[0]
+        used, inv = np.unique(p.tets[sel].ravel(), return_inverse=True)
+        m = fem.Mesh(inv.reshape(-1, 4).astype(np.int32), p.coords[used])
+        A = fem.assemble_operator(m, p.velocity[sel], p.freq)
+        rng = np.random.default_rng(1)
+        B = rng.standard_normal((m.n, s)) + 1j * rng.standard_normal((m.n, s))
         V = rng.standard_normal((m.n, 20 * s)) + 0j
+        ta = time.perf_counter()
+        A @ B
+        tb = time.perf_counter()
         H = V.conj().T @ B
         B - V @ H
-        t5 = time.perf_counter()
-    scale = n_global / m.n
-    t_iter = p.n_sub * (t3 - t2) + scale * ((t4 - t3) + 4 * (t5 - t4))
-    return {
-        "value": s / (iters * t_iter),
-        "unit": "sources/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"one overlapped subdomain ({m.n} dofs, {len(sel)} tets) of the same workload: SuperLU factor "
-                   f"{t2 - t1:.1f} s, {s}-RHS local solve {t3 - t2:.2f} s, SpMM {t4 - t3:.3f} s, CGS pass "
-                   f"{t5 - t4:.2f} s; extrapolated to {p.n_sub} subdomains x {iters} iterations "
-                   f"({t_iter:.1f} s per iteration); sample wall {time.perf_counter() - t0:.1f} s"),
-        "extrapolated": True,
-        "setup_s_extrapolated": p.n_sub * (t2 - t1),
-    }
+        tc = time.perf_counter()
+    scale = w.kuhn_ndofs(nx, ny, nz) / m.n
+    n_i = [r[0] for r in res]
+    t_fac = float(np.mean([r[1] for r in res]))
+    t_sol = float(np.mean([r[2] for r in res]))
+    rounds = -(-p.n_sub // cores)
+    t_iter = rounds * t_sol + scale * ((tb - ta) + 4 * (tc - tb))
+    try:
+        model = next((l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")), "")
+    except OSError:
+        model = platform.processor()
+    return dict(t_iter=t_iter, setup=rounds * t_fac, cores=cores, nproc=os.cpu_count(), cpu_model=model,
+                sample=(f"{cores} worker processes at once, each one overlapped subdomain of the deepest box layer "
+                        f"({min(n_i)}-{max(n_i)} dofs; the smallest of the {p.n_sub}): SuperLU factor {t_fac:.1f} s, "
+                        f"{s}-RHS solve {t_sol:.2f} s (means); SpMM {tb - ta:.3f} s and a CGS pass "
+                        f"{tc - tb:.2f} s on a {m.n}-dof slice scaled x{scale:.0f}; per iteration "
+                        f"{rounds} rounds of local solves over {p.n_sub} subdomains + scaled SpMM + 4 CGS passes "
+                        f"= {t_iter:.1f} s; sample wall {time.perf_counter() - t0:.1f} s (parallel part {t_par:.1f} s)"))
+
+
+def cpu_baseline_result(est, iters, s):
+    if est is None:
+        return None
+    return {"value": s / (iters * est["t_iter"]), "unit": "sources/s", "cores": est["cores"], "kind": "oracle",
+            "sample": est["sample"] + f"; x {iters} iterations (the GPU's count)", "extrapolated": True,
+            "setup_s_extrapolated": est["setup"], "nproc": est["nproc"], "cpu_model": est["cpu_model"]}
 
 
 SERVE_FREQS = (2.5, 3.5)
@@ -225,22 +299,33 @@ def run_serve(args):
         "iters": [max(i["iters"] for i in info) for _, info, _ in done]}))
 
 
+def _survey_ratio(levels, s, e):
+    """Per sweep direction, bytes of the survey's count (factor once + two passes over the pivot
+    rows of the right-hand side) over the kernels' own count (which also moves the update rows)."""
+    useful = sum(l["factor_useful"] for l in levels)
+    sp = sum(l["sum_pivots"] for l in levels)
+    sf = sum(l["sum_front"] for l in levels)
+    survey = e * (useful + 2.0 * sp * s)
+    return {"oras_fwd": survey / (e * (useful + 2.0 * sf * s)), "oras_bwd": survey / (e * (useful + (sf + sp) * s))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="layered-2.5hz",
-                    choices=["layered-2.5hz", "cube8", "layered-1hz"])
-    ap.add_argument("--restart", type=int, default=0)
-    ap.add_argument("--block", type=int, default=0)
-    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", default="layered-5hz", choices=list(WORKLOADS) + ["cube8"])
+    ap.add_argument("--restart", type=int, default=0, help="FGMRES restart length (0: the workload's)")
+    ap.add_argument("--block", type=int, default=-1, help="Arnoldi block width (-1: the workload's, 0: automatic)")
+    ap.add_argument("--fp64-steps", type=int, default=2, help="timed steps of the FP64 solve (0: skip it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for counter scaling)")
     ap.add_argument("--serve", type=int, default=0, metavar="N",
-                    help="instead: serve N requests on the 2.5 and 3.5 Hz operators (continuous batching)")
+                    help="instead: serve N requests on the 2.5, 3.5 and 5 Hz operators (continuous batching)")
+    ap.add_argument("--serve-fp64", action="store_true",
+                    help="with --serve: also solve the same stream one request at a time with plain FP64 hz_solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no collectives); use --gpus 1", file=sys.stderr)
@@ -249,13 +334,24 @@ def main():
         run_serve(args)
         return
 
-    import torch
-
-    from paper_2004_07930_amd import hz
-
     def log(*a):
         if args.verbose:
             print(*a, file=sys.stderr, flush=True)
+
+    t_all = time.perf_counter()
+    p, spec = build_workload(args.workload)
+    S = spec["step_sources"]
+    restart = args.restart or spec["restart"]
+    block = spec["block"] if args.block < 0 else args.block
+    # the CPU sample forks worker processes: it runs before anything touches the GPU
+    cpu_est = None
+    if not args.no_cpu_baseline and p.sources is not None:
+        cpu_est = cpu_baseline_sample(p, S)
+        log(f"cpu baseline sample: {cpu_est['sample']}")
+
+    import torch
+
+    from paper_2004_07930_amd import hz
 
     if args.copy_calibration:  # 1 GiB read + 1 GiB written by one copy kernel
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -263,7 +359,6 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    p, desc = build_workload(args.workload)
     stream = torch.cuda.current_stream()
     ctx = hz.Context(0, stream=stream)
     t0 = time.perf_counter()
@@ -272,32 +367,48 @@ def main():
     torch.cuda.synchronize()
     t_asm = time.perf_counter() - t0
     log(f"mesh+assembly {t_asm:.2f}s n={mesh.n}")
-    coarse = (p.coarse_tets, p.coarse_coords) if p.coarse_tets is not None else None
-    src = p.sources if p.sources is not None else np.array([[0.37, 0.52, 0.61]])  # unit cube: one interior source
-    B = ctx.point_sources(mesh, src, out=torch.empty((len(src), mesh.n), dtype=torch.complex128, device="cuda"))
-    s = B.shape[0]
-    X = torch.empty_like(B)
-    results = {}
-    precisions = [("mixed", hz.HZ_PREC_MIXED)] + ([] if args.no_fp64 else [("fp64", hz.HZ_PREC_C128)])
-    for label, prec in precisions:
+    coarse = (p.coarse_tets, p.coarse_coords) if spec["coarse"] and p.coarse_tets is not None else None
+    srcs = p.sources if p.sources is not None else np.array([[0.37, 0.52, 0.61]])  # unit cube: one interior source
+    blocks = [srcs[k:k + S] for k in range(0, len(srcs), S)]
+    Bb = torch.empty((len(blocks[0]), mesh.n), dtype=torch.complex128, device="cuda")
+    Xb = torch.empty_like(Bb)
+    results, x_first = {}, {}
+    runs = [("mixed", hz.HZ_PREC_MIXED, args.steps, args.warmup)]
+    if args.fp64_steps > 0:
+        runs.append(("fp64", hz.HZ_PREC_C128, args.fp64_steps, min(1, args.warmup)))
+    kraw, ratio = None, {}
+    for label, prec, steps, warmup in runs:
+        torch.cuda.empty_cache()
         t0 = time.perf_counter()
-        d = ctx.setup_ddm(op, p.partition, p.n_sub, p.overlap, coarse=coarse, precision=prec)
+        try:
+            d = ctx.setup_ddm(op, p.partition, p.n_sub, p.overlap, coarse=coarse, precision=prec)
+        except hz.HzError as e:  # FP64 factors may not fit next to the operator
+            results[label] = {"error": str(e)}
+            log(f"{label}: {e}")
+            continue
         torch.cuda.synchronize()
         t_setup = time.perf_counter() - t0
         st = ctx.ddm_stats(d)
+        levels = ctx.ddm_levels(d)
         log(f"{label}: setup {t_setup:.2f}s {st}")
-        kw = dict(tol=p.tol, max_iter=500, restart=args.restart, block=args.block, out=X)
-        for _ in range(args.warmup):
-            ctx.solve(d, B, **kw)
+        kw = dict(tol=p.tol, max_iter=500, restart=restart, block=block, out=Xb)
+
+        def step(k):
+            ctx.point_sources(mesh, blocks[k % len(blocks)], out=Bb)
+            return ctx.solve(d, Bb, **kw)[1]
+
+        info0 = step(0)  # the first sub-block, untimed: its solution is kept for the mixed-vs-FP64 error
+        torch.cuda.synchronize()
+        x_first[label] = Xb.cpu()
+        for k in range(1, warmup):
+            step(k)
         torch.cuda.synchronize()
         ctx.profile(True)
-        lat = []
-        infos = None
-        torch.cuda.synchronize()
+        lat, infos = [], []
         t_start = time.perf_counter()
-        for _ in range(args.steps):
+        for k in range(steps):
             a = time.perf_counter()
-            _, infos = ctx.solve(d, B, **kw)
+            infos.append(step(k))
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - a)
         torch.cuda.synchronize()
@@ -305,34 +416,47 @@ def main():
         kstats = ctx.profile_stats()
         ctx.profile(False)
         results[label] = dict(
-            sources_per_s=s * args.steps / el, ms_per_step=1e3 * el / args.steps,
+            sources_per_s=S * steps / el, ms_per_step=1e3 * el / steps, steps=steps, warmup=warmup,
             p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
-            iters=infos[0]["iters"], max_rel_residual=max(i["rel_residual"] for i in infos),
+            iters=[i[0]["iters"] for i in infos], restarts=[i[0]["restarts"] for i in infos],
+            restart_len=infos[0][0]["restart_len"], block=infos[0][0]["block"],
+            max_rel_residual=max(c["rel_residual"] for i in infos for c in i), first_block_iters=info0[0]["iters"],
             setup_s=t_setup, static_pivots=st["static_pivots"], factor_entries=st["factor_entries"],
             device_gb=st["device_bytes"] / 1e9, n_fronts=st["n_fronts"], levels=st["n_levels"],
-            max_front=st["max_front"], local_dofs=st["local_dofs_total"],
+            max_front=st["max_front"], local_dofs=st["local_dofs_total"], n_coarse=st["n_coarse"],
             kernels={k: dict(launches=v["launches"], seconds=v["seconds"],
                              gbps=(v["bytes"] / v["seconds"] / 1e9) if v["seconds"] > 0 else None,
                              tflops=(v["flops"] / v["seconds"] / 1e12) if v["seconds"] > 0 else None)
-                     for k, v in kstats.items()},
-            _kraw=kstats)
-        log(label, {k: v for k, v in results[label].items() if k != "_kraw"})
+                     for k, v in kstats.items()})
+        if label == "mixed":
+            kraw = kstats
+            ratio = _survey_ratio(levels, S, 8.0)
+        log(label, results[label])
         ctx.release(d)
+        del d
     head = results["mixed"]
-    kraw = head.pop("_kraw")
-    if "fp64" in results:
-        results["fp64"].pop("_kraw")
+    err = None
+    if "fp64" in x_first:
+        xm, xf = x_first["mixed"], x_first["fp64"]
+        err = float(torch.linalg.vector_norm(xm - xf) / torch.linalg.vector_norm(xf))
     dom = max(kraw, key=lambda k: kraw[k]["seconds"])
     kd = kraw[dom]
-    achieved = kd["bytes"] / kd["seconds"] if kd["seconds"] > 0 else 0.0
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": counter_traffic(dom, args.workload),
+    own = kd["bytes"] / kd["seconds"] if kd["seconds"] > 0 else 0.0
+    sur = own * ratio.get(dom, 1.0)
+    per_launch = kd["bytes"] / max(1, kd["launches"])
+    traffic = counter_traffic(dom, args.workload)
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": sur / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": sur / HBM_PEAK, "traffic": traffic,
                 "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x fetch scale + WRITE_SIZE x write scale)",
-                "launches": kd["launches"], "avg_launch_ms": 1e3 * kd["seconds"] / max(1, kd["launches"]),
-                "algorithmic_bytes_per_launch": kd["bytes"] / max(1, kd["launches"])}
-    cpu = None
-    if not args.no_cpu_baseline and p.sources is not None:
-        cpu = cpu_baseline(p, mesh.n, head["iters"], s)
+                "bytes_count": "survey: factor read once + 2 right-hand-side passes over the pivot rows",
+                "achieved_kernel_count": own / 1e9, "frac_kernel_count": own / HBM_PEAK,
+                "algorithmic_bytes_per_launch": per_launch * ratio.get(dom, 1.0),
+                "algorithmic_bytes_per_launch_kernel_count": per_launch,
+                "traffic_over_algorithmic": (traffic * 1e9 / (per_launch * ratio.get(dom, 1.0))) if traffic else None,
+                "traffic_over_kernel_count": (traffic * 1e9 / per_launch) if traffic else None,
+                "launches": kd["launches"], "avg_launch_ms": 1e3 * kd["seconds"] / max(1, kd["launches"])}
+    cpu = cpu_baseline_result(cpu_est, int(np.median(head["iters"])), S)
+    fp = results.get("fp64")
     out = {
         "metric": METRIC,
         "value": head["sources_per_s"],
@@ -346,15 +470,18 @@ def main():
         "vs_baseline": None,
         "dtype": "c64 preconditioner, f64 Krylov",
         "data": "synthetic",
-        "config": {"workload": desc, "n_dofs": mesh.n, "nnz": int(ctx.csr(op, values=False)[1].size),
-                   "n_sources": s, "n_sub": p.n_sub, "overlap": p.overlap, "tol": p.tol,
-                   "assembly_s": t_asm},
-        "latency": {"p50_s": head["p50_s"], "p99_s": head["p99_s"]},
+        "config": {"workload": spec["desc"], "step": f"{S} point sources formed on the GPU and solved to {p.tol}",
+                   "n_dofs": mesh.n, "nnz": int(ctx.csr(op, values=False)[1].size), "n_sources": len(srcs),
+                   "n_sub": p.n_sub, "overlap": p.overlap, "coarse": coarse is not None, "tol": p.tol,
+                   "restart": restart, "block": block, "assembly_s": t_asm},
+        "latency": {"p50_s": head["p50_s"], "p99_s": head["p99_s"], "of": "one 16-source step (solve latency)"},
+        "err_mixed_vs_fp64": err,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed": head,
-        "fp64": results.get("fp64"),
-        "mixed_over_fp64": (head["sources_per_s"] / results["fp64"]["sources_per_s"]) if "fp64" in results else None,
+        "fp64": fp,
+        "mixed_over_fp64": (head["sources_per_s"] / fp["sources_per_s"]) if fp and "sources_per_s" in fp else None,
+        "wall_s": time.perf_counter() - t_all,
     }
     print(json.dumps(out))
 

@@ -276,7 +276,7 @@ def layered_problem(freq=2.5, r=1.4, parts=(8, 8, 1), overlap=2, n_sources=(4, 4
         sources=src,
         grid=(nx, ny, nz),
         tol=1e-6,
-        extra={"r": r},
+        extra={"r": r, "parts": tuple(parts)},
     )
 
 
