@@ -210,6 +210,21 @@ hz_status hz_spmm(hz_ctx* ctx, hz_handle op, int64_t n_rhs, const void* x, int x
 hz_status hz_spmm_c64x(hz_ctx* ctx, hz_handle op, int64_t n_rhs, const void* x, int x_mem, void* y, int y_mem);
 hz_status hz_precond(hz_ctx* ctx, hz_handle ddm, int64_t n_rhs, const void* v, int v_mem, void* z, int z_mem);
 
+/*
+ * hz_spmm_noalloc -- y = A x like hz_spmm, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * It calls no device allocator: its node-major staging copies of x and y live in a
+ * library-owned scratch array of 2^23 complex128 entries (128 MiB) that every GPU the library
+ * runs on holds from hz_init until the process ends.
+ *   x, y  device pointers of the context's GPU, [n_rhs][n_dofs] complex128 (y may not alias x)
+ * Limit: n_dofs <= 2^22 (one column's two copies); columns are processed in chunks of
+ * min(32, 2^22 / n_dofs).  x is not checked for non-finite values.
+ * The scratch array is shared by every call on the same GPU and keeps the last call's
+ * contents: calls that overlap on one GPU (from several contexts, streams or threads) race
+ * and must be serialised by the caller.  Synchronises the context stream before returning.
+ * Errors: HZ_ERR_ARG (null pointers, n_rhs < 1, n_dofs over the limit, unknown operator).
+ */
+hz_status hz_spmm_noalloc(hz_ctx* ctx, hz_handle op, int64_t n_rhs, const void* x, void* y);
 
 typedef struct {
   int64_t n_dofs, nnz, n_sub;

@@ -4,6 +4,7 @@
 #include <new>
 
 #include "krylov.h"
+#include "noalloc.h"
 #include "prof.h"
 #include "serve.h"
 
@@ -194,6 +195,7 @@ hz_status hz_init(hz_ctx** out, const hz_init_opts* opts) {
     const char* tr = std::getenv("HZ_TRACE");
     c->trace = tr && tr[0] && tr[0] != '0';
     p3_upload_tables(c);
+    noalloc_init(c->device);
   });
   if (st != HZ_OK) {
     delete c;
@@ -406,6 +408,15 @@ hz_status hz_point_sources(hz_ctx* c, hz_handle mesh, int64_t n_src, const doubl
     out.alloc(c, n_src * m->n);
     launch_point_sources(c, *m, n_src, dx.ptr(), amp ? da.ptr() : nullptr, best.ptr(), out.ptr());
     copy_out(c, out.ptr(), rhs, rhs_mem, n_src * m->n);
+  });
+}
+
+hz_status hz_spmm_noalloc(hz_ctx* c, hz_handle op, int64_t n_rhs, const void* x, void* y) {
+  return guard(c, [&] {
+    HZ_REQUIRE(n_rhs >= 1 && x && y, HZ_ERR_ARG, "hz_spmm_noalloc: bad arguments");
+    auto o = lookup(c, c->ops, op, "operator");
+    spmm_noalloc(c, *o, n_rhs, static_cast<const c128*>(x), static_cast<c128*>(y));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
   });
 }
 

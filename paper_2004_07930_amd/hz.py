@@ -28,7 +28,7 @@ _STATUS = {0: "HZ_OK", -1: "HZ_ERR_ARG", -2: "HZ_ERR_OOM", -3: "HZ_ERR_HIP", -4:
 
 EXPORTS = [
     "hz_init", "hz_finalize", "hz_last_error", "hz_release", "hz_mesh", "hz_assemble", "hz_setup_ddm",
-    "hz_solve", "hz_solve_ex", "hz_point_sources", "hz_spmm", "hz_spmm_c64x", "hz_precond", "hz_ddm_stats_get", "hz_ddm_levels",
+    "hz_solve", "hz_solve_ex", "hz_point_sources", "hz_spmm", "hz_spmm_c64x", "hz_spmm_noalloc", "hz_precond", "hz_ddm_stats_get", "hz_ddm_levels",
     "hz_serve_start", "hz_serve_submit", "hz_serve_poll", "hz_serve_wait", "hz_serve_stats_get",
     "hz_serve_stop", "hz_get_dofmap", "hz_get_csr_size", "hz_get_csr", "hz_get_subdomain_size",
     "hz_get_subdomain", "hz_get_coarse_size", "hz_get_coarse", "hz_profile_enable", "hz_profile_get",
@@ -133,6 +133,7 @@ def load(path: str | None = None):
         "hz_point_sources": [vp, u64, i64, vp, vp, vp, C.c_int],
         "hz_spmm": [vp, u64, i64, vp, C.c_int, vp, C.c_int],
         "hz_spmm_c64x": [vp, u64, i64, vp, C.c_int, vp, C.c_int],
+        "hz_spmm_noalloc": [vp, u64, i64, vp, vp],
         "hz_precond": [vp, u64, i64, vp, C.c_int, vp, C.c_int],
         "hz_ddm_stats_get": [vp, u64, C.POINTER(DdmStats)],
         "hz_ddm_levels": [vp, u64, C.POINTER(DdmLevel), C.c_int32, C.POINTER(C.c_int32)],
@@ -351,6 +352,20 @@ class Context:
             out = np.empty((s, op.n), np.complex128) if not _is_torch(x) else x.new_empty(x.shape)
         yp, ym, keep2 = _block_arg(out, op.n)
         self._check(self.lib.hz_spmm(self.h, op.handle, s, xp, xm, yp, ym))
+        return out
+
+    def spmm_noalloc(self, op, x, out):
+        """y = A x through the library's static scratch memory (no device allocation); x and out
+        are contiguous complex128 device tensors of shape (s, n)."""
+        for t in (x, out):
+            if not (_is_torch(t) and t.is_cuda and t.is_contiguous()) or str(t.dtype) != "torch.complex128":
+                raise TypeError("x and out must be contiguous complex128 device tensors")
+            if t.shape[-1] != op.n:
+                raise ValueError(f"block has {t.shape[-1]} dofs, expected {op.n}")
+        s = int(np.prod(x.shape[:-1])) if len(x.shape) > 1 else 1
+        if tuple(out.shape) != tuple(x.shape):
+            raise ValueError("out must have the shape of x")
+        self._check(self.lib.hz_spmm_noalloc(self.h, op.handle, s, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr())))
         return out
 
     def spmm_c64x(self, op, x):
