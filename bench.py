@@ -51,7 +51,7 @@ WORKLOADS = {
     "layered-5hz": dict(
         problem=dict(freq=5.0, r=1.4, parts=(8, 8, 4), overlap=1, n_sources=(16, 8), src_depth=0.5,
                      equal_depth_zcuts=True),
-        coarse=False, block=16, restart=24, step_sources=16,
+        coarse=False, block=0, restart=24, step_sources=16,
         desc="layered 20x20x4.65 km, 5 Hz, Kuhn P3 %dx%dx%d cubes, 256 subdomains (8x8x4 boxes cut at equal "
              "depth, uneven), overlap 1, one-level ORAS, 128 point sources at 0.5 km in 16-source steps, tol 1e-6"),
     "layered-2.5hz": dict(

@@ -297,6 +297,8 @@ hz_status hz_assemble(hz_ctx* c, hz_handle mesh, const double* velocity, const d
     launch_gather_fill(c->stream, m->n, m->d_rowptr.ptr(), m->d_col.ptr(), m->d_gptr.ptr(), m->d_gsrc.ptr(),
                        o->d_elem.ptr(), m->d_dirichlet.ptr(), o->d_val.ptr(), o->d_val32.ptr());
     HIP_CHECK(hipStreamSynchronize(c->stream));
+    // the element matrices are recomputed when a decomposition needs its local operators
+    o->d_elem = DevArray<c128>();
     const hz_handle h = new_handle(c);
     std::lock_guard<std::mutex> lk(c->mu);
     c->ops[h] = o;
@@ -329,8 +331,11 @@ hz_status hz_solve_ex(hz_ctx* c, hz_handle ddm, int64_t n_rhs, const void* rhs, 
     Staged B;
     stage_in(c, rhs, rhs_mem, n_rhs * n, B);
     HZ_REQUIRE(count_nonfinite(c, B.ptr, n_rhs * n) == 0, HZ_ERR_ARG, "hz_solve: non-finite right-hand side");
+    // device x: the blocks' solutions go straight to it; host x: through one device copy
     DevArray<c128> Xd;
-    Xd.alloc(c, n_rhs * n);
+    HZ_REQUIRE(x_mem == HZ_MEM_HOST || x_mem == HZ_MEM_DEVICE, HZ_ERR_ARG, "hz_solve: bad memory kind");
+    if (x_mem == HZ_MEM_HOST) Xd.alloc(c, n_rhs * n);
+    c128* Xout = x_mem == HZ_MEM_HOST ? Xd.ptr() : static_cast<c128*>(x);
     SolveOptions so;
     so.tol = opts->tol;
     so.max_iter = opts->max_iter > 0 ? opts->max_iter : 500;
@@ -368,7 +373,7 @@ hz_status hz_solve_ex(hz_ctx* c, hz_handle ddm, int64_t n_rhs, const void* rhs, 
       K.to_node(B.ptr + c0 * n, Bn.ptr());
       std::vector<ColInfo> ci;
       fgmres(c, d, s, Bn.ptr(), Xn.ptr(), so, m, ci);
-      K.from_node(Xn.ptr(), Xd.ptr() + c0 * n);
+      K.from_node(Xn.ptr(), Xout + c0 * n);
       for (int k = 0; k < s; ++k) {
         info[c0 + k].iters = ci[k].iters;
         info[c0 + k].restarts = ci[k].restarts;
@@ -379,7 +384,8 @@ hz_status hz_solve_ex(hz_ctx* c, hz_handle ddm, int64_t n_rhs, const void* rhs, 
         all_ok = all_ok && ci[k].status == HZ_OK;
       }
     }
-    copy_out(c, Xd.ptr(), x, x_mem, n_rhs * n);
+    if (x_mem == HZ_MEM_HOST) copy_out(c, Xd.ptr(), x, x_mem, n_rhs * n);
+    HIP_CHECK(hipStreamSynchronize(c->stream));
     if (!all_ok) fail(HZ_ERR_NOT_CONVERGED, "hz_solve: max_iter reached before the tolerance");
   });
 }
@@ -583,7 +589,11 @@ hz_status hz_get_subdomain(hz_ctx* c, hz_handle ddm, int32_t i, int32_t* gdofs, 
     if (owned) std::copy(S.owned.begin(), S.owned.end(), owned);
     if (rowptr) std::copy(S.rowptr.begin(), S.rowptr.end(), rowptr);
     if (col) std::copy(S.col.begin(), S.col.end(), col);
-    if (val) copy_out(c, d->d_lval.ptr() + S.csr_off, val, HZ_MEM_HOST, (int64_t)S.col.size());
+    if (val) {
+      HZ_REQUIRE(d->d_lval.ptr() != nullptr, HZ_ERR_STATE,
+                 "hz_get_subdomain: the local operator values were released after the factorisation (over 2 GiB)");
+      copy_out(c, d->d_lval.ptr() + S.csr_off, val, HZ_MEM_HOST, (int64_t)S.col.size());
+    }
   });
 }
 

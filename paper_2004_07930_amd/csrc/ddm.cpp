@@ -776,6 +776,13 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     d->d_lgsrc.upload(ctx, gs);
     d->d_ldir.upload(ctx, dr);
     d->d_lval.alloc(ctx, csr);
+    // element matrices of the operator (released after hz_assemble; the same kernel on the same
+    // coefficients gives the same bits), kept only while the local operators are filled
+    DevArray<double> dv, dq;
+    dv.upload(ctx, op->velocity);
+    if (op->has_q) dq.upload(ctx, op->Q);
+    op->d_elem.alloc(ctx, m.T * kElemStride);
+    launch_element_matrices(ctx, m, *op, dv.ptr(), op->has_q ? dq.ptr() : nullptr);
     // one launch per subdomain (row pointers are subdomain-relative)
     for (int32_t i = 0; i < n_sub; ++i) {
       const Subdomain& S = d->subs[i];
@@ -789,11 +796,19 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   HIP_CHECK(hipStreamSynchronize(ctx->stream));
   d->d_lgptr = DevArray<int64_t>();
   d->d_lgsrc = DevArray<uint32_t>();
+  op->d_elem = DevArray<c128>();
   phase("device maps, local operators");
   // --- numeric factorisation
   factor_all(ctx, *d);
   HIP_CHECK(hipStreamSynchronize(ctx->stream));
   phase("numeric factorisation");
+  // set-up-only data: the scatter lists, and the local operator values unless small enough to
+  // keep for introspection (hz_get_subdomain)
+  d->d_orig_src = DevArray<int64_t>();
+  d->d_orig_dst = DevArray<int64_t>();
+  std::vector<int64_t>().swap(d->orig_src);
+  std::vector<int64_t>().swap(d->orig_dst);
+  if (d->d_lval.bytes() > (size_t(2) << 30)) d->d_lval = DevArray<c128>();
   // --- coarse space
   if (coarse) {
     d->coarse = std::make_unique<CoarseSpace>();

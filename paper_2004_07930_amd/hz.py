@@ -331,6 +331,13 @@ class Context:
         xp, xm, keep2 = _block_arg(out, ddm.n)
         info = (ColInfo * s)()
         o = SolveOpts(C.sizeof(SolveOpts), float(tol), int(max_iter), int(restart), int(fixed_iters), int(block))
+        if self._alloc_cbs is not None:
+            # the library sizes the Krylov basis by the device's free memory: memory that earlier
+            # calls returned to torch's cache goes back to the device first, so that the block
+            # width and restart length do not depend on what earlier calls left cached
+            import torch
+
+            torch.cuda.empty_cache()
         st = self.lib.hz_solve_ex(self.h, ddm.handle, s, rp, rm, C.byref(o), xp, xm, info)
         self._check(st, allow=() if raise_on_not_converged else (HZ_ERR_NOT_CONVERGED,))
         return out, _info_dicts(info)
