@@ -202,26 +202,37 @@ def cpu_baseline_result(est, iters, s):
             "setup_s_extrapolated": est["setup"], "nproc": est["nproc"], "cpu_model": est["cpu_model"]}
 
 
-SERVE_FREQS = (2.5, 3.5)
+SERVE_FREQS = (2.5, 3.5, 5.0)
 
 
 def serve_workloads():
-    """Operators of the serving run: the layered model at 2.5 Hz (8 x 8 columns) and 3.5 Hz
-    (8 x 8 x 2 boxes cut at equal depth), overlap 2, P1 coarse space, mixed precision."""
+    """Operators of the serving run (mixed precision): the layered model at 2.5 Hz (8 x 8
+    full-depth columns, overlap 2, P1 coarse space), 3.5 Hz (8 x 8 x 2 boxes cut at equal depth,
+    overlap 2, P1 coarse space) and 5 Hz (the headline workload: 8 x 8 x 4 boxes, overlap 1,
+    one-level)."""
     import workloads as w
 
     out = []
     for f in SERVE_FREQS:
-        parts = (8, 8, 1) if f <= 2.5 else (8, 8, 2)
-        out.append(w.layered_problem(freq=f, r=1.4, parts=parts, overlap=2, n_sources=(4, 4), src_depth=0.5,
-                                     equal_depth_zcuts=parts[2] > 1))
+        if f <= 2.5:
+            q = w.layered_problem(freq=f, r=1.4, parts=(8, 8, 1), overlap=2, n_sources=(4, 4), src_depth=0.5)
+            coarse = True
+        elif f <= 3.5:
+            q = w.layered_problem(freq=f, r=1.4, parts=(8, 8, 2), overlap=2, n_sources=(4, 4), src_depth=0.5,
+                                  equal_depth_zcuts=True)
+            coarse = True
+        else:
+            q = build_workload("layered-5hz")[0]
+            coarse = False
+        out.append((q, coarse))
     return out
 
 
 def serve_requests(n_req, seed=4):
-    """Poisson arrivals (mean gap 0.25 s); operator uniform; n_src = round(exp(U[0, ln 128]));
-    the sources are the first n_src of a seeded permutation of a 16 x 8 grid at 0.5 km depth
-    (x = 0.625 + 1.25 i km, y = 1.25 + 2.5 j km)."""
+    """The first n_req requests of the seeded stream: Poisson arrivals (mean gap 0.25 s);
+    operator uniform; n_src = round(exp(U[0, ln 128])); the sources are the first n_src of a
+    seeded permutation of a 16 x 8 grid at 0.5 km depth (x = 0.625 + 1.25 i km,
+    y = 1.25 + 2.5 j km)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     grid = np.array([[0.625 + 1.25 * i, 1.25 + 2.5 * j, 0.5] for j in range(8) for i in range(16)])
     t, reqs = 0.0, []
@@ -234,35 +245,49 @@ def serve_requests(n_req, seed=4):
     return reqs
 
 
+def fifo_timeline(arrivals, service):
+    """Completion times of one server that takes requests in arrival order."""
+    done, free = [], 0.0
+    for a, s in zip(arrivals, service):
+        free = max(free, a) + s
+        done.append(free)
+    return np.array(done)
+
+
 def run_serve(args):
     """Continuous-batching run: every request is submitted at its arrival time to one serving
-    context holding both operators; prints one JSON line with p50 / p99 latency (submission to
-    completion) and sources per second."""
+    context holding the three operators; prints one JSON line with p50 / p99 latency
+    (submission to completion) and sources per second.  With --serve-fp64, the same stream is
+    also costed for plain FP64 hz_solve one request at a time: each operator's FP64 service
+    rate (sources/s) is measured on its requests of the stream, in arrival order, for up to
+    --fp64-budget seconds per operator, and the arrival times are replayed through one FIFO
+    server with those service times (measured where solved, else the operator's rate)."""
     import torch
 
     from paper_2004_07930_amd import hz
 
+    t_all = time.perf_counter()
     reqs = serve_requests(args.serve)
     probs = serve_workloads()
     free0, _ = torch.cuda.mem_get_info()
-    # caller-side tensors (right-hand sides and solutions of every request) are torch's,
-    # outside the library's accounting: keep them out of the serving budget
     import workloads as w
 
-    n = [w.kuhn_ndofs(*q.grid) for q in probs]
+    n = [w.kuhn_ndofs(*q.grid) for q, _ in probs]
+    # caller-side tensors (right-hand sides and solutions of every request) are torch's, outside
+    # the library's accounting: keep them out of the serving budget
     caller = sum(2 * len(src) * n[op] * 16 for _, op, src in reqs)
-    ctx = hz.Context(0, stream=torch.cuda.current_stream(), hbm_budget=int(0.8 * free0) - caller)
+    ctx = hz.Context(0, stream=torch.cuda.current_stream(), hbm_budget=int(0.85 * free0) - caller)
     ops, setup = [], {}
-    for k, q in enumerate(probs):
+    for k, (q, coarse) in enumerate(probs):
         t0 = time.perf_counter()
         mesh = ctx.mesh(q.tets, q.coords, q.face_bc)
         op = ctx.assemble(mesh, q.velocity, q.freq, q.quality)
-        d = ctx.setup_ddm(op, q.partition, q.n_sub, q.overlap, coarse=(q.coarse_tets, q.coarse_coords),
-                          precision=hz.HZ_PREC_MIXED)
+        d = ctx.setup_ddm(op, q.partition, q.n_sub, q.overlap,
+                          coarse=(q.coarse_tets, q.coarse_coords) if coarse else None, precision=hz.HZ_PREC_MIXED)
         torch.cuda.synchronize()
-        setup[SERVE_FREQS[k]] = dict(n_dofs=mesh.n, n_sub=q.n_sub, seconds=time.perf_counter() - t0,
-                                    ddm_gb=ctx.ddm_stats(d)["device_bytes"] / 1e9)
-        ops.append((mesh, d))
+        setup[SERVE_FREQS[k]] = dict(n_dofs=mesh.n, n_sub=q.n_sub, overlap=q.overlap, coarse=coarse,
+                                    seconds=time.perf_counter() - t0, ddm_gb=ctx.ddm_stats(d)["device_bytes"] / 1e9)
+        ops.append([mesh, op, d, q, coarse])
         print(f"serve: {SERVE_FREQS[k]} Hz ready {setup[SERVE_FREQS[k]]}", file=sys.stderr, flush=True)
     rhs = [ctx.point_sources(ops[op][0], src, out=torch.empty((len(src), ops[op][0].n), dtype=torch.complex128,
                                                                 device="cuda")) for _, op, src in reqs]
@@ -275,28 +300,73 @@ def run_serve(args):
             delay = t_start + t_arr - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
-            tickets.append(ctx.submit(ops[op][1], b, tol=1e-6))
+            tickets.append(ctx.submit(ops[op][2], b, tol=1e-6))
         done = []
         for k, tk in enumerate(tickets):
             done.append(ctx.wait(tk))
-            print(f"serve: request {k} done ({len(reqs[k][2])} sources at {SERVE_FREQS[reqs[k][1]]} Hz)",
-                  file=sys.stderr, flush=True)
+            print(f"serve: request {k} done ({len(reqs[k][2])} sources at {SERVE_FREQS[reqs[k][1]]} Hz, "
+                  f"{time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
         st = ctx.serve_stats()
     finally:
         ctx.serve_stop()
     wall = time.perf_counter() - t_start
     ok = all(status == 0 and all(i["rel_residual"] <= 1e-6 for i in info) for _, info, status in done)
     n_src = sum(len(r[2]) for r in reqs)
+    per_op = {SERVE_FREQS[k]: dict(requests=sum(1 for r in reqs if r[1] == k),
+                                   sources=sum(len(r[2]) for r in reqs if r[1] == k)) for k in range(len(ops))}
+    del done, tickets
+    fp64 = None
+    if args.serve_fp64:
+        arrivals = [r[0] for r in reqs]
+        service = [None] * len(reqs)
+        rates = {}
+        for k, (mesh, op, d, q, coarse) in enumerate(ops):
+            ctx.release(d)
+            ops[k][2] = None
+            torch.cuda.empty_cache()
+            t0 = time.perf_counter()
+            d64 = ctx.setup_ddm(op, q.partition, q.n_sub, q.overlap,
+                                coarse=(q.coarse_tets, q.coarse_coords) if coarse else None, precision=hz.HZ_PREC_C128)
+            t_setup = time.perf_counter() - t0
+            solved, t_sum, s_sum = 0, 0.0, 0
+            t_op = time.perf_counter()
+            for j, (t_arr, o, src) in enumerate(reqs):
+                if o != k or time.perf_counter() - t_op > args.fp64_budget:
+                    continue
+                a = time.perf_counter()
+                ctx.solve(d64, rhs[j], tol=1e-6)
+                torch.cuda.synchronize()
+                service[j] = time.perf_counter() - a
+                t_sum += service[j]
+                s_sum += len(src)
+                solved += 1
+            rates[SERVE_FREQS[k]] = dict(sources_per_s=s_sum / t_sum if t_sum > 0 else None, requests_solved=solved,
+                                         sources_solved=s_sum, setup_s=t_setup)
+            print(f"serve fp64: {SERVE_FREQS[k]} Hz {rates[SERVE_FREQS[k]]}", file=sys.stderr, flush=True)
+            ctx.release(d64)
+            torch.cuda.empty_cache()
+        svc = [service[j] if service[j] is not None else len(r[2]) / rates[SERVE_FREQS[r[1]]]["sources_per_s"]
+               for j, r in enumerate(reqs)]
+        fin = fifo_timeline(arrivals, svc)
+        lat = fin - np.array(arrivals)
+        fp64 = {"sources_per_s": n_src / (fin[-1] - arrivals[0]) if len(reqs) else None,
+                "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                "per_operator": rates, "measured_requests": sum(x is not None for x in service),
+                "how": "plain FP64 hz_solve one request at a time; service times measured where solved, else the "
+                       "operator's measured rate; arrivals replayed through one FIFO server"}
     print(json.dumps({
         "metric": "served sources/s at 1e-6 rel. residual with p50/p99 request latency", "value": st["sources_per_s"],
         "unit": "sources/s", "n_gpus": 1, "higher_is_better": True, "dtype": "c64 preconditioner, f64 Krylov",
         "data": "synthetic",
-        "config": {"workload": "serving: layered model at 2.5 and 3.5 Hz resident, Poisson arrivals (mean gap "
-                               "0.25 s, seed 4), n_src log-uniform in [1, 128], tol 1e-6, 8 slots",
-                   "requests": len(reqs), "sources": n_src, "operators": setup},
+        "config": {"workload": "serving: layered model at 2.5, 3.5 and 5 Hz resident, the first %d requests of the "
+                               "seeded 300-request stream (Poisson arrivals, mean gap 0.25 s, seed 4), n_src "
+                               "log-uniform in [1, 128], tol 1e-6, 8 slots" % len(reqs),
+                   "requests": len(reqs), "sources": n_src, "operators": setup, "per_operator": per_op},
         "latency": {"p50_s": st["p50_s"], "p99_s": st["p99_s"]}, "wall_s": wall,
         "completed": st["completed"], "rejected": st["rejected"], "all_converged": ok,
-        "iters": [max(i["iters"] for i in info) for _, info, _ in done]}))
+        "fp64_sequential": fp64,
+        "mixed_served_over_fp64": (st["sources_per_s"] / fp64["sources_per_s"]) if fp64 else None,
+        "total_wall_s": time.perf_counter() - t_all}))
 
 
 def _survey_ratio(levels, s, e):
@@ -325,7 +395,9 @@ def main():
     ap.add_argument("--serve", type=int, default=0, metavar="N",
                     help="instead: serve N requests on the 2.5, 3.5 and 5 Hz operators (continuous batching)")
     ap.add_argument("--serve-fp64", action="store_true",
-                    help="with --serve: also solve the same stream one request at a time with plain FP64 hz_solve")
+                    help="with --serve: also cost the same stream for plain FP64 hz_solve, one request at a time")
+    ap.add_argument("--fp64-budget", type=float, default=90.0,
+                    help="with --serve-fp64: seconds of FP64 solves per operator")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no collectives); use --gpus 1", file=sys.stderr)

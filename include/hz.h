@@ -79,7 +79,8 @@ hz_status hz_init(hz_ctx** out, const hz_init_opts* opts);
 void hz_finalize(hz_ctx* ctx);
 /* Message of the last failure on ctx (valid until the next call on ctx). */
 const char* hz_last_error(const hz_ctx* ctx);
-/* Drop the caller's reference to a handle. */
+/* Drop the caller's reference to a handle.  Also drops the Krylov workspace that hz_solve
+ * keeps with the context between calls (so that repeated solves allocate nothing). */
 hz_status hz_release(hz_ctx* ctx, hz_handle h);
 
 /*
@@ -308,10 +309,11 @@ typedef struct {
  *   >= 1 bounds the parts (blocks of at most 32 sources) running at once.
  * hz_serve_submit: queues a request (FIFO) and returns its ticket.  Each request is solved
  *   like hz_solve (x0 = 0, per-column relative residual req->tol, req->max_iter inner
- *   iterations, 0 = 500) with a restart length chosen at submission: the largest up to 40
- *   with which its first part fits in hbm_budget next to the resident objects and the
- *   requests in flight.  Its parts are admitted in order when a slot is free and their
- *   memory fits.  rhs / x / info (info nullable, [n_rhs]) stay caller-owned and must stay
+ *   iterations, 0 = 500) in parts of w sources with restart length m, both chosen at
+ *   submission from hbm_budget minus the resident objects and the requests in flight: for
+ *   each w in min(n_rhs, 32) and its halvings, the longest m up to 40 with which the first
+ *   part fits; the widest w whose m reaches 20, else the w with the longest m.  Its parts are
+ *   admitted in order when a slot is free and their memory fits.  rhs / x / info (info nullable, [n_rhs]) stay caller-owned and must stay
  *   valid until the ticket completes; req->mem says whether rhs and x are host or device.
  *   Errors: HZ_ERR_ARG (unknown ddm, n_rhs < 1, null buffers, bad mem), HZ_ERR_ABI
  *   (struct_size), HZ_ERR_BUSY (fits at no restart length >= 8: never admissible),

@@ -215,6 +215,8 @@ void hz_finalize(hz_ctx* c) {
   {
     std::lock_guard<std::mutex> lk(c->mu);
     for (auto& kv : c->ddms) precond_release_workspace(*kv.second);
+    c->krylov_ws.release();
+    c->krylov_io.release();
     c->ddms.clear();
     c->ops.clear();
     c->meshes.clear();
@@ -229,6 +231,7 @@ const char* hz_last_error(const hz_ctx* c) { return c ? c->last_error.c_str() : 
 hz_status hz_release(hz_ctx* c, hz_handle h) {
   return guard(c, [&] {
     HIP_CHECK(hipStreamSynchronize(c->stream));
+    krylov_cache_release(c);  // releasing objects gives back the solves' cached workspace too
     std::lock_guard<std::mutex> lk(c->mu);
     if (c->meshes.erase(h)) return;
     if (c->ops.erase(h)) return;
@@ -311,6 +314,7 @@ hz_status hz_setup_ddm(hz_ctx* c, hz_handle op, const int32_t* partition, int32_
   return guard(c, [&] {
     HZ_REQUIRE(ddm, HZ_ERR_ARG, "hz_setup_ddm: null output");
     auto o = lookup(c, c->ops, op, "operator");
+    krylov_cache_release(c);  // set-up sizes its arena by the free memory
     auto d = build_ddm(c, o, partition, n_sub, overlap, coarse, precision);
     const hz_handle h = new_handle(c);
     std::lock_guard<std::mutex> lk(c->mu);
@@ -364,16 +368,20 @@ hz_status hz_solve_ex(hz_ctx* c, hz_handle ddm, int64_t n_rhs, const void* rhs, 
                so.fixed_iters > 0 ? "hz_solve: the Krylov basis for fixed_iters steps does not fit in device memory"
                                   : "hz_solve: not even a restart length of 8 fits in device memory");
     bool all_ok = true;
-    DevArray<c128> Bn, Xn;
+    // the blocks' node-major right-hand side and solution, kept with the context between solves
+    if ((int64_t)c->krylov_io.bytes < 2 * n * blk * (int64_t)sizeof(c128)) {
+      c->krylov_io.release();
+      c->krylov_io.alloc(c, 2 * n * blk * sizeof(c128));
+    }
+    c128* Bn = c->krylov_io.as<c128>();
+    c128* Xn = Bn + n * blk;
     for (int64_t c0 = 0; c0 < n_rhs; c0 += blk) {
       const int s = (int)std::min<int64_t>(blk, n_rhs - c0);
-      Bn.alloc(c, n * s);
-      Xn.alloc(c, n * s);
       KrylovKernels K(c, n, s);
-      K.to_node(B.ptr + c0 * n, Bn.ptr());
+      K.to_node(B.ptr + c0 * n, Bn);
       std::vector<ColInfo> ci;
-      fgmres(c, d, s, Bn.ptr(), Xn.ptr(), so, m, ci);
-      K.from_node(Xn.ptr(), Xout + c0 * n);
+      fgmres(c, d, s, Bn, Xn, so, m, ci);
+      K.from_node(Xn, Xout + c0 * n);
       for (int k = 0; k < s; ++k) {
         info[c0 + k].iters = ci[k].iters;
         info[c0 + k].restarts = ci[k].restarts;

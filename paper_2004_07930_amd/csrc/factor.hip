@@ -8,13 +8,15 @@
 // Per level: scatter the original entries into the fronts, extend-add the children's
 // update blocks (one child slot per launch, so every sum has a fixed order), then for each
 // panel of kNb pivot columns: factor the diagonal block, solve the panel rows below it,
-// and apply the rank-kNb update to the trailing lower triangle (L region and Schur block).
+// and apply the rank-kNb update to the trailing lower triangle (L region and Schur block) on
+// the matrix cores.
 // Finally each kNb x kNb diagonal block gets its inverse unit-lower factor stored
 // transposed in its (otherwise unused) strict upper triangle, for the triangular solves.
 #include <cmath>
 #include <cstdlib>
 
 #include "ddm.h"
+#include "mfma_cplx.h"
 
 namespace hz {
 
@@ -155,12 +157,17 @@ __global__ __launch_bounds__(256) void k_panel_rows(const int32_t* __restrict__ 
   }
 }
 
-// trailing update: F[i][j] -= sum_l L[i][l] d_l L[j][l] for i >= j >= k0 + nb
+// trailing update: F[i][j] -= sum_l L[i][l] d_l L[j][l] for i >= j >= k0 + nb, one lower 64 x 64
+// tile of the trailing region per block, on the matrix cores (CAcc: the three-product form,
+// complex64 on v_mfma_f32_16x16x4f32, complex128 on v_mfma_f64_16x16x4f64).  The panel's rows
+// of the tile (As) and its d-scaled rows of the tile's columns (Bs) are staged in LDS; each
+// wavefront forms one 32 x 32 quarter of the tile as 2 x 2 matrix-core tiles over the panel's
+// nb <= 32 columns (entries past nb are zero).
 template <typename T>
 __global__ __launch_bounds__(256) void k_trailing(const int32_t* __restrict__ lf, const FrontDesc* __restrict__ fr,
                                                   int k0, cplx<T>* __restrict__ L, cplx<T>* __restrict__ U) {
-  __shared__ cplx<T> As[kNb][kTile + 1];
-  __shared__ cplx<T> Bs[kNb][kTile + 1];
+  __shared__ cplx<T> As[kNb][kTile + 1];  // As[l][r] = L[i0 + r][k0 + l]
+  __shared__ cplx<T> Bs[kNb][kTile + 1];  // Bs[l][r] = d_l L[j0 + r][k0 + l]
   const FrontDesc F = fr[lf[blockIdx.x]];
   const int nb = min(kNb, F.p - k0);
   const int64_t f = F.p + F.r;
@@ -190,36 +197,40 @@ __global__ __launch_bounds__(256) void k_trailing(const int32_t* __restrict__ lf
     Bs[l][r] = b;
   }
   __syncthreads();
-  // each thread: 4 x 4 micro tile
-  const int tr = (threadIdx.x % 16) * 4, tc = (threadIdx.x / 16) * 4;
-  cplx<T> acc[4][4];
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, lr = ln & 15, lq = ln >> 4;
+  const int wr = (wv & 1) * 32, wc = (wv >> 1) * 32;  // this wavefront's quarter of the tile
+  CAcc<T> acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = cmk((T)0, (T)0);
-  for (int l = 0; l < nb; ++l) {
-    cplx<T> av[4], bv[4];
+    for (int g = 0; g < 2; ++g) acc[m][g].zero();
+#pragma unroll 2
+  for (int k = 0; k < kNb; k += 4) {
+    const int kk = k + lq;
+    cplx<T> a[2], b[2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) av[a] = As[l][tr + a];
+    for (int m = 0; m < 2; ++m) a[m] = As[kk][wr + 16 * m + lr];  // A[i][k]
 #pragma unroll
-    for (int b = 0; b < 4; ++b) bv[b] = Bs[l][tc + b];
+    for (int g = 0; g < 2; ++g) b[g] = Bs[kk][wc + 16 * g + lr];  // B[k][j]
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int m = 0; m < 2; ++m)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) cfma(acc[a][b], av[a], bv[b]);
+      for (int g = 0; g < 2; ++g) acc[m][g].mac(a[m], b[g]);
   }
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int64_t j = j0 + tc + b;
-    if (j >= f) continue;
+  for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int64_t i = i0 + tr + a;
-      if (i >= f || i < j) continue;
-      cplx<T>* dst = at_front(L, U, F, i, j);
-      *dst = *dst - acc[a][b];
+    for (int g = 0; g < 2; ++g) {
+      const int64_t j = j0 + wc + 16 * g + lr;
+      if (j >= f) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = i0 + wr + 16 * m + CAcc<T>::row(lq, v);
+        if (i >= f || i < j) continue;
+        cplx<T>* dst = at_front(L, U, F, i, j);
+        *dst = *dst - acc[m][g].get(v);
+      }
     }
-  }
 }
 
 // ---- partitioned inverse: [L11; L21] -> [L11^{-1}; L21 L11^{-1}] (unit diagonal kept)
@@ -286,12 +297,14 @@ __global__ __launch_bounds__(256) void k_inv_block(const int32_t* __restrict__ a
     const int a = e / kNb, b = e % kNb;  // Ljj[a][b] = L11[j0 + a][j0 + b]
     Ljj[a][b] = (a < nbJ && b < nbJ) ? Pp[(int64_t)b * prow + a] : cmk((T)0, (T)0);
   }
-  const int r = threadIdx.x & 63, g = threadIdx.x >> 6;  // row, column group (8 columns each)
+  const int r = threadIdx.x & 63;
   const int64_t i = i0 + r;
-  cplx<T> acc[8];
-#pragma unroll
-  for (int a = 0; a < 8; ++a) acc[a] = cmk((T)0, (T)0);
-  // GEMM over the transformed columns K = [j0 + nbJ, kend)
+  // GEMM over the transformed columns K = [j0 + nbJ, kend) on the matrix cores: wavefront wv
+  // forms rows [16 wv, 16 wv + 16) of the tile, both 16-column halves of the block
+  const int wv = threadIdx.x >> 6, lr = threadIdx.x & 15, lq = (threadIdx.x >> 4) & 3;
+  CAcc<T> acc[2];
+  acc[0].zero();
+  acc[1].zero();
   const int64_t k1 = j0 + nbJ;
   const int64_t kend = i0 < F.p ? min<int64_t>(F.p, i0 + RT) : F.p;
   for (int64_t kc = k1; kc < kend; kc += KC) {
@@ -306,24 +319,29 @@ __global__ __launch_bounds__(256) void k_inv_block(const int32_t* __restrict__ a
       Mt[k][rr] = (k < kn && i0 + rr < f) ? Lf[(kc + k) * F.ld + i0 + rr] : cmk((T)0, (T)0);
     }
     __syncthreads();
-    for (int k = 0; k < kn; ++k) {
-      const cplx<T> m = Mt[k][r];
+#pragma unroll 2
+    for (int k = 0; k < KC; k += 4) {  // entries past kn are zero
+      const cplx<T> a = Mt[k + lq][16 * wv + lr];  // A[i][k]
 #pragma unroll
-      for (int a = 0; a < 8; ++a) cfma(acc[a], m, Lt[k][g * 8 + a]);
+      for (int h = 0; h < 2; ++h) acc[h].mac(a, Lt[k + lq][16 * h + lr]);  // B[k][j]
     }
   }
   // R = base - acc ; base = e_J on the top block, L21[i, J] below
 #pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    const int jj = g * 8 + a;
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Rr[16 * wv + CAcc<T>::row(lq, v)][16 * h + lr] = acc[h].get(v);
+  __syncthreads();
+  for (int jj = 0; jj < nbJ; ++jj) {
+    if (threadIdx.x >= RT) break;
     cplx<T> base = cmk((T)0, (T)0);
-    if (i < f && jj < nbJ) {
+    if (i < f) {
       if (i < F.p)
         base = cmk((T)(i == j0 + jj ? 1 : 0), (T)0);
       else
         base = Lf[(int64_t)(j0 + jj) * F.ld + i];
     }
-    Rr[r][jj] = base - acc[a];
+    Rr[r][jj] = base - Rr[r][jj];
   }
   __syncthreads();
   // x L_JJ = R  (unit lower L_JJ):  x_jj = R_jj - sum_{l > jj} x_l L_JJ[l][jj]

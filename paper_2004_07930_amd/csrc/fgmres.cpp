@@ -21,13 +21,59 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <type_traits>
 
 #include "krylov.h"
 #include "prof.h"
 
 namespace hz {
 
+// workspace layout of a job: every array at a 256-byte boundary
+int64_t FgmresJob::carve(char* base) {
+  const int64_t ns = n * s;
+  int64_t off = 0;
+  auto take = [&](auto& arr, int64_t count) {
+    using T = std::remove_pointer_t<decltype(arr.p)>;
+    arr.p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (std::max<int64_t>(1, count) * (int64_t)sizeof(T) + 255) / 256 * 256;
+  };
+  take(V, (m + 1) * ns);
+  if (z32)
+    take(Zs, m * ns);
+  else
+    take(Zb, m * ns);
+  take(W, ns);
+  take(Wt, ns);
+  take(R, ns);
+  take(part, (int64_t)K.nchunk * (m + 2) * s * s * (dcgs ? 2 : 1));
+  take(Hc, (int64_t)(m + 2) * s * s);
+  if (dcgs) {
+    take(Hc2, (int64_t)(m + 2) * s * s);
+    take(Gm, (int64_t)(m + 2) * s * 2 * s);
+    take(Cm, (int64_t)(m + 2) * s * 2 * s);
+    take(Rprev, (int64_t)s * s);
+  } else {
+    take(Hp, (int64_t)(m + 1) * s * s);
+  }
+  take(Rm, (int64_t)m * s * ldr);
+  take(refl, (int64_t)m * 2 * s * s);
+  take(tau, (int64_t)m * s);
+  take(tmat, (int64_t)m * s * s);
+  take(G, ldr * s);
+  take(Y, (int64_t)m * s * s);
+  take(Gs, s * s);
+  take(Rs, s * s);
+  take(Ri, s * s);
+  take(Racc, s * s);
+  take(res, s);
+  take(npart, (int64_t)K.nchunk * s);
+  take(nrm, s);
+  take(flag, 2);
+  return off;
+}
+
 int64_t FgmresJob::bytes_needed(int64_t n, int s, int m, bool z32) {
+  // the same layout as carve(): 26 arrays, each padded to 256 bytes
   const int64_t ns = n * s;
   const int nchunk = (int)((n + 4095) / 4096);
   const int64_t ldr = (int64_t)(m + 1) * s;
@@ -36,7 +82,7 @@ int64_t FgmresJob::bytes_needed(int64_t n, int s, int m, bool z32) {
   e += (int64_t)nchunk * (m + 2) * s * s * pw;            // partial sums
   e += (int64_t)(2 * m + 3) * s * s + (int64_t)m * s * ldr + 3 * (int64_t)m * s * s + ldr * s + 8 * s * s;
   if (delayed(s)) e += (int64_t)(m + 3) * s * s + 2 * (int64_t)(m + 2) * s * 2 * s;  // Hc2, Rprev, Gm, Cm
-  return e * (int64_t)sizeof(c128) + (int64_t)m * ns * (int64_t)(z32 ? sizeof(c64) : sizeof(c128));  // + Z
+  return e * (int64_t)sizeof(c128) + (int64_t)m * ns * (int64_t)(z32 ? sizeof(c64) : sizeof(c128)) + 26 * 256;
 }
 
 int FgmresJob::restart_fit(Ctx* ctx, int64_t n, int s, int want, int fixed, bool z32, int64_t extra) {
@@ -44,14 +90,22 @@ int FgmresJob::restart_fit(Ctx* ctx, int64_t n, int s, int want, int fixed, bool
   if (fixed > 0) m = std::max(m, fixed);
   size_t fr = 0, tot = 0;
   HIP_CHECK(hipMemGetInfo(&fr, &tot));
-  const double avail = 0.8 * (double)fr;
+  // the context's cached workspace is free for the next job
+  const double cached = (ctx->krylov_busy ? 0.0 : (double)ctx->krylov_ws.bytes) + (double)ctx->krylov_io.bytes;
+  const double avail = 0.8 * ((double)fr + cached);
   const int floor_m = fixed > 0 ? m : std::min(m, kMinRestart);
   for (int k = m; k >= floor_m; --k)
     if ((double)(bytes_needed(n, s, k, z32) + extra) <= avail) return k;
   return 0;
 }
 
-FgmresJob::FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c128* X_, const SolveOptions& o_, int m_)
+void krylov_cache_release(Ctx* ctx) {
+  if (!ctx->krylov_busy) ctx->krylov_ws.release();
+  ctx->krylov_io.release();
+}
+
+FgmresJob::FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c128* X_, const SolveOptions& o_, int m_,
+                     bool use_cache)
     : ctx(c),
       d(std::move(dd)),
       s(s_),
@@ -64,40 +118,22 @@ FgmresJob::FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c1
       z32(d->precision == HZ_PREC_MIXED),
       dcgs(delayed(s_)) {
   HZ_REQUIRE(s >= 1 && s <= 32, HZ_ERR_ARG, "fgmres: block size must be 1..32");
-  const int64_t ns = n * s;
   ldr = (int64_t)(m + 1) * s;
-  V.alloc(ctx, (m + 1) * ns);
-  if (z32)
-    Zs.alloc(ctx, m * ns);
-  else
-    Zb.alloc(ctx, m * ns);
-  W.alloc(ctx, ns);
-  Wt.alloc(ctx, ns);
-  R.alloc(ctx, ns);
-  part.alloc(ctx, (int64_t)K.nchunk * (m + 2) * s * s * (dcgs ? 2 : 1));
-  Hc.alloc(ctx, (int64_t)(m + 2) * s * s);
-  if (dcgs) {
-    Hc2.alloc(ctx, (int64_t)(m + 2) * s * s);
-    Gm.alloc(ctx, (int64_t)(m + 2) * s * 2 * s);
-    Cm.alloc(ctx, (int64_t)(m + 2) * s * 2 * s);
-    Rprev.alloc(ctx, (int64_t)s * s);
+  const int64_t total = carve(nullptr);
+  char* base = nullptr;
+  if (use_cache && !ctx->krylov_busy) {
+    if ((int64_t)ctx->krylov_ws.bytes < total) {
+      ctx->krylov_ws.release();
+      ctx->krylov_ws.alloc(ctx, (size_t)total);
+    }
+    base = ctx->krylov_ws.as<char>();
+    ctx->krylov_busy = true;
+    ws_cached = true;
   } else {
-    Hp.alloc(ctx, (int64_t)(m + 1) * s * s);
+    ws_own.alloc(ctx, (size_t)total);
+    base = ws_own.as<char>();
   }
-  Rm.alloc(ctx, (int64_t)m * s * ldr);
-  refl.alloc(ctx, (int64_t)m * 2 * s * s);
-  tau.alloc(ctx, (int64_t)m * s);
-  tmat.alloc(ctx, (int64_t)m * s * s);
-  G.alloc(ctx, ldr * s);
-  Y.alloc(ctx, (int64_t)m * s * s);
-  Gs.alloc(ctx, s * s);
-  Rs.alloc(ctx, s * s);
-  Ri.alloc(ctx, s * s);
-  Racc.alloc(ctx, s * s);
-  res.alloc(ctx, s);
-  npart.alloc(ctx, (int64_t)K.nchunk * s);
-  nrm.alloc(ctx, s);
-  flag.alloc(ctx, 2);
+  carve(base);
   bnorm.assign(s, 0.0);
   est.alloc(s);
   hflags.alloc(2);
@@ -110,6 +146,10 @@ FgmresJob::FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c1
 }
 
 FgmresJob::~FgmresJob() {
+  if (ws_cached) {  // the workspace stays with the context; the stream orders its next use
+    if (side) (void)hipStreamSynchronize(side);
+    ctx->krylov_busy = false;
+  }
   if (side) {
     (void)hipStreamSynchronize(side);
     (void)hipStreamDestroy(side);
@@ -326,7 +366,7 @@ bool FgmresJob::end_cycle() {
 
 void fgmres(Ctx* ctx, std::shared_ptr<Ddm> d, int s, const c128* B, c128* X, const SolveOptions& o, int m,
             std::vector<ColInfo>& info) {
-  FgmresJob job(ctx, d, s, B, X, o, m);
+  FgmresJob job(ctx, d, s, B, X, o, m, /*use_cache=*/true);
   job.start();
   // each cycle completes at least one column with at most one step more than it completes
   const int limit = 2 * (o.fixed_iters > 0 ? o.fixed_iters : o.max_iter) + 1;

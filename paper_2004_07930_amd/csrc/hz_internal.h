@@ -230,6 +230,9 @@ struct Ctx {
   std::atomic<bool> serving{false};  // a scheduler thread owns the stream: only hz_serve_* calls
   struct Prof* prof = nullptr;  // live kernel accounting (hz_profile_*)
   bool trace = false;           // HZ_TRACE=1 at hz_init: per-step solver lines on stderr
+  DevBuf krylov_ws;             // Krylov workspace kept between hz_solve calls
+  DevBuf krylov_io;             // hz_solve's node-major right-hand-side and solution blocks
+  bool krylov_busy = false;     // a job is using krylov_ws
 };
 
 // reference element tables (host), see p3ref.cpp

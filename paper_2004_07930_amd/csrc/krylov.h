@@ -60,6 +60,14 @@ struct ColInfo {
   int m = 0, block = 0;  // restart length and Arnoldi block width the column ran with
 };
 
+// A view of one array carved out of a job's workspace buffer (the DevArray interface minus
+// ownership).
+template <typename T>
+struct Carved {
+  T* p = nullptr;
+  T* ptr() const { return p; }
+};
+
 // One block FGMRES(m) solve as a resumable state machine.  Driver protocol:
 //   start();  loop { matvec() (Z = M^{-1} v_cur(), W = A Z);  after_matvec();
 //                    synchronise;  if (cycle_done() && end_cycle()) finished; }
@@ -76,10 +84,14 @@ struct FgmresJob {
   KrylovKernels K;
   bool z32;   // preconditioned blocks kept in complex64 (mixed-precision preconditioner)
   bool dcgs;  // delayed reorthogonalisation (16 or 32 columns); CGS2 + CholQR2 otherwise
-  DevArray<c128> V, Zb, W, Wt, R, part, Hc, Hp, Hc2, Gm, Cm, Rprev, Rm, refl, tau, tmat, G, Y, Gs, Rs, Ri, Racc;
-  DevArray<c64> Zs;
-  DevArray<double> res, npart, nrm;
-  DevArray<int> flag;
+  // every device array of the job lives in one workspace buffer: the context's cached one
+  // (hz_solve: kept between solves, so repeated solves allocate nothing) or the job's own
+  Carved<c128> V, Zb, W, Wt, R, part, Hc, Hp, Hc2, Gm, Cm, Rprev, Rm, refl, tau, tmat, G, Y, Gs, Rs, Ri, Racc;
+  Carved<c64> Zs;
+  Carved<double> res, npart, nrm;
+  Carved<int> flag;
+  DevBuf ws_own;
+  bool ws_cached = false;
   std::vector<double> bnorm, rel;
   HostPinned<double> est;  // per-column residual estimates of the latest least-squares step
   int total = 0, restarts = 0, jj = 0;
@@ -96,7 +108,8 @@ struct FgmresJob {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
-  FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c128* X_, const SolveOptions& o_, int m_);
+  FgmresJob(Ctx* c, std::shared_ptr<Ddm> dd, int s_, const c128* B_, c128* X_, const SolveOptions& o_, int m_,
+            bool use_cache = false);
   ~FgmresJob();
   FgmresJob(const FgmresJob&) = delete;
   FgmresJob& operator=(const FgmresJob&) = delete;
@@ -105,6 +118,8 @@ struct FgmresJob {
   // largest restart length <= want (>= fixed) whose Krylov memory for an s-column block, plus
   // `extra` bytes, fits in 80% of the free device memory; 0 if not even kMinRestart (or fixed) fits
   static int restart_fit(Ctx* ctx, int64_t n, int s, int want, int fixed, bool z32, int64_t extra = 0);
+  // carves the workspace of an (n, s, m) job from base (null: only sizes it); returns its bytes
+  int64_t carve(char* base);
   static constexpr int kMinRestart = 8;
   void start();                 // norms of B (synchronises), X = 0, first cycle
   c128* v_cur();                // block to precondition this step
@@ -130,5 +145,8 @@ struct FgmresJob {
 // max_iter is hit.
 void fgmres(Ctx* ctx, std::shared_ptr<Ddm> d, int s, const c128* B, c128* X, const SolveOptions& o, int m,
             std::vector<ColInfo>& info);
+// drops the context's cached Krylov workspace (before set-up and serving, which size their
+// memory by what is free)
+void krylov_cache_release(Ctx* ctx);
 
 }  // namespace hz

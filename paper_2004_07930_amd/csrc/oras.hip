@@ -10,6 +10,7 @@
 #include <type_traits>
 
 #include "ddm.h"
+#include "mfma_cplx.h"
 #include "prof.h"
 
 namespace hz {
@@ -244,47 +245,8 @@ __global__ __launch_bounds__(256) void k_bwd_gemm(const int32_t* __restrict__ wo
   }
 }
 
-// ---- complex64 sweeps on the matrix cores (blocks of 16 or 32 columns)
-//
-// Complex products in the three-multiplication form: with A = Ar + i Ai, B = Br + i Bi,
-//   P1 = Ar Br,  P2 = Ai Bi,  P3 = (Ar + Ai)(Br + Bi),  AB = (P1 - P2) + i (P3 - P1 - P2),
-// three real products where the direct form needs four.  Each is a v_mfma_f32_16x16x4f32
-// (lane l: A[l%16][l/16], B[l/16][l%16], D[4(l/16)+v][l%16]) over 4 complex k at a time:
-// lane l reads one complex entry of each operand for k = l/16 of the step.
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void mfma_3m(c64 a, c64 b, f32x4& p1, f32x4& p2, f32x4& p3) {
-  p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, b.re, p1, 0, 0, 0);
-  p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.im, b.im, p2, 0, 0, 0);
-  p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re + a.im, b.re + b.im, p3, 0, 0, 0);
-}
-
-// Complex accumulator of a 16 x 16 output tile on the matrix cores: the three products above,
-// on v_mfma_f32_16x16x4f32 (complex64) or v_mfma_f64_16x16x4f64 (complex128: same operand
-// layout, lane l: A[l%16][l/16], B[l/16][l%16]; D[l/16+4v][l%16]).
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-template <typename T>
-struct CAcc;
-template <>
-struct CAcc<float> {
-  f32x4 p1, p2, p3;
-  __device__ __forceinline__ void zero() { p1 = p2 = p3 = f32x4{0.f, 0.f, 0.f, 0.f}; }
-  __device__ __forceinline__ void mac(c64 a, c64 b) { mfma_3m(a, b, p1, p2, p3); }
-  __device__ __forceinline__ c64 get(int v) const { return cmk(p1[v] - p2[v], p3[v] - p1[v] - p2[v]); }
-  static __device__ __forceinline__ int row(int lq, int v) { return 4 * lq + v; }
-};
-template <>
-struct CAcc<double> {
-  f64x4 p1, p2, p3;
-  __device__ __forceinline__ void zero() { p1 = p2 = p3 = f64x4{0.0, 0.0, 0.0, 0.0}; }
-  __device__ __forceinline__ void mac(c128 a, c128 b) {
-    p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, p1, 0, 0, 0);
-    p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.im, p2, 0, 0, 0);
-    p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re + a.im, b.re + b.im, p3, 0, 0, 0);
-  }
-  __device__ __forceinline__ c128 get(int v) const { return cmk(p1[v] - p2[v], p3[v] - p1[v] - p2[v]); }
-  static __device__ __forceinline__ int row(int lq, int v) { return lq + 4 * v; }
-};
+// ---- sweeps on the matrix cores (blocks of 16 or 32 columns): complex products in the
+// three-multiplication form, CAcc (mfma_cplx.h)
 
 // Forward rows [i0, i0 + 64 MT) (the k_fwd_gemm product on a wider tile): wavefront wv owns
 // MT tiles of 16 rows, NG groups of 16 columns.  Each thread stages a fixed share of the next

@@ -4,8 +4,10 @@
 // parts (block-FGMRES jobs of at most 32 sources).  Requests wait in a FIFO queue; the parts
 // of the queue head are admitted one at a time when a slot is free and the part's Krylov
 // memory fits in the HBM budget next to the resident operators, factors and running parts.
-// Each request's restart length is the largest up to 40 with which one of its parts fits
-// next to the resident objects (requests that fit at no useful length are refused).  Each
+// Each request's part width and restart length are chosen at submission: the widest part
+// (32 columns and its halvings) whose restart length reaches 20 next to the resident objects,
+// else the width that allows the longest restart (requests that fit at no restart length of at
+// least 8 are refused).  Each
 // scheduler tick advances every active job by one Arnoldi step: the blocks M^{-1} v of all
 // jobs on the same operator are packed column-wise (first-fit decreasing, at most 32 columns
 // a launch) into shared launches of the preconditioner and of the SpMM (so the factors and the
@@ -57,7 +59,8 @@ struct Ticket {
   int state = 0;  // 0 queued, 1 running, 2 done
   int32_t status = HZ_OK;
   int m = 0;             // restart length (chosen at submission)
-  int nparts = 0;        // blocks of at most 32 sources
+  int w = 32;            // part width: sources per part (chosen at submission)
+  int nparts = 0;        // parts of at most w sources
   int admitted = 0;      // parts admitted by the scheduler
   int finished = 0;      // parts done
   int64_t held = 0;      // memory reserved for the admitted parts (and the host copies)
@@ -96,9 +99,10 @@ struct Serve {
 };
 
 static constexpr int kServeRestart = 40;
+static constexpr int kGoodRestart = 20;
 static constexpr int kMinRestart = 8;
 
-static int part_cols(const Ticket& t, int k) { return (int)std::min<int64_t>(32, t.req.n_rhs - 32 * (int64_t)k); }
+static int part_cols(const Ticket& t, int k) { return (int)std::min<int64_t>(t.w, t.req.n_rhs - t.w * (int64_t)k); }
 
 // device memory of part k (Krylov workspace and its node-major right-hand side and
 // solution); the first part also carries the request's host copies
@@ -121,7 +125,7 @@ static void start_part(Serve& S, Ticket& t, int k) {
   o.max_iter = t.req.max_iter > 0 ? t.req.max_iter : 500;
   o.restart = t.m;
   auto p = std::make_unique<Ticket::Part>();
-  p->c0 = 32 * k;
+  p->c0 = t.w * k;
   p->s = part_cols(t, k);
   p->Bn.alloc(ctx, n * p->s);
   p->Xn.alloc(ctx, n * p->s);
@@ -402,6 +406,7 @@ hz_status hz_serve_start(hz_ctx* c, int32_t max_slots) {
   if (!x || max_slots < 1) return HZ_ERR_ARG;
   if (x->poisoned) return HZ_ERR_HIP;
   if (x->serve) return HZ_ERR_STATE;
+  krylov_cache_release(x);  // admission counts what the context holds
   auto* S = new Serve();
   S->ctx = x;
   S->max_slots = max_slots;
@@ -430,18 +435,36 @@ hz_status hz_serve_submit(hz_ctx* c, const hz_request* req, uint64_t* ticket) {
   t->req = *req;
   t->ddm = d;
   t->t_submit = now_s();
-  t->nparts = (int)((req->n_rhs + 31) / 32);
   std::lock_guard<std::mutex> lk(S->mu);
   if (S->failed) return HZ_ERR_STATE;
-  // restart length: the largest (up to 40) with which the first part fits in the budget
-  // left after the resident objects; never admissible below kMinRestart
+  // part width and restart length: for each width (32 and its halvings, never past n_rhs) the
+  // longest restart (up to 40) with which the first part fits in the budget left after the
+  // resident objects; the widest width reaching kGoodRestart, else the longest restart (the
+  // wider width on a tie); never admissible below kMinRestart
   const int64_t avail = (int64_t)x->hbm_budget - (x->bytes_in_use - S->held);
   t->m = 0;
-  for (int m = kServeRestart; m >= kMinRestart; --m)
-    if (part_bytes(*t, 0, m) <= avail) {
-      t->m = m;
+  int best_w = 0, best_m = 0;
+  for (int w = (int)std::min<int64_t>(32, req->n_rhs); w >= 1; w = w > 1 ? w / 2 : 0) {
+    t->w = w;
+    int mw = 0;
+    for (int m = kServeRestart; m >= kMinRestart; --m)
+      if (part_bytes(*t, 0, m) <= avail) {
+        mw = m;
+        break;
+      }
+    if (mw >= kGoodRestart) {
+      best_w = w;
+      best_m = mw;
       break;
     }
+    if (mw > best_m) {
+      best_w = w;
+      best_m = mw;
+    }
+  }
+  t->w = best_w > 0 ? best_w : 32;
+  t->m = best_m;
+  t->nparts = (int)((req->n_rhs + t->w - 1) / t->w);
   if (t->m == 0) {
     S->rejected += 1;
     return HZ_ERR_BUSY;

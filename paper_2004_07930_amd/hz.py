@@ -304,6 +304,12 @@ class Context:
             keep += [ct, cc]
             cm = CoarseMesh(ct.shape[0], ct.ctypes.data, cc.shape[0], cc.ctypes.data)
         h = C.c_uint64()
+        if self._alloc_cbs is not None:
+            # memory that earlier calls returned to torch's cache goes back to the device: the
+            # set-up sizes its factorisation groups by the device's free memory
+            import torch
+
+            torch.cuda.empty_cache()
         st = self.lib.hz_setup_ddm(self.h, op.handle, _np_ptr(p), int(n_sub), int(overlap),
                                    None if cm is None else C.byref(cm), int(precision), C.byref(h))
         if self._alloc_cbs is not None:
@@ -331,13 +337,6 @@ class Context:
         xp, xm, keep2 = _block_arg(out, ddm.n)
         info = (ColInfo * s)()
         o = SolveOpts(C.sizeof(SolveOpts), float(tol), int(max_iter), int(restart), int(fixed_iters), int(block))
-        if self._alloc_cbs is not None:
-            # the library sizes the Krylov basis by the device's free memory: memory that earlier
-            # calls returned to torch's cache goes back to the device first, so that the block
-            # width and restart length do not depend on what earlier calls left cached
-            import torch
-
-            torch.cuda.empty_cache()
         st = self.lib.hz_solve_ex(self.h, ddm.handle, s, rp, rm, C.byref(o), xp, xm, info)
         self._check(st, allow=() if raise_on_not_converged else (HZ_ERR_NOT_CONVERGED,))
         return out, _info_dicts(info)
