@@ -12,7 +12,9 @@ Follows the paper's section "Domain decomposition preconditioner":
 Readings (the abstract gives no construction details; listed in the design doc):
 * overlap: delta layers of tets, each layer adds every tet sharing a vertex;
 * partition of unity: Boolean, a dof belongs to the lowest subdomain id whose
-  non-overlapping part touches it;
+  non-overlapping part touches it; or (variant) smooth: a dof's raw weight in subdomain i is
+  1 - l/(delta + 1), l its overlap layer in i (0 on the tets of the non-overlapping part, k on
+  those the k-th growth step added), normalised over the subdomains that hold the dof;
 * transmission condition: the same first-order Robin term i k |f| Fhat_f as the
   absorbing boundary, on every face of the overlapped subdomain whose neighbour tet lies
   outside it; Dirichlet dofs of the global problem stay identity rows locally;
@@ -35,6 +37,41 @@ def vertex_to_tets(tets, n_verts):
     rows = t.ravel()
     cols = np.repeat(np.arange(t.shape[0]), 4)
     return sp.csr_matrix((np.ones(rows.size, np.int8), (rows, cols)), shape=(n_verts, t.shape[0]))
+
+
+def tet_layers(tets, n_verts, partition, i, delta, v2t=None):
+    """Layer of every tet in subdomain i grown by delta vertex-adjacency layers: 0 for the
+    tets of the non-overlapping part, k for those the k-th growth step added, -1 outside."""
+    if v2t is None:
+        v2t = vertex_to_tets(tets, n_verts)
+    t = np.asarray(tets, np.int64)
+    lay = np.where(np.asarray(partition) == i, 0, -1)
+    for k in range(1, delta + 1):
+        verts = np.zeros(n_verts, bool)
+        verts[t[lay >= 0].ravel()] = True
+        touched = np.asarray(v2t[verts].sum(axis=0)).ravel() > 0
+        lay = np.where((lay < 0) & touched, k, lay)
+    return lay
+
+
+def smooth_pou(mesh: Mesh, partition, n_sub, delta, subs):
+    """Weights D_i of the smooth partition of unity, aligned with each subdomain's sorted dofs:
+    raw weight 1 - l/(delta + 1) with l the smallest layer of the subdomain's tets holding
+    the dof, divided by the sum of the raw weights of all subdomains holding it (summed in
+    subdomain order)."""
+    nverts = mesh.coords.shape[0]
+    v2t = vertex_to_tets(mesh.tets, nverts)
+    raw = []
+    for i, sd in enumerate(subs):
+        lay = tet_layers(mesh.tets, nverts, partition, i, delta, v2t)
+        sel = np.nonzero(lay >= 0)[0]
+        dl = np.full(mesh.n, delta + 1, np.int64)
+        np.minimum.at(dl, mesh.tet_dofs[sel].ravel().astype(np.int64), np.repeat(lay[sel], 20))
+        raw.append(1.0 - dl[sd.gdofs] / (delta + 1.0))
+    tot = np.zeros(mesh.n)
+    for sd, r in zip(subs, raw):
+        tot[sd.gdofs] += r
+    return [r / tot[sd.gdofs] for sd, r in zip(subs, raw)]
 
 
 def overlap_tets(tets, n_verts, partition, i, delta, v2t=None):
@@ -174,19 +211,23 @@ class Coarse:
 class ORAS:
     """Two-level ORAS preconditioner, eqs. (2lvl) and (oras)."""
 
-    def __init__(self, A, subs, coarse=None, dtype=np.complex128):
+    def __init__(self, A, subs, coarse=None, dtype=np.complex128, weights=None):
         self.A = A
         self.subs = subs
         self.coarse = coarse
         self.dtype = dtype
+        self.weights = weights  # None: Boolean partition of unity; else smooth_pou's weights
 
     def one_level(self, t):
         """sum_i R_i^T D_i A_i^{-1} R_i t for a block t (n, s)."""
         z = np.zeros_like(t, dtype=np.complex128)
-        for s in self.subs:
+        for k, s in enumerate(self.subs):
             ti = t[s.gdofs].astype(self.dtype)
             yi = s.lu.solve(ti).astype(np.complex128)
-            z[s.gdofs[s.owned]] += yi[s.owned]
+            if self.weights is None:
+                z[s.gdofs[s.owned]] += yi[s.owned]
+            else:
+                z[s.gdofs] += self.weights[k][:, None] * yi if yi.ndim == 2 else self.weights[k] * yi
         return z
 
     def apply(self, v):
@@ -204,11 +245,12 @@ class ORAS:
 
 
 def build_preconditioner(mesh: Mesh, A, velocity, freq, Q, partition, n_sub, delta,
-                         coarse_tets=None, coarse_coords=None, dtype=np.complex128):
+                         coarse_tets=None, coarse_coords=None, dtype=np.complex128, pou="boolean"):
     subs, own = build_subdomains(mesh, velocity, freq, Q, partition, n_sub, delta)
     factor_subdomains(subs, dtype)
     coarse = None
     if coarse_tets is not None:
         Z = coarse_interpolation(mesh, coarse_tets, coarse_coords)
         coarse = Coarse(Z, A, dtype)
-    return ORAS(A, subs, coarse, dtype)
+    weights = smooth_pou(mesh, partition, n_sub, delta, subs) if pou == "smooth" else None
+    return ORAS(A, subs, coarse, dtype, weights)

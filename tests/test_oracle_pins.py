@@ -139,3 +139,37 @@ def test_attenuating_operator_absorbs_inside():
         im = np.vdot(x, A @ x).imag
         assert im > 0
         np.testing.assert_allclose(im, -(k * k).imag * mass, rtol=1e-10)
+
+
+def test_smooth_pou_hand_values_and_unity():
+    """Smooth partition of unity on two cubes.  Overlap 0: the 16 interface dofs get 1/2 in
+    each subdomain, the others 1.  Overlap 1: every tet of one cube touches the interface
+    vertex shared with the other, so each subdomain holds both cubes; a dof of cube 0 off the
+    interface has layer 0 in subdomain 0 and 1 in subdomain 1: raw weights 1 and 1/2,
+    normalised 2/3 and 1/3.  The weights sum to 1 at every dof."""
+    mesh = _two_cubes()
+    part = np.repeat([0, 1], 6).astype(np.int32)
+    d0, d1 = set(mesh.tet_dofs[:6].ravel().tolist()), set(mesh.tet_dofs[6:].ravel().tolist())
+    shared = np.array(sorted(d0 & d1))
+    only0 = np.array(sorted(d0 - d1))
+    for delta in (0, 1):
+        subs, own = ddm.build_subdomains(mesh, np.ones(12), 0.3, None, part, 2, delta)
+        wts = ddm.smooth_pou(mesh, part, 2, delta, subs)
+        acc = np.zeros(mesh.n)
+        for sd, wi in zip(subs, wts):
+            acc[sd.gdofs] += wi
+            assert np.all(wi > 0) and np.all(wi <= 1)
+        np.testing.assert_allclose(acc, 1.0, rtol=0, atol=1e-15)
+        full0 = np.zeros(mesh.n)
+        full0[subs[0].gdofs] = wts[0]
+        np.testing.assert_allclose(full0[shared], 0.5, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(full0[only0], 1.0 if delta == 0 else 2.0 / 3.0, rtol=0, atol=1e-15)
+    # a larger cut with two overlap layers: weights still sum to 1 everywhere
+    tets, coords = _lattice(6)
+    m6 = fem.Mesh(tets, coords)
+    part6 = w.box_partition(6, 6, 6, 3, 2, 1)
+    subs, own = ddm.build_subdomains(m6, np.ones(tets.shape[0]), 0.3, None, part6, 6, 2)
+    acc = np.zeros(m6.n)
+    for sd, wi in zip(subs, ddm.smooth_pou(m6, part6, 6, 2, subs)):
+        acc[sd.gdofs] += wi
+    np.testing.assert_allclose(acc, 1.0, rtol=0, atol=1e-15)
