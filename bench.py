@@ -270,13 +270,9 @@ def run_serve(args):
     reqs = serve_requests(args.serve)
     probs = serve_workloads()
     free0, _ = torch.cuda.mem_get_info()
-    import workloads as w
-
-    n = [w.kuhn_ndofs(*q.grid) for q, _ in probs]
-    # caller-side tensors (right-hand sides and solutions of every request) are torch's, outside
-    # the library's accounting: keep them out of the serving budget
-    caller = sum(2 * len(src) * n[op] * 16 for _, op, src in reqs)
-    ctx = hz.Context(0, stream=torch.cuda.current_stream(), hbm_budget=int(0.85 * free0) - caller)
+    # requests are host-memory blocks (the library stages each while it runs): the budget is
+    # the device's free memory less a margin for torch's own use
+    ctx = hz.Context(0, stream=torch.cuda.current_stream(), hbm_budget=int(0.92 * free0))
     ops, setup = [], {}
     for k, (q, coarse) in enumerate(probs):
         t0 = time.perf_counter()
@@ -289,9 +285,12 @@ def run_serve(args):
                                     seconds=time.perf_counter() - t0, ddm_gb=ctx.ddm_stats(d)["device_bytes"] / 1e9)
         ops.append([mesh, op, d, q, coarse])
         print(f"serve: {SERVE_FREQS[k]} Hz ready {setup[SERVE_FREQS[k]]}", file=sys.stderr, flush=True)
-    rhs = [ctx.point_sources(ops[op][0], src, out=torch.empty((len(src), ops[op][0].n), dtype=torch.complex128,
-                                                                device="cuda")) for _, op, src in reqs]
+    rhs = []  # host blocks
+    for k, (_, op, src) in enumerate(reqs):
+        rhs.append(ctx.point_sources(ops[op][0], src))
+        print(f"serve: request {k} formed ({len(src)} sources at {SERVE_FREQS[op]} Hz)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     ctx.serve_start(max_slots=8)
     tickets = []
     t_start = time.perf_counter()
@@ -301,11 +300,21 @@ def run_serve(args):
             if delay > 0:
                 time.sleep(delay)
             tickets.append(ctx.submit(ops[op][2], b, tol=1e-6))
-        done = []
-        for k, tk in enumerate(tickets):
-            done.append(ctx.wait(tk))
-            print(f"serve: request {k} done ({len(reqs[k][2])} sources at {SERVE_FREQS[reqs[k][1]]} Hz, "
-                  f"{time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
+        done = [None] * len(tickets)
+        pending = set(range(len(tickets)))
+        while pending:  # completions in any order
+            for k in sorted(pending):
+                if not ctx.poll(tickets[k]):
+                    continue
+                x, info, status = ctx.wait(tickets[k])
+                done[k] = (None, info, status)  # the solution is checked through its residuals, then dropped
+                tickets[k] = None
+                pending.discard(k)
+                print(f"serve: request {k} done ({len(reqs[k][2])} sources at {SERVE_FREQS[reqs[k][1]]} Hz, "
+                      f"{time.perf_counter() - t_start:.1f} s, part width {info[0]['block']}, restart "
+                      f"{info[0]['restart_len']}, {max(i['iters'] for i in info)} iterations)", file=sys.stderr,
+                      flush=True)
+            time.sleep(0.05)
         st = ctx.serve_stats()
     finally:
         ctx.serve_stop()
@@ -364,6 +373,8 @@ def run_serve(args):
                    "requests": len(reqs), "sources": n_src, "operators": setup, "per_operator": per_op},
         "latency": {"p50_s": st["p50_s"], "p99_s": st["p99_s"]}, "wall_s": wall,
         "completed": st["completed"], "rejected": st["rejected"], "all_converged": ok,
+        "iters": [max(i["iters"] for i in info) for _, info, _ in done],
+        "part_width": [info[0]["block"] for _, info, _ in done],
         "fp64_sequential": fp64,
         "mixed_served_over_fp64": (st["sources_per_s"] / fp64["sources_per_s"]) if fp64 else None,
         "total_wall_s": time.perf_counter() - t_all}))
@@ -387,7 +398,9 @@ def main():
     ap.add_argument("--workload", default="layered-5hz", choices=list(WORKLOADS) + ["cube8"])
     ap.add_argument("--restart", type=int, default=0, help="FGMRES restart length (0: the workload's)")
     ap.add_argument("--block", type=int, default=-1, help="Arnoldi block width (-1: the workload's, 0: automatic)")
-    ap.add_argument("--fp64-steps", type=int, default=2, help="timed steps of the FP64 solve (0: skip it)")
+    ap.add_argument("--fp64-steps", type=int, default=1, help="timed steps of the FP64 solve (0: skip it)")
+    ap.add_argument("--pou", default="boolean", choices=["boolean", "smooth"],
+                    help="partition of unity of the one-level preconditioner (the smooth one is an ablation)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -453,7 +466,8 @@ def main():
         torch.cuda.empty_cache()
         t0 = time.perf_counter()
         try:
-            d = ctx.setup_ddm(op, p.partition, p.n_sub, p.overlap, coarse=coarse, precision=prec)
+            d = ctx.setup_ddm(op, p.partition, p.n_sub, p.overlap, coarse=coarse, precision=prec,
+                              pou=hz.HZ_POU_SMOOTH if args.pou == "smooth" else hz.HZ_POU_BOOLEAN)
         except hz.HzError as e:  # FP64 factors may not fit next to the operator
             results[label] = {"error": str(e)}
             log(f"{label}: {e}")
@@ -544,7 +558,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec["desc"], "step": f"{S} point sources formed on the GPU and solved to {p.tol}",
                    "n_dofs": mesh.n, "nnz": int(ctx.csr(op, values=False)[1].size), "n_sources": len(srcs),
-                   "n_sub": p.n_sub, "overlap": p.overlap, "coarse": coarse is not None, "tol": p.tol,
+                   "n_sub": p.n_sub, "overlap": p.overlap, "coarse": coarse is not None, "pou": args.pou, "tol": p.tol,
                    "restart": restart, "block": block, "assembly_s": t_asm},
         "latency": {"p50_s": head["p50_s"], "p99_s": head["p99_s"], "of": "one 16-source step (solve latency)"},
         "err_mixed_vs_fp64": err,

@@ -56,6 +56,7 @@ typedef uint64_t hz_handle;
 enum { HZ_BC_NONE = 0, HZ_BC_IMPEDANCE = 1, HZ_BC_DIRICHLET = 2 };
 enum { HZ_PREC_C128 = 0, HZ_PREC_MIXED = 1 };
 enum { HZ_MEM_HOST = 0, HZ_MEM_DEVICE = 1 };
+enum { HZ_POU_BOOLEAN = 0, HZ_POU_SMOOTH = 1 };
 
 typedef struct {
   size_t struct_size;  /* sizeof(hz_init_opts)                                        */
@@ -135,6 +136,28 @@ typedef struct {
  */
 hz_status hz_setup_ddm(hz_ctx* ctx, hz_handle op, const int32_t* partition, int32_t n_sub,
                        int32_t overlap, const hz_coarse_mesh* coarse, int precision, hz_handle* ddm);
+
+/*
+ * hz_setup_ddm_ex -- hz_setup_ddm with options.  Paper: eq. (oras), D_i "local diagonal
+ * matrices representing the partition of unity" (no construction is given).
+ *   opts->precision  as in hz_setup_ddm
+ *   opts->pou        HZ_POU_BOOLEAN: each dof belongs to the lowest subdomain id whose
+ *                    non-overlapping tets hold it (D_i = 0 or 1; hz_setup_ddm's choice);
+ *                    HZ_POU_SMOOTH: a dof's raw weight in subdomain i is 1 - l / (overlap + 1),
+ *                    l its layer in i (0 on the non-overlapping tets, k on the tets the k-th
+ *                    overlap step added; the smallest over the tets holding it), divided by the
+ *                    sum of its raw weights over the subdomains holding it (subdomain order).
+ * Errors: as hz_setup_ddm; HZ_ERR_ABI on struct_size; HZ_ERR_ARG on an unknown pou or an
+ * overlap above 250.
+ */
+typedef struct {
+  size_t struct_size;  /* sizeof(hz_ddm_opts) */
+  int precision;       /* HZ_PREC_C128 or HZ_PREC_MIXED */
+  int pou;             /* HZ_POU_BOOLEAN or HZ_POU_SMOOTH */
+} hz_ddm_opts;
+hz_status hz_setup_ddm_ex(hz_ctx* ctx, hz_handle op, const int32_t* partition, int32_t n_sub,
+                          int32_t overlap, const hz_coarse_mesh* coarse, const hz_ddm_opts* opts,
+                          hz_handle* ddm);
 
 typedef struct {
   int32_t iters;        /* inner FGMRES iterations done for this column's block */
@@ -343,6 +366,9 @@ hz_status hz_get_csr(hz_ctx* ctx, hz_handle op, int64_t* rowptr, int32_t* col, d
 hz_status hz_get_subdomain_size(hz_ctx* ctx, hz_handle ddm, int32_t i, int64_t* n_i, int64_t* nnz_i);
 hz_status hz_get_subdomain(hz_ctx* ctx, hz_handle ddm, int32_t i, int32_t* gdofs, uint8_t* owned,
                            int64_t* rowptr, int32_t* col, double* val /*c128, nullable*/);
+/* partition-of-unity weights D_i of subdomain i, aligned with its sorted dofs (0/1 for the
+ * Boolean partition) */
+hz_status hz_get_pou(hz_ctx* ctx, hz_handle ddm, int32_t i, double* weights);
 hz_status hz_get_coarse_size(hz_ctx* ctx, hz_handle ddm, int64_t* n_c, int64_t* nnz);
 hz_status hz_get_coarse(hz_ctx* ctx, hz_handle ddm, int64_t* rowptr, int32_t* col, double* val /*Z, real*/);
 

@@ -309,17 +309,39 @@ hz_status hz_assemble(hz_ctx* c, hz_handle mesh, const double* velocity, const d
   });
 }
 
-hz_status hz_setup_ddm(hz_ctx* c, hz_handle op, const int32_t* partition, int32_t n_sub, int32_t overlap,
-                       const hz_coarse_mesh* coarse, int precision, hz_handle* ddm) {
+hz_status hz_setup_ddm_ex(hz_ctx* c, hz_handle op, const int32_t* partition, int32_t n_sub, int32_t overlap,
+                          const hz_coarse_mesh* coarse, const hz_ddm_opts* opts, hz_handle* ddm) {
   return guard(c, [&] {
     HZ_REQUIRE(ddm, HZ_ERR_ARG, "hz_setup_ddm: null output");
+    HZ_REQUIRE(opts && opts->struct_size == sizeof(hz_ddm_opts), HZ_ERR_ABI, "hz_setup_ddm_ex: bad options struct");
     auto o = lookup(c, c->ops, op, "operator");
     krylov_cache_release(c);  // set-up sizes its arena by the free memory
-    auto d = build_ddm(c, o, partition, n_sub, overlap, coarse, precision);
+    auto d = build_ddm(c, o, partition, n_sub, overlap, coarse, opts->precision, opts->pou);
     const hz_handle h = new_handle(c);
     std::lock_guard<std::mutex> lk(c->mu);
     c->ddms[h] = d;
     *ddm = h;
+  });
+}
+
+hz_status hz_setup_ddm(hz_ctx* c, hz_handle op, const int32_t* partition, int32_t n_sub, int32_t overlap,
+                       const hz_coarse_mesh* coarse, int precision, hz_handle* ddm) {
+  hz_ddm_opts o{};
+  o.struct_size = sizeof(o);
+  o.precision = precision;
+  o.pou = HZ_POU_BOOLEAN;
+  return hz_setup_ddm_ex(c, op, partition, n_sub, overlap, coarse, &o, ddm);
+}
+
+hz_status hz_get_pou(hz_ctx* c, hz_handle ddm, int32_t i, double* weights) {
+  return guard(c, [&] {
+    auto d = lookup(c, c->ddms, ddm, "ddm");
+    HZ_REQUIRE(i >= 0 && i < d->n_sub && weights, HZ_ERR_ARG, "hz_get_pou: bad arguments");
+    const Subdomain& S = d->subs[i];
+    if (d->pou == HZ_POU_SMOOTH)
+      std::copy(S.pouw.begin(), S.pouw.end(), weights);
+    else
+      for (int64_t l = 0; l < S.n; ++l) weights[l] = S.owned[l] ? 1.0 : 0.0;
   });
 }
 

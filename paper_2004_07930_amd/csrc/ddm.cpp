@@ -177,6 +177,8 @@ void build_subdomain(const Mesh& m, const std::vector<int32_t>& part, const std:
   const int64_t T = m.T;
   // --- overlap: delta vertex-adjacency layers
   std::vector<int64_t> cur;
+  // inside[t] = 1 + the tet's layer (0: outside): 1 for the non-overlapping part, k + 1 for
+  // the tets the k-th growth step adds
   for (int64_t t = 0; t < T; ++t)
     if (part[t] == i) {
       cur.push_back(t);
@@ -190,7 +192,7 @@ void build_subdomain(const Mesh& m, const std::vector<int32_t>& part, const std:
         for (int64_t k = v2t_ptr[g]; k < v2t_ptr[g + 1]; ++k) {
           const int64_t u = v2t[k];
           if (!inside[u]) {
-            inside[u] = 1;
+            inside[u] = (uint8_t)(layer + 2);
             add.push_back(u);
           }
         }
@@ -213,6 +215,12 @@ void build_subdomain(const Mesh& m, const std::vector<int32_t>& part, const std:
     S.owned[k] = owner[gd[k]] == i;
     S.dir[k] = m.dirichlet[gd[k]];
   }
+  S.layer.assign(S.n, (uint8_t)(delta + 1));
+  for (int64_t t : cur)
+    for (int l = 0; l < 20; ++l) {
+      uint8_t& y = S.layer[loc[m.tet_dofs[t * 20 + l]]];
+      y = std::min<uint8_t>(y, (uint8_t)(inside[t] - 1));
+    }
   // --- Robin faces: physical impedance or a cut (neighbour outside the overlapped set)
   std::vector<uint8_t> robin(cur.size(), 0);
   for (size_t q = 0; q < cur.size(); ++q) {
@@ -345,6 +353,7 @@ int64_t Ddm::device_bytes() const {
        d_orig_dst.bytes() + d_own_src.bytes() + d_lrowptr.bytes() + d_lgptr.bytes() + d_lcol.bytes() +
        d_lgsrc.bytes() + d_ldir.bytes() + d_lval.bytes() + d_level_fronts.bytes() + d_flf.bytes();
   b += d_factor.bytes + d_update.bytes + d_dinv.bytes;
+  b += d_pou_ptr.bytes() + d_pou_pos.bytes() + d_pou_w.bytes();
   b += d_fwd_work.bytes() + d_bwd_work.bytes() + d_imap.bytes();
   for (int t = 0; t < 2; ++t) b += d_fwdm_work[t].bytes() + d_bwdm_work[t].bytes();
   if (coarse)
@@ -357,11 +366,13 @@ int64_t Ddm::device_bytes() const {
 void build_coarse_host(const Mesh& m, const hz_coarse_mesh* cm, CoarseSpace& cs);
 
 std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int32_t* partition, int32_t n_sub,
-                               int32_t overlap, const hz_coarse_mesh* coarse, int precision) {
+                               int32_t overlap, const hz_coarse_mesh* coarse, int precision, int pou) {
   const double t0 = wall_time();
   const Mesh& m = *op->mesh;
   HZ_REQUIRE(partition && n_sub >= 1 && overlap >= 0, HZ_ERR_ARG, "hz_setup_ddm: bad arguments");
   HZ_REQUIRE(precision == HZ_PREC_C128 || precision == HZ_PREC_MIXED, HZ_ERR_ARG, "hz_setup_ddm: bad precision");
+  HZ_REQUIRE(pou == HZ_POU_BOOLEAN || pou == HZ_POU_SMOOTH, HZ_ERR_ARG, "hz_setup_ddm: bad partition of unity");
+  HZ_REQUIRE(overlap <= 250, HZ_ERR_ARG, "hz_setup_ddm: overlap above 250 layers");
   std::vector<int32_t> part(partition, partition + m.T);
   std::vector<int64_t> cnt(n_sub, 0);
   for (int64_t t = 0; t < m.T; ++t) {
@@ -372,6 +383,7 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   auto d = std::make_shared<Ddm>();
   d->op = op;
   d->precision = precision;
+  d->pou = pou;
   d->n_sub = n_sub;
   d->overlap = overlap;
   // owners: lowest subdomain whose own tets touch the dof
@@ -644,6 +656,36 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     }
   }
   for (int64_t g = 0; g < m.n; ++g) HZ_REQUIRE(d->own_src[g] >= 0, HZ_ERR_STATE, "hz_setup_ddm: unowned dof");
+  if (pou == HZ_POU_SMOOTH) {
+    // raw weight 1 - layer / (overlap + 1), normalised over the subdomains holding the dof
+    // (sums in subdomain order); per global dof its (position, weight) pairs in that order
+    std::vector<double> tot(m.n, 0.0);
+    std::vector<int64_t> cnt(m.n + 1, 0);
+    for (int32_t i = 0; i < n_sub; ++i) {
+      const Subdomain& S = d->subs[i];
+      for (int64_t l = 0; l < S.n; ++l) {
+        tot[S.gdofs[l]] += 1.0 - (double)S.layer[l] / (overlap + 1.0);
+        cnt[S.gdofs[l] + 1]++;
+      }
+    }
+    for (int64_t g = 0; g < m.n; ++g) cnt[g + 1] += cnt[g];
+    std::vector<int64_t> pos(cnt[m.n]), fill(cnt.begin(), cnt.end() - 1);
+    std::vector<double> wt(cnt[m.n]);
+    for (int32_t i = 0; i < n_sub; ++i) {
+      Subdomain& S = d->subs[i];
+      S.pouw.resize(S.n);
+      for (int64_t l = 0; l < S.n; ++l) {
+        const int32_t g = S.gdofs[l];
+        S.pouw[l] = (1.0 - (double)S.layer[l] / (overlap + 1.0)) / tot[g];
+        const int64_t k = fill[g]++;
+        pos[k] = S.vec_off + S.ipos[l];
+        wt[k] = S.pouw[l];
+      }
+    }
+    d->d_pou_ptr.upload(ctx, cnt);
+    d->d_pou_pos.upload(ctx, pos);
+    d->d_pou_w.upload(ctx, wt);
+  }
   // --- device: front descriptors, maps, local operators
   std::vector<FrontDesc> fd(d->fronts.size());
   int64_t wrows = 0;

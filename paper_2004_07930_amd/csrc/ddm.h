@@ -52,6 +52,8 @@ struct Subdomain {
   std::vector<int32_t> col;
   GatherMap gm;
   std::vector<uint8_t> dir;       // local Dirichlet flags
+  std::vector<uint8_t> layer;     // overlap layer of each local dof (smallest over its tets)
+  std::vector<double> pouw;       // smooth partition of unity: weight of each local dof
   int64_t vec_off = 0;            // offset in the concatenated local vector
   int64_t csr_off = 0;            // offset of its nnz in the concatenated local CSR values
   int64_t row_off = 0;            // offset of its rows in the concatenated rowptr
@@ -99,6 +101,7 @@ constexpr int kBwdColsMfma[2] = {64, 128};
 struct Ddm {
   std::shared_ptr<Operator> op;
   int precision = HZ_PREC_C128;
+  int pou = HZ_POU_BOOLEAN;
   int32_t n_sub = 0, overlap = 0;
   std::vector<Subdomain> subs;
   std::vector<Front> fronts;
@@ -151,13 +154,17 @@ struct Ddm {
   // (index 0: blocks of up to 16 columns, 1: up to 32); empty until tuned
   std::vector<uint8_t> tile_fwd[2], tile_bwd[2];
   DevArray<int32_t> d_imap;
+  // smooth partition of unity: per global dof, its (local vector position, weight) pairs in
+  // subdomain order
+  DevArray<int64_t> d_pou_ptr, d_pou_pos;
+  DevArray<double> d_pou_w;
   PrecondWork pw;  // solve workspace (precond_apply)
   int64_t device_bytes() const;
 };
 
 // ddm.cpp
 std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int32_t* partition, int32_t n_sub,
-                               int32_t overlap, const hz_coarse_mesh* coarse, int precision);
+                               int32_t overlap, const hz_coarse_mesh* coarse, int precision, int pou);
 // factor.hip
 void factor_all(Ctx* ctx, Ddm& d);
 // coarse.hip

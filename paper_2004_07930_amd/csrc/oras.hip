@@ -38,6 +38,25 @@ __global__ void k_scatter_owner(int64_t n, int s, const int64_t* __restrict__ ow
   z[k] = cmk((TZ)r.re, (TZ)r.im);
 }
 
+// the smooth partition of unity instead: z = sum over the subdomains holding the dof (in
+// subdomain order) of weight x local value, summed in FP64 (+ add)
+template <typename T, typename TQ, typename TZ>
+__global__ void k_scatter_pou(int64_t n, int s, const int64_t* __restrict__ ptr, const int64_t* __restrict__ pos,
+                              const double* __restrict__ wt, const cplx<T>* __restrict__ loc,
+                              const cplx<TQ>* __restrict__ add, cplx<TZ>* __restrict__ z) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n * s) return;
+  const int64_t g = k / s;
+  const int c = (int)(k - g * s);
+  c128 r = cmk(0.0, 0.0);
+  for (int64_t e = ptr[g]; e < ptr[g + 1]; ++e) {
+    const cplx<T> v = loc[pos[e] * s + c];
+    r = r + cmk(wt[e] * (double)v.re, wt[e] * (double)v.im);
+  }
+  if (add) r = r + cmk((double)add[k].re, (double)add[k].im);
+  z[k] = cmk((TZ)r.re, (TZ)r.im);
+}
+
 // Forward, step 1 of a level: work block w = [b_p; 0] + extend-add of the children's
 // contributions, through the inverse maps (own, child 0, child 1: a fixed order).  One block
 // per 64-row tile of a front (the forward worklist: tiles of one front on one XCD).
@@ -655,8 +674,12 @@ void one_level(Ctx* ctx, Ddm& d, int s, const cplx<TS>* v, const cplx<TQ>* add, 
     sweep<T, 32, TS>(ctx, d, s, v, bi, bo, wb);
   else
     fail(HZ_ERR_ARG, "preconditioner: at most 32 columns per block");
-  hipLaunchKernelGGL((k_scatter_owner<T, TQ, TZ>), dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, st, n, s,
-                     d.d_own_src.ptr(), bi, add, z);
+  if (d.pou == HZ_POU_SMOOTH)
+    hipLaunchKernelGGL((k_scatter_pou<T, TQ, TZ>), dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, st, n, s,
+                       d.d_pou_ptr.ptr(), d.d_pou_pos.ptr(), d.d_pou_w.ptr(), bi, add, z);
+  else
+    hipLaunchKernelGGL((k_scatter_owner<T, TQ, TZ>), dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, st, n, s,
+                       d.d_own_src.ptr(), bi, add, z);
   HIP_CHECK(hipGetLastError());
 }
 

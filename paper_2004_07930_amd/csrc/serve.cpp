@@ -4,6 +4,9 @@
 // parts (block-FGMRES jobs of at most 32 sources).  Requests wait in a FIFO queue; the parts
 // of the queue head are admitted one at a time when a slot is free and the part's Krylov
 // memory fits in the HBM budget next to the resident operators, factors and running parts.
+// While the head waits for memory, parts of later requests that fit may start in its place
+// (backfill), for at most kBackfillWindow seconds of the head's wait; after that admission is
+// strictly FIFO until the head has started, so no request waits behind others forever.
 // Each request's part width and restart length are chosen at submission: the widest part
 // (32 columns and its halvings) whose restart length reaches 20 next to the resident objects,
 // else the width that allows the longest restart (requests that fit at no restart length of at
@@ -57,6 +60,7 @@ struct Ticket {
   std::shared_ptr<Ddm> ddm;
   double t_submit = 0, t_done = 0;
   int state = 0;  // 0 queued, 1 running, 2 done
+  double t_blocked = 0;  // when this request, at the queue head, first waited for memory (0: not waiting)
   int32_t status = HZ_OK;
   int m = 0;             // restart length (chosen at submission)
   int w = 32;            // part width: sources per part (chosen at submission)
@@ -101,6 +105,7 @@ struct Serve {
 static constexpr int kServeRestart = 40;
 static constexpr int kGoodRestart = 20;
 static constexpr int kMinRestart = 8;
+static constexpr double kBackfillWindow = 30.0;
 
 static int part_cols(const Ticket& t, int k) { return (int)std::min<int64_t>(t.w, t.req.n_rhs - t.w * (int64_t)k); }
 
@@ -277,16 +282,30 @@ static void scheduler(Serve* S) {
         std::unique_lock<std::mutex> lk(S->mu);
         S->cv.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->running.empty(); });
         if (S->stop && S->running.empty() && S->queue.empty()) break;  // stop drains every request
-        // FIFO admission of parts by slots and memory (no overtaking, so large requests are
-        // not starved); the first part of an idle server is always admitted
+        // FIFO admission of parts by slots and memory; while the head waits for memory, later
+        // requests whose parts fit may go first (backfill) for kBackfillWindow seconds of that
+        // wait; the first part of an idle server is always admitted
         int64_t pending = 0;
-        while (!S->queue.empty()) {
-          auto t = S->queue.front();
+        const double tnow = now_s();
+        for (auto it = S->queue.begin(); it != S->queue.end();) {
+          auto t = *it;
+          const bool head = it == S->queue.begin();
           const int64_t pb = part_bytes(*t, t->admitted, t->m);
           const bool idle = S->active_parts == 0;
           const bool slots_ok = idle || S->active_parts + 1 <= S->max_slots;
           const bool mem_ok = idle || ctx->bytes_in_use + pending + pb <= (int64_t)ctx->hbm_budget;
-          if (!slots_ok || !mem_ok) break;
+          if (!slots_ok) break;
+          if (!mem_ok) {
+            if (!head) {
+              ++it;  // a later request may still fit
+              continue;
+            }
+            if (t->t_blocked == 0) t->t_blocked = tnow;
+            if (tnow - t->t_blocked > kBackfillWindow) break;  // strict FIFO from now on
+            ++it;
+            continue;
+          }
+          if (head) t->t_blocked = 0;
           ++S->active_parts;
           pending += pb;
           t->held += pb;
@@ -296,7 +315,7 @@ static void scheduler(Serve* S) {
             S->running.push_back(t);
           }
           admit.emplace_back(t, t->admitted++);
-          if (t->admitted == t->nparts) S->queue.pop_front();
+          if (t->admitted == t->nparts) it = S->queue.erase(it);  // else: its next part, same request
         }
       }
       // start the admitted parts; a part whose memory the allocator cannot give now goes
@@ -317,7 +336,11 @@ static void scheduler(Serve* S) {
             S->held -= pb;
             --S->active_parts;
             --tb->admitted;
-            if (S->queue.empty() || S->queue.front() != tb) S->queue.push_front(tb);
+            if (std::find(S->queue.begin(), S->queue.end(), tb) == S->queue.end()) {  // back in FIFO place
+              auto pos = std::find_if(S->queue.begin(), S->queue.end(),
+                                      [&](const std::shared_ptr<Ticket>& q) { return q->id > tb->id; });
+              S->queue.insert(pos, tb);
+            }
           }
           if (e.code == HZ_ERR_ARG || S->active_parts == 0) {  // bad block, or it cannot fit even alone:
             t->status = e.code;                                  // the request fails

@@ -22,12 +22,14 @@ HZ_ERR_SINGULAR, HZ_ERR_BUSY, HZ_ERR_STATE, HZ_ERR_ABI = -5, -6, -7, -8
 HZ_BC_NONE, HZ_BC_IMPEDANCE, HZ_BC_DIRICHLET = 0, 1, 2
 HZ_PREC_C128, HZ_PREC_MIXED = 0, 1
 HZ_MEM_HOST, HZ_MEM_DEVICE = 0, 1
+HZ_POU_BOOLEAN, HZ_POU_SMOOTH = 0, 1
 
 _STATUS = {0: "HZ_OK", -1: "HZ_ERR_ARG", -2: "HZ_ERR_OOM", -3: "HZ_ERR_HIP", -4: "HZ_ERR_NOT_CONVERGED",
            -5: "HZ_ERR_SINGULAR", -6: "HZ_ERR_BUSY", -7: "HZ_ERR_STATE", -8: "HZ_ERR_ABI"}
 
 EXPORTS = [
     "hz_init", "hz_finalize", "hz_last_error", "hz_release", "hz_mesh", "hz_assemble", "hz_setup_ddm",
+    "hz_setup_ddm_ex", "hz_get_pou",
     "hz_solve", "hz_solve_ex", "hz_point_sources", "hz_spmm", "hz_spmm_c64x", "hz_spmm_noalloc", "hz_precond", "hz_ddm_stats_get", "hz_ddm_levels",
     "hz_serve_start", "hz_serve_submit", "hz_serve_poll", "hz_serve_wait", "hz_serve_stats_get",
     "hz_serve_stop", "hz_get_dofmap", "hz_get_csr_size", "hz_get_csr", "hz_get_subdomain_size",
@@ -65,6 +67,10 @@ class ColInfo(C.Structure):
 def _info_dicts(arr):
     return [dict(iters=i.iters, restarts=i.restarts, rel_residual=i.rel_residual, status=i.status,
                  restart_len=i.restart_len, block=i.block) for i in arr]
+
+
+class DdmOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("precision", C.c_int), ("pou", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -128,6 +134,8 @@ def load(path: str | None = None):
         "hz_mesh": [vp, i64, vp, i64, vp, vp, C.POINTER(u64), C.POINTER(i64)],
         "hz_assemble": [vp, u64, vp, vp, C.c_double, C.POINTER(u64)],
         "hz_setup_ddm": [vp, u64, vp, i32, i32, C.POINTER(CoarseMesh), C.c_int, C.POINTER(u64)],
+        "hz_setup_ddm_ex": [vp, u64, vp, i32, i32, C.POINTER(CoarseMesh), C.POINTER(DdmOpts), C.POINTER(u64)],
+        "hz_get_pou": [vp, u64, i32, vp],
         "hz_solve": [vp, u64, i64, vp, C.c_int, C.c_double, i32, vp, C.c_int, vp],
         "hz_solve_ex": [vp, u64, i64, vp, C.c_int, C.POINTER(SolveOpts), vp, C.c_int, vp],
         "hz_point_sources": [vp, u64, i64, vp, vp, vp, C.c_int],
@@ -294,7 +302,7 @@ class Context:
                                          float(freq), C.byref(h)))
         return Operator(self, h.value, mesh)
 
-    def setup_ddm(self, op, partition, n_sub, overlap, coarse=None, precision=HZ_PREC_C128):
+    def setup_ddm(self, op, partition, n_sub, overlap, coarse=None, precision=HZ_PREC_C128, pou=HZ_POU_BOOLEAN):
         p = np.ascontiguousarray(partition, np.int32)
         cm = None
         keep = []
@@ -310,8 +318,9 @@ class Context:
             import torch
 
             torch.cuda.empty_cache()
-        st = self.lib.hz_setup_ddm(self.h, op.handle, _np_ptr(p), int(n_sub), int(overlap),
-                                   None if cm is None else C.byref(cm), int(precision), C.byref(h))
+        o = DdmOpts(C.sizeof(DdmOpts), int(precision), int(pou))
+        st = self.lib.hz_setup_ddm_ex(self.h, op.handle, _np_ptr(p), int(n_sub), int(overlap),
+                                      None if cm is None else C.byref(cm), C.byref(o), C.byref(h))
         if self._alloc_cbs is not None:
             # the factorisation's transient buffers went back to torch's cache: hand them back to
             # the device, where the library's free-memory queries (Krylov sizing) see them
@@ -500,6 +509,14 @@ class Context:
         self._check(self.lib.hz_get_subdomain(self.h, ddm.handle, int(i), _np_ptr(g), _np_ptr(own), _np_ptr(rp),
                                               _np_ptr(ci), None if va is None else _np_ptr(va)))
         return g, own.astype(bool), rp, ci, va
+
+    def pou_weights(self, ddm, i):
+        """Partition-of-unity weights of subdomain i, aligned with its sorted dofs."""
+        n, nnz = C.c_int64(), C.c_int64()
+        self._check(self.lib.hz_get_subdomain_size(self.h, ddm.handle, int(i), C.byref(n), C.byref(nnz)))
+        out = np.empty(n.value, np.float64)
+        self._check(self.lib.hz_get_pou(self.h, ddm.handle, int(i), _np_ptr(out)))
+        return out
 
     def coarse(self, ddm):
         nc, nnz = C.c_int64(), C.c_int64()

@@ -41,7 +41,7 @@ def test_binding_refuses_missing_library(tmp_path):
 
 STRUCTS = {  # header type -> binding class name
     "hz_init_opts": "InitOpts", "hz_coarse_mesh": "CoarseMesh", "hz_col_info": "ColInfo",
-    "hz_solve_opts": "SolveOpts", "hz_ddm_stats": "DdmStats", "hz_ddm_level": "DdmLevel",
+    "hz_solve_opts": "SolveOpts", "hz_ddm_opts": "DdmOpts", "hz_ddm_stats": "DdmStats", "hz_ddm_level": "DdmLevel",
     "hz_kernel_stat": "KernelStat", "hz_request": "Request", "hz_serve_stats": "ServeStats",
 }
 
