@@ -272,7 +272,7 @@ def run_serve(args):
     free0, _ = torch.cuda.mem_get_info()
     # requests are host-memory blocks (the library stages each while it runs): the budget is
     # the device's free memory less a margin for torch's own use
-    ctx = hz.Context(0, stream=torch.cuda.current_stream(), hbm_budget=int(0.92 * free0))
+    ctx = hz.Context(0, stream=torch.cuda.current_stream(), hbm_budget=int(0.92 * free0), allocator="hip")
     ops, setup = [], {}
     for k, (q, coarse) in enumerate(probs):
         t0 = time.perf_counter()
@@ -302,7 +302,15 @@ def run_serve(args):
             tickets.append(ctx.submit(ops[op][2], b, tol=1e-6))
         done = [None] * len(tickets)
         pending = set(range(len(tickets)))
+        t_note, steps_noted = time.perf_counter(), 0
         while pending:  # completions in any order
+            if time.perf_counter() - t_note > 20.0:  # the server's own progress (parts finished, steps taken)
+                sp = ctx.serve_stats()
+                if sp["steps"] > steps_noted:
+                    print(f"serve: {time.perf_counter() - t_start:.0f} s: {sp['parts_done']} parts done, "
+                          f"{sp['steps']} block steps, {sp['active_parts']} parts running", file=sys.stderr, flush=True)
+                    steps_noted = sp["steps"]
+                t_note = time.perf_counter()
             for k in sorted(pending):
                 if not ctx.poll(tickets[k]):
                     continue
@@ -312,7 +320,7 @@ def run_serve(args):
                 pending.discard(k)
                 print(f"serve: request {k} done ({len(reqs[k][2])} sources at {SERVE_FREQS[reqs[k][1]]} Hz, "
                       f"{time.perf_counter() - t_start:.1f} s, part width {info[0]['block']}, restart "
-                      f"{info[0]['restart_len']}, {max(i['iters'] for i in info)} iterations)", file=sys.stderr,
+                      f"{info[0]['restart_len']}, {max(i['iters'] for i in info)} iterations, status {status})", file=sys.stderr,
                       flush=True)
             time.sleep(0.05)
         st = ctx.serve_stats()
@@ -323,6 +331,9 @@ def run_serve(args):
     n_src = sum(len(r[2]) for r in reqs)
     per_op = {SERVE_FREQS[k]: dict(requests=sum(1 for r in reqs if r[1] == k),
                                    sources=sum(len(r[2]) for r in reqs if r[1] == k)) for k in range(len(ops))}
+    iters = [max(i["iters"] for i in info) for _, info, _ in done]
+    widths = [info[0]["block"] for _, info, _ in done]
+    statuses = [status for _, _, status in done]
     del done, tickets
     fp64 = None
     if args.serve_fp64:
@@ -333,22 +344,34 @@ def run_serve(args):
             ctx.release(d)
             ops[k][2] = None
             torch.cuda.empty_cache()
+            print(f"serve fp64: {SERVE_FREQS[k]} Hz setting up", file=sys.stderr, flush=True)
             t0 = time.perf_counter()
             d64 = ctx.setup_ddm(op, q.partition, q.n_sub, q.overlap,
                                 coarse=(q.coarse_tets, q.coarse_coords) if coarse else None, precision=hz.HZ_PREC_C128)
             t_setup = time.perf_counter() - t0
+            print(f"serve fp64: {SERVE_FREQS[k]} Hz set up in {t_setup:.1f} s", file=sys.stderr, flush=True)
             solved, t_sum, s_sum = 0, 0.0, 0
             t_op = time.perf_counter()
             for j, (t_arr, o, src) in enumerate(reqs):
                 if o != k or time.perf_counter() - t_op > args.fp64_budget:
                     continue
-                a = time.perf_counter()
-                ctx.solve(d64, rhs[j], tol=1e-6)
-                torch.cuda.synchronize()
-                service[j] = time.perf_counter() - a
-                t_sum += service[j]
-                s_sum += len(src)
-                solved += 1
+                # in sub-blocks of 16 sources, each reported (one request can take minutes)
+                t_req = 0.0
+                for c0 in range(0, len(src), 16):
+                    a = time.perf_counter()
+                    ctx.solve(d64, rhs[j][c0:c0 + 16], tol=1e-6)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - a
+                    t_req += dt
+                    t_sum += dt
+                    s_sum += min(16, len(src) - c0)
+                    print(f"serve fp64: {SERVE_FREQS[k]} Hz request {j} sources {c0}..{min(len(src), c0 + 16)} "
+                          f"{dt:.1f} s", file=sys.stderr, flush=True)
+                    if time.perf_counter() - t_op > args.fp64_budget:
+                        break
+                else:
+                    service[j] = t_req
+                    solved += 1
             rates[SERVE_FREQS[k]] = dict(sources_per_s=s_sum / t_sum if t_sum > 0 else None, requests_solved=solved,
                                          sources_solved=s_sum, setup_s=t_setup)
             print(f"serve fp64: {SERVE_FREQS[k]} Hz {rates[SERVE_FREQS[k]]}", file=sys.stderr, flush=True)
@@ -373,8 +396,7 @@ def run_serve(args):
                    "requests": len(reqs), "sources": n_src, "operators": setup, "per_operator": per_op},
         "latency": {"p50_s": st["p50_s"], "p99_s": st["p99_s"]}, "wall_s": wall,
         "completed": st["completed"], "rejected": st["rejected"], "all_converged": ok,
-        "iters": [max(i["iters"] for i in info) for _, info, _ in done],
-        "part_width": [info[0]["block"] for _, info, _ in done],
+        "iters": iters, "part_width": widths, "status": statuses,
         "fp64_sequential": fp64,
         "mixed_served_over_fp64": (st["sources_per_s"] / fp64["sources_per_s"]) if fp64 else None,
         "total_wall_s": time.perf_counter() - t_all}))
@@ -477,6 +499,7 @@ def main():
         st = ctx.ddm_stats(d)
         levels = ctx.ddm_levels(d)
         log(f"{label}: setup {t_setup:.2f}s {st}")
+        log(f"{label}: levels {levels}")
         kw = dict(tol=p.tol, max_iter=500, restart=restart, block=block, out=Xb)
 
         def step(k):
@@ -507,7 +530,9 @@ def main():
             iters=[i[0]["iters"] for i in infos], restarts=[i[0]["restarts"] for i in infos],
             restart_len=infos[0][0]["restart_len"], block=infos[0][0]["block"],
             max_rel_residual=max(c["rel_residual"] for i in infos for c in i), first_block_iters=info0[0]["iters"],
-            setup_s=t_setup, static_pivots=st["static_pivots"], factor_entries=st["factor_entries"],
+            setup_s=t_setup, factor_s=st["factor_seconds"],
+            factor_tflops=st["factor_flops"] / st["factor_seconds"] / 1e12 if st["factor_seconds"] > 0 else None,
+            static_pivots=st["static_pivots"], factor_entries=st["factor_entries"],
             device_gb=st["device_bytes"] / 1e9, n_fronts=st["n_fronts"], levels=st["n_levels"],
             max_front=st["max_front"], local_dofs=st["local_dofs_total"], n_coarse=st["n_coarse"],
             kernels={k: dict(launches=v["launches"], seconds=v["seconds"],

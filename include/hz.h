@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define HZ_ABI_VERSION 2
+#define HZ_ABI_VERSION 3
 
 typedef enum {
   HZ_OK = 0,
@@ -261,6 +261,10 @@ typedef struct {
   int64_t factor_useful;      /* stored factor nonzeros: sum over fronts of p(p+1)/2 + r p */
   int64_t device_bytes;       /* device memory held by the ddm (operator excluded) */
   double setup_seconds;
+  double factor_seconds;      /* numeric factorisation (GPU), part of setup_seconds */
+  double factor_flops;        /* its algorithmic real flops: 8 per complex multiply-add of the
+                                 diagonal blocks, panel solves, trailing updates and the
+                                 partitioned inverse (direct complex form) */
 } hz_ddm_stats;
 hz_status hz_ddm_stats_get(hz_ctx* ctx, hz_handle ddm, hz_ddm_stats* out);
 
@@ -322,6 +326,9 @@ typedef struct {
 typedef struct {
   double p50_s, p99_s, sources_per_s;
   int64_t completed, rejected;
+  int64_t parts_done;   /* request parts finished so far (progress of long requests) */
+  int64_t steps;        /* block Arnoldi steps taken so far, summed over the parts */
+  int64_t active_parts; /* parts running now */
 } hz_serve_stats;
 
 /*

@@ -550,6 +550,8 @@ hz_status hz_ddm_stats_get(hz_ctx* c, hz_handle ddm, hz_ddm_stats* out) {
     out->factor_useful = d->factor_useful;
     out->device_bytes = d->device_bytes();
     out->setup_seconds = d->setup_seconds;
+    out->factor_seconds = d->factor_seconds;
+    out->factor_flops = d->factor_flops;
   });
 }
 

@@ -111,6 +111,8 @@ struct Ddm {
   int64_t max_front = 0;
   int64_t static_pivots = 0;
   double setup_seconds = 0;
+  double factor_seconds = 0;  // numeric factorisation (wall clock, synchronised)
+  double factor_flops = 0;    // its algorithmic real flops (8 per complex multiply-add)
   std::unique_ptr<CoarseSpace> coarse;
 
   // host index arrays

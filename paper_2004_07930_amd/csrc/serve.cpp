@@ -17,6 +17,7 @@
 // matrix are read once for all of them), then each job does its own orthogonalisation and
 // least-squares step.  A finished job
 // frees its Krylov memory at once; a request completes when all its parts have.
+#include <cstdio>
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -70,6 +71,7 @@ struct Ticket {
   int64_t held = 0;      // memory reserved for the admitted parts (and the host copies)
   bool oom = false;      // a part could not start: no memory even alone, or a dependent block
   DevArray<c128> Bu;     // device copy of the rhs in user layout (host requests only)
+  DevArray<c128> Xu;     // device copy of the solution in user layout (host requests only)
   struct Part {
     int c0 = 0, s = 0;
     DevArray<c128> Bn, Xn;
@@ -94,9 +96,10 @@ struct Serve {
   uint64_t next_id = 1;
   int active_parts = 0;
   int64_t held = 0;  // memory reserved by all admitted requests
+  int64_t base = 0;  // device memory of the resident objects and the packing buffers (fixed while serving)
   // stats
   std::vector<double> lat;
-  int64_t completed = 0, rejected = 0, sources = 0;
+  int64_t completed = 0, rejected = 0, sources = 0, parts_done = 0, steps = 0;
   double t_first = -1, t_last = 0;
   DevArray<c128> packV, packZ, packW;
   DevArray<c64> packZ32;  // packed preconditioned columns of mixed-precision jobs
@@ -123,7 +126,10 @@ static int64_t part_bytes(const Ticket& t, int k, int m) {
 static void start_part(Serve& S, Ticket& t, int k) {
   Ctx* ctx = S.ctx;
   const int64_t n = t.ddm->op->mesh->n;
-  if (k == 0 && t.req.mem == HZ_MEM_HOST) t.Bu.upload(ctx, static_cast<const c128*>(t.req.rhs), t.req.n_rhs * n);
+  if (k == 0 && t.req.mem == HZ_MEM_HOST) {  // both staging copies now: finishing allocates nothing
+    t.Bu.upload(ctx, static_cast<const c128*>(t.req.rhs), t.req.n_rhs * n);
+    t.Xu.alloc(ctx, t.req.n_rhs * n);
+  }
   const c128* base = t.req.mem == HZ_MEM_HOST ? t.Bu.ptr() : static_cast<const c128*>(t.req.rhs);
   SolveOptions o;
   o.tol = t.req.tol;
@@ -144,11 +150,9 @@ static void start_part(Serve& S, Ticket& t, int k) {
 static void finish_ticket(Serve& S, Ticket& t) {
   Ctx* ctx = S.ctx;
   const int64_t n = t.ddm->op->mesh->n;
-  DevArray<c128> Xu;
   c128* out = nullptr;
   if (t.req.mem == HZ_MEM_HOST) {
-    Xu.alloc(ctx, t.req.n_rhs * n);
-    out = Xu.ptr();
+    out = t.Xu.ptr();
   } else {
     out = static_cast<c128*>(t.req.x);
   }
@@ -171,10 +175,11 @@ static void finish_ticket(Serve& S, Ticket& t) {
     }
   }
   if (t.req.mem == HZ_MEM_HOST)
-    HIP_CHECK(hipMemcpyAsync(t.req.x, Xu.ptr(), t.req.n_rhs * n * sizeof(c128), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_CHECK(hipMemcpyAsync(t.req.x, t.Xu.ptr(), t.req.n_rhs * n * sizeof(c128), hipMemcpyDeviceToHost, ctx->stream));
   HIP_CHECK(hipStreamSynchronize(ctx->stream));
   t.parts.clear();
   t.Bu = DevArray<c128>();
+  t.Xu = DevArray<c128>();
   t.status = st;
 }
 
@@ -258,6 +263,8 @@ static void tick(Serve& S) {
       }
     }
     for (FgmresJob* j : jobs) j->after_matvec();
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.steps += (int64_t)jobs.size();
   }
   HIP_CHECK(hipStreamSynchronize(st));
   for (auto& t : S.running)
@@ -269,6 +276,7 @@ static void tick(Serve& S) {
         std::lock_guard<std::mutex> lk(S.mu);
         ++t->finished;
         --S.active_parts;
+        ++S.parts_done;
       }
 }
 
@@ -345,6 +353,7 @@ static void scheduler(Serve* S) {
           if (e.code == HZ_ERR_ARG || S->active_parts == 0) {  // bad block, or it cannot fit even alone:
             t->status = e.code;                                  // the request fails
             t->oom = true;
+            std::fprintf(stderr, "hz: serve: request %llu failed at part %d: %s\n", (unsigned long long)t->id, k, e.what());
           }
           break;
         }
@@ -361,6 +370,7 @@ static void scheduler(Serve* S) {
               if (!p->done) --S->active_parts;
             t->parts.clear();
             t->Bu = DevArray<c128>();
+            t->Xu = DevArray<c128>();
             S->held -= t->held;
             t->held = 0;
             t->t_done = now_s();
@@ -433,6 +443,31 @@ hz_status hz_serve_start(hz_ctx* c, int32_t max_slots) {
   auto* S = new Serve();
   S->ctx = x;
   S->max_slots = max_slots;
+  // the shared launches' packing buffers, sized for the largest resident operator, so that a
+  // tick allocates nothing; with them the resident memory is fixed until hz_serve_stop (the
+  // context refuses other calls meanwhile)
+  try {
+    int64_t nmax = 0;
+    bool mixed = false, full = false;
+    {
+      std::lock_guard<std::mutex> lk(x->mu);
+      for (auto& kv : x->ddms) {
+        nmax = std::max<int64_t>(nmax, kv.second->op->mesh->n);
+        (kv.second->precision == HZ_PREC_MIXED ? mixed : full) = true;
+      }
+    }
+    if (nmax > 0) {
+      S->packV.alloc(x, nmax * 32);
+      S->packW.alloc(x, nmax * 32);
+      if (mixed) S->packZ32.alloc(x, nmax * 32);
+      if (full) S->packZ.alloc(x, nmax * 32);
+    }
+  } catch (const Error& e) {
+    x->last_error = e.what();
+    delete S;
+    return e.code;
+  }
+  S->base = x->bytes_in_use;
   x->serving = true;
   x->serve = S;
   S->th = std::thread(scheduler, S);
@@ -464,7 +499,7 @@ hz_status hz_serve_submit(hz_ctx* c, const hz_request* req, uint64_t* ticket) {
   // longest restart (up to 40) with which the first part fits in the budget left after the
   // resident objects; the widest width reaching kGoodRestart, else the longest restart (the
   // wider width on a tie); never admissible below kMinRestart
-  const int64_t avail = (int64_t)x->hbm_budget - (x->bytes_in_use - S->held);
+  const int64_t avail = (int64_t)x->hbm_budget - S->base;  // what a part running alone may use
   t->m = 0;
   int best_w = 0, best_m = 0;
   for (int w = (int)std::min<int64_t>(32, req->n_rhs); w >= 1; w = w > 1 ? w / 2 : 0) {
@@ -552,6 +587,9 @@ hz_status hz_serve_stats_get(hz_ctx* c, hz_serve_stats* out) {
   out->sources_per_s = (S->completed > 0 && S->t_last > S->t_first) ? S->sources / (S->t_last - S->t_first) : 0.0;
   out->completed = S->completed;
   out->rejected = S->rejected;
+  out->parts_done = S->parts_done;
+  out->steps = S->steps;
+  out->active_parts = S->active_parts;
   return HZ_OK;
 }
 

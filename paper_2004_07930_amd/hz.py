@@ -83,7 +83,8 @@ class DdmStats(C.Structure):
                 ("factor_entries", C.c_int64), ("n_fronts", C.c_int64), ("n_levels", C.c_int64),
                 ("max_front", C.c_int64), ("n_coarse", C.c_int64), ("static_pivots", C.c_int64),
                 ("update_entries", C.c_int64), ("factor_useful", C.c_int64),
-                ("device_bytes", C.c_int64), ("setup_seconds", C.c_double)]
+                ("device_bytes", C.c_int64), ("setup_seconds", C.c_double), ("factor_seconds", C.c_double),
+                ("factor_flops", C.c_double)]
 
 
 class DdmLevel(C.Structure):
@@ -104,7 +105,8 @@ class KernelStat(C.Structure):
 
 class ServeStats(C.Structure):
     _fields_ = [("p50_s", C.c_double), ("p99_s", C.c_double), ("sources_per_s", C.c_double),
-                ("completed", C.c_int64), ("rejected", C.c_int64)]
+                ("completed", C.c_int64), ("rejected", C.c_int64), ("parts_done", C.c_int64),
+                ("steps", C.c_int64), ("active_parts", C.c_int64)]
 
 
 _lib = None
@@ -226,10 +228,15 @@ def _torch_allocator(device):
     import torch
 
     def _alloc(nbytes, stream, user):
-        try:
-            return torch.cuda.caching_allocator_alloc(int(nbytes), device, int(stream or 0))
-        except Exception:  # out of memory or a bad request: the library reports HZ_ERR_OOM
-            return None
+        for attempt in range(2):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device, int(stream or 0))
+            except Exception:  # out of memory or a bad request: the library reports HZ_ERR_OOM
+                if attempt:
+                    return None
+                # blocks torch keeps cached (of other sizes) go back to the device, then retry once
+                torch.cuda.empty_cache()
+        return None
 
     def _free(ptr, stream, user):
         try:
