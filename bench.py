@@ -54,6 +54,15 @@ WORKLOADS = {
         coarse=False, block=0, restart=24, step_sources=16,
         desc="layered 20x20x4.65 km, 5 Hz, Kuhn P3 %dx%dx%d cubes, 256 subdomains (8x8x4 boxes cut at equal "
              "depth, uneven), overlap 1, one-level ORAS, 128 point sources at 0.5 km in 16-source steps, tol 1e-6"),
+    "layered-7.5hz-q": dict(
+        problem=dict(freq=7.5, r=1.4, parts=(16, 16, 2), overlap=1, n_sources=(8, 8), src_depth=0.5,
+                     lateral=(2.08, 17.92, 2.08, 17.92), max_cubes=(168, 168), with_q=True, equal_depth_zcuts=True,
+                     coarse_factor=0),
+        coarse=False, block=0, restart=24, step_sources=16, ref_tol=1e-10,
+        desc="layered model with attenuation (c = v (1 + i/(2Q)), Q = 80 + 120 z/4.65 km), 7.5 Hz, the centred "
+             "15.84 x 15.84 km block, full depth (Dirichlet top, impedance on the cut sides and the bottom), Kuhn P3 "
+             "%dx%dx%d cubes, 512 subdomains (16x16x2 boxes cut at equal depth), overlap 1, one-level ORAS, 64 point "
+             "sources at 0.5 km in 16-source steps, tol 1e-6"),
     "layered-2.5hz": dict(
         problem=dict(freq=2.5, r=1.4, parts=(8, 8, 1), overlap=2, n_sources=(4, 4), src_depth=0.5),
         coarse=True, block=16, restart=40, step_sources=16,
@@ -423,6 +432,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed steps of the FP64 solve (0: skip it)")
     ap.add_argument("--pou", default="boolean", choices=["boolean", "smooth"],
                     help="partition of unity of the one-level preconditioner (the smooth one is an ablation)")
+    ap.add_argument("--ref-tol", type=float, default=0.0,
+                    help="also solve the first sub-block with the mixed solver at this tolerance and report the "
+                         "1e-6 solution's error against it (the reference where complex128 factors do not fit)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -480,6 +492,7 @@ def main():
     Bb = torch.empty((len(blocks[0]), mesh.n), dtype=torch.complex128, device="cuda")
     Xb = torch.empty_like(Bb)
     results, x_first = {}, {}
+    ref_tight = None
     runs = [("mixed", hz.HZ_PREC_MIXED, args.steps, args.warmup)]
     if args.fp64_steps > 0:
         runs.append(("fp64", hz.HZ_PREC_C128, args.fp64_steps, min(1, args.warmup)))
@@ -542,6 +555,19 @@ def main():
         if label == "mixed":
             kraw = kstats
             ratio = _survey_ratio(levels, S, 8.0)
+            if args.ref_tol or spec.get("ref_tol"):  # the same solver at a tight tolerance, on the first sub-block
+                rt = args.ref_tol or spec["ref_tol"]
+                ctx.point_sources(mesh, blocks[0], out=Bb)
+                a = time.perf_counter()
+                _, iref = ctx.solve(d, Bb, **dict(kw, tol=rt, max_iter=2000))
+                torch.cuda.synchronize()
+                xr = Xb.cpu()
+                ref_tight = dict(tol=rt, iters=iref[0]["iters"], seconds=time.perf_counter() - a,
+                                 max_rel_residual=max(c["rel_residual"] for c in iref),
+                                 err_vs_tight=float(torch.linalg.vector_norm(x_first["mixed"] - xr)
+                                                    / torch.linalg.vector_norm(xr)))
+                del xr
+                log("mixed: tight-tolerance reference", ref_tight)
         log(label, results[label])
         ctx.release(d)
         del d
@@ -587,6 +613,7 @@ def main():
                    "restart": restart, "block": block, "assembly_s": t_asm},
         "latency": {"p50_s": head["p50_s"], "p99_s": head["p99_s"], "of": "one 16-source step (solve latency)"},
         "err_mixed_vs_fp64": err,
+        "err_vs_tight_tolerance": ref_tight,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed": head,

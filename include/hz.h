@@ -340,10 +340,12 @@ typedef struct {
  * hz_serve_submit: queues a request (FIFO) and returns its ticket.  Each request is solved
  *   like hz_solve (x0 = 0, per-column relative residual req->tol, req->max_iter inner
  *   iterations, 0 = 500) in parts of w sources with restart length m, both chosen at
- *   submission from hbm_budget minus the resident objects and the requests in flight: for
- *   each w in min(n_rhs, 32) and its halvings, the longest m up to 40 with which the first
- *   part fits; the widest w whose m reaches 20, else the w with the longest m.  Its parts are
- *   admitted in order when a slot is free and their memory fits.  rhs / x / info (info nullable, [n_rhs]) stay caller-owned and must stay
+ *   submission from hbm_budget minus the resident objects (the ddms, operators and meshes,
+ *   and the packing buffers hz_serve_start allocates for the largest operator): for each w in
+ *   min(n_rhs, 32) and its halvings, the longest m up to 40 with which one part fits alone;
+ *   the widest w whose m reaches 20, else the w with the longest m.  Its parts are admitted in
+ *   order when a slot is free and their memory fits; each part stages its own columns of a
+ *   host rhs / x (no copy of the whole request is held on the device).  rhs / x / info (info nullable, [n_rhs]) stay caller-owned and must stay
  *   valid until the ticket completes; req->mem says whether rhs and x are host or device.
  *   Errors: HZ_ERR_ARG (unknown ddm, n_rhs < 1, null buffers, bad mem), HZ_ERR_ABI
  *   (struct_size), HZ_ERR_BUSY (fits at no restart length >= 8: never admissible),

@@ -46,7 +46,11 @@ void DevBuf::alloc(Ctx* c, size_t nbytes) {
     const hipError_t e = hipMalloc(&q, nbytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      fail(HZ_ERR_OOM, "device allocation of " + std::to_string(nbytes) + " bytes failed");
+      size_t fr = 0, tot = 0;
+      (void)hipMemGetInfo(&fr, &tot);
+      fail(HZ_ERR_OOM, "device allocation of " + std::to_string(nbytes) + " bytes failed (device: " +
+                           std::to_string(fr >> 20) + " of " + std::to_string(tot >> 20) + " MiB free; the library holds " +
+                           std::to_string((int64_t)c->bytes_in_use >> 20) + " MiB)");
     }
   }
   p = q;

@@ -282,8 +282,12 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
                                                   cplx<T>* __restrict__ wbuf, cplx<T>* __restrict__ bout, int s) {
   constexpr int RT = 64 * MT, SC = 16 * NG;
   constexpr int NF = JC * RT / 256, NW = JC * SC / 256;
-  __shared__ cplx<T> Ft[JC][RT + 1];
+  // unpadded tile (20 KB for complex64, 64-row tiles: eight blocks per CU); a complex64 row's
+  // 16-entry halves swap on odd columns, so the four columns a wavefront's products read at
+  // once fall on the two halves of the LDS banks
+  __shared__ cplx<T> Ft[JC][RT];
   __shared__ cplx<T> Wt[JC][SC];
+  constexpr int SW = sizeof(cplx<T>) == 8 ? 16 : 0;
   const int fid = work[2 * blockIdx.x];
   if (fid < 0) return;  // padding entry of the XCD-interleaved worklist (block-uniform)
   const int64_t i0 = work[2 * blockIdx.x + 1];
@@ -336,7 +340,7 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
 #pragma unroll
     for (int u = 0; u < NF; ++u) {
       const int e = tid + 256 * u, jj = e / RT, rr = e - (e / RT) * RT;
-      Ft[jj][rr] = csel(jj < jn && i0 + rr < f, rf[u], zero);
+      Ft[jj][rr ^ (SW * (jj & 1))] = csel(jj < jn && i0 + rr < f, rf[u], zero);
     }
 #pragma unroll
     for (int u = 0; u < NW; ++u) {
@@ -356,7 +360,7 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
       for (int g = 0; g < NG; ++g) wb[g] = Wt[kc][16 * g + lr];
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
-        const cplx<T> av = Ft[kc][16 * (wv * MT + m) + lr];
+        const cplx<T> av = Ft[kc][(16 * (wv * MT + m) + lr) ^ (SW * (kc & 1))];
 #pragma unroll
         for (int g = 0; g < NG; ++g) acc[m][g].mac(av, wb[g]);
       }

@@ -15,8 +15,8 @@
 // jobs on the same operator are packed column-wise (first-fit decreasing, at most 32 columns
 // a launch) into shared launches of the preconditioner and of the SpMM (so the factors and the
 // matrix are read once for all of them), then each job does its own orthogonalisation and
-// least-squares step.  A finished job
-// frees its Krylov memory at once; a request completes when all its parts have.
+// least-squares step.  A finished job writes its columns of the solution to the caller's
+// block and frees its memory at once; a request completes when all its parts have.
 #include <cstdio>
 #include <algorithm>
 #include <chrono>
@@ -68,10 +68,8 @@ struct Ticket {
   int nparts = 0;        // parts of at most w sources
   int admitted = 0;      // parts admitted by the scheduler
   int finished = 0;      // parts done
-  int64_t held = 0;      // memory reserved for the admitted parts (and the host copies)
+  int64_t held = 0;      // memory reserved for the admitted parts
   bool oom = false;      // a part could not start: no memory even alone, or a dependent block
-  DevArray<c128> Bu;     // device copy of the rhs in user layout (host requests only)
-  DevArray<c128> Xu;     // device copy of the solution in user layout (host requests only)
   struct Part {
     int c0 = 0, s = 0;
     DevArray<c128> Bn, Xn;
@@ -112,25 +110,18 @@ static constexpr double kBackfillWindow = 30.0;
 
 static int part_cols(const Ticket& t, int k) { return (int)std::min<int64_t>(t.w, t.req.n_rhs - t.w * (int64_t)k); }
 
-// device memory of part k (Krylov workspace and its node-major right-hand side and
-// solution); the first part also carries the request's host copies
+// device memory of part k: its Krylov workspace and its node-major right-hand side and
+// solution (which also stage its columns of a host request in and out)
 static int64_t part_bytes(const Ticket& t, int k, int m) {
   const int64_t n = t.ddm->op->mesh->n;
   const int s = part_cols(t, k);
-  int64_t b = FgmresJob::bytes_needed(n, s, m, t.ddm->precision == HZ_PREC_MIXED) + 2 * n * s * (int64_t)sizeof(c128);
-  if (k == 0 && t.req.mem == HZ_MEM_HOST) b += 2 * n * t.req.n_rhs * (int64_t)sizeof(c128);
-  return b;
+  return FgmresJob::bytes_needed(n, s, m, t.ddm->precision == HZ_PREC_MIXED) + 2 * n * s * (int64_t)sizeof(c128);
 }
 
 // start of part k of a request (scheduler thread, no lock held)
 static void start_part(Serve& S, Ticket& t, int k) {
   Ctx* ctx = S.ctx;
   const int64_t n = t.ddm->op->mesh->n;
-  if (k == 0 && t.req.mem == HZ_MEM_HOST) {  // both staging copies now: finishing allocates nothing
-    t.Bu.upload(ctx, static_cast<const c128*>(t.req.rhs), t.req.n_rhs * n);
-    t.Xu.alloc(ctx, t.req.n_rhs * n);
-  }
-  const c128* base = t.req.mem == HZ_MEM_HOST ? t.Bu.ptr() : static_cast<const c128*>(t.req.rhs);
   SolveOptions o;
   o.tol = t.req.tol;
   o.max_iter = t.req.max_iter > 0 ? t.req.max_iter : 500;
@@ -141,25 +132,42 @@ static void start_part(Serve& S, Ticket& t, int k) {
   p->Bn.alloc(ctx, n * p->s);
   p->Xn.alloc(ctx, n * p->s);
   KrylovKernels K(ctx, n, p->s);
-  K.to_node(base + (int64_t)p->c0 * n, p->Bn.ptr());
+  // the part's columns are contiguous in the caller's [n_rhs][n] block; a host block is staged
+  // through Xn (the solve zeroes it before use)
+  const c128* cols = static_cast<const c128*>(t.req.rhs) + (int64_t)p->c0 * n;
+  if (t.req.mem == HZ_MEM_HOST) {
+    HIP_CHECK(hipMemcpyAsync(p->Xn.ptr(), cols, n * p->s * sizeof(c128), hipMemcpyHostToDevice, ctx->stream));
+    K.to_node(p->Xn.ptr(), p->Bn.ptr());
+  } else {
+    K.to_node(cols, p->Bn.ptr());
+  }
   p->job = std::make_unique<FgmresJob>(ctx, t.ddm, p->s, p->Bn.ptr(), p->Xn.ptr(), o, t.m);
   p->job->start();
   t.parts.push_back(std::move(p));
 }
 
-static void finish_ticket(Serve& S, Ticket& t) {
+// a finished part's solution to the caller's block (through Bn, free now, for a host block);
+// its device memory goes back at once
+static void part_out(Serve& S, Ticket& t, Ticket::Part& p) {
   Ctx* ctx = S.ctx;
   const int64_t n = t.ddm->op->mesh->n;
-  c128* out = nullptr;
+  KrylovKernels K(ctx, n, p.s);
+  c128* cols = static_cast<c128*>(t.req.x) + (int64_t)p.c0 * n;
   if (t.req.mem == HZ_MEM_HOST) {
-    out = t.Xu.ptr();
+    K.from_node(p.Xn.ptr(), p.Bn.ptr());
+    HIP_CHECK(hipMemcpyAsync(cols, p.Bn.ptr(), n * p.s * sizeof(c128), hipMemcpyDeviceToHost, ctx->stream));
   } else {
-    out = static_cast<c128*>(t.req.x);
+    K.from_node(p.Xn.ptr(), cols);
   }
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  p.Bn = DevArray<c128>();
+  p.Xn = DevArray<c128>();
+}
+
+static void finish_ticket(Serve& S, Ticket& t) {
+  (void)S;
   int32_t st = HZ_OK;
   for (auto& p : t.parts) {
-    KrylovKernels K(ctx, n, p->s);
-    K.from_node(p->Xn.ptr(), out + (int64_t)p->c0 * n);
     for (int k = 0; k < p->s; ++k) {
       const ColInfo& ci = p->info[k];
       if (t.req.info) {
@@ -174,12 +182,7 @@ static void finish_ticket(Serve& S, Ticket& t) {
       if (ci.status != HZ_OK) st = HZ_ERR_NOT_CONVERGED;
     }
   }
-  if (t.req.mem == HZ_MEM_HOST)
-    HIP_CHECK(hipMemcpyAsync(t.req.x, t.Xu.ptr(), t.req.n_rhs * n * sizeof(c128), hipMemcpyDeviceToHost, ctx->stream));
-  HIP_CHECK(hipStreamSynchronize(ctx->stream));
   t.parts.clear();
-  t.Bu = DevArray<c128>();
-  t.Xu = DevArray<c128>();
   t.status = st;
 }
 
@@ -273,6 +276,7 @@ static void tick(Serve& S) {
         p->done = true;
         p->info = p->job->info;
         p->job.reset();  // the Krylov workspace goes back at once
+        part_out(S, *t, *p);
         std::lock_guard<std::mutex> lk(S.mu);
         ++t->finished;
         --S.active_parts;
@@ -369,8 +373,6 @@ static void scheduler(Serve* S) {
             for (auto& p : t->parts)
               if (!p->done) --S->active_parts;
             t->parts.clear();
-            t->Bu = DevArray<c128>();
-            t->Xu = DevArray<c128>();
             S->held -= t->held;
             t->held = 0;
             t->t_done = now_s();
