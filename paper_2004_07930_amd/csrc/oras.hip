@@ -57,6 +57,14 @@ __global__ void k_scatter_pou(int64_t n, int s, const int64_t* __restrict__ ptr,
   z[k] = cmk((TZ)r.re, (TZ)r.im);
 }
 
+// streamed load through a buffer resource (32-bit byte offset; non-temporal)
+__device__ __forceinline__ cplx<float> ld_stream_buf(__amdgpu_buffer_rsrc_t r, unsigned off, const cplx<float>*) {
+  return __builtin_bit_cast(cplx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 2));
+}
+__device__ __forceinline__ cplx<double> ld_stream_buf(__amdgpu_buffer_rsrc_t r, unsigned off, const cplx<double>*) {
+  return __builtin_bit_cast(cplx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 2));
+}
+
 // Forward, step 1 of a level: work block w = [b_p; 0] + extend-add of the children's
 // contributions, through the inverse maps (own, child 0, child 1: a fixed order).  One block
 // per 64-row tile of a front (the forward worklist: tiles of one front on one XCD).
@@ -145,10 +153,11 @@ __global__ __launch_bounds__(256) void k_fwd_assemble(const int32_t* __restrict_
 
 // Forward, step 2: rows [i0, i0 + 64) of  [y; c] = [F_top w_p; w_r - F_bot w_p].
 // F_top = L11^{-1} is unit lower triangular, so a tile of top rows stops at its diagonal.
+// The pivot rows are stored divided by their pivots (y_p / d), what the backward sweep uses.
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_fwd_gemm(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
-                                                  const cplx<T>* __restrict__ L, cplx<T>* __restrict__ wbuf,
-                                                  cplx<T>* __restrict__ bout, int s) {
+                                                  const cplx<T>* __restrict__ L, const cplx<T>* __restrict__ dinv,
+                                                  cplx<T>* __restrict__ wbuf, cplx<T>* __restrict__ bout, int s) {
   constexpr int RT = 64, JC = 32, NA = (S + 3) / 4;
   __shared__ cplx<T> Ft[JC][RT + 1];
   __shared__ cplx<T> Wt[JC][S];
@@ -191,8 +200,9 @@ __global__ __launch_bounds__(256) void k_fwd_gemm(const int32_t* __restrict__ wo
     for (int q = 0; q < NA; ++q) {
       const int c = cg + 4 * q;
       if (c >= s) continue;
-      if (i < F.p) {
-        bout[(F.vec_off + F.pos0 + i) * s + c] = acc[q];
+      if (i < F.p) {  // pivot rows leave y_p / d for the backward sweep
+        const int64_t pos = F.vec_off + F.pos0 + i;
+        bout[pos * s + c] = acc[q] * dinv[pos];
       } else {
         cplx<T>* w = &wbuf[(F.w_off + i) * s + c];
         *w = *w - acc[q];
@@ -202,11 +212,11 @@ __global__ __launch_bounds__(256) void k_fwd_gemm(const int32_t* __restrict__ wo
 }
 
 // Backward: columns [j0, j0 + 32) of  x_p = F^T u,  u = [y_p / d; -x_r]  (rows from j0 on;
-// F_top is unit lower so rows above a column contribute nothing).
+// F_top is unit lower so rows above a column contribute nothing; the forward sweep stored y_p / d).
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_bwd_gemm(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
                                                   const cplx<T>* __restrict__ L, const int32_t* __restrict__ urows,
-                                                  const cplx<T>* __restrict__ dinv, const cplx<T>* __restrict__ bout,
+                                                  const cplx<T>* __restrict__ bout,
                                                   cplx<T>* __restrict__ bin, int s) {
   constexpr int CT = 32, RC = 64, NB = (S + 7) / 8;
   __shared__ cplx<T> Ft[RC][CT + 1];
@@ -236,7 +246,7 @@ __global__ __launch_bounds__(256) void k_bwd_gemm(const int32_t* __restrict__ wo
         const int64_t row = i + rr;
         if (row < F.p) {
           const int64_t pos = F.vec_off + F.pos0 + row;
-          v = bout[pos * s + c] * dinv[pos];
+          v = bout[pos * s + c];  // y_p / d, left so by the forward sweep
         } else {
           const int64_t pos = F.vec_off + urows[F.rows_off + (row - F.p)];
           const cplx<T> x = bin[pos * s + c];
@@ -279,7 +289,8 @@ __global__ __launch_bounds__(256) void k_bwd_gemm(const int32_t* __restrict__ wo
 template <typename T, int NG, int MT, int JC>
 __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
                                                   const cplx<T>* __restrict__ L, const int32_t* __restrict__ imap,
-                                                  cplx<T>* __restrict__ wbuf, cplx<T>* __restrict__ bout, int s) {
+                                                  const cplx<T>* __restrict__ dinv, cplx<T>* __restrict__ wbuf,
+                                                  cplx<T>* __restrict__ bout, int s) {
   constexpr int RT = 64 * MT, SC = 16 * NG;
   constexpr int NF = JC * RT / 256, NW = JC * SC / 256;
   // unpadded tile (20 KB for complex64, 64-row tiles: eight blocks per CU); a complex64 row's
@@ -377,8 +388,9 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
         const int64_t i = i0 + 16 * (wv * MT + m) + CAcc<T>::row(lq, v);
         if (i >= f) continue;
         const cplx<T> val = acc[m][g].get(v);
-        if (i < F.p) {
-          bout[(F.vec_off + F.pos0 + i) * s + c] = val;
+        if (i < F.p) {  // y_p / d for the backward sweep
+          const int64_t pos = F.vec_off + F.pos0 + i;
+          bout[pos * s + c] = val * dinv[pos];
         } else {  // update row: (0 + child 0 + child 1) - F_bot w_p
           cplx<T> wr = zero;
           if (w0) {
@@ -403,12 +415,16 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const int32_t* __restrict__ wo
 template <typename T, int NG, int NT, int RC>
 __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ work, const FrontDesc* __restrict__ fr,
                                                   const cplx<T>* __restrict__ L, const int32_t* __restrict__ urows,
-                                                  const cplx<T>* __restrict__ dinv, const cplx<T>* __restrict__ bout,
+                                                  const cplx<T>* __restrict__ bout,
                                                   cplx<T>* __restrict__ bin, int s) {
   constexpr int CT = 64 * NT, SC = 16 * NG;
   constexpr int NF = RC * CT / 256, NU = RC * SC / 256;
-  __shared__ cplx<T> Ft[RC][CT + 1];
+  // unpadded tile with an XOR swizzle of the column by the row (sw): the 32 rows of one column
+  // that consecutive lanes store fall on distinct banks, and so do the entries the products
+  // read (complex64: the two rows a half-wavefront reads at once use the two halves of the banks)
+  __shared__ cplx<T> Ft[RC][CT];
   __shared__ cplx<T> Ut[RC][SC];
+  auto sw = [](int r) { return sizeof(cplx<T>) == 8 ? (((r & 1) << 4) | ((r >> 1) & 15)) : (r & 15); };
   const int fid = work[2 * blockIdx.x];
   if (fid < 0) return;  // padding entry of the XCD-interleaved worklist (block-uniform)
   const int64_t j0 = work[2 * blockIdx.x + 1];
@@ -418,10 +434,13 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ wo
   const int tid = threadIdx.x;
   const int wv = tid >> 6, l = tid & 63;
   const int lr = l & 15, lq = l >> 4;
-  const cplx<T>* Lf = L + F.L_off;
+  // the tile's columns of the front's panel as a buffer (byte offsets fit 32 bits: a panel is
+  // ld p entries, far below 4 GB)
+  const __amdgpu_buffer_rsrc_t Lr = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(L + F.L_off + j0 * F.ld), (short)0, (int)((int64_t)F.ld * nj * (int64_t)sizeof(cplx<T>)), 0x00020000);
   const int64_t pbase = F.vec_off + F.pos0;  // first pivot position: a valid clamp target
   const cplx<T> zero = cmk((T)0, (T)0);
-  cplx<T> rf[NF], rx[NU], rd[NU];
+  cplx<T> rf[NF], rx[NU];
   auto fetch = [&](int64_t i) {
     const int rn = (int)min<int64_t>(RC, f - i);
     // update-row indices from a clamped (valid) index; a front without update rows reads
@@ -441,7 +460,8 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ wo
 #pragma unroll
     for (int u = 0; u < NF; ++u) {
       const int e = tid + 256 * u, cc = e / RC, rr = e - (e / RC) * RC;  // element e of [CT][RC]
-      rf[u] = ld_stream(&Lf[(rr < rn && cc < nj) ? (j0 + cc) * F.ld + i + rr : 0]);
+      const unsigned off = (rr < rn && cc < nj) ? (unsigned)(cc * F.ld + (int)i + rr) * (unsigned)sizeof(cplx<T>) : 0u;
+      rf[u] = ld_stream_buf(Lr, off, (const cplx<T>*)nullptr);
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
@@ -451,7 +471,6 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ wo
       const bool piv = row < F.p;
       const int64_t pos = piv ? pbase + row : F.vec_off + ui[u];
       rx[u] = (piv ? bout : bin)[(ok ? pos : pbase) * s + (ok ? c : 0)];
-      rd[u] = dinv[(ok && piv) ? pos : pbase];
     }
   };
   CAcc<T> acc[NT][NG];
@@ -466,7 +485,7 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ wo
 #pragma unroll
     for (int u = 0; u < NF; ++u) {
       const int e = tid + 256 * u, cc = e / RC, rr = e - (e / RC) * RC;
-      Ft[rr][cc] = csel(rr < rn && cc < nj, rf[u], zero);
+      Ft[rr][cc ^ sw(rr)] = csel(rr < rn && cc < nj, rf[u], zero);
     }
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
@@ -474,7 +493,7 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ wo
       const bool ok = rr < rn && c < s;
       const bool piv = i + rr < F.p;
       const cplx<T> x = rx[u];
-      Ut[rr][c] = csel(ok, csel(piv, x * rd[u], cmk(-x.re, -x.im)), zero);
+      Ut[rr][c] = csel(ok, csel(piv, x, cmk(-x.re, -x.im)), zero);  // [y_p / d; -x_r]
     }
     __syncthreads();
     if (i + RC < f) fetch(i + RC);
@@ -487,7 +506,7 @@ __global__ __launch_bounds__(256) void k_bwd_mfma(const int32_t* __restrict__ wo
       for (int g = 0; g < NG; ++g) ub[g] = Ut[rr][16 * g + lr];
 #pragma unroll
       for (int m = 0; m < NT; ++m) {
-        const cplx<T> av = Ft[rr][16 * (wv * NT + m) + lr];
+        const cplx<T> av = Ft[rr][(16 * (wv * NT + m) + lr) ^ sw(rr)];
 #pragma unroll
         for (int g = 0; g < NG; ++g) acc[m][g].mac(av, ub[g]);
       }
@@ -535,15 +554,15 @@ void sweep_valu(Ctx* ctx, Ddm& d, int s, const cplx<TS>* src, cplx<T>* bin, cplx
     ProfScope ps(ctx, HZ_K_ORAS_FWD, esz * ((double)Lv.useful + 2.0 * (double)Lv.sum_f * s),
                  8.0 * (double)Lv.useful * s);
     hipLaunchKernelGGL((k_fwd_gemm<T, S>), dim3((unsigned)(d.fwd_off[lv + 1] - d.fwd_off[lv])), dim3(256), 0, st,
-                       d.d_fwd_work.ptr() + 2 * d.fwd_off[lv], d.d_fronts.ptr(), L, wbuf, bout, s);
+                       d.d_fwd_work.ptr() + 2 * d.fwd_off[lv], d.d_fronts.ptr(), L, d.d_dinv.as<cplx<T>>(), wbuf,
+                       bout, s);
   }
   for (size_t lv = d.levels.size(); lv-- > 0;) {
     const Level& Lv = d.levels[lv];
     ProfScope ps(ctx, HZ_K_ORAS_BWD, esz * ((double)Lv.useful + (double)(Lv.sum_f + Lv.sum_p) * s),
                  8.0 * (double)Lv.useful * s);
     hipLaunchKernelGGL((k_bwd_gemm<T, S>), dim3((unsigned)(d.bwd_off[lv + 1] - d.bwd_off[lv])), dim3(256), 0, st,
-                       d.d_bwd_work.ptr() + 2 * d.bwd_off[lv], d.d_fronts.ptr(), L, d.d_urows.ptr(),
-                       d.d_dinv.as<cplx<T>>(), bout, bin, s);
+                       d.d_bwd_work.ptr() + 2 * d.bwd_off[lv], d.d_fronts.ptr(), L, d.d_urows.ptr(), bout, bin, s);
   }
   HIP_CHECK(hipGetLastError());
 }
@@ -567,20 +586,20 @@ void sweep_mfma(Ctx* ctx, Ddm& d, int s, const cplx<TS>* src, cplx<T>* bin, cplx
     const int32_t* wl = d.d_fwdm_work[t].ptr() + 2 * d.fwdm_off[t][lv];
     if (t == 0)
       hipLaunchKernelGGL((k_fwd_mfma<T, NG, kFwdRowsMfma[0] / 64, 32>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(), L,
-                         d.d_imap.ptr(), wbuf, bout, s);
+                         d.d_imap.ptr(), d.d_dinv.as<cplx<T>>(), wbuf, bout, s);
     else
       hipLaunchKernelGGL((k_fwd_mfma<T, NG, kFwdRowsMfma[1] / 64, 32>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(), L,
-                         d.d_imap.ptr(), wbuf, bout, s);
+                         d.d_imap.ptr(), d.d_dinv.as<cplx<T>>(), wbuf, bout, s);
   };
   auto bwd = [&](size_t lv, int t) {
     const dim3 grid((unsigned)(d.bwdm_off[t][lv + 1] - d.bwdm_off[t][lv]));
     const int32_t* wl = d.d_bwdm_work[t].ptr() + 2 * d.bwdm_off[t][lv];
     if (t == 0)
       hipLaunchKernelGGL((k_bwd_mfma<T, NG, kBwdColsMfma[0] / 64, 32>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(), L,
-                         d.d_urows.ptr(), d.d_dinv.as<cplx<T>>(), bout, bin, s);
+                         d.d_urows.ptr(), bout, bin, s);
     else
       hipLaunchKernelGGL((k_bwd_mfma<T, NG, kBwdColsMfma[1] / 64, 32>), grid, dim3(256), 0, st, wl, d.d_fronts.ptr(), L,
-                         d.d_urows.ptr(), d.d_dinv.as<cplx<T>>(), bout, bin, s);
+                         d.d_urows.ptr(), bout, bin, s);
   };
   if (!tune) {
     for (size_t lv = 0; lv < nl; ++lv) {
