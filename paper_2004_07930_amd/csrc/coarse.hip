@@ -10,6 +10,7 @@
 #include <cmath>
 
 #include "ddm.h"
+#include "mfma_cplx.h"
 
 namespace hz {
 
@@ -199,55 +200,147 @@ __global__ void k_to_colmajor(int64_t nc, const c128* __restrict__ Er, c128* __r
   E[c + d * nc] = Er[k];
 }
 
-// ---- LU with partial pivoting, right looking, one column per step
+// ---- LU with partial pivoting, blocked right looking: panels of kLuNb columns.  Per panel:
+// k_lu_panel factors it (one block, column by column), k_lu_swaps applies its row
+// interchanges to the other columns, k_lu_trsm forms U12 = L11^{-1} A12 and k_lu_gemm updates
+// the trailing matrix A22 -= L21 U12 on the matrix cores (three-product form, CAcc).
+constexpr int kLuNb = 32, kLuTile = 64;
+
+// panel columns [k0, k0 + nb) over rows [k0, nc): pivot = the largest |re| + |im| in the
+// column (the lowest row among equals), rows swapped within the panel, multipliers below the
+// diagonal, rank-1 update of the panel's later columns
 template <typename T>
-__global__ void k_lu_pivot(int64_t nc, int64_t k, cplx<T>* A, int32_t* piv) {
-  __shared__ T bv[256];
-  __shared__ int64_t bi[256];
-  T best = -1;
-  int64_t arg = k;
-  for (int64_t i = k + threadIdx.x; i < nc; i += blockDim.x) {
-    const cplx<T> v = A[i + k * nc];
-    const T a = fabs(v.re) + fabs(v.im);
-    if (a > best) {
-      best = a;
-      arg = i;
-    }
-  }
-  bv[threadIdx.x] = best;
-  bi[threadIdx.x] = arg;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      const T o = bv[threadIdx.x + s];
-      const int64_t oi = bi[threadIdx.x + s];
-      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
-        bv[threadIdx.x] = o;
-        bi[threadIdx.x] = oi;
+__global__ __launch_bounds__(1024) void k_lu_panel(int64_t nc, int64_t k0, int nb, cplx<T>* A, int32_t* piv) {
+  __shared__ T bv[1024];
+  __shared__ int64_t bi[1024];
+  const int t = threadIdx.x;
+  for (int jj = 0; jj < nb; ++jj) {
+    const int64_t k = k0 + jj;
+    T best = -1;
+    int64_t arg = k;
+    for (int64_t i = k + t; i < nc; i += 1024) {
+      const cplx<T> v = A[i + k * nc];
+      const T a = fabs(v.re) + fabs(v.im);
+      if (a > best) {
+        best = a;
+        arg = i;
       }
+    }
+    bv[t] = best;
+    bi[t] = arg;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+      if (t < h) {
+        const T o = bv[t + h];
+        const int64_t oi = bi[t + h];
+        if (o > bv[t] || (o == bv[t] && oi < bi[t])) {
+          bv[t] = o;
+          bi[t] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int64_t p = bi[0];
+    if (t == 0) piv[k] = (int32_t)p;
+    if (p != k)
+      for (int64_t j = k0 + t; j < k0 + nb; j += 1024) {
+        const cplx<T> x = A[k + j * nc];
+        A[k + j * nc] = A[p + j * nc];
+        A[p + j * nc] = x;
+      }
+    __syncthreads();
+    const cplx<T> d = A[k + k * nc];
+    for (int64_t i = k + 1 + t; i < nc; i += 1024) A[i + k * nc] = cdiv(A[i + k * nc], d);
+    __syncthreads();
+    const int64_t mr = nc - k - 1, mcol = k0 + nb - k - 1;
+    for (int64_t e = t; e < mr * mcol; e += 1024) {
+      const int64_t i = k + 1 + e % mr, j = k + 1 + e / mr;
+      cfms(A[i + j * nc], A[i + k * nc], A[k + j * nc]);
     }
     __syncthreads();
   }
-  const int64_t p = bi[0];
-  if (threadIdx.x == 0) piv[k] = (int32_t)p;
-  // swap rows k and p over all columns
-  if (p != k)
-    for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) {
-      const cplx<T> t = A[k + j * nc];
-      A[k + j * nc] = A[p + j * nc];
-      A[p + j * nc] = t;
-    }
-  __syncthreads();
-  const cplx<T> d = A[k + k * nc];
-  for (int64_t i = k + 1 + threadIdx.x; i < nc; i += blockDim.x) A[i + k * nc] = cdiv(A[i + k * nc], d);
 }
 
+// the panel's interchanges, in order, on every column outside it
 template <typename T>
-__global__ void k_lu_update(int64_t nc, int64_t k, cplx<T>* A) {
-  const int64_t i = k + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t j = k + 1 + blockIdx.y;
-  if (i >= nc || j >= nc) return;
-  cfms(A[i + j * nc], A[i + k * nc], A[k + j * nc]);
+__global__ void k_lu_swaps(int64_t nc, int64_t k0, int nb, cplx<T>* A, const int32_t* __restrict__ piv) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nc - nb) return;
+  if (j >= k0) j += nb;
+  for (int jj = 0; jj < nb; ++jj) {
+    const int64_t k = k0 + jj, p = piv[k];
+    if (p != k) {
+      const cplx<T> x = A[k + j * nc];
+      A[k + j * nc] = A[p + j * nc];
+      A[p + j * nc] = x;
+    }
+  }
+}
+
+// U12 = L11^{-1} A12 (L11 unit lower), one column per thread
+template <typename T>
+__global__ void k_lu_trsm(int64_t nc, int64_t k0, int nb, cplx<T>* A) {
+  const int64_t j = k0 + nb + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nc) return;
+  cplx<T>* c = A + j * nc + k0;
+  const cplx<T>* L = A + k0 * nc + k0;
+  for (int r = 1; r < nb; ++r) {
+    cplx<T> x = c[r];
+    for (int q = 0; q < r; ++q) cfms(x, L[r + (int64_t)q * nc], c[q]);
+    c[r] = x;
+  }
+}
+
+// A22 -= L21 U12 over 64 x 64 tiles, k = nb <= kLuNb: each wavefront a 32 x 32 quarter
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_gemm(int64_t nc, int64_t k0, int nb, cplx<T>* A) {
+  __shared__ cplx<T> As[kLuNb][kLuTile + 1];  // As[l][r] = L21[i0 + r][l]
+  __shared__ cplx<T> Bs[kLuNb][kLuTile + 1];  // Bs[l][c] = U12[l][j0 + c]
+  const int64_t c0 = k0 + nb;
+  const int64_t i0 = c0 + (int64_t)blockIdx.x * kLuTile, j0 = c0 + (int64_t)blockIdx.y * kLuTile;
+  for (int e = threadIdx.x; e < kLuNb * kLuTile; e += 256) {
+    const int l = e / kLuTile, r = e % kLuTile;
+    cplx<T> a = cmk((T)0, (T)0), b = cmk((T)0, (T)0);
+    if (l < nb) {
+      if (i0 + r < nc) a = A[i0 + r + (k0 + l) * nc];
+      if (j0 + r < nc) b = A[k0 + l + (j0 + r) * nc];
+    }
+    As[l][r] = a;
+    Bs[l][r] = b;
+  }
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, lr = ln & 15, lq = ln >> 4;
+  const int wr = (wv & 1) * 32, wc = (wv >> 1) * 32;
+  CAcc<T> acc[2][2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int g = 0; g < 2; ++g) acc[m][g].zero();
+#pragma unroll 2
+  for (int k = 0; k < kLuNb; k += 4) {
+    const int kk = k + lq;
+    cplx<T> a[2], b[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) a[m] = As[kk][wr + 16 * m + lr];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) b[g] = Bs[kk][wc + 16 * g + lr];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int g = 0; g < 2; ++g) acc[m][g].mac(a[m], b[g]);
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int64_t j = j0 + wc + 16 * g + lr;
+      if (j >= nc) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = i0 + wr + 16 * m + CAcc<T>::row(lq, v);
+        if (i < nc) A[i + j * nc] = A[i + j * nc] - acc[m][g].get(v);
+      }
+    }
 }
 
 // X = E^{-1}: block j solves L U x = P e_j in place in column j of X, rows in parallel
@@ -291,11 +384,17 @@ __global__ void k_c128_to_c64(int64_t n, const c128* a, c64* b) {
 template <typename T>
 void lu_and_inverse(Ctx* ctx, int64_t nc, cplx<T>* E, int32_t* piv, cplx<T>* Einv) {
   hipStream_t st = ctx->stream;
-  for (int64_t k = 0; k < nc; ++k) {
-    hipLaunchKernelGGL(k_lu_pivot<T>, dim3(1), dim3(256), 0, st, nc, k, E, piv);
-    if (k + 1 < nc) {
-      const int64_t m = nc - k - 1;
-      hipLaunchKernelGGL(k_lu_update<T>, dim3((unsigned)((m + 255) / 256), (unsigned)m), dim3(256), 0, st, nc, k, E);
+  for (int64_t k0 = 0; k0 < nc; k0 += kLuNb) {
+    const int nb = (int)std::min<int64_t>(kLuNb, nc - k0);
+    hipLaunchKernelGGL(k_lu_panel<T>, dim3(1), dim3(1024), 0, st, nc, k0, nb, E, piv);
+    if (nc > nb)
+      hipLaunchKernelGGL(k_lu_swaps<T>, dim3((unsigned)((nc - nb + 255) / 256)), dim3(256), 0, st, nc, k0, nb, E,
+                         (const int32_t*)piv);
+    const int64_t m = nc - k0 - nb;
+    if (m > 0) {
+      hipLaunchKernelGGL(k_lu_trsm<T>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, nc, k0, nb, E);
+      const unsigned t = (unsigned)((m + kLuTile - 1) / kLuTile);
+      hipLaunchKernelGGL(k_lu_gemm<T>, dim3(t, t), dim3(256), 0, st, nc, k0, nb, E);
     }
   }
   HIP_CHECK(hipGetLastError());

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <numeric>
+#include <set>
 #include <thread>
 
 #include "ddm.h"
@@ -527,6 +528,7 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     }
   });
   d->orig_total = orig;
+  phase("  update rows, scatter lists");
   // levels
   d->levels.assign(max_level + 1, Level{});
   for (size_t fi = 0; fi < d->fronts.size(); ++fi) d->levels[d->fronts[fi].level].fronts.push_back((int32_t)fi);
@@ -548,58 +550,65 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   }
   d->level_off.push_back((int64_t)lf.size());
   // Update (Schur) blocks live from their front's level until their parent's level has
-  // absorbed them.  Place them in one arena with a first-fit allocator over those lifetimes:
-  // at each level the new blocks are placed while the children being absorbed at that level
-  // are still held, and only then are those children released.  The subdomains are factored
-  // in groups of consecutive ids, one group after the other, each group packed from offset 0:
-  // the arena then holds one group's blocks at a time.  A front's arithmetic does not depend
-  // on the fronts it shares a launch with, so the grouping changes memory, not results.
-  auto pack_arena = [&](int32_t s0, int32_t s1) -> int64_t {
-    std::map<int64_t, int64_t> holes;  // offset -> length
+  // absorbed them.  Place them in one arena with a best-fit allocator over those lifetimes: at
+  // each level the new blocks are placed (largest p first) while the children being absorbed at
+  // that level are still held, and only then are those children released.  The subdomains are
+  // factored in groups of consecutive ids, one group after the other, each group packed from
+  // offset 0: the arena then holds one group's blocks at a time.  A front's arithmetic does not
+  // depend on the fronts it shares a launch with, so the grouping changes memory, not results.
+  auto pack_arena = [&](const std::vector<std::vector<int32_t>>& lvl_fronts) -> int64_t {
+    std::map<int64_t, int64_t> holes;          // offset -> length
+    std::set<std::pair<int64_t, int64_t>> by_len;  // (length, offset) of the same holes
     int64_t arena = 0;
+    auto drop = [&](std::map<int64_t, int64_t>::iterator it) {
+      by_len.erase({it->second, it->first});
+      return holes.erase(it);
+    };
     auto take = [&](int64_t len) {
-      for (auto it = holes.begin(); it != holes.end(); ++it)
-        if (it->second >= len) {
-          const int64_t off = it->first, rest = it->second - len;
-          holes.erase(it);
-          if (rest > 0) holes[off + len] = rest;
-          return off;
+      auto b = by_len.lower_bound({len, INT64_MIN});
+      if (b != by_len.end()) {  // the smallest hole that holds len (lowest offset among equals)
+        const int64_t off = b->second, rest = b->first - len;
+        drop(holes.find(off));
+        if (rest > 0) {
+          holes[off + len] = rest;
+          by_len.insert({rest, off + len});
         }
+        return off;
+      }
       const int64_t off = arena;
       arena += len;
       return off;
     };
     auto give = [&](int64_t off, int64_t len) {
-      auto it = holes.emplace(off, len).first;
-      if (it != holes.begin()) {
-        auto pv = std::prev(it);
-        if (pv->first + pv->second == it->first) {
-          pv->second += it->second;
-          holes.erase(it);
-          it = pv;
+      auto nx = holes.lower_bound(off);
+      if (nx != holes.begin()) {  // merge with the hole ending at off
+        auto pv = std::prev(nx);
+        if (pv->first + pv->second == off) {
+          off = pv->first;
+          len += pv->second;
+          drop(pv);
         }
       }
-      auto nx = std::next(it);
-      if (nx != holes.end() && it->first + it->second == nx->first) {
-        it->second += nx->second;
-        holes.erase(nx);
+      if (nx != holes.end() && off + len == nx->first) {  // and with the one starting at its end
+        len += nx->second;
+        drop(nx);
       }
-      if (it->first + it->second == arena) {  // trailing hole: shrink the arena
-        arena = it->first;
-        holes.erase(it);
+      if (off + len == arena) {  // trailing hole: shrink the arena
+        arena = off;
+        return;
       }
+      holes[off] = len;
+      by_len.insert({len, off});
     };
     int64_t peak = 0;
-    for (const Level& L : d->levels) {
-      for (int32_t fi : L.fronts) {
+    for (const auto& fl : lvl_fronts) {
+      for (int32_t fi : fl) {
         Front& F = d->fronts[fi];
-        if (F.sub < s0 || F.sub >= s1) continue;
         F.U_off = F.r > 0 ? take(F.r * F.r) : 0;
         peak = std::max(peak, arena);
       }
-      for (int32_t fi : L.fronts) {
+      for (int32_t fi : fl) {
         const Front& F = d->fronts[fi];
-        if (F.sub < s0 || F.sub >= s1) continue;
         for (int k = 0; k < F.nchild; ++k) {
           const Front& C = d->fronts[F.child[k]];
           if (C.r > 0) give(C.U_off, C.r * C.r);
@@ -623,7 +632,14 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
       int64_t peak = 0;
       d->fgroup_off.clear();
       for (int g = 0; g <= G; ++g) d->fgroup_off.push_back((int32_t)((int64_t)n_sub * g / G));
-      for (int g = 0; g < G; ++g) peak = std::max(peak, pack_arena(d->fgroup_off[g], d->fgroup_off[g + 1]));
+      // each group's fronts per level, in the level's order (p descending)
+      std::vector<int32_t> gsub(n_sub);
+      for (int g = 0; g < G; ++g)
+        for (int32_t i = d->fgroup_off[g]; i < d->fgroup_off[g + 1]; ++i) gsub[i] = g;
+      std::vector<std::vector<std::vector<int32_t>>> gl(G, std::vector<std::vector<int32_t>>(d->levels.size()));
+      for (size_t lv = 0; lv < d->levels.size(); ++lv)
+        for (int32_t fi : d->levels[lv].fronts) gl[gsub[d->fronts[fi].sub]][lv].push_back(fi);
+      for (int g = 0; g < G; ++g) peak = std::max(peak, pack_arena(gl[g]));
       d->update_entries = peak;
       if (forced > 0 || G >= n_sub || (double)peak * elem <= budget) break;
       G = std::min<int>(2 * G, n_sub);
@@ -686,6 +702,7 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     d->d_pou_pos.upload(ctx, pos);
     d->d_pou_w.upload(ctx, wt);
   }
+  phase("  local-global maps");
   // --- device: front descriptors, maps, local operators
   std::vector<FrontDesc> fd(d->fronts.size());
   int64_t wrows = 0;
@@ -732,6 +749,7 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   d->d_flf.upload(ctx, d->flf);
   d->w_total = wrows;
   d->d_imap.upload(ctx, imap);
+  phase("  front descriptors, uploads");
   {  // solve worklists: forward row tiles of 64, backward column tiles of 32 (vector-unit
      // sweeps) and the wider tiles of the matrix-core sweeps.  Workgroups are dealt to the 8
      // XCDs round-robin by launch index, each XCD with its own L2.  All tiles of a front go to
@@ -796,6 +814,7 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
       build(kFwdRowsMfma[t], kBwdColsMfma[t], d->fwdm_off[t], d->bwdm_off[t], d->d_fwdm_work[t], d->d_bwdm_work[t]);
   }
   {
+    phase("  solve worklists");
     // concatenated local CSR patterns, gather maps and Dirichlet flags (one subdomain per task)
     std::vector<int64_t> goff(n_sub + 1, 0);
     for (int32_t i = 0; i < n_sub; ++i) goff[i + 1] = goff[i] + d->subs[i].gm.ptr.back();
@@ -818,6 +837,7 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     d->d_lgsrc.upload(ctx, gs);
     d->d_ldir.upload(ctx, dr);
     d->d_lval.alloc(ctx, csr);
+    phase("  local patterns, uploads");
     // element matrices of the operator (released after hz_assemble; the same kernel on the same
     // coefficients gives the same bits), kept only while the local operators are filled
     DevArray<double> dv, dq;
