@@ -254,7 +254,7 @@ hz_status hz_mesh(hz_ctx* c, int64_t n_tets, const int32_t* tets, int64_t n_vert
   return guard(c, [&] {
     HZ_REQUIRE(mesh && n_dofs, HZ_ERR_ARG, "hz_mesh: null output");
     auto m = build_mesh(c, n_tets, tets, n_verts, coords, face_bc);
-    // global pattern + assembly map (impedance faces of the physical boundary)
+    // global pattern and its rows' element incidences (impedance faces of the physical boundary)
     std::vector<int64_t> all(m->T);
     for (int64_t t = 0; t < m->T; ++t) all[t] = t;
     std::vector<int32_t> loc(m->n);
@@ -263,12 +263,13 @@ hz_status hz_mesh(hz_ctx* c, int64_t n_tets, const int32_t* tets, int64_t n_vert
     for (int64_t t = 0; t < m->T; ++t)
       for (int f = 0; f < 4; ++f)
         if (m->tag[4 * t + f] == HZ_BC_IMPEDANCE) robin[t] |= (uint8_t)(1u << f);
-    GatherMap gm;
-    build_pattern_and_map(*m, all, loc, m->n, robin, m->rowptr, m->col, gm);
+    RowIncidence inc;
+    build_pattern_and_incidence(*m, all, loc, m->n, m->rowptr, m->col, inc);
     m->d_rowptr.upload(c, m->rowptr);
     m->d_col.upload(c, m->col);
-    m->d_gptr.upload(c, gm.ptr);
-    m->d_gsrc.upload(c, gm.src);
+    m->d_inc_ptr.upload(c, inc.ptr);
+    m->d_inc.upload(c, inc.idx);
+    m->d_robin.upload(c, robin);
     const hz_handle h = new_handle(c);
     std::lock_guard<std::mutex> lk(c->mu);
     c->meshes[h] = m;
@@ -301,8 +302,9 @@ hz_status hz_assemble(hz_ctx* c, hz_handle mesh, const double* velocity, const d
     launch_element_matrices(c, *m, *o, dv.ptr(), Q ? dq.ptr() : nullptr);
     o->d_val.alloc(c, m->nnz());
     o->d_val32.alloc(c, m->nnz());
-    launch_gather_fill(c->stream, m->n, m->d_rowptr.ptr(), m->d_col.ptr(), m->d_gptr.ptr(), m->d_gsrc.ptr(),
-                       o->d_elem.ptr(), m->d_dirichlet.ptr(), o->d_val.ptr(), o->d_val32.ptr());
+    launch_incidence_fill(c->stream, m->n, m->d_rowptr.ptr(), m->d_col.ptr(), nullptr, m->d_inc_ptr.ptr(),
+                          m->d_inc.ptr(), nullptr, m->d_robin.ptr(), m->d_tet_dofs.ptr(), o->d_elem.ptr(),
+                          m->d_dirichlet.ptr(), o->d_val.ptr(), o->d_val32.ptr());
     HIP_CHECK(hipStreamSynchronize(c->stream));
     // the element matrices are recomputed when a decomposition needs its local operators
     o->d_elem = DevArray<c128>();

@@ -127,24 +127,54 @@ __global__ __launch_bounds__(kElemThreads) void k_element(int64_t T, const int32
   }
 }
 
-// one 64-lane wavefront per row
-__global__ __launch_bounds__(256) void k_gather_fill(int64_t n_rows, const int64_t* __restrict__ rowptr,
-                                                     const int32_t* __restrict__ col, const int64_t* __restrict__ gptr,
-                                                     const uint32_t* __restrict__ gsrc, const c128* __restrict__ elem,
-                                                     const uint8_t* __restrict__ dir, c128* __restrict__ val,
-                                                     c64* __restrict__ val32) {
+// position of each element node on each face (-1: not on it)
+struct FacePos {
+  int8_t p[4][20];
+};
+
+// one wavefront per row, its entries 64 at a time (lane: one entry); for each element
+// incidence of the row (ascending tet) and each node j of that tet, the lane holding column
+// j's dof adds the element entry, then the Robin face entries, in the order of the host's
+// former gather lists
+__global__ __launch_bounds__(256) void k_incidence_fill(int64_t n_rows, const int64_t* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ col, const int32_t* __restrict__ gdofs,
+                                                        const int64_t* __restrict__ inc_ptr, const int32_t* __restrict__ inc,
+                                                        const int32_t* __restrict__ tsel, const uint8_t* __restrict__ robin,
+                                                        const int32_t* __restrict__ tet_dofs, const c128* __restrict__ elem,
+                                                        const uint8_t* __restrict__ dir, c128* __restrict__ val,
+                                                        c64* __restrict__ val32, FacePos fp) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n_rows) return;
   const bool drow = dir && dir[row];
-  for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += 64) {
+  const int64_t k0 = inc_ptr[row], k1 = inc_ptr[row + 1];
+  for (int64_t base = rowptr[row]; base < rowptr[row + 1]; base += 64) {
+    const int64_t e = base + lane;
+    const bool mine = e < rowptr[row + 1];
+    const int32_t c = mine ? col[e] : -1;
+    const int32_t gc = mine ? (gdofs ? gdofs[c] : c) : -1;
     c128 s = cmk(0.0, 0.0);
-    const int32_t c = col[e];
-    if (drow || (dir && dir[c])) {
-      s = cmk(c == row ? 1.0 : 0.0, 0.0);
-    } else {
-      for (int64_t k = gptr[e]; k < gptr[e + 1]; ++k) s = s + elem[gsrc[k]];
+    for (int64_t k = k0; k < k1; ++k) {
+      const int32_t qi = inc[k];
+      const int32_t q = qi / 20, i = qi - (qi / 20) * 20;
+      const int64_t t = tsel ? (int64_t)tsel[q] : (int64_t)q;
+      const uint8_t rm = robin ? robin[q] : (uint8_t)0;
+      const c128* et = elem + t * kElemStride;
+      for (int j = 0; j < 20; ++j) {
+        if (tet_dofs[t * 20 + j] != gc) continue;
+        const int pij = i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
+        s = s + et[pij];
+        for (int f = 0; f < 4; ++f) {
+          const int fi = fp.p[f][i], fj = fp.p[f][j];
+          if (((rm >> f) & 1) && fi >= 0 && fj >= 0) {
+            const int pf = fi >= fj ? fi * (fi + 1) / 2 + fj : fj * (fj + 1) / 2 + fi;
+            s = s + et[kElemVol + f * kFaceEnt + pf];
+          }
+        }
+      }
     }
+    if (!mine) continue;
+    if (drow || (dir && dir[c])) s = cmk(c == row ? 1.0 : 0.0, 0.0);
     val[e] = s;
     if (val32) val32[e] = cmk((float)s.re, (float)s.im);
   }
@@ -230,13 +260,20 @@ void launch_element_matrices(Ctx* ctx, const Mesh& m, Operator& op, const double
   HIP_CHECK(hipGetLastError());
 }
 
-void launch_gather_fill(hipStream_t st, int64_t n_rows, const int64_t* d_rowptr, const int32_t* d_col,
-                        const int64_t* d_gptr, const uint32_t* d_gsrc, const c128* d_elem, const uint8_t* d_dir,
-                        c128* d_val, c64* d_val32) {
+void launch_incidence_fill(hipStream_t st, int64_t n_rows, const int64_t* d_rowptr, const int32_t* d_col,
+                           const int32_t* d_gdofs, const int64_t* d_inc_ptr, const int32_t* d_inc,
+                           const int32_t* d_tsel, const uint8_t* d_robin, const int32_t* d_tet_dofs,
+                           const c128* d_elem, const uint8_t* d_dir, c128* d_val, c64* d_val32) {
   if (n_rows == 0) return;
+  const P3Tables& tab = p3_tables();
+  FacePos fp;
+  for (int f = 0; f < 4; ++f) {
+    for (int i = 0; i < 20; ++i) fp.p[f][i] = -1;
+    for (int a = 0; a < 10; ++a) fp.p[f][tab.face_nodes[f][a]] = (int8_t)a;
+  }
   const int64_t blocks = (n_rows + 3) / 4;
-  hipLaunchKernelGGL(k_gather_fill, dim3((unsigned)blocks), dim3(256), 0, st, n_rows, d_rowptr, d_col, d_gptr, d_gsrc,
-                     d_elem, d_dir, d_val, d_val32);
+  hipLaunchKernelGGL(k_incidence_fill, dim3((unsigned)blocks), dim3(256), 0, st, n_rows, d_rowptr, d_col, d_gdofs,
+                     d_inc_ptr, d_inc, d_tsel, d_robin, d_tet_dofs, d_elem, d_dir, d_val, d_val32, fp);
   HIP_CHECK(hipGetLastError());
 }
 

@@ -233,7 +233,9 @@ void build_subdomain(const Mesh& m, const std::vector<int32_t>& part, const std:
       if (imp || cut) robin[q] |= (uint8_t)(1u << f);
     }
   }
-  build_pattern_and_map(m, cur, loc, S.n, robin, S.rowptr, S.col, S.gm);
+  build_pattern_and_incidence(m, cur, loc, S.n, S.rowptr, S.col, S.inc);
+  S.tsel.assign(cur.begin(), cur.end());
+  S.robin = std::move(robin);
   // --- nested dissection over the overlapped tets
   std::vector<int32_t> ltd(cur.size() * 20);
   for (size_t q = 0; q < cur.size(); ++q)
@@ -351,8 +353,8 @@ inline int64_t front_index(const Front& F, const std::vector<int32_t>& U, int64_
 int64_t Ddm::device_bytes() const {
   int64_t b = 0;
   b += d_fronts.bytes() + d_urows.bytes() + d_emap.bytes() + d_gidx.bytes() + d_orig_src.bytes() +
-       d_orig_dst.bytes() + d_own_src.bytes() + d_lrowptr.bytes() + d_lgptr.bytes() + d_lcol.bytes() +
-       d_lgsrc.bytes() + d_ldir.bytes() + d_lval.bytes() + d_level_fronts.bytes() + d_flf.bytes();
+       d_orig_dst.bytes() + d_own_src.bytes() + d_lrowptr.bytes() + d_lcol.bytes() + d_ldir.bytes() +
+       d_lval.bytes() + d_level_fronts.bytes() + d_flf.bytes();
   b += d_factor.bytes + d_update.bytes + d_dinv.bytes;
   b += d_pou_ptr.bytes() + d_pou_pos.bytes() + d_pou_w.bytes();
   b += d_fwd_work.bytes() + d_bwd_work.bytes() + d_imap.bytes();
@@ -815,28 +817,40 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   }
   {
     phase("  solve worklists");
-    // concatenated local CSR patterns, gather maps and Dirichlet flags (one subdomain per task)
-    std::vector<int64_t> goff(n_sub + 1, 0);
-    for (int32_t i = 0; i < n_sub; ++i) goff[i + 1] = goff[i] + d->subs[i].gm.ptr.back();
-    std::vector<int64_t> rp(rows), gp(csr + 1);
-    std::vector<int32_t> cl(csr);
-    std::vector<uint32_t> gs(goff[n_sub]);
-    std::vector<uint8_t> dr(vec);
+    // concatenated local CSR patterns, Dirichlet flags, and what the device fill of the local
+    // values reads: each subdomain's row incidences, tets, Robin masks and local-to-global map
+    // (one subdomain per task)
+    std::vector<int64_t> ioff(n_sub + 1, 0), toff(n_sub + 1, 0);
+    for (int32_t i = 0; i < n_sub; ++i) {
+      ioff[i + 1] = ioff[i] + (int64_t)d->subs[i].inc.idx.size();
+      toff[i + 1] = toff[i] + (int64_t)d->subs[i].tsel.size();
+    }
+    std::vector<int64_t> rp(rows), ip(rows);
+    std::vector<int32_t> cl(csr), ix(ioff[n_sub]), ts(toff[n_sub]), gd(vec);
+    std::vector<uint8_t> dr(vec), rb(toff[n_sub]);
     each_sub([&](int32_t i) {
       const Subdomain& S = d->subs[i];
       std::copy(S.rowptr.begin(), S.rowptr.begin() + S.n + 1, rp.begin() + S.row_off);
+      std::copy(S.inc.ptr.begin(), S.inc.ptr.begin() + S.n + 1, ip.begin() + S.row_off);
       std::copy(S.col.begin(), S.col.end(), cl.begin() + S.csr_off);
-      for (size_t k = 0; k + 1 < S.gm.ptr.size(); ++k) gp[S.csr_off + k] = S.gm.ptr[k] + goff[i];
-      std::copy(S.gm.src.begin(), S.gm.src.end(), gs.begin() + goff[i]);
+      std::copy(S.inc.idx.begin(), S.inc.idx.end(), ix.begin() + ioff[i]);
+      std::copy(S.tsel.begin(), S.tsel.end(), ts.begin() + toff[i]);
+      std::copy(S.robin.begin(), S.robin.end(), rb.begin() + toff[i]);
+      std::copy(S.gdofs.begin(), S.gdofs.end(), gd.begin() + S.vec_off);
       std::copy(S.dir.begin(), S.dir.end(), dr.begin() + S.vec_off);
     });
-    gp[csr] = goff[n_sub];
     d->d_lrowptr.upload(ctx, rp);
     d->d_lcol.upload(ctx, cl);
-    d->d_lgptr.upload(ctx, gp);
-    d->d_lgsrc.upload(ctx, gs);
     d->d_ldir.upload(ctx, dr);
     d->d_lval.alloc(ctx, csr);
+    DevArray<int64_t> d_ip;
+    DevArray<int32_t> d_ix, d_ts, d_gd;
+    DevArray<uint8_t> d_rb;
+    d_ip.upload(ctx, ip);
+    d_ix.upload(ctx, ix);
+    d_ts.upload(ctx, ts);
+    d_rb.upload(ctx, rb);
+    d_gd.upload(ctx, gd);
     phase("  local patterns, uploads");
     // element matrices of the operator (released after hz_assemble; the same kernel on the same
     // coefficients gives the same bits), kept only while the local operators are filled
@@ -848,16 +862,19 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     // one launch per subdomain (row pointers are subdomain-relative)
     for (int32_t i = 0; i < n_sub; ++i) {
       const Subdomain& S = d->subs[i];
-      launch_gather_fill(ctx->stream, S.n, d->d_lrowptr.ptr() + S.row_off, d->d_lcol.ptr() + S.csr_off,
-                         d->d_lgptr.ptr() + S.csr_off, d->d_lgsrc.ptr(), op->d_elem.ptr(), d->d_ldir.ptr() + S.vec_off,
-                         d->d_lval.ptr() + S.csr_off, nullptr);
+      launch_incidence_fill(ctx->stream, S.n, d->d_lrowptr.ptr() + S.row_off, d->d_lcol.ptr() + S.csr_off,
+                            d_gd.ptr() + S.vec_off, d_ip.ptr() + S.row_off, d_ix.ptr() + ioff[i],
+                            d_ts.ptr() + toff[i], d_rb.ptr() + toff[i], m.d_tet_dofs.ptr(), op->d_elem.ptr(),
+                            d->d_ldir.ptr() + S.vec_off, d->d_lval.ptr() + S.csr_off, nullptr);
     }
+    // the local values are assembled: what only their fill needed goes (host and device)
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
   }
-  for (auto& S : d->subs) S.gm = GatherMap();
-  // the local values are assembled: their gather maps are no longer needed on either side
-  HIP_CHECK(hipStreamSynchronize(ctx->stream));
-  d->d_lgptr = DevArray<int64_t>();
-  d->d_lgsrc = DevArray<uint32_t>();
+  for (auto& S : d->subs) {
+    S.inc = RowIncidence();
+    S.tsel = std::vector<int32_t>();
+    S.robin = std::vector<uint8_t>();
+  }
   op->d_elem = DevArray<c128>();
   phase("device maps, local operators");
   // --- numeric factorisation; its algorithmic work per front (p pivots, f rows, panels of 32):

@@ -50,7 +50,9 @@ struct Subdomain {
   std::vector<int32_t> ipos;      // local id -> elimination position
   std::vector<int64_t> rowptr;    // local CSR pattern (local ids)
   std::vector<int32_t> col;
-  GatherMap gm;
+  RowIncidence inc;               // element incidences of the local rows (set-up only)
+  std::vector<int32_t> tsel;      // the overlapped set's tets (global ids, ascending; set-up only)
+  std::vector<uint8_t> robin;     // Robin faces (bitmask) of each of those tets (set-up only)
   std::vector<uint8_t> dir;       // local Dirichlet flags
   std::vector<uint8_t> layer;     // overlap layer of each local dof (smallest over its tets)
   std::vector<double> pouw;       // smooth partition of unity: weight of each local dof
@@ -127,9 +129,9 @@ struct Ddm {
   DevArray<FrontDesc> d_fronts;
   DevArray<int32_t> d_urows, d_emap, d_gidx;
   DevArray<int64_t> d_orig_src, d_orig_dst, d_own_src;
-  DevArray<int64_t> d_lrowptr, d_lgptr;
+  DevArray<int64_t> d_lrowptr;
   DevArray<int32_t> d_lcol;
-  DevArray<uint32_t> d_lgsrc;
+
   DevArray<uint8_t> d_ldir;
   DevArray<c128> d_lval;          // local operator values (FP64), concatenated
   DevArray<int32_t> d_level_fronts;  // fronts of every level, concatenated

@@ -181,17 +181,19 @@ struct Mesh {
   DevArray<double> d_coords;
   DevArray<int32_t> d_tet_dofs;
   DevArray<uint8_t> d_dirichlet;
-  // global pattern and its assembly gather map (impedance faces included)
-  DevArray<int64_t> d_rowptr, d_gptr;
-  DevArray<int32_t> d_col;
-  DevArray<uint32_t> d_gsrc;
+  // global pattern and the per-row element incidences that assemble it (impedance faces
+  // flagged per tet)
+  DevArray<int64_t> d_rowptr, d_inc_ptr;
+  DevArray<int32_t> d_col, d_inc;
+  DevArray<uint8_t> d_robin;
   int64_t nnz() const { return (int64_t)col.size(); }
 };
 
-// gather map: value of CSR entry e = sum_{k in [ptr[e], ptr[e+1])} elem[src[k]]
-struct GatherMap {
+// element incidences of the rows of an assembled operator: row r's are idx[ptr[r] ..
+// ptr[r + 1]), each 20 q + l (selected tet q, element node l), in ascending q
+struct RowIncidence {
   std::vector<int64_t> ptr;
-  std::vector<uint32_t> src;
+  std::vector<int32_t> idx;
 };
 
 struct Operator {
@@ -252,22 +254,27 @@ inline int packed(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j +
 // mesh.cpp
 std::shared_ptr<Mesh> build_mesh(Ctx* ctx, int64_t T, const int32_t* tets, int64_t V, const double* coords,
                                  const int8_t* face_bc);
-// builds the gather map for a set of tets (global ids `tets_sel`, ascending) with local dof
-// numbering `loc` (global dof -> local id or -1), robin faces per selected tet (bitmask of 4),
-// and produces the local CSR pattern.
-void build_pattern_and_map(const Mesh& m, const std::vector<int64_t>& tets_sel, const std::vector<int32_t>& loc,
-                           int64_t n_local, const std::vector<uint8_t>& robin_mask, std::vector<int64_t>& rowptr,
-                           std::vector<int32_t>& col, GatherMap& gm, int64_t elem_base_stride = kElemStride);
+// the CSR pattern of the operator assembled from a set of tets (global ids `tets_sel`,
+// ascending) with local dof numbering `loc` (global dof -> local id or -1), and its rows'
+// element incidences (which the device fill sums over)
+void build_pattern_and_incidence(const Mesh& m, const std::vector<int64_t>& tets_sel, const std::vector<int32_t>& loc,
+                                 int64_t n_local, std::vector<int64_t>& rowptr, std::vector<int32_t>& col,
+                                 RowIncidence& inc);
 
 // assemble.hip
 void launch_element_matrices(Ctx* ctx, const Mesh& m, Operator& op, const double* d_vel, const double* d_q);
 void launch_point_sources(Ctx* ctx, const Mesh& m, int64_t ns, const double* d_xyz, const double* d_amp,
                           unsigned long long* d_best, c128* d_rhs);
-// value of CSR entry e of row r: sum of elem[src[k]] over k in [gptr[e], gptr[e+1]);
-// rows/cols flagged in dir (per local dof) become identity rows/columns.
-void launch_gather_fill(hipStream_t st, int64_t n_rows, const int64_t* d_rowptr, const int32_t* d_col,
-                        const int64_t* d_gptr, const uint32_t* d_gsrc, const c128* d_elem, const uint8_t* d_dir,
-                        c128* d_val, c64* d_val32);
+// values of an operator assembled from its rows' element incidences: entry (r, c) sums, over
+// the incidences of row r in ascending tet order, the element entry (node of r, node of c)
+// and then the face entries of the tet's Robin faces (bitmask robin[q]; null: none) that hold
+// both nodes.  Local ids map to global dofs through gdofs (null: the identity); tsel maps a
+// selected tet to its global id (null: the identity).  Rows and columns flagged in dir (per
+// local dof, nullable) become identity rows and columns.
+void launch_incidence_fill(hipStream_t st, int64_t n_rows, const int64_t* d_rowptr, const int32_t* d_col,
+                           const int32_t* d_gdofs, const int64_t* d_inc_ptr, const int32_t* d_inc,
+                           const int32_t* d_tsel, const uint8_t* d_robin, const int32_t* d_tet_dofs,
+                           const c128* d_elem, const uint8_t* d_dir, c128* d_val, c64* d_val32);
 
 // spmm.hip: y = alpha A x + beta yin (yin may be null), A complex128 CSR, x complex<TX>
 // (complex64 x is widened exactly), y complex128; node-major [n][s] blocks

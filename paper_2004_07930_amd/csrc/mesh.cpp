@@ -196,33 +196,27 @@ std::shared_ptr<Mesh> build_mesh(Ctx* ctx, int64_t T, const int32_t* tets, int64
   return m;
 }
 
-void build_pattern_and_map(const Mesh& m, const std::vector<int64_t>& tets_sel, const std::vector<int32_t>& loc,
-                           int64_t n_local, const std::vector<uint8_t>& robin_mask, std::vector<int64_t>& rowptr,
-                           std::vector<int32_t>& col, GatherMap& gm, int64_t stride) {
-  const P3Tables& tab = p3_tables();
-  int fpos[4][20];
-  for (int f = 0; f < 4; ++f) {
-    for (int i = 0; i < 20; ++i) fpos[f][i] = -1;
-    for (int a = 0; a < 10; ++a) fpos[f][tab.face_nodes[f][a]] = a;
-  }
+void build_pattern_and_incidence(const Mesh& m, const std::vector<int64_t>& tets_sel, const std::vector<int32_t>& loc,
+                                 int64_t n_local, std::vector<int64_t>& rowptr, std::vector<int32_t>& col,
+                                 RowIncidence& inc) {
   const int64_t Ts = (int64_t)tets_sel.size();
-  HZ_REQUIRE(m.T * stride < (int64_t)UINT32_MAX, HZ_ERR_ARG, "assembly map: element index overflow");
+  HZ_REQUIRE(Ts * 20 < (int64_t)INT32_MAX, HZ_ERR_ARG, "assembly: too many tets in one operator");
   // local dof -> (selected tet position, node) in ascending tet order
-  std::vector<int64_t> cnt(n_local + 1, 0);
+  inc.ptr.assign(n_local + 1, 0);
   for (int64_t q = 0; q < Ts; ++q)
     for (int l = 0; l < 20; ++l) {
       int32_t r = loc[m.tet_dofs[tets_sel[q] * 20 + l]];
       HZ_REQUIRE(r >= 0 && r < n_local, HZ_ERR_STATE, "pattern: dof outside local numbering");
-      cnt[r + 1]++;
+      inc.ptr[r + 1]++;
     }
-  for (int64_t r = 0; r < n_local; ++r) cnt[r + 1] += cnt[r];
-  std::vector<int64_t> inc(cnt[n_local]);
+  for (int64_t r = 0; r < n_local; ++r) inc.ptr[r + 1] += inc.ptr[r];
+  inc.idx.resize(inc.ptr[n_local]);
   {
-    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    std::vector<int64_t> fill(inc.ptr.begin(), inc.ptr.end() - 1);
     for (int64_t q = 0; q < Ts; ++q)
       for (int l = 0; l < 20; ++l) {
         int32_t r = loc[m.tet_dofs[tets_sel[q] * 20 + l]];
-        inc[fill[r]++] = q * 20 + l;
+        inc.idx[fill[r]++] = (int32_t)(q * 20 + l);
       }
   }
   // pattern
@@ -232,8 +226,8 @@ void build_pattern_and_map(const Mesh& m, const std::vector<int64_t>& tets_sel, 
     std::vector<int32_t> buf;
     for (int64_t r = a; r < b; ++r) {
       buf.clear();
-      for (int64_t k = cnt[r]; k < cnt[r + 1]; ++k) {
-        int64_t q = inc[k] / 20;
+      for (int64_t k = inc.ptr[r]; k < inc.ptr[r + 1]; ++k) {
+        int64_t q = inc.idx[k] / 20;
         for (int j = 0; j < 20; ++j) buf.push_back(loc[m.tet_dofs[tets_sel[q] * 20 + j]]);
       }
       std::sort(buf.begin(), buf.end());
@@ -245,41 +239,6 @@ void build_pattern_and_map(const Mesh& m, const std::vector<int64_t>& tets_sel, 
   col.resize(rowptr[n_local]);
   parallel_for(n_local, [&](int64_t a, int64_t b) {
     for (int64_t r = a; r < b; ++r) std::copy(rows[r].begin(), rows[r].end(), col.begin() + rowptr[r]);
-  });
-  rows.clear();
-  rows.shrink_to_fit();
-  // gather map: two passes (count, fill), contributions ordered by tet then volume/faces
-  const int64_t nnz = rowptr[n_local];
-  gm.ptr.assign(nnz + 1, 0);
-  auto visit = [&](int64_t r, auto&& emit) {
-    const int32_t* cb = col.data() + rowptr[r];
-    const int64_t len = rowptr[r + 1] - rowptr[r];
-    for (int64_t k = cnt[r]; k < cnt[r + 1]; ++k) {
-      int64_t q = inc[k] / 20;
-      int i = (int)(inc[k] % 20);
-      int64_t e = tets_sel[q];
-      uint8_t rm = robin_mask.empty() ? 0 : robin_mask[q];
-      for (int j = 0; j < 20; ++j) {
-        int32_t c = loc[m.tet_dofs[e * 20 + j]];
-        int64_t pos = std::lower_bound(cb, cb + len, c) - cb;
-        emit(rowptr[r] + pos, (uint64_t)(e * stride + packed(i, j)));
-        for (int f = 0; f < 4; ++f)
-          if ((rm >> f) & 1) {
-            int fi = fpos[f][i], fj = fpos[f][j];
-            if (fi >= 0 && fj >= 0) emit(rowptr[r] + pos, (uint64_t)(e * stride + kElemVol + f * kFaceEnt + packed(fi, fj)));
-          }
-      }
-    }
-  };
-  parallel_for(n_local, [&](int64_t a, int64_t b) {
-    for (int64_t r = a; r < b; ++r) visit(r, [&](int64_t e, uint64_t) { gm.ptr[e + 1]++; });
-  });
-  for (int64_t e = 0; e < nnz; ++e) gm.ptr[e + 1] += gm.ptr[e];
-  gm.src.resize(gm.ptr[nnz]);
-  std::vector<int64_t> fillp(gm.ptr.begin(), gm.ptr.end() - 1);
-  parallel_for(n_local, [&](int64_t a, int64_t b) {
-    for (int64_t r = a; r < b; ++r)
-      visit(r, [&](int64_t e, uint64_t s) { gm.src[fillp[e]++] = (uint32_t)s; });
   });
 }
 
