@@ -280,9 +280,9 @@ def run_serve(args):
     reqs = serve_requests(args.serve)
     probs = serve_workloads()
     free0, _ = torch.cuda.mem_get_info()
-    # requests are host-memory blocks (the library stages each while it runs): the budget is
-    # the device's free memory less a margin for torch's own use
-    ctx = hz.Context(0, stream=torch.cuda.current_stream(), hbm_budget=int(0.92 * free0), allocator="hip")
+    # requests are host-memory blocks (the library stages each part's columns while it runs):
+    # the budget is the device's free memory less a margin for torch and the runtime
+    ctx = hz.Context(0, stream=torch.cuda.current_stream(), hbm_budget=int(0.96 * free0), allocator="hip")
     ops, setup = [], {}
     for k, (q, coarse) in enumerate(probs):
         t0 = time.perf_counter()

@@ -345,8 +345,10 @@ typedef struct {
  *   min(n_rhs, 32) and its halvings, the longest m up to 40 with which one part fits alone;
  *   the widest w whose m reaches 20, else the w with the longest m.  Its parts are admitted in
  *   order when a slot is free and their memory fits; each part stages its own columns of a
- *   host rhs / x (no copy of the whole request is held on the device).  rhs / x / info (info nullable, [n_rhs]) stay caller-owned and must stay
- *   valid until the ticket completes; req->mem says whether rhs and x are host or device.
+ *   host rhs / x (no copy of the whole request is held on the device) through a page-locked
+ *   host buffer that hz_serve_start allocates for one part of the largest operator.
+ *   rhs / x / info (info nullable, [n_rhs]) stay caller-owned and must stay valid until the
+ *   ticket completes; req->mem says whether rhs and x are host or device.
  *   Errors: HZ_ERR_ARG (unknown ddm, n_rhs < 1, null buffers, bad mem), HZ_ERR_ABI
  *   (struct_size), HZ_ERR_BUSY (fits at no restart length >= 8: never admissible),
  *   HZ_ERR_STATE (not serving, or the scheduler failed).

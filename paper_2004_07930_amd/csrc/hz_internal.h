@@ -235,6 +235,9 @@ struct Ctx {
   DevBuf krylov_ws;             // Krylov workspace kept between hz_solve calls
   DevBuf krylov_io;             // hz_solve's node-major right-hand-side and solution blocks
   bool krylov_busy = false;     // a job is using krylov_ws
+  // while serving: one preconditioner solve workspace shared by every ddm (the scheduler
+  // applies them one after another on the context stream); null otherwise
+  struct PrecondWork* shared_pw = nullptr;
 };
 
 // reference element tables (host), see p3ref.cpp

@@ -714,7 +714,7 @@ namespace {
 
 template <typename TZ>
 void precond_apply_t(Ctx* ctx, Ddm& d, int s, const c128* v, cplx<TZ>* z) {
-  PrecondWork& w = d.pw;
+  PrecondWork& w = ctx->shared_pw ? *ctx->shared_pw : d.pw;
   const int64_t n = d.op->mesh->n;
   const bool mixed = d.precision == HZ_PREC_MIXED;
   if (d.coarse) {  // q and t in the coarse precision

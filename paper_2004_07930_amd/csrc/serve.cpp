@@ -18,6 +18,7 @@
 // least-squares step.  A finished job writes its columns of the solution to the caller's
 // block and frees its memory at once; a request completes when all its parts have.
 #include <cstdio>
+#include <cstring>
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -101,6 +102,11 @@ struct Serve {
   double t_first = -1, t_last = 0;
   DevArray<c128> packV, packZ, packW;
   DevArray<c64> packZ32;  // packed preconditioned columns of mixed-precision jobs
+  // page-locked staging of a host request's columns (one part at a time): the caller's pageable
+  // block is copied through it by host threads, so the device copies run at pinned-memory speed
+  HostPinned<c128> stage;
+  // the preconditioner solve workspace every resident ddm shares while serving
+  PrecondWork pw;
 };
 
 static constexpr int kServeRestart = 40;
@@ -136,7 +142,10 @@ static void start_part(Serve& S, Ticket& t, int k) {
   // through Xn (the solve zeroes it before use)
   const c128* cols = static_cast<const c128*>(t.req.rhs) + (int64_t)p->c0 * n;
   if (t.req.mem == HZ_MEM_HOST) {
-    HIP_CHECK(hipMemcpyAsync(p->Xn.ptr(), cols, n * p->s * sizeof(c128), hipMemcpyHostToDevice, ctx->stream));
+    const int64_t cnt = n * p->s;
+    parallel_for(cnt, [&](int64_t a, int64_t b) { std::memcpy(S.stage.p + a, cols + a, (b - a) * sizeof(c128)); });
+    HIP_CHECK(hipMemcpyAsync(p->Xn.ptr(), S.stage.p, cnt * sizeof(c128), hipMemcpyHostToDevice, ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));  // the staging buffer is reused at once
     K.to_node(p->Xn.ptr(), p->Bn.ptr());
   } else {
     K.to_node(cols, p->Bn.ptr());
@@ -154,12 +163,15 @@ static void part_out(Serve& S, Ticket& t, Ticket::Part& p) {
   KrylovKernels K(ctx, n, p.s);
   c128* cols = static_cast<c128*>(t.req.x) + (int64_t)p.c0 * n;
   if (t.req.mem == HZ_MEM_HOST) {
+    const int64_t cnt = n * p.s;
     K.from_node(p.Xn.ptr(), p.Bn.ptr());
-    HIP_CHECK(hipMemcpyAsync(cols, p.Bn.ptr(), n * p.s * sizeof(c128), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_CHECK(hipMemcpyAsync(S.stage.p, p.Bn.ptr(), cnt * sizeof(c128), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    parallel_for(cnt, [&](int64_t a, int64_t b) { std::memcpy(cols + a, S.stage.p + a, (b - a) * sizeof(c128)); });
   } else {
     K.from_node(p.Xn.ptr(), cols);
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
   }
-  HIP_CHECK(hipStreamSynchronize(ctx->stream));
   p.Bn = DevArray<c128>();
   p.Xn = DevArray<c128>();
 }
@@ -463,8 +475,27 @@ hz_status hz_serve_start(hz_ctx* c, int32_t max_slots) {
       S->packW.alloc(x, nmax * 32);
       if (mixed) S->packZ32.alloc(x, nmax * 32);
       if (full) S->packZ.alloc(x, nmax * 32);
+      S->stage.alloc(nmax * 32);
+      // one solve workspace for all ddms, grown here to what a 32-column apply of each needs
+      // (which also tunes their sweep tiles for 32 columns), so that serving's memory is fixed
+      std::vector<std::shared_ptr<Ddm>> ds;
+      {
+        std::lock_guard<std::mutex> lk(x->mu);
+        for (auto& kv : x->ddms) ds.push_back(kv.second);
+      }
+      for (auto& d : ds) precond_release_workspace(*d);
+      x->shared_pw = &S->pw;
+      HIP_CHECK(hipMemsetAsync(S->packV.ptr(), 0, (size_t)nmax * 32 * sizeof(c128), x->stream));
+      for (auto& d : ds) {
+        if (d->precision == HZ_PREC_MIXED)
+          precond_apply(x, *d, 32, S->packV.ptr(), S->packZ32.ptr());
+        else
+          precond_apply(x, *d, 32, S->packV.ptr(), S->packZ.ptr());
+      }
+      HIP_CHECK(hipStreamSynchronize(x->stream));
     }
   } catch (const Error& e) {
+    x->shared_pw = nullptr;
     x->last_error = e.what();
     delete S;
     return e.code;
@@ -610,6 +641,7 @@ hz_status hz_serve_stop(hz_ctx* c) {
   if (failed) x->last_error = "serving stopped: " + S->error;
   x->serve = nullptr;
   x->serving = false;
+  x->shared_pw = nullptr;  // the ddms grow their own workspaces again
   delete S;
   if (failed) x->poisoned = true;
   return failed ? HZ_ERR_HIP : HZ_OK;
