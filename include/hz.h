@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define HZ_ABI_VERSION 3
+#define HZ_ABI_VERSION 4
 
 typedef enum {
   HZ_OK = 0,
@@ -57,6 +57,8 @@ enum { HZ_BC_NONE = 0, HZ_BC_IMPEDANCE = 1, HZ_BC_DIRICHLET = 2 };
 enum { HZ_PREC_C128 = 0, HZ_PREC_MIXED = 1 };
 enum { HZ_MEM_HOST = 0, HZ_MEM_DEVICE = 1 };
 enum { HZ_POU_BOOLEAN = 0, HZ_POU_SMOOTH = 1 };
+/* local solver of the one-level preconditioner (hz_ddm_opts.local_solver) */
+enum { HZ_LOCAL_EXACT = 0, HZ_LOCAL_ICC = 1 };
 
 typedef struct {
   size_t struct_size;  /* sizeof(hz_init_opts)                                        */
@@ -147,13 +149,25 @@ hz_status hz_setup_ddm(hz_ctx* ctx, hz_handle op, const int32_t* partition, int3
  *                    l its layer in i (0 on the non-overlapping tets, k on the tets the k-th
  *                    overlap step added; the smallest over the tets holding it), divided by the
  *                    sum of its raw weights over the subdomains holding it (subdomain order).
- * Errors: as hz_setup_ddm; HZ_ERR_ABI on struct_size; HZ_ERR_ARG on an unknown pou or an
- * overlap above 250.
+ *   opts->local_solver  HZ_LOCAL_EXACT: A_i^{-1} of eq. (oras) by the multifrontal LDL^T factors
+ *                    (hz_setup_ddm's choice).  HZ_LOCAL_ICC: by an incomplete factorisation,
+ *                    the approximate local solver of the paper's numerical section (which names
+ *                    no variant; read here as level 0, no fill): A_i ~ L D L^T (transpose, not
+ *                    conjugate), L unit lower triangular on the strict lower pattern of A_i in
+ *                    its local order (ascending global dof), no shift or pivoting.  The factors
+ *                    are computed in FP64 on the GPU and stored in the preconditioner precision;
+ *                    the solve is forward substitution, scaling by D^{-1} and backward
+ *                    substitution, one launch per dependency level.  The multifrontal factors
+ *                    are then not built (hz_ddm_stats still reports their symbolic size).
+ * Errors: as hz_setup_ddm; HZ_ERR_ABI on struct_size; HZ_ERR_ARG on an unknown pou or local
+ * solver or an overlap above 250; HZ_ERR_SINGULAR when the incomplete factorisation meets a
+ * zero or non-finite pivot.
  */
 typedef struct {
   size_t struct_size;  /* sizeof(hz_ddm_opts) */
   int precision;       /* HZ_PREC_C128 or HZ_PREC_MIXED */
   int pou;             /* HZ_POU_BOOLEAN or HZ_POU_SMOOTH */
+  int local_solver;    /* HZ_LOCAL_EXACT or HZ_LOCAL_ICC */
 } hz_ddm_opts;
 hz_status hz_setup_ddm_ex(hz_ctx* ctx, hz_handle op, const int32_t* partition, int32_t n_sub,
                           int32_t overlap, const hz_coarse_mesh* coarse, const hz_ddm_opts* opts,
@@ -253,7 +267,8 @@ hz_status hz_spmm_noalloc(hz_ctx* ctx, hz_handle op, int64_t n_rhs, const void* 
 typedef struct {
   int64_t n_dofs, nnz, n_sub;
   int64_t local_dofs_total;   /* sum of overlapped subdomain sizes */
-  int64_t factor_entries;     /* stored entries of all L factors (diagonal blocks and column padding to 16 included) */
+  int64_t factor_entries;     /* stored entries of all L factors (diagonal blocks and column padding to 16 included;
+                                 with HZ_LOCAL_ICC the symbolic size of the exact factors, not allocated) */
   int64_t n_fronts, n_levels, max_front;
   int64_t n_coarse;
   int64_t static_pivots;      /* pivots replaced by the static threshold */
@@ -264,7 +279,10 @@ typedef struct {
   double factor_seconds;      /* numeric factorisation (GPU), part of setup_seconds */
   double factor_flops;        /* its algorithmic real flops: 8 per complex multiply-add of the
                                  diagonal blocks, panel solves, trailing updates and the
-                                 partitioned inverse (direct complex form) */
+                                 partitioned inverse (direct complex form); 0 with HZ_LOCAL_ICC */
+  int64_t local_solver;       /* HZ_LOCAL_EXACT or HZ_LOCAL_ICC */
+  int64_t icc_entries;        /* HZ_LOCAL_ICC: stored entries of L (strict lower) and D; else 0 */
+  int64_t icc_levels;         /* HZ_LOCAL_ICC: dependency levels of the forward substitution */
 } hz_ddm_stats;
 hz_status hz_ddm_stats_get(hz_ctx* ctx, hz_handle ddm, hz_ddm_stats* out);
 

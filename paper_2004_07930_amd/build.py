@@ -13,7 +13,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhz.so")
 
 SOURCES = ["api.cpp", "mesh.cpp", "p3ref.cpp", "ddm.cpp", "fgmres.cpp", "serve.cpp", "prof.cpp",
-           "assemble.hip", "spmm.hip", "factor.hip", "oras.hip", "coarse.hip", "krylov.hip", "noalloc.hip"]
+           "assemble.hip", "spmm.hip", "factor.hip", "icc.hip", "oras.hip", "coarse.hip", "krylov.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",

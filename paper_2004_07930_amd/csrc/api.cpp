@@ -322,7 +322,7 @@ hz_status hz_setup_ddm_ex(hz_ctx* c, hz_handle op, const int32_t* partition, int
     HZ_REQUIRE(opts && opts->struct_size == sizeof(hz_ddm_opts), HZ_ERR_ABI, "hz_setup_ddm_ex: bad options struct");
     auto o = lookup(c, c->ops, op, "operator");
     krylov_cache_release(c);  // set-up sizes its arena by the free memory
-    auto d = build_ddm(c, o, partition, n_sub, overlap, coarse, opts->precision, opts->pou);
+    auto d = build_ddm(c, o, partition, n_sub, overlap, coarse, opts->precision, opts->pou, opts->local_solver);
     const hz_handle h = new_handle(c);
     std::lock_guard<std::mutex> lk(c->mu);
     c->ddms[h] = d;
@@ -336,6 +336,7 @@ hz_status hz_setup_ddm(hz_ctx* c, hz_handle op, const int32_t* partition, int32_
   o.struct_size = sizeof(o);
   o.precision = precision;
   o.pou = HZ_POU_BOOLEAN;
+  o.local_solver = HZ_LOCAL_EXACT;
   return hz_setup_ddm_ex(c, op, partition, n_sub, overlap, coarse, &o, ddm);
 }
 
@@ -558,6 +559,9 @@ hz_status hz_ddm_stats_get(hz_ctx* c, hz_handle ddm, hz_ddm_stats* out) {
     out->setup_seconds = d->setup_seconds;
     out->factor_seconds = d->factor_seconds;
     out->factor_flops = d->factor_flops;
+    out->local_solver = d->local_solver;
+    out->icc_entries = d->icc ? d->icc->nnz + d->n_local_total : 0;
+    out->icc_levels = d->icc ? d->icc->n_fwd : 0;
   });
 }
 

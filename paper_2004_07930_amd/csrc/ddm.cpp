@@ -357,6 +357,7 @@ int64_t Ddm::device_bytes() const {
        d_lval.bytes() + d_level_fronts.bytes() + d_flf.bytes();
   b += d_factor.bytes + d_update.bytes + d_dinv.bytes;
   b += d_pou_ptr.bytes() + d_pou_pos.bytes() + d_pou_w.bytes();
+  if (icc) b += (int64_t)icc->bytes();
   b += d_fwd_work.bytes() + d_bwd_work.bytes() + d_imap.bytes();
   for (int t = 0; t < 2; ++t) b += d_fwdm_work[t].bytes() + d_bwdm_work[t].bytes();
   if (coarse)
@@ -369,12 +370,15 @@ int64_t Ddm::device_bytes() const {
 void build_coarse_host(const Mesh& m, const hz_coarse_mesh* cm, CoarseSpace& cs);
 
 std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int32_t* partition, int32_t n_sub,
-                               int32_t overlap, const hz_coarse_mesh* coarse, int precision, int pou) {
+                               int32_t overlap, const hz_coarse_mesh* coarse, int precision, int pou,
+                               int local_solver) {
   const double t0 = wall_time();
   const Mesh& m = *op->mesh;
   HZ_REQUIRE(partition && n_sub >= 1 && overlap >= 0, HZ_ERR_ARG, "hz_setup_ddm: bad arguments");
   HZ_REQUIRE(precision == HZ_PREC_C128 || precision == HZ_PREC_MIXED, HZ_ERR_ARG, "hz_setup_ddm: bad precision");
   HZ_REQUIRE(pou == HZ_POU_BOOLEAN || pou == HZ_POU_SMOOTH, HZ_ERR_ARG, "hz_setup_ddm: bad partition of unity");
+  HZ_REQUIRE(local_solver == HZ_LOCAL_EXACT || local_solver == HZ_LOCAL_ICC, HZ_ERR_ARG,
+             "hz_setup_ddm: bad local solver");
   HZ_REQUIRE(overlap <= 250, HZ_ERR_ARG, "hz_setup_ddm: overlap above 250 layers");
   std::vector<int32_t> part(partition, partition + m.T);
   std::vector<int64_t> cnt(n_sub, 0);
@@ -387,6 +391,7 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   d->op = op;
   d->precision = precision;
   d->pou = pou;
+  d->local_solver = local_solver;
   d->n_sub = n_sub;
   d->overlap = overlap;
   // owners: lowest subdomain whose own tets touch the dof
@@ -894,11 +899,17 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     }
     d->factor_flops = 8.0 * cm;
   }
-  const double tf0 = wall_time();
-  factor_all(ctx, *d);
-  HIP_CHECK(hipStreamSynchronize(ctx->stream));
-  d->factor_seconds = wall_time() - tf0;
-  phase("numeric factorisation");
+  if (local_solver == HZ_LOCAL_ICC) {
+    // the incomplete factors replace the exact ones (whose symbolic size stays reported)
+    icc_setup(ctx, *d);
+    phase("incomplete factorisation");
+  } else {
+    const double tf0 = wall_time();
+    factor_all(ctx, *d);
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    d->factor_seconds = wall_time() - tf0;
+    phase("numeric factorisation");
+  }
   // set-up-only data: the scatter lists, and the local operator values unless small enough to
   // keep for introspection (hz_get_subdomain)
   d->d_orig_src = DevArray<int64_t>();

@@ -90,6 +90,29 @@ struct CoarseSpace {
   DevBuf w_y, w_y2, w_part;       // apply workspace (restricted vector, product, K-chunk partials)
 };
 
+// Incomplete LDL^T of every local operator (level 0: L keeps the strict lower pattern of A_i,
+// in the local order of A_i), the paper's approximate local solver in place of the exact
+// factors.  Rows are numbered over the concatenated subdomains (row r = vec_off + local id).
+struct IccFactor {
+  int64_t nnz = 0;                       // stored strict-lower entries
+  int32_t n_fwd = 0, n_bwd = 0;          // dependency levels of the two substitutions
+  std::vector<int64_t> fwd_off, bwd_off;  // rows of each level in d_fwd_rows / d_bwd_rows
+  DevArray<int64_t> d_lp;                // strict lower rows: pointers (absolute)
+  DevArray<int32_t> d_lc;                // their columns (concatenated row numbers, ascending)
+  DevArray<int64_t> d_up;                // the same entries by column (rows of L^T)
+  DevArray<int32_t> d_ur;                // row of each such entry
+  DevArray<int64_t> d_uk;                // its position in the strict lower rows
+  DevArray<int32_t> d_fwd_rows, d_bwd_rows;
+  DevArray<int32_t> d_g;                 // row -> global dof
+  DevArray<int64_t> d_out;               // row -> local vector position (elimination order)
+  DevBuf d_L;                            // L values in the factor precision
+  DevBuf d_dinv;                         // 1 / d per row, factor precision
+  size_t bytes() const {
+    return d_lp.bytes() + d_lc.bytes() + d_up.bytes() + d_ur.bytes() + d_uk.bytes() + d_fwd_rows.bytes() +
+           d_bwd_rows.bytes() + d_g.bytes() + d_out.bytes() + d_L.bytes + d_dinv.bytes;
+  }
+};
+
 // solve workspace of the preconditioner, grown on demand and kept with its ddm
 struct PrecondWork {
   DevBuf bin, bout, wbuf, q, t;
@@ -104,6 +127,7 @@ struct Ddm {
   std::shared_ptr<Operator> op;
   int precision = HZ_PREC_C128;
   int pou = HZ_POU_BOOLEAN;
+  int local_solver = HZ_LOCAL_EXACT;
   int32_t n_sub = 0, overlap = 0;
   std::vector<Subdomain> subs;
   std::vector<Front> fronts;
@@ -116,6 +140,7 @@ struct Ddm {
   double factor_seconds = 0;  // numeric factorisation (wall clock, synchronised)
   double factor_flops = 0;    // its algorithmic real flops (8 per complex multiply-add)
   std::unique_ptr<CoarseSpace> coarse;
+  std::unique_ptr<IccFactor> icc;  // HZ_LOCAL_ICC: replaces the multifrontal factors
 
   // host index arrays
   std::vector<int32_t> urows;     // update-row positions per front (subdomain-local)
@@ -168,9 +193,17 @@ struct Ddm {
 
 // ddm.cpp
 std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int32_t* partition, int32_t n_sub,
-                               int32_t overlap, const hz_coarse_mesh* coarse, int precision, int pou);
+                               int32_t overlap, const hz_coarse_mesh* coarse, int precision, int pou,
+                               int local_solver);
 // factor.hip
 void factor_all(Ctx* ctx, Ddm& d);
+// icc.hip: the incomplete factors of every local operator (in place of factor_all), and their
+// solve for a block in node-major layout: out (local vectors, elimination order) from the
+// global block v; y is a work block of n_local_total x s entries
+void icc_setup(Ctx* ctx, Ddm& d);
+void icc_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c128* out, c128* y);
+void icc_apply(Ctx* ctx, Ddm& d, int s, const c128* v, c64* out, c64* y);
+void icc_apply(Ctx* ctx, Ddm& d, int s, const c64* v, c64* out, c64* y);
 // coarse.hip
 void coarse_setup(Ctx* ctx, Ddm& d);
 // oras.hip: z = M^{-1} v for a block in node-major layout [n][s] (c128 in/out)

@@ -679,11 +679,15 @@ void one_level(Ctx* ctx, Ddm& d, int s, const cplx<TS>* v, const cplx<TQ>* add, 
   };
   ensure(bin, nl * s);
   ensure(bout, nl * s);
-  ensure(wbuf, d.w_total * s);
+  if (!d.icc) ensure(wbuf, d.w_total * s);
   cplx<T>* bi = bin.as<cplx<T>>();
   cplx<T>* bo = bout.as<cplx<T>>();
   cplx<T>* wb = wbuf.as<cplx<T>>();
-  if (s <= 1)
+  if (s > 32)
+    fail(HZ_ERR_ARG, "preconditioner: at most 32 columns per block");
+  else if (d.icc)
+    icc_apply(ctx, d, s, v, bi, bo);  // incomplete factors: the local solutions straight into bi
+  else if (s <= 1)
     sweep<T, 1, TS>(ctx, d, s, v, bi, bo, wb);
   else if (s <= 2)
     sweep<T, 2, TS>(ctx, d, s, v, bi, bo, wb);
@@ -693,10 +697,8 @@ void one_level(Ctx* ctx, Ddm& d, int s, const cplx<TS>* v, const cplx<TQ>* add, 
     sweep<T, 8, TS>(ctx, d, s, v, bi, bo, wb);
   else if (s <= 16)
     sweep<T, 16, TS>(ctx, d, s, v, bi, bo, wb);
-  else if (s <= 32)
-    sweep<T, 32, TS>(ctx, d, s, v, bi, bo, wb);
   else
-    fail(HZ_ERR_ARG, "preconditioner: at most 32 columns per block");
+    sweep<T, 32, TS>(ctx, d, s, v, bi, bo, wb);
   if (d.pou == HZ_POU_SMOOTH)
     hipLaunchKernelGGL((k_scatter_pou<T, TQ, TZ>), dim3((unsigned)((n * s + 255) / 256)), dim3(256), 0, st, n, s,
                        d.d_pou_ptr.ptr(), d.d_pou_pos.ptr(), d.d_pou_w.ptr(), bi, add, z);

@@ -23,6 +23,7 @@ HZ_BC_NONE, HZ_BC_IMPEDANCE, HZ_BC_DIRICHLET = 0, 1, 2
 HZ_PREC_C128, HZ_PREC_MIXED = 0, 1
 HZ_MEM_HOST, HZ_MEM_DEVICE = 0, 1
 HZ_POU_BOOLEAN, HZ_POU_SMOOTH = 0, 1
+HZ_LOCAL_EXACT, HZ_LOCAL_ICC = 0, 1
 
 _STATUS = {0: "HZ_OK", -1: "HZ_ERR_ARG", -2: "HZ_ERR_OOM", -3: "HZ_ERR_HIP", -4: "HZ_ERR_NOT_CONVERGED",
            -5: "HZ_ERR_SINGULAR", -6: "HZ_ERR_BUSY", -7: "HZ_ERR_STATE", -8: "HZ_ERR_ABI"}
@@ -70,7 +71,7 @@ def _info_dicts(arr):
 
 
 class DdmOpts(C.Structure):
-    _fields_ = [("struct_size", C.c_size_t), ("precision", C.c_int), ("pou", C.c_int)]
+    _fields_ = [("struct_size", C.c_size_t), ("precision", C.c_int), ("pou", C.c_int), ("local_solver", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -84,7 +85,8 @@ class DdmStats(C.Structure):
                 ("max_front", C.c_int64), ("n_coarse", C.c_int64), ("static_pivots", C.c_int64),
                 ("update_entries", C.c_int64), ("factor_useful", C.c_int64),
                 ("device_bytes", C.c_int64), ("setup_seconds", C.c_double), ("factor_seconds", C.c_double),
-                ("factor_flops", C.c_double)]
+                ("factor_flops", C.c_double), ("local_solver", C.c_int64), ("icc_entries", C.c_int64),
+                ("icc_levels", C.c_int64)]
 
 
 class DdmLevel(C.Structure):
@@ -309,7 +311,8 @@ class Context:
                                          float(freq), C.byref(h)))
         return Operator(self, h.value, mesh)
 
-    def setup_ddm(self, op, partition, n_sub, overlap, coarse=None, precision=HZ_PREC_C128, pou=HZ_POU_BOOLEAN):
+    def setup_ddm(self, op, partition, n_sub, overlap, coarse=None, precision=HZ_PREC_C128, pou=HZ_POU_BOOLEAN,
+                  local_solver=HZ_LOCAL_EXACT):
         p = np.ascontiguousarray(partition, np.int32)
         cm = None
         keep = []
@@ -325,7 +328,7 @@ class Context:
             import torch
 
             torch.cuda.empty_cache()
-        o = DdmOpts(C.sizeof(DdmOpts), int(precision), int(pou))
+        o = DdmOpts(C.sizeof(DdmOpts), int(precision), int(pou), int(local_solver))
         st = self.lib.hz_setup_ddm_ex(self.h, op.handle, _np_ptr(p), int(n_sub), int(overlap),
                                       None if cm is None else C.byref(cm), C.byref(o), C.byref(h))
         if self._alloc_cbs is not None:
