@@ -422,6 +422,61 @@ def _survey_ratio(levels, s, e):
     return {"oras_fwd": survey / (e * (useful + 2.0 * sf * s)), "oras_bwd": survey / (e * (useful + (sf + sp) * s))}
 
 
+def run_local_solvers(args):
+    """The exact multifrontal factors against the level-0 incomplete ones (HZ_LOCAL_ICC) in the
+    workload's mixed-precision preconditioner: set-up time, stored entries (the exact factors'
+    nonzeros; L and D of the incomplete ones), device memory of the ddm, the time of one
+    16-column preconditioner apply (mean of 5, after 2 untimed), and FGMRES for the first 16
+    sources (the workload's tolerance, block 16, restart 40, at most 300 iterations).  One JSON
+    line."""
+    import torch
+
+    from paper_2004_07930_amd import hz
+
+    p, spec = build_workload(args.workload)
+    ctx = hz.Context(0, stream=torch.cuda.current_stream())
+    mesh = ctx.mesh(p.tets, p.coords, p.face_bc)
+    op = ctx.assemble(mesh, p.velocity, p.freq, p.quality)
+    coarse = (p.coarse_tets, p.coarse_coords) if spec["coarse"] and p.coarse_tets is not None else None
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    V = torch.randn((16, mesh.n), dtype=torch.complex128, device="cuda", generator=gen)
+    Z = torch.empty_like(V)
+    B = ctx.point_sources(mesh, p.sources[:16])
+    res = {}
+    for label, ls in (("exact", hz.HZ_LOCAL_EXACT), ("icc", hz.HZ_LOCAL_ICC)):
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        d = ctx.setup_ddm(op, p.partition, p.n_sub, p.overlap, coarse=coarse, precision=hz.HZ_PREC_MIXED,
+                          local_solver=ls)
+        torch.cuda.synchronize()
+        st = ctx.ddm_stats(d)
+        r = {"setup_s": round(time.perf_counter() - t0, 2), "factor_s": round(st["factor_seconds"], 2),
+             "entries": st["icc_entries"] if ls == hz.HZ_LOCAL_ICC else st["factor_useful"],
+             "device_gb": round(st["device_bytes"] / 1e9, 2), "icc_levels": st["icc_levels"]}
+        print(f"{label}: set-up {r}", file=sys.stderr, flush=True)
+        for _ in range(2):
+            ctx.precond(d, V, out=Z)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            ctx.precond(d, V, out=Z)
+        torch.cuda.synchronize()
+        r["apply16_ms"] = round((time.perf_counter() - t0) / 5 * 1e3, 2)
+        t0 = time.perf_counter()
+        X, info = ctx.solve(d, B, tol=p.tol, max_iter=300, restart=40, block=16, raise_on_not_converged=False)
+        torch.cuda.synchronize()
+        r["solve_s"] = round(time.perf_counter() - t0, 2)
+        r["iters"] = max(i["iters"] for i in info)
+        r["max_rel_residual"] = max(i["rel_residual"] for i in info)
+        r["converged"] = all(i["status"] == 0 for i in info)
+        print(f"{label}: {r}", file=sys.stderr, flush=True)
+        res[label] = r
+        ctx.release(d)
+        del X
+    print(json.dumps({"workload": args.workload, "n_dofs": mesh.n, "precision": "mixed", "sources": 16,
+                      "local_solvers": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -446,12 +501,18 @@ def main():
                     help="with --serve: also cost the same stream for plain FP64 hz_solve, one request at a time")
     ap.add_argument("--fp64-budget", type=float, default=90.0,
                     help="with --serve-fp64: seconds of FP64 solves per operator")
+    ap.add_argument("--compare-local-solvers", action="store_true",
+                    help="instead: the workload's preconditioner (mixed precision) with exact and with incomplete "
+                         "local factors: set-up, stored entries, 16-column apply time, iterations for 16 sources")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no collectives); use --gpus 1", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU only (no collectives); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.serve:
         run_serve(args)
+        return
+    if args.compare_local_solvers:
+        run_local_solvers(args)
         return
 
     def log(*a):
