@@ -26,20 +26,23 @@ def qr_pos(W):
     return Q, R
 
 
-def block_fgmres(A, B, precond, tol=1e-6, m=40, max_iter=500, fixed_iters=None, x0=None):
+def block_fgmres(A, B, precond, tol=1e-6, m=40, max_iter=500, fixed_iters=None, x0=None, dtype=np.complex128):
     """Solve A X = B for a block B (n, s).
 
     A and precond are callables on (n, s) blocks.  Returns X and a dict with the number
     of inner iterations, restarts, per-column true relative residuals and the history of
     least-squares residual estimates.  With fixed_iters=k the first cycle runs exactly k
-    steps (tol is ignored) and no restart happens."""
-    B = np.asarray(B, np.complex128)
+    steps (tol is ignored) and no restart happens.  dtype=np.complex64 runs every array of
+    the method (basis, Hessenberg matrix, least squares, iterate, residual) in single
+    precision, the paper's "whole computation in single precision" (section "Numerical
+    results"); A and precond must then return complex64 blocks."""
+    B = np.asarray(B, dtype)
     if B.ndim == 1:
         B = B[:, None]
     n, s = B.shape
     bnorm = np.linalg.norm(B, axis=0)
     bnorm = np.where(bnorm > 0, bnorm, 1.0)
-    X = np.zeros((n, s), np.complex128) if x0 is None else np.array(x0, np.complex128).reshape(n, s)
+    X = np.zeros((n, s), dtype) if x0 is None else np.array(x0, dtype).reshape(n, s)
     total = 0
     restarts = 0
     hist = []
@@ -48,8 +51,8 @@ def block_fgmres(A, B, precond, tol=1e-6, m=40, max_iter=500, fixed_iters=None, 
         V1, S = qr_pos(R)
         V = [V1]
         Zs = []
-        Hbar = np.zeros(((m + 1) * s, m * s), np.complex128)
-        G0 = np.zeros(((m + 1) * s, s), np.complex128)
+        Hbar = np.zeros(((m + 1) * s, m * s), dtype)
+        G0 = np.zeros(((m + 1) * s, s), dtype)
         G0[:s] = S
         steps = m if fixed_iters is None else min(m, fixed_iters)
         j_done = 0
@@ -57,7 +60,7 @@ def block_fgmres(A, B, precond, tol=1e-6, m=40, max_iter=500, fixed_iters=None, 
             Zj = precond(V[j])
             W = A(Zj)
             Vb = np.concatenate(V, axis=1)  # (n, (j+1)s)
-            Hcol = np.zeros(((j + 1) * s, s), np.complex128)
+            Hcol = np.zeros(((j + 1) * s, s), dtype)
             for _ in range(2):  # classical Gram-Schmidt, twice
                 Hp = Vb.conj().T @ W
                 W = W - Vb @ Hp

@@ -167,3 +167,31 @@ def test_dirichlet_coarse_rows_zero():
     rs = np.asarray(abs(Z).sum(axis=1)).ravel()
     assert np.all(rs[mesh.dirichlet] == 0)
     np.testing.assert_allclose((Z @ np.ones(Z.shape[1]))[~mesh.dirichlet], 1.0, atol=1e-12)
+
+
+def test_fgmres_single_precision_option():
+    """The whole computation in complex64 (the paper's single-precision runs): every array is
+    complex64, the Arnoldi relation holds to single-precision rounding, the fixed-iteration
+    iterate is the FP64 one to single-precision accuracy, and a solve to the paper's 1e-3
+    takes the FP64 iteration count."""
+    p, mesh = _cube(3, freq=1.0)
+    A = fem.assemble_operator(mesh, p.velocity, p.freq)
+    A32 = A.astype(np.complex64)
+    subs, _ = ddm.build_subdomains(mesh, p.velocity, p.freq, None, p.partition, p.n_sub, 1)
+    ddm.factor_subdomains(subs, np.complex64)
+    P32 = ddm.ORAS(A, subs, dtype=np.complex64)
+    P64 = ddm.build_preconditioner(mesh, A, p.velocity, p.freq, None, p.partition, p.n_sub, 1)
+    rng = np.random.default_rng(2)
+    B = rng.standard_normal((mesh.n, 2)) + 1j * rng.standard_normal((mesh.n, 2))
+    X32, i32 = krylov.block_fgmres(lambda x: A32 @ x, B, lambda v: P32.apply(v).astype(np.complex64),
+                                   fixed_iters=4, m=10, dtype=np.complex64)
+    X64, _ = krylov.block_fgmres(lambda x: A @ x, B, P64.apply, fixed_iters=4, m=10)
+    assert X32.dtype == np.complex64 and i32["V"].dtype == np.complex64 and i32["Hbar"].dtype == np.complex64
+    V, Z, H = (i32[k].astype(np.complex128) for k in ("V", "Z", "Hbar"))
+    assert abs(A32 @ i32["Z"] - i32["V"] @ i32["Hbar"]).max() < 1e-5 * abs(A @ Z).max()
+    assert abs(V.conj().T @ V - np.eye(V.shape[1])).max() < 1e-5
+    assert np.linalg.norm(X32 - X64) / np.linalg.norm(X64) < 1e-4
+    _, a = krylov.block_fgmres(lambda x: A32 @ x, B, lambda v: P32.apply(v).astype(np.complex64), tol=1e-3,
+                               dtype=np.complex64)
+    _, b = krylov.block_fgmres(lambda x: A @ x, B, P64.apply, tol=1e-3)
+    assert a["iters"] == b["iters"]
