@@ -20,7 +20,12 @@ Readings (the abstract gives no construction details; listed in the design doc):
   outside it; Dirichlet dofs of the global problem stay identity rows locally;
 * coarse space: P1 on a coarse tet mesh, Z[j, c] = barycentric c of fine node j in the
   lowest-id coarse tet containing it, |Z| <= 1e-12 dropped, rows of Dirichlet dofs zero;
-* coarse solve: dense LU with partial pivoting (the paper iterates 10 GMRES steps instead).
+* coarse solve: dense LU with partial pivoting; or (InexactCoarse) the paper's iterative one,
+  10 GMRES iterations on E preconditioned by one-level ORAS on the coarse level, read as: the
+  coarse subdomain i holds the coarse dofs whose basis functions are nonzero on its overlapped
+  fine dofs, its local operator is the Galerkin projection Z_i^T A_i Z_i of the fine local
+  operator onto them (Z_i: the rows of Z on those fine dofs), and a coarse dof belongs to the
+  subdomain that owns the fine dof at its vertex (Boolean partition of unity).
 """
 from __future__ import annotations
 
@@ -29,6 +34,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+from . import krylov
 from .fem import BC_IMPEDANCE, Mesh, assemble, dof_coordinates, element_matrices
 
 
@@ -203,6 +209,48 @@ class Coarse:
         """q = Z E^{-1} Z^T v for a block v (n, s)."""
         y = self.Z.T @ v
         return self.Z @ sla.lu_solve(self.lu, y.astype(self.dtype)).astype(np.complex128)
+
+
+def coarse_owners(mesh: Mesh, coarse_coords, own):
+    """Owner subdomain of each coarse dof: the owner of the fine dof at its vertex (the
+    coarse vertices are fine vertices: the coarse mesh takes every k-th vertex plane)."""
+    xyz = dof_coordinates(mesh.tets, mesh.coords, mesh.tet_dofs, mesh.n)
+    cc = np.asarray(coarse_coords, np.float64)
+    scale = max(1.0, float(np.abs(xyz).max()))
+    key = lambda x: tuple(np.round(x / scale * 1e9).astype(np.int64))
+    at = {key(xyz[j]): j for j in range(mesh.n)}
+    return np.array([own[at[key(c)]] for c in cc], np.int64)
+
+
+class InexactCoarse:
+    """The paper's coarse solve (section "Domain decomposition preconditioner", after eq.
+    oras): E y = Z^T v solved by `iters` block GMRES iterations from y = 0, right-
+    preconditioned by one-level ORAS on the coarse level, M_c^{-1} = sum_i Rc_i^T Dc_i
+    E_i^{-1} Rc_i with E_i = Z_i^T A_i Z_i (dense LU per coarse subdomain)."""
+
+    def __init__(self, Z, A, subs, cown, iters=10):
+        self.Z = Z
+        self.iters = iters
+        self.E = (Z.T.astype(np.complex128) @ (A @ Z.astype(np.complex128))).toarray()
+        self.loc = []
+        for i, s in enumerate(subs):
+            Zi = Z[s.gdofs].tocsr()
+            J = np.unique(Zi.indices)
+            Zi = Zi[:, J].astype(np.complex128)
+            Ei = (Zi.T @ (s.A @ Zi)).toarray()
+            self.loc.append((J, sla.lu_factor(Ei), cown[J] == i))
+
+    def precond(self, r):
+        z = np.zeros_like(r)
+        for J, lu, own in self.loc:
+            z[J[own]] += sla.lu_solve(lu, r[J])[own]
+        return z
+
+    def solve(self, v):
+        """q = Z y with y the GMRES iterate for E y = Z^T v, for a block v (n, s)."""
+        y0 = self.Z.T @ v
+        y, _ = krylov.block_fgmres(lambda x: self.E @ x, y0, self.precond, fixed_iters=self.iters, m=self.iters)
+        return self.Z @ y
 
 
 # ------------------------------------------------------------------------ preconditioner

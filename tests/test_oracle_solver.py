@@ -195,3 +195,57 @@ def test_fgmres_single_precision_option():
                                dtype=np.complex64)
     _, b = krylov.block_fgmres(lambda x: A @ x, B, P64.apply, tol=1e-3)
     assert a["iters"] == b["iters"]
+
+
+def _cube_with_coarse(n, parts, overlap=1, freq=1.0, k=2):
+    p, mesh = _cube(n, freq=freq, parts=parts, overlap=overlap)
+    xs = np.linspace(0.0, 1.0, n + 1)[::k]
+    ct, cc = w.kuhn_mesh(xs, xs, xs)
+    A = fem.assemble_operator(mesh, p.velocity, p.freq)
+    subs, own = ddm.build_subdomains(mesh, p.velocity, p.freq, None, p.partition, p.n_sub, overlap)
+    Z = ddm.coarse_interpolation(mesh, ct, cc)
+    cown = ddm.coarse_owners(mesh, cc, own)
+    return p, mesh, A, subs, Z, cown
+
+
+def test_inexact_coarse_one_subdomain_is_exact():
+    """With one subdomain and no overlap the local operator is the global one, so the coarse
+    ORAS is E^{-1} itself and one GMRES step gives the exact coarse solve."""
+    p, mesh, A, subs, Z, cown = _cube_with_coarse(4, (1, 1, 1), overlap=0)
+    rng = np.random.default_rng(4)
+    V = rng.standard_normal((mesh.n, 3)) + 1j * rng.standard_normal((mesh.n, 3))
+    exact = ddm.Coarse(Z, A).solve(V)
+    for iters in (1, 10):
+        q = ddm.InexactCoarse(Z, A, subs, cown, iters=iters).solve(V)
+        assert np.linalg.norm(q - exact) <= 1e-10 * np.linalg.norm(exact), iters
+
+
+def test_inexact_coarse_full_krylov_space_is_exact():
+    """As many GMRES iterations as coarse dofs span the whole coarse space: the result is the
+    exact coarse solve whatever the coarse preconditioner (four subdomains, overlap 1)."""
+    p, mesh, A, subs, Z, cown = _cube_with_coarse(4, (2, 2, 1))
+    nc = Z.shape[1]
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal((mesh.n, 1)) + 1j * rng.standard_normal((mesh.n, 1))
+    exact = ddm.Coarse(Z, A).solve(v)
+    q = ddm.InexactCoarse(Z, A, subs, cown, iters=nc).solve(v)
+    assert np.linalg.norm(q - exact) <= 1e-8 * np.linalg.norm(exact)
+    # ten iterations do not reach it, but reduce the coarse residual
+    ic = ddm.InexactCoarse(Z, A, subs, cown, iters=10)
+    r = Z.T @ v
+    y, _ = krylov.block_fgmres(lambda x: ic.E @ x, r, ic.precond, fixed_iters=10, m=10)
+    assert np.linalg.norm(ic.E @ y - r) < 0.5 * np.linalg.norm(r)
+
+
+def test_coarse_partition_of_unity_owns_each_coarse_dof_once():
+    """Every coarse dof is in some coarse subdomain and owned by exactly one of them, the one
+    owning the fine dof at its vertex (the lowest subdomain id whose own tets hold it)."""
+    p, mesh, A, subs, Z, cown = _cube_with_coarse(4, (2, 2, 2))
+    ic = ddm.InexactCoarse(Z, A, subs, cown)
+    owned = np.concatenate([J[o] for J, _, o in ic.loc])
+    assert np.array_equal(np.sort(owned), np.arange(Z.shape[1]))
+    # the vertex at the origin lies in subdomain 0 only; the centre vertex (2,2,2) of the 4^3
+    # cube touches all eight boxes, so it belongs to the lowest id, 0; the far corner to box 7
+    cc = w.kuhn_mesh(*(np.linspace(0.0, 1.0, 5)[::2],) * 3)[1]
+    at = {tuple(np.round(c * 2).astype(int)): j for j, c in enumerate(cc)}
+    assert cown[at[(0, 0, 0)]] == 0 and cown[at[(1, 1, 1)]] == 0 and cown[at[(2, 2, 2)]] == 7
