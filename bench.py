@@ -422,6 +422,54 @@ def _survey_ratio(levels, s, e):
     return {"oras_fwd": survey / (e * (useful + 2.0 * sf * s)), "oras_bwd": survey / (e * (useful + (sf + sp) * s))}
 
 
+def run_coarse_spaces(args):
+    """The workload's mixed-precision solve without a coarse space (K = 0) and with the P1
+    coarse mesh on every K-th vertex plane of the fine mesh (exact coarse solve): set-up time,
+    coarse dofs, device memory of the ddm, and FGMRES for the first 16 sources (the workload's
+    tolerance, block 16, restart 40, at most 400 iterations).  One JSON line."""
+    import torch
+
+    import workloads as w
+    from paper_2004_07930_amd import hz
+
+    if args.workload not in WORKLOADS:
+        raise SystemExit("--compare-coarse needs a layered workload")
+    prob = dict(WORKLOADS[args.workload]["problem"])
+    p = w.layered_problem(**prob)
+    ctx = hz.Context(0, stream=torch.cuda.current_stream())
+    mesh = ctx.mesh(p.tets, p.coords, p.face_bc)
+    op = ctx.assemble(mesh, p.velocity, p.freq, p.quality)
+    B = ctx.point_sources(mesh, p.sources[:16])
+    res = {}
+    for k in args.compare_coarse:
+        coarse = None
+        if k > 0:
+            pk = w.layered_problem(**dict(prob, coarse_factor=k))
+            if pk.coarse_tets is None:
+                raise SystemExit(f"the grid {p.grid} is not divisible by {k}")
+            coarse = (pk.coarse_tets, pk.coarse_coords)
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        d = ctx.setup_ddm(op, p.partition, p.n_sub, p.overlap, coarse=coarse, precision=hz.HZ_PREC_MIXED)
+        torch.cuda.synchronize()
+        st = ctx.ddm_stats(d)
+        r = {"setup_s": round(time.perf_counter() - t0, 2), "n_coarse": st["n_coarse"],
+             "device_gb": round(st["device_bytes"] / 1e9, 2)}
+        t0 = time.perf_counter()
+        X, info = ctx.solve(d, B, tol=p.tol, max_iter=400, restart=40, block=16, raise_on_not_converged=False)
+        torch.cuda.synchronize()
+        r["solve_s"] = round(time.perf_counter() - t0, 2)
+        r["iters"] = max(i["iters"] for i in info)
+        r["max_rel_residual"] = max(i["rel_residual"] for i in info)
+        r["converged"] = all(i["status"] == 0 for i in info)
+        print(f"coarse {k}: {r}", file=sys.stderr, flush=True)
+        res[str(k)] = r
+        ctx.release(d)
+        del X
+    print(json.dumps({"workload": args.workload, "n_dofs": mesh.n, "precision": "mixed", "sources": 16,
+                      "coarse_factor": res}), flush=True)
+
+
 def run_local_solvers(args):
     """The exact multifrontal factors against the level-0 incomplete ones (HZ_LOCAL_ICC) in the
     workload's mixed-precision preconditioner: set-up time, stored entries (the exact factors'
@@ -501,6 +549,9 @@ def main():
                     help="with --serve: also cost the same stream for plain FP64 hz_solve, one request at a time")
     ap.add_argument("--fp64-budget", type=float, default=90.0,
                     help="with --serve-fp64: seconds of FP64 solves per operator")
+    ap.add_argument("--compare-coarse", type=int, nargs="+", metavar="K",
+                    help="instead: the workload (mixed precision) one-level (K = 0) and with the P1 coarse space on "
+                         "every K-th vertex plane: set-up, coarse dofs, iterations and time for 16 sources")
     ap.add_argument("--compare-local-solvers", action="store_true",
                     help="instead: the workload's preconditioner (mixed precision) with exact and with incomplete "
                          "local factors: set-up, stored entries, 16-column apply time, iterations for 16 sources")
@@ -513,6 +564,9 @@ def main():
         return
     if args.compare_local_solvers:
         run_local_solvers(args)
+        return
+    if args.compare_coarse:
+        run_coarse_spaces(args)
         return
 
     def log(*a):

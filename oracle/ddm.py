@@ -231,7 +231,7 @@ class InexactCoarse:
     def __init__(self, Z, A, subs, cown, iters=10):
         self.Z = Z
         self.iters = iters
-        self.E = (Z.T.astype(np.complex128) @ (A @ Z.astype(np.complex128))).toarray()
+        self.E = (Z.T.astype(np.complex128) @ (A @ Z.astype(np.complex128))).tocsr()  # sparse
         self.loc = []
         for i, s in enumerate(subs):
             Zi = Z[s.gdofs].tocsr()
