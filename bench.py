@@ -20,7 +20,7 @@ relative difference of the two solutions of the first sub-block is stated.
 The roofline object is computed live: the library brackets every launch of its main kernel
 classes with HIP events on the solve stream during the timed steps and sums each launch's
 algorithmic bytes (hz_profile_*); the class with the largest time is reported, with the
-achieved rate under two byte counts (the survey's: factor read once plus two right-hand-side
+achieved rate under two byte counts (the plain one: factor read once plus two right-hand-side
 passes over the pivot rows; the kernels' own, which adds the multifrontal update rows).
 
 The CPU baseline times the oracle (NumPy / SciPy) on a bounded sample of the same workload --
@@ -412,14 +412,14 @@ def run_serve(args):
         "total_wall_s": time.perf_counter() - t_all}))
 
 
-def _survey_ratio(levels, s, e):
-    """Per sweep direction, bytes of the survey's count (factor once + two passes over the pivot
+def _plain_count_ratio(levels, s, e):
+    """Per sweep direction, bytes of the plain count (factor once + two passes over the pivot
     rows of the right-hand side) over the kernels' own count (which also moves the update rows)."""
     useful = sum(l["factor_useful"] for l in levels)
     sp = sum(l["sum_pivots"] for l in levels)
     sf = sum(l["sum_front"] for l in levels)
-    survey = e * (useful + 2.0 * sp * s)
-    return {"oras_fwd": survey / (e * (useful + 2.0 * sf * s)), "oras_bwd": survey / (e * (useful + (sf + sp) * s))}
+    plain = e * (useful + 2.0 * sp * s)
+    return {"oras_fwd": plain / (e * (useful + 2.0 * sf * s)), "oras_bwd": plain / (e * (useful + (sf + sp) * s))}
 
 
 def run_coarse_spaces(args):
@@ -670,7 +670,7 @@ def main():
                      for k, v in kstats.items()})
         if label == "mixed":
             kraw = kstats
-            ratio = _survey_ratio(levels, S, 8.0)
+            ratio = _plain_count_ratio(levels, S, 8.0)
             if args.ref_tol or spec.get("ref_tol"):  # the same solver at a tight tolerance, on the first sub-block
                 rt = args.ref_tol or spec["ref_tol"]
                 ctx.point_sources(mesh, blocks[0], out=Bb)
@@ -705,7 +705,7 @@ def main():
     roofline = {"kernel": dom, "bound": "hbm", "achieved": sur / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": sur / HBM_PEAK, "traffic": traffic,
                 "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x fetch scale + WRITE_SIZE x write scale)",
-                "bytes_count": "survey: factor read once + 2 right-hand-side passes over the pivot rows",
+                "bytes_count": "plain: factor read once + 2 right-hand-side passes over the pivot rows",
                 "achieved_kernel_count": own / 1e9, "frac_kernel_count": own / HBM_PEAK,
                 "algorithmic_bytes_per_launch": per_launch * ratio.get(dom, 1.0),
                 "algorithmic_bytes_per_launch_kernel_count": per_launch,
