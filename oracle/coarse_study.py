@@ -26,10 +26,10 @@ from . import ddm as odd
 from . import fem, krylov, rhs
 
 
-def problem():
+def problem(n_sources=(2, 1)):
     hxy = 1980.0 / 5.0 / 1000.0 / 2.8  # the family's cube size at 5 Hz (km)
     side = 32 * hxy * 0.999
-    return w.layered_problem(freq=5.0, r=1.4, parts=(4, 4, 4), overlap=1, n_sources=(2, 1), src_depth=0.5,
+    return w.layered_problem(freq=5.0, r=1.4, parts=(4, 4, 4), overlap=1, n_sources=n_sources, src_depth=0.5,
                              lateral=(0.0, side, 0.0, side), equal_depth_zcuts=True, coarse_factor=0)
 
 

@@ -92,3 +92,99 @@ def block_fgmres(A, B, precond, tol=1e-6, m=40, max_iter=500, fixed_iters=None, 
 def dense_solve(A, B):
     """Direct solve with the dense matrix (tiny problems only)."""
     return np.linalg.solve(A.toarray(), np.asarray(B, np.complex128))
+
+
+def _harmonic_ritz(G, WV, k):
+    """k eigenvectors of G^H G p = theta G^H WV p with the smallest |theta| (finite ones)."""
+    import scipy.linalg as sla
+
+    th, P = sla.eig(G.conj().T @ G, G.conj().T @ WV)
+    th = np.where(np.isfinite(th), th, np.inf)
+    return P[:, np.argsort(np.abs(th))[:k]]
+
+
+def gcrodr(A, b, precond, tol=1e-6, m=40, k=10, max_iter=2000, recycle=None):
+    """GCRO-DR(m, k) for one right-hand side (Parks, de Sturler, Mackey, Johnson, Maiti,
+    "Recycling Krylov subspaces for sequences of linear systems", 2006), the recycling method
+    the paper's conclusion proposes for many sources.  Right-preconditioned with a fixed
+    (linear) preconditioner: it solves (A M^{-1}) y = b and returns x = M^{-1} y.
+
+    recycle = (U, C) with (A M^{-1}) U = C and C^H C = I, from an earlier solve with the same
+    operator and preconditioner (None: the first cycle is a GMRES(m) cycle).  Each later
+    cycle runs m - k Arnoldi steps of (I - C C^H) A M^{-1}, minimises the residual over
+    [U, V], and replaces (U, C) by the k harmonic Ritz vectors of the cycle's space.  With
+    k = 0 it is restarted GMRES(m).  Returns x, info (iterations = applications of A M^{-1},
+    cycles, explicit relative residual) and the recycle pair for the next solve."""
+    b = np.asarray(b, np.complex128).ravel()
+    Ah = lambda v: np.asarray(A(precond(v[:, None])))[:, 0]
+    bn = np.linalg.norm(b)
+    y = np.zeros_like(b)
+    r = b.copy()
+    U, C = (None, None) if recycle is None or k == 0 else recycle
+    if U is not None:  # the part of b in range(C) is solved at once
+        c = C.conj().T @ r
+        y = y + U @ c
+        r = r - C @ c
+    total = cycles = 0
+    while np.linalg.norm(r) > tol * bn and total < max_iter:
+        kk = 0 if U is None else k
+        p = m - kk
+        beta = np.linalg.norm(r)
+        V = [r / beta]
+        H = np.zeros((p + 1, p), np.complex128)
+        Bc = np.zeros((kk, p), np.complex128)
+        dn = None if U is None else 1.0 / np.linalg.norm(U, axis=0)
+
+        def small(steps):
+            """The cycle's (kk + steps + 1) x (kk + steps) matrix G with A M^{-1} Vhat = What G,
+            and What^H r = beta e_{kk+1} (r is orthogonal to C)."""
+            G = np.zeros((kk + steps + 1, kk + steps), np.complex128)
+            if kk:
+                G[:kk, :kk] = np.diag(dn)
+                G[:kk, kk:] = Bc[:, :steps]
+            G[kk:, kk:] = H[: steps + 1, :steps]
+            c = np.zeros(kk + steps + 1, np.complex128)
+            c[kk] = beta
+            return G, c
+
+        steps = p
+        for j in range(p):
+            w = Ah(V[j])
+            total += 1
+            if kk:
+                Bc[:, j] = C.conj().T @ w
+                w = w - C @ Bc[:, j]
+            Vb = np.stack(V, axis=1)
+            for _ in range(2):  # classical Gram-Schmidt, twice
+                h = Vb.conj().T @ w
+                w = w - Vb @ h
+                H[: j + 1, j] += h
+            H[j + 1, j] = np.linalg.norm(w)
+            breakdown = H[j + 1, j] <= 1e-14 * np.abs(H[: j + 1, j]).max()
+            V.append(np.zeros_like(w) if breakdown else w / H[j + 1, j])
+            G, c = small(j + 1)
+            z, *_ = np.linalg.lstsq(G, c, rcond=None)
+            if breakdown or np.linalg.norm(c - G @ z) <= tol * bn or total >= max_iter:
+                steps = j + 1
+                break
+        G, c = small(steps)
+        Vm1 = np.stack(V[: steps + 1], axis=1)
+        if kk:
+            What = np.concatenate([C, Vm1], axis=1)
+            Vhat = np.concatenate([U * dn[None, :], Vm1[:, :steps]], axis=1)
+            WV = What.conj().T @ Vhat
+        else:
+            What, Vhat = Vm1, Vm1[:, :steps]
+            WV = np.eye(steps + 1, steps)
+        z, *_ = np.linalg.lstsq(G, c, rcond=None)
+        y = y + Vhat @ z
+        r = r - What @ (G @ z)
+        cycles += 1
+        if k > 0 and G.shape[1] >= k:
+            P = _harmonic_ritz(G, WV, k)
+            Q, R = np.linalg.qr(G @ P)
+            C = What @ Q
+            U = Vhat @ P @ np.linalg.inv(R)
+    x = np.asarray(precond(y[:, None]))[:, 0]
+    res = np.linalg.norm(b - np.asarray(A(x[:, None]))[:, 0]) / bn
+    return x, {"iters": total, "cycles": cycles, "rel_residual": res}, (U, C)

@@ -249,3 +249,38 @@ def test_coarse_partition_of_unity_owns_each_coarse_dof_once():
     cc = w.kuhn_mesh(*(np.linspace(0.0, 1.0, 5)[::2],) * 3)[1]
     at = {tuple(np.round(c * 2).astype(int)): j for j, c in enumerate(cc)}
     assert cown[at[(0, 0, 0)]] == 0 and cown[at[(1, 1, 1)]] == 0 and cown[at[(2, 2, 2)]] == 7
+
+
+def test_gcrodr_without_recycling_is_restarted_gmres():
+    """GCRO-DR with k = 0 is GMRES(m): with a fixed preconditioner the flexible oracle runs the
+    same iteration, so iterations and iterate agree (restarts forced by m = 8)."""
+    p, mesh = _cube(3, freq=1.0)
+    A = fem.assemble_operator(mesh, p.velocity, p.freq)
+    P = ddm.build_preconditioner(mesh, A, p.velocity, p.freq, None, p.partition, p.n_sub, 1)
+    rng = np.random.default_rng(6)
+    b = rng.standard_normal(mesh.n) + 1j * rng.standard_normal(mesh.n)
+    x, info, _ = krylov.gcrodr(lambda v: A @ v, b, P.apply, tol=1e-10, m=8, k=0)
+    xo, io = krylov.block_fgmres(lambda v: A @ v, b[:, None], P.apply, tol=1e-10, m=8)
+    assert info["iters"] == io["iters"] and info["iters"] > 8
+    assert np.linalg.norm(x - xo[:, 0]) <= 1e-8 * np.linalg.norm(xo)
+
+
+def test_gcrodr_recycle_space_and_recycled_solves():
+    """After a solve, the recycle pair satisfies A M^{-1} U = C with C^H C = I; solves of new
+    right-hand sides that start from it reach the direct solution."""
+    p, mesh = _cube(3, freq=1.5)
+    A = fem.assemble_operator(mesh, p.velocity, p.freq)
+    P = ddm.build_preconditioner(mesh, A, p.velocity, p.freq, None, p.partition, p.n_sub, 1)
+    rng = np.random.default_rng(7)
+    Bs = rng.standard_normal((mesh.n, 3)) + 1j * rng.standard_normal((mesh.n, 3))
+    Xd = krylov.dense_solve(A, Bs)
+    rec = None
+    for c in range(3):
+        x, info, rec = krylov.gcrodr(lambda v: A @ v, Bs[:, c], P.apply, tol=1e-10, m=10, k=4, recycle=rec)
+        assert info["rel_residual"] <= 1e-9
+        assert np.linalg.norm(x - Xd[:, c]) <= 1e-7 * np.linalg.norm(Xd[:, c])
+        U, C = rec
+        assert U.shape[1] == 4
+        assert abs(C.conj().T @ C - np.eye(4)).max() <= 1e-10
+        AU = A @ P.apply(U)
+        assert np.linalg.norm(AU - C) <= 1e-8 * np.linalg.norm(C)
