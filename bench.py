@@ -482,6 +482,8 @@ def run_local_solvers(args):
     from paper_2004_07930_amd import hz
 
     p, spec = build_workload(args.workload)
+    if p.sources is None:
+        raise SystemExit("--compare-local-solvers needs a workload with point sources")
     ctx = hz.Context(0, stream=torch.cuda.current_stream())
     mesh = ctx.mesh(p.tets, p.coords, p.face_bc)
     op = ctx.assemble(mesh, p.velocity, p.freq, p.quality)
