@@ -284,3 +284,23 @@ def test_gcrodr_recycle_space_and_recycled_solves():
         assert abs(C.conj().T @ C - np.eye(4)).max() <= 1e-10
         AU = A @ P.apply(U)
         assert np.linalg.norm(AU - C) <= 1e-8 * np.linalg.norm(C)
+
+
+def test_gcrodr_recycling_deflates_a_positive_definite_operator():
+    """The case the method is built for: restarted GMRES(20) stalls on a stiffness-dominated
+    (symmetric positive definite) operator, GCRO-DR(20, 8) converges, and each later right-hand
+    side that starts from the recycled space takes fewer iterations than the first."""
+    p, mesh = _cube(3, freq=1.0)
+    K, M, _ = fem.assemble_parts(mesh)
+    A = (K + 0.01 * M).astype(np.complex128)
+    rng = np.random.default_rng(1)
+    Bs = rng.standard_normal((mesh.n, 3)) + 1j * rng.standard_normal((mesh.n, 3))
+    _, g, _ = krylov.gcrodr(lambda v: A @ v, Bs[:, 0], lambda v: v, tol=1e-8, m=20, k=0, max_iter=250)
+    assert g["rel_residual"] > 1e-6
+    rec, its = None, []
+    for c in range(3):
+        x, info, rec = krylov.gcrodr(lambda v: A @ v, Bs[:, c], lambda v: v, tol=1e-8, m=20, k=8, recycle=rec,
+                                     max_iter=1500)
+        assert info["rel_residual"] <= 1e-8
+        its.append(info["iters"])
+    assert its[0] < 250 and its[1] < 0.8 * its[0] and its[2] < 0.8 * its[0], its
