@@ -11,7 +11,7 @@ FGMRES iterations and the largest final residual:
   mesh has 2.5), the coarse problem solved exactly (dense LU) or as the paper does (10 GMRES
   iterations with one-level ORAS on the coarse level, InexactCoarse).
 
-    python3 -m oracle.coarse_study [k ...]      (default: 4 2 1)
+    python3 -m oracle.coarse_study [--parts PX PY PZ] [k ...]      (default: 4 4 4 boxes; k = 4 2 1)
 """
 from __future__ import annotations
 
@@ -26,16 +26,16 @@ from . import ddm as odd
 from . import fem, krylov, rhs
 
 
-def problem(n_sources=(2, 1)):
+def problem(n_sources=(2, 1), parts=(4, 4, 4)):
     hxy = 1980.0 / 5.0 / 1000.0 / 2.8  # the family's cube size at 5 Hz (km)
     side = 32 * hxy * 0.999
-    return w.layered_problem(freq=5.0, r=1.4, parts=(4, 4, 4), overlap=1, n_sources=n_sources, src_depth=0.5,
+    return w.layered_problem(freq=5.0, r=1.4, parts=parts, overlap=1, n_sources=n_sources, src_depth=0.5,
                              lateral=(0.0, side, 0.0, side), equal_depth_zcuts=True, coarse_factor=0)
 
 
-def main(factors=(4, 2, 1)):
+def main(factors=(4, 2, 1), parts=(4, 4, 4)):
     t0 = time.perf_counter()
-    p = problem()
+    p = problem(parts=parts)
     om = fem.Mesh(p.tets, p.coords, p.face_bc)
     A = fem.assemble_operator(om, p.velocity, p.freq)
     B = rhs.point_sources(om, p.sources).T
@@ -65,4 +65,8 @@ def main(factors=(4, 2, 1)):
 
 
 if __name__ == "__main__":
-    main(tuple(int(a) for a in sys.argv[1:]) or (4, 2, 1))
+    argv = sys.argv[1:]
+    parts = (4, 4, 4)
+    if argv[:1] == ["--parts"]:
+        parts, argv = tuple(int(a) for a in argv[1:4]), argv[4:]
+    main(tuple(int(a) for a in argv) or (4, 2, 1), parts)
