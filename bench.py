@@ -69,6 +69,13 @@ WORKLOADS = {
         coarse=True, block=16, restart=40, step_sources=16,
         desc="layered 20x20x4.65 km, 2.5 Hz, Kuhn P3 %dx%dx%d cubes, 64 subdomains, overlap 2, "
              "P1 coarse (4x coarser), 16 point sources at 0.5 km, tol 1e-6"),
+    "layered-3.5hz": dict(
+        problem=dict(freq=3.5, r=1.4, parts=(8, 8, 2), overlap=2, n_sources=(4, 4), src_depth=0.5,
+                     equal_depth_zcuts=True),
+        coarse=True, block=16, restart=40, step_sources=16,
+        desc="layered 20x20x4.65 km, 3.5 Hz, Kuhn P3 %dx%dx%d cubes, 128 subdomains (8x8x2 boxes cut at equal "
+             "depth), overlap 2, P1 coarse (4x coarser), 16 point sources at 0.5 km, tol 1e-6 (the serving run's "
+             "3.5 Hz operator)"),
     "layered-1hz": dict(
         problem=dict(freq=1.0, r=1.4, parts=(4, 4, 1), overlap=2, n_sources=(4, 4), src_depth=0.5),
         coarse=True, block=16, restart=40, step_sources=16,
