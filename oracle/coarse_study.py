@@ -33,35 +33,42 @@ def problem(n_sources=(2, 1), parts=(4, 4, 4)):
                              lateral=(0.0, side, 0.0, side), equal_depth_zcuts=True, coarse_factor=0)
 
 
-def main(factors=(4, 2, 1), parts=(4, 4, 4)):
+def run(p, factors=(4, 2, 1), tol=1e-6, sources=None, label="5 Hz window"):
+    """The study on problem p (its own point sources unless `sources` is given); returns
+    {variant name: (iterations, largest residual)}."""
     t0 = time.perf_counter()
-    p = problem(parts=parts)
     om = fem.Mesh(p.tets, p.coords, p.face_bc)
     A = fem.assemble_operator(om, p.velocity, p.freq)
-    B = rhs.point_sources(om, p.sources).T
+    B = rhs.point_sources(om, p.sources if sources is None else sources).T
     subs, own = odd.build_subdomains(om, p.velocity, p.freq, None, p.partition, p.n_sub, p.overlap)
     odd.factor_subdomains(subs)
-    print(f"5 Hz window {p.grid} cubes, n = {om.n}, {p.n_sub} subdomains, set-up {time.perf_counter() - t0:.0f} s",
+    print(f"{label} {p.grid} cubes, n = {om.n}, {p.n_sub} subdomains, set-up {time.perf_counter() - t0:.0f} s",
           flush=True)
-    nx, ny, nz = p.grid
     xs = np.unique(p.coords[:, 0])
     ys = np.unique(p.coords[:, 1])
     zs = np.unique(p.coords[:, 2])
-    variants = [("one-level", None, None)]
+    variants = [("one-level", None)]
     for k in factors:
         ct, cc = w.kuhn_mesh(xs[::k], ys[::k], zs[::k])
         Z = odd.coarse_interpolation(om, ct, cc)
         cown = odd.coarse_owners(om, cc, own)
-        variants.append((f"two-level {k}x, exact coarse (nc = {cc.shape[0]})", odd.Coarse(Z, A), None))
-        variants.append((f"two-level {k}x, 10 GMRES + coarse ORAS", odd.InexactCoarse(Z, A, subs, cown), None))
+        variants.append((f"two-level {k}x, exact coarse (nc = {cc.shape[0]})", odd.Coarse(Z, A)))
+        variants.append((f"two-level {k}x, 10 GMRES + coarse ORAS", odd.InexactCoarse(Z, A, subs, cown)))
         print(f"coarse {k}x: {cc.shape[0]} coarse dofs ({time.perf_counter() - t0:.0f} s)", flush=True)
-    for name, coarse, _ in variants:
+    out = {}
+    for name, coarse in variants:
         t = time.perf_counter()
         P = odd.ORAS(A, subs, coarse)
-        X, info = krylov.block_fgmres(lambda x: A @ x, B, P.apply, tol=1e-6, m=40, max_iter=300)
+        X, info = krylov.block_fgmres(lambda x: A @ x, B, P.apply, tol=tol, m=40, max_iter=300)
         res = np.linalg.norm(B - A @ X, axis=0) / np.linalg.norm(B, axis=0)
+        out[name] = (info["iters"], float(res.max()))
         print(f"{name:44s} iterations {info['iters']:4d}  largest residual {res.max():.2e}  "
               f"({time.perf_counter() - t:.0f} s)", flush=True)
+    return out
+
+
+def main(factors=(4, 2, 1), parts=(4, 4, 4)):
+    return run(problem(parts=parts), factors)
 
 
 if __name__ == "__main__":
