@@ -478,9 +478,10 @@ def run_coarse_spaces(args):
 
 
 def run_local_solvers(args):
-    """The exact multifrontal factors against the level-0 incomplete ones (HZ_LOCAL_ICC) in the
-    workload's mixed-precision preconditioner: set-up time, stored entries (the exact factors'
-    nonzeros; L and D of the incomplete ones), device memory of the ddm, the time of one
+    """The exact multifrontal factors against the incomplete ones (HZ_LOCAL_ICC, level 0;
+    HZ_LOCAL_ICC_A2, on the pattern of A_i^2) in the workload's mixed-precision
+    preconditioner: set-up time, stored entries (the exact factors' nonzeros; L and D of the
+    incomplete ones), device memory of the ddm, the time of one
     16-column preconditioner apply (mean of 5, after 2 untimed), and FGMRES for the first 16
     sources (the workload's tolerance, block 16, restart 40, at most 300 iterations).  One JSON
     line."""
@@ -500,7 +501,9 @@ def run_local_solvers(args):
     Z = torch.empty_like(V)
     B = ctx.point_sources(mesh, p.sources[:16])
     res = {}
-    for label, ls in (("exact", hz.HZ_LOCAL_EXACT), ("icc", hz.HZ_LOCAL_ICC)):
+    kinds = {"exact": hz.HZ_LOCAL_EXACT, "icc": hz.HZ_LOCAL_ICC, "icc_a2": hz.HZ_LOCAL_ICC_A2}
+    for label in args.compare_local_solvers or list(kinds):
+        ls = kinds[label]
         torch.cuda.empty_cache()
         t0 = time.perf_counter()
         d = ctx.setup_ddm(op, p.partition, p.n_sub, p.overlap, coarse=coarse, precision=hz.HZ_PREC_MIXED,
@@ -508,7 +511,7 @@ def run_local_solvers(args):
         torch.cuda.synchronize()
         st = ctx.ddm_stats(d)
         r = {"setup_s": round(time.perf_counter() - t0, 2), "factor_s": round(st["factor_seconds"], 2),
-             "entries": st["icc_entries"] if ls == hz.HZ_LOCAL_ICC else st["factor_useful"],
+             "entries": st["factor_useful"] if ls == hz.HZ_LOCAL_EXACT else st["icc_entries"],
              "device_gb": round(st["device_bytes"] / 1e9, 2), "icc_levels": st["icc_levels"]}
         print(f"{label}: set-up {r}", file=sys.stderr, flush=True)
         for _ in range(2):
@@ -561,9 +564,10 @@ def main():
     ap.add_argument("--compare-coarse", type=int, nargs="+", metavar="K",
                     help="instead: the workload (mixed precision) one-level (K = 0) and with the P1 coarse space on "
                          "every K-th vertex plane: set-up, coarse dofs, iterations and time for 16 sources")
-    ap.add_argument("--compare-local-solvers", action="store_true",
+    ap.add_argument("--compare-local-solvers", nargs="*", choices=["exact", "icc", "icc_a2"], metavar="SOLVER",
                     help="instead: the workload's preconditioner (mixed precision) with exact and with incomplete "
-                         "local factors: set-up, stored entries, 16-column apply time, iterations for 16 sources")
+                         "local factors (exact, icc, icc_a2; default all): set-up, stored entries, 16-column "
+                         "apply time, iterations for 16 sources")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the solver runs on one GPU only (no collectives); use --gpus 1", file=sys.stderr)
@@ -571,7 +575,7 @@ def main():
     if args.serve:
         run_serve(args)
         return
-    if args.compare_local_solvers:
+    if args.compare_local_solvers is not None:
         run_local_solvers(args)
         return
     if args.compare_coarse:

@@ -58,7 +58,7 @@ enum { HZ_PREC_C128 = 0, HZ_PREC_MIXED = 1 };
 enum { HZ_MEM_HOST = 0, HZ_MEM_DEVICE = 1 };
 enum { HZ_POU_BOOLEAN = 0, HZ_POU_SMOOTH = 1 };
 /* local solver of the one-level preconditioner (hz_ddm_opts.local_solver) */
-enum { HZ_LOCAL_EXACT = 0, HZ_LOCAL_ICC = 1 };
+enum { HZ_LOCAL_EXACT = 0, HZ_LOCAL_ICC = 1, HZ_LOCAL_ICC_A2 = 2 };
 
 typedef struct {
   size_t struct_size;  /* sizeof(hz_init_opts)                                        */
@@ -159,6 +159,9 @@ hz_status hz_setup_ddm(hz_ctx* ctx, hz_handle op, const int32_t* partition, int3
  *                    the solve is forward substitution, scaling by D^{-1} and backward
  *                    substitution, one launch per dependency level.  The multifrontal factors
  *                    are then not built (hz_ddm_stats still reports their symbolic size).
+ *                    HZ_LOCAL_ICC_A2: the same factorisation on the lower pattern of A_i^2
+ *                    (every pair of local dofs joined through one neighbour; entries of A_i
+ *                    absent there start from zero).
  * Errors: as hz_setup_ddm; HZ_ERR_ABI on struct_size; HZ_ERR_ARG on an unknown pou or local
  * solver or an overlap above 250; HZ_ERR_SINGULAR when the incomplete factorisation meets a
  * zero or non-finite pivot.
@@ -167,7 +170,7 @@ typedef struct {
   size_t struct_size;  /* sizeof(hz_ddm_opts) */
   int precision;       /* HZ_PREC_C128 or HZ_PREC_MIXED */
   int pou;             /* HZ_POU_BOOLEAN or HZ_POU_SMOOTH */
-  int local_solver;    /* HZ_LOCAL_EXACT or HZ_LOCAL_ICC */
+  int local_solver;    /* HZ_LOCAL_EXACT, HZ_LOCAL_ICC or HZ_LOCAL_ICC_A2 */
 } hz_ddm_opts;
 hz_status hz_setup_ddm_ex(hz_ctx* ctx, hz_handle op, const int32_t* partition, int32_t n_sub,
                           int32_t overlap, const hz_coarse_mesh* coarse, const hz_ddm_opts* opts,
@@ -280,9 +283,9 @@ typedef struct {
   double factor_flops;        /* its algorithmic real flops: 8 per complex multiply-add of the
                                  diagonal blocks, panel solves, trailing updates and the
                                  partitioned inverse (direct complex form); 0 with HZ_LOCAL_ICC */
-  int64_t local_solver;       /* HZ_LOCAL_EXACT or HZ_LOCAL_ICC */
-  int64_t icc_entries;        /* HZ_LOCAL_ICC: stored entries of L (strict lower) and D; else 0 */
-  int64_t icc_levels;         /* HZ_LOCAL_ICC: dependency levels of the forward substitution */
+  int64_t local_solver;       /* HZ_LOCAL_EXACT, HZ_LOCAL_ICC or HZ_LOCAL_ICC_A2 */
+  int64_t icc_entries;        /* incomplete factors: stored entries of L (strict lower) and D; else 0 */
+  int64_t icc_levels;         /* incomplete factors: dependency levels of the forward substitution */
 } hz_ddm_stats;
 hz_status hz_ddm_stats_get(hz_ctx* ctx, hz_handle ddm, hz_ddm_stats* out);
 

@@ -377,7 +377,8 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
   HZ_REQUIRE(partition && n_sub >= 1 && overlap >= 0, HZ_ERR_ARG, "hz_setup_ddm: bad arguments");
   HZ_REQUIRE(precision == HZ_PREC_C128 || precision == HZ_PREC_MIXED, HZ_ERR_ARG, "hz_setup_ddm: bad precision");
   HZ_REQUIRE(pou == HZ_POU_BOOLEAN || pou == HZ_POU_SMOOTH, HZ_ERR_ARG, "hz_setup_ddm: bad partition of unity");
-  HZ_REQUIRE(local_solver == HZ_LOCAL_EXACT || local_solver == HZ_LOCAL_ICC, HZ_ERR_ARG,
+  HZ_REQUIRE(local_solver == HZ_LOCAL_EXACT || local_solver == HZ_LOCAL_ICC || local_solver == HZ_LOCAL_ICC_A2,
+             HZ_ERR_ARG,
              "hz_setup_ddm: bad local solver");
   HZ_REQUIRE(overlap <= 250, HZ_ERR_ARG, "hz_setup_ddm: overlap above 250 layers");
   std::vector<int32_t> part(partition, partition + m.T);
@@ -899,7 +900,7 @@ std::shared_ptr<Ddm> build_ddm(Ctx* ctx, std::shared_ptr<Operator> op, const int
     }
     d->factor_flops = 8.0 * cm;
   }
-  if (local_solver == HZ_LOCAL_ICC) {
+  if (local_solver != HZ_LOCAL_EXACT) {
     // the incomplete factors replace the exact ones (whose symbolic size stays reported)
     icc_setup(ctx, *d);
     phase("incomplete factorisation");

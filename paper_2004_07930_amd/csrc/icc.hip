@@ -2,7 +2,8 @@
 // (its comparison of complete and incomplete Cholesky for the local matrices of eq. (oras)).
 // The paper names no variant; the reading taken is level 0 without fill: A_i ~ L D L^T with L
 // unit lower triangular on the strict lower pattern of A_i (transpose, not conjugate, since
-// A_i is complex symmetric), in the local order of A_i, no shift and no pivoting.
+// A_i is complex symmetric), in the local order of A_i, no shift and no pivoting.  A variant
+// keeps L on the lower pattern of A_i^2 instead (rows joined through one neighbour).
 //
 // Set-up: the host lists each row's strict lower entries and both substitutions' dependency
 // levels (a row's level is one more than the deepest row it reads); the numeric factorisation
@@ -37,7 +38,9 @@ __global__ __launch_bounds__(256) void k_icc_factor(int nrows, const int32_t* __
   const int64_t b0 = lp[i], b1 = lp[i + 1];
   for (int64_t k = b0; k < b1; ++k) {
     const int32_t j = lc[k];
-    c128 acc = a[src[k]];
+    const int64_t sk = src[k];
+    c128 acc = cmk(0.0, 0.0);
+    if (sk >= 0) acc = a[sk];  // a fill position starts from zero
     int64_t x = b0, y = lp[j];
     const int64_t ye = lp[j + 1];
     while (x < k && y < ye) {
@@ -171,35 +174,86 @@ void icc_setup(Ctx* ctx, Ddm& d) {
   const int64_t nl = d.n_local_total;
   HZ_REQUIRE(nl < (int64_t)INT32_MAX, HZ_ERR_ARG, "incomplete factorisation: over 2^31 local rows");
   auto F = std::make_unique<IccFactor>();
-  // strict lower rows (columns ascending) with the index of each value in the local operator,
-  // and each row's diagonal entry
-  std::vector<int64_t> lp((size_t)nl + 1, 0), dsrc((size_t)nl, -1);
-  for (const Subdomain& S : d.subs)
-    for (int64_t l = 0; l < S.n; ++l) {
-      int64_t c = 0;
-      for (int64_t k = S.rowptr[l]; k < S.rowptr[l + 1]; ++k) c += S.col[k] < l;
-      lp[(size_t)(S.vec_off + l) + 1] = c;
+  // strict lower rows (columns ascending) with the index of each value in the local operator
+  // (-1 for a fill position, whose value in A_i is zero), and each row's diagonal entry; with
+  // the square pattern a row also holds every earlier column joined to it through one
+  // neighbour (the lower pattern of A_i^2).  One subdomain per task.
+  const bool square = d.local_solver == HZ_LOCAL_ICC_A2;
+  const int64_t ns = (int64_t)d.subs.size();
+  std::vector<std::vector<int32_t>> scol((size_t)ns);
+  std::vector<std::vector<int64_t>> ssrc((size_t)ns), sptr((size_t)ns);
+  std::vector<int64_t> dsrc((size_t)nl, -1);
+  parallel_for(ns, [&](int64_t b, int64_t e) {
+    std::vector<std::pair<int32_t, int64_t>> row;
+    for (int64_t i = b; i < e; ++i) {
+      const Subdomain& S = d.subs[(size_t)i];
+      auto& C = scol[(size_t)i];
+      auto& R = ssrc[(size_t)i];
+      auto& P = sptr[(size_t)i];
+      P.assign((size_t)S.n + 1, 0);
+      std::vector<int32_t> mark(square ? (size_t)S.n : 0, -1);
+      for (int64_t l = 0; l < S.n; ++l) {
+        row.clear();
+        for (int64_t k = S.rowptr[l]; k < S.rowptr[l + 1]; ++k) {
+          const int32_t c = S.col[k];
+          if (c < l) {
+            row.emplace_back(c, S.csr_off + k);
+            if (square) mark[(size_t)c] = (int32_t)l;
+          } else if (c == l) {
+            dsrc[(size_t)(S.vec_off + l)] = S.csr_off + k;
+          }
+        }
+        if (square)
+          for (int64_t k = S.rowptr[l]; k < S.rowptr[l + 1]; ++k) {
+            const int32_t j = S.col[k];
+            for (int64_t kk = S.rowptr[j]; kk < S.rowptr[j + 1]; ++kk) {
+              const int32_t c = S.col[kk];
+              if (c < l && mark[(size_t)c] != (int32_t)l) {
+                mark[(size_t)c] = (int32_t)l;
+                row.emplace_back(c, -1);
+              }
+            }
+          }
+        std::sort(row.begin(), row.end());
+        for (const auto& pr : row) {
+          C.push_back(pr.first);
+          R.push_back(pr.second);
+        }
+        P[(size_t)l + 1] = (int64_t)C.size();
+      }
     }
-  for (int64_t r = 0; r < nl; ++r) lp[(size_t)r + 1] += lp[(size_t)r];
+  });
+  std::vector<int64_t> lp((size_t)nl + 1, 0);
+  {
+    int64_t base = 0, rows = 0;
+    for (int64_t i = 0; i < ns; ++i) {
+      const Subdomain& S = d.subs[(size_t)i];
+      HZ_REQUIRE(S.vec_off == rows, HZ_ERR_STATE, "incomplete factorisation: local vectors not contiguous");
+      for (int64_t l = 0; l < S.n; ++l) lp[(size_t)(S.vec_off + l)] = base + sptr[(size_t)i][(size_t)l];
+      base += (int64_t)scol[(size_t)i].size();
+      rows += S.n;
+    }
+    HZ_REQUIRE(rows == nl, HZ_ERR_STATE, "incomplete factorisation: row count");
+    lp[(size_t)nl] = base;
+  }
   const int64_t nnz = lp[(size_t)nl];
   std::vector<int32_t> lc((size_t)nnz);
   std::vector<int64_t> src((size_t)nnz);
-  for (const Subdomain& S : d.subs)
-    for (int64_t l = 0; l < S.n; ++l) {
-      std::vector<std::pair<int32_t, int64_t>> row;
-      for (int64_t k = S.rowptr[l]; k < S.rowptr[l + 1]; ++k) {
-        if (S.col[k] < l) row.emplace_back(S.col[k], k);
-        if (S.col[k] == l) dsrc[(size_t)(S.vec_off + l)] = S.csr_off + k;
+  parallel_for(ns, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) {
+      const Subdomain& S = d.subs[(size_t)i];
+      const int64_t o = lp[(size_t)S.vec_off];
+      const auto& C = scol[(size_t)i];
+      for (size_t q = 0; q < C.size(); ++q) {
+        lc[(size_t)o + q] = (int32_t)(S.vec_off + C[q]);
+        src[(size_t)o + q] = ssrc[(size_t)i][q];
       }
-      std::sort(row.begin(), row.end());
-      int64_t e = lp[(size_t)(S.vec_off + l)];
-      for (const auto& pr : row) {
-        lc[(size_t)e] = (int32_t)(S.vec_off + pr.first);
-        src[(size_t)e] = S.csr_off + pr.second;
-        ++e;
-      }
-      HZ_REQUIRE(dsrc[(size_t)(S.vec_off + l)] >= 0, HZ_ERR_STATE, "incomplete factorisation: row without diagonal");
+      std::vector<int32_t>().swap(scol[(size_t)i]);
+      std::vector<int64_t>().swap(ssrc[(size_t)i]);
     }
+  });
+  for (int64_t r = 0; r < nl; ++r)
+    HZ_REQUIRE(dsrc[(size_t)r] >= 0, HZ_ERR_STATE, "incomplete factorisation: row without diagonal");
   // the same entries by column: the rows of L^T (rows ascending within a column)
   std::vector<int64_t> up((size_t)nl + 1, 0);
   for (int64_t e = 0; e < nnz; ++e) ++up[(size_t)lc[(size_t)e] + 1];

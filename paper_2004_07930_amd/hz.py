@@ -23,7 +23,7 @@ HZ_BC_NONE, HZ_BC_IMPEDANCE, HZ_BC_DIRICHLET = 0, 1, 2
 HZ_PREC_C128, HZ_PREC_MIXED = 0, 1
 HZ_MEM_HOST, HZ_MEM_DEVICE = 0, 1
 HZ_POU_BOOLEAN, HZ_POU_SMOOTH = 0, 1
-HZ_LOCAL_EXACT, HZ_LOCAL_ICC = 0, 1
+HZ_LOCAL_EXACT, HZ_LOCAL_ICC, HZ_LOCAL_ICC_A2 = 0, 1, 2
 
 _STATUS = {0: "HZ_OK", -1: "HZ_ERR_ARG", -2: "HZ_ERR_OOM", -3: "HZ_ERR_HIP", -4: "HZ_ERR_NOT_CONVERGED",
            -5: "HZ_ERR_SINGULAR", -6: "HZ_ERR_BUSY", -7: "HZ_ERR_STATE", -8: "HZ_ERR_ABI"}

@@ -201,3 +201,39 @@ def test_icc_iterations_and_entries_vs_exact(name, ctx):
           f"(residual {res['icc'][1]:.1e}, {res['icc'][2]} entries, {res['icc'][3]} device bytes)", flush=True)
     assert res["exact"][1] <= 1e-8
     assert res["icc"][2] < res["exact"][2]
+
+
+@pytest.mark.parametrize("name", ["cube3"])
+def test_icc_square_pattern_matches_oracle(name, ctx):
+    """Incomplete factors on the pattern of A_i^2 (HZ_LOCAL_ICC_A2) against the oracle's
+    (oracle/icc.py with_square_pattern): the same stored entries, preconditioner within 1e-10
+    (FP64) and 1e-4 per column (mixed), fixed-iteration FGMRES within 1e-10.  (The layered
+    case passes too; its pure-Python oracle factorisation takes over a minute.)"""
+    from paper_2004_07930_amd import hz
+
+    p = CASES[name]()
+    om = fem.Mesh(p.tets, p.coords, p.face_bc)
+    A = fem.assemble_operator(om, p.velocity, p.freq, p.quality)
+    gm = ctx.mesh(p.tets, p.coords, p.face_bc)
+    gop = ctx.assemble(gm, p.velocity, p.freq, p.quality)
+    subs, _ = odd.build_subdomains(om, p.velocity, p.freq, p.quality, p.partition, p.n_sub, p.overlap)
+    icc.factor_subdomains_icc(subs, square_pattern=True)
+    P = odd.ORAS(A, subs)
+    d = ctx.setup_ddm(gop, p.partition, p.n_sub, p.overlap, local_solver=hz.HZ_LOCAL_ICC_A2)
+    st = ctx.ddm_stats(d)
+    assert st["local_solver"] == hz.HZ_LOCAL_ICC_A2
+    assert st["icc_entries"] == sum(s.lu.L.nnz + s.lu.n for s in subs)
+    rng = np.random.default_rng(35)
+    V = rng.standard_normal((16, om.n)) + 1j * rng.standard_normal((16, om.n))
+    Zo = P.apply(V.T).T
+    for s in (1, 16):
+        assert _rel(ctx.precond(d, V[:s]), Zo[:s]) <= 1e-10, (name, s)
+    X, info = ctx.solve(d, V[:3], fixed_iters=4, restart=4)
+    Xo, io = krylov.block_fgmres(lambda x: A @ x, V[:3].T, P.apply, fixed_iters=4, m=4)
+    assert _rel(X, Xo.T) <= 1e-10
+    ctx.release(d)
+    d32 = ctx.setup_ddm(gop, p.partition, p.n_sub, p.overlap, precision=hz.HZ_PREC_MIXED,
+                        local_solver=hz.HZ_LOCAL_ICC_A2)
+    Z = ctx.precond(d32, V)
+    assert max(_rel(Z[c], Zo[c]) for c in range(16)) <= 1e-4
+    ctx.release(d32)

@@ -40,3 +40,32 @@ def test_icc_matches_operator_on_its_pattern():
     assert np.max(np.abs(got - low.data)) <= 1e-12 * np.max(np.abs(low.data))
     # and it is incomplete: the product has entries (dropped fill) outside that pattern
     assert sp.tril(M).tocsr().nnz > sp.tril(A_i).nnz
+
+
+def test_icc_square_pattern_matches_operator_on_its_pattern():
+    """ICC on the pattern of A_i^2: L D L^T equals A_i on the lower part of that pattern (zero on
+    its fill positions), the pattern contains A_i's, and the filled factors solve closer to the
+    exact solution than the level-0 ones."""
+    p = w.unit_cube_problem(3, freq=2.0, parts=(2, 1, 1), overlap=1)
+    om = fem.Mesh(p.tets, p.coords, p.face_bc)
+    subs, _ = odd.build_subdomains(om, p.velocity, p.freq, None, p.partition, p.n_sub, p.overlap)
+    A_i = subs[0].A.tocsr()
+    F2 = icc.with_square_pattern(A_i)
+    assert F2.nnz > A_i.nnz
+    low = sp.tril(A_i).tocoo()
+    low2_all = sp.tril(F2).tocoo()
+    pat2 = set(zip(low2_all.row.tolist(), low2_all.col.tolist()))
+    assert set(zip(low.row.tolist(), low.col.tolist())) <= pat2
+    f = icc.ICC(F2)
+    I = sp.identity(f.n, format="csr")
+    M = ((I + f.L) @ sp.diags(f.d) @ (I + f.L).T).tocsr()
+    low2 = sp.tril(F2).tocoo()
+    got = np.asarray(M[low2.row, low2.col]).ravel()
+    want = np.asarray(A_i[low2.row, low2.col]).ravel()
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(A_i.data))
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(f.n) + 1j * rng.standard_normal(f.n)
+    x = spla.spsolve(A_i.tocsc(), b)
+    e2 = np.linalg.norm(f.solve(b) - x)
+    e0 = np.linalg.norm(icc.ICC(A_i).solve(b) - x)
+    assert e2 < e0
