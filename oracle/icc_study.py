@@ -1,10 +1,11 @@
 """Study (oracle only): ORAS-FGMRES iterations with exact and incomplete local solves.
 
 TEST INFRASTRUCTURE ONLY.  Prints, for the unit cube at k = 8 pi (6 x 6 x 6 cubes, P3, 8
-subdomains, overlap 1, one random right-hand side, tol 1e-8, restart 40, at most 200
-iterations), the iteration count and final residual of ORAS-FGMRES with the local operators
-factored exactly (SuperLU), by ICC (level 0, natural and reverse Cuthill-McKee orders), and by
-the same incomplete factorisation on the pattern of A_i^2 (level-one fill and more).
+subdomains, overlap 1) and the layered model at 0.4 Hz (8 x 8 x 4 cubes, 4 subdomains,
+overlap 1), with one random right-hand side, tol 1e-8, restart 40, at most 200 iterations,
+the iteration count and final residual of ORAS-FGMRES with the local operators factored
+exactly (SuperLU), by ICC (level 0; natural and, on the cube, reverse Cuthill-McKee order),
+and by the same incomplete factorisation on the pattern of A_i^2 (level-one fill and more).
 
     python3 -m oracle.icc_study
 """
@@ -44,15 +45,24 @@ class _Permuted:
 
 
 def main():
+    study(w.unit_cube_problem(6), "unit cube 6^3, k = 8 pi", full=True)
+    study(w.layered_problem(freq=0.4, r=1.4, parts=(2, 2, 1), overlap=1, n_sources=(2, 2),
+                            max_cubes=(8, 8, 4)), "layered 8x8x4 cubes, 0.4 Hz", full=False)
+
+
+def study(p, label, full=True):
+    """Exact and incomplete local factors on problem p (one random right-hand side, tol 1e-8,
+    restart 40, at most 200 iterations); full: also ICC(0) in reverse Cuthill-McKee order."""
     rng = np.random.default_rng(0)
-    p = w.unit_cube_problem(6)
     om = fem.Mesh(p.tets, p.coords, p.face_bc)
-    A = fem.assemble_operator(om, p.velocity, p.freq)
-    subs, _ = odd.build_subdomains(om, p.velocity, p.freq, None, p.partition, p.n_sub, p.overlap)
+    A = fem.assemble_operator(om, p.velocity, p.freq, p.quality)
+    subs, _ = odd.build_subdomains(om, p.velocity, p.freq, p.quality, p.partition, p.n_sub, p.overlap)
     B = rng.standard_normal((om.n, 1)) + 1j * rng.standard_normal((om.n, 1))
-    print(f"unit cube 6^3, n = {om.n}, subdomains of {min(s.gdofs.size for s in subs)}-{max(s.gdofs.size for s in subs)} dofs")
-    variants = [("exact (SuperLU)", None), ("ICC(0), natural order", (False, False)),
-                ("ICC(0), reverse Cuthill-McKee", (True, False)), ("incomplete, pattern of A^2", (False, True))]
+    print(f"{label}, n = {om.n}, subdomains of {min(s.gdofs.size for s in subs)}-{max(s.gdofs.size for s in subs)} dofs")
+    variants = [("exact (SuperLU)", None), ("ICC(0), natural order", (False, False))]
+    if full:
+        variants.append(("ICC(0), reverse Cuthill-McKee", (True, False)))
+    variants.append(("incomplete, pattern of A^2", (False, True)))
     for name, v in variants:
         t = time.perf_counter()
         if v is None:
