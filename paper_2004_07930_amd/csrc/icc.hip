@@ -177,7 +177,8 @@ void icc_setup(Ctx* ctx, Ddm& d) {
   // strict lower rows (columns ascending) with the index of each value in the local operator
   // (-1 for a fill position, whose value in A_i is zero), and each row's diagonal entry; with
   // the square pattern a row also holds every earlier column joined to it through one
-  // neighbour (the lower pattern of A_i^2).  One subdomain per task.
+  // neighbour (the lower pattern of A_i^2).  One subdomain per task of parallel_for (which runs
+  // serially for fewer than 4096 tasks, so for any realistic subdomain count).
   const bool square = d.local_solver == HZ_LOCAL_ICC_A2;
   const int64_t ns = (int64_t)d.subs.size();
   std::vector<std::vector<int32_t>> scol((size_t)ns);
