@@ -304,3 +304,19 @@ def test_gcrodr_recycling_deflates_a_positive_definite_operator():
         assert info["rel_residual"] <= 1e-8
         its.append(info["iters"])
     assert its[0] < 250 and its[1] < 0.8 * its[0] and its[2] < 0.8 * its[0], its
+
+
+def test_inexact_coarse_full_overlap_is_exact():
+    """Two subdomains that each grow over the whole cube: every local coarse operator is E,
+    so the coarse ORAS (each coarse dof taken from its owner only) is E^{-1} itself (summing the
+    two subdomains' results instead would give 2 E^{-1}), and one GMRES step is exact."""
+    p, mesh, A, subs, Z, cown = _cube_with_coarse(4, (2, 1, 1), overlap=4)
+    assert all(s.gdofs.size == mesh.n for s in subs)
+    ic = ddm.InexactCoarse(Z, A, subs, cown, iters=1)
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal((Z.shape[1], 2)) + 1j * rng.standard_normal((Z.shape[1], 2))
+    Ed = ic.E.toarray()
+    assert np.linalg.norm(ic.precond(r) - np.linalg.solve(Ed, r)) <= 1e-10 * np.linalg.norm(np.linalg.solve(Ed, r))
+    V = rng.standard_normal((mesh.n, 2)) + 1j * rng.standard_normal((mesh.n, 2))
+    exact = ddm.Coarse(Z, A).solve(V)
+    assert np.linalg.norm(ic.solve(V) - exact) <= 1e-10 * np.linalg.norm(exact)
