@@ -163,8 +163,9 @@ hz_status hz_setup_ddm(hz_ctx* ctx, hz_handle op, const int32_t* partition, int3
  *                    (every pair of local dofs joined through one neighbour; entries of A_i
  *                    absent there start from zero).  It stores about 11 times the entries of
  *                    level 0 (P3 on tets).  Memory per stored entry: on the device the value
- *                    (8 or 16 bytes) and 24 bytes of column, row and position indices; on the
- *                    host during set-up about 36 bytes.
+ *                    (8 or 16 bytes) and 16 bytes of column, row and position indices, plus 24
+ *                    bytes during set-up (its source index and FP64 working value); on the
+ *                    host up to 36 bytes during set-up.
  * Errors: as hz_setup_ddm; HZ_ERR_ABI on struct_size; HZ_ERR_ARG on an unknown pou or local
  * solver or an overlap above 250; HZ_ERR_SINGULAR when the incomplete factorisation meets a
  * zero or non-finite pivot.
